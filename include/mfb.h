@@ -1,0 +1,198 @@
+/*
+ * mfb.h -- multifrontal log-det barrier kernels for one AMD MI355X (gfx950).
+ *
+ * The library evaluates the logarithmic barrier f(X) = -log det X of the
+ * cone of positive definite matrices with a filled (chordal) sparsity
+ * pattern V, and the dual barrier f_*, by the supernodal multifrontal
+ * recursions of Andersen, Dahl and Vandenberghe, "Logarithmic barriers for
+ * sparse matrix cones":
+ *
+ *   factor                X = L D L^T over the clique tree (Algorithm 7.1)
+ *   logdet                log det X, so f(X) = -logdet (Section 1.1)
+ *   projected_inverse     S = P(X^-1) = -grad f(X) (eq. e-grad-def, Algorithm 7.2)
+ *   hessian               T = P(X^-1 Y X^-1) for k matrices Y (Section 5.2, Algorithm 5.1
+ *                         in block form)
+ *   inv_hessian           Y = H^-1(T), i.e. solve P(X^-1 Y X^-1) = T (Section 5.3,
+ *                         Algorithm 5.2 in block form)
+ *   completion            the factor of X-hat with P(X-hat^-1) = S, i.e. -grad f_*(S)
+ *                         (eq. e-Xhat-eq, Algorithm 7.3); f_*(S) = log det X-hat - n
+ *   cholesky_product      values of L D L^T on V (Algorithm 3.2 in block form)
+ *   factor_export_ldl     the scalar factors D, L in the pattern's CCS order
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Values.  All numeric values are IEEE double.  A symmetric matrix in S^n_V
+ * is passed as its lower triangle (diagonal included) in the compressed
+ * column (CCS) order of the pattern handed to mfb_plan_symbolic: one double
+ * per pattern entry, column by column, rows ascending.  k right-hand sides
+ * are k such arrays stored back to back (k * nnz doubles).
+ *
+ * Memory.  Pointers named *_dev are device pointers on the current HIP
+ * device; pointers named *_host are host pointers.  The caller owns every
+ * value array, every workspace and every arena and keeps them alive until
+ * the work that uses them has completed on the stream.  The library owns
+ * only its opaque handles and the plan's device-resident index arrays
+ * (allocated once in mfb_plan_symbolic, freed by mfb_plan_destroy).  The
+ * numeric entry points do not allocate device memory.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Numeric entry points only enqueue work.  Argument and state
+ * errors are returned synchronously (MFB_EINVAL, MFB_ESTATE) and enqueue
+ * nothing.  Numerical failures (a pivot block that is not positive
+ * definite) are recorded on the device and read back by mfb_get_status;
+ * outputs computed after such a failure are unspecified.  A factor handle
+ * may be used from one stream at a time.
+ *
+ * Determinism.  Children are assembled in a fixed order and no atomics are
+ * used, so repeated calls with equal inputs give bitwise equal outputs.
+ */
+#ifndef MFB_H
+#define MFB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mfb_status_t;
+#define MFB_OK 0
+#define MFB_EINVAL 1          /* bad argument (null pointer, bad CCS, k < 0, short buffer) */
+#define MFB_ENOTCHORDAL 2     /* the pattern is not filled in the given order */
+#define MFB_ENOTPD 3          /* X (or the S_AA blocks for inv_hessian) not positive definite */
+#define MFB_ENOCOMPLETION 4   /* S has no positive definite completion */
+#define MFB_ENOMEM 5          /* host or device allocation failed */
+#define MFB_EHIP 6            /* a HIP runtime call failed */
+#define MFB_ESTATE 7          /* call order violated (e.g. hessian before factor) */
+
+typedef struct mfb_plan_s* mfb_plan_t;
+typedef struct mfb_factor_s* mfb_factor_t;
+
+/* Plan flags. */
+#define MFB_PLAN_TIE_LAST 1u  /* Pothen-Sun tie-break: join the highest-labelled
+                                 eligible child instead of the lowest */
+
+typedef struct {
+  int64_t n;                 /* order of X */
+  int64_t nnz;               /* entries of V in the lower triangle, diagonal included */
+  int64_t nsuper;            /* supernodes (cliques) */
+  int64_t nlevels_up;        /* levels of the leaf-to-root schedule (tree height + 1) */
+  int64_t nlevels_down;      /* levels of the root-to-leaf schedule (tree depth + 1) */
+  int64_t max_front;         /* max |J_s| = |N_s| + |A_s| */
+  int64_t max_ncols;         /* max |N_s| */
+  int64_t max_nanc;          /* max |A_s| */
+  int64_t update_doubles;    /* sum over supernodes of |A|(|A|+1)/2 */
+  size_t factor_workspace_bytes;  /* device bytes for mfb_factor_create */
+  size_t rhs_arena_bytes;         /* device bytes per right-hand side for hessian/inv_hessian */
+  /* canonical algorithmic flop counts (LAPACK conventions, summed per supernode) */
+  double flops_factor, flops_projinv, flops_hessian, flops_inv_hessian, flops_inv_hessian_x,
+      flops_completion, flops_product;
+} mfb_plan_info_t;
+
+/* Symbolic analysis of a filled pattern (Sections 2 and 6; Algorithm 6.1).
+ *   n          order (>= 0).
+ *   colptr_host  int64[n+1], colptr[0] = 0, strictly increasing.
+ *   rowind_host  int32[colptr[n]]: rows of each column, sorted ascending, the
+ *              diagonal first, all < n.  Both arrays are read during the call only.
+ *   flags      MFB_PLAN_* bits.
+ *   out        receives the plan; immutable afterwards and safe to share between
+ *              factor handles and threads.
+ * Builds the elimination tree (parent(j) = min I_j), checks that the pattern is
+ * filled in the given order (I_j \ {parent} within I_parent for every j:
+ * eqs. e-filled, e-etree-ch), forms the supernodes and the clique tree by the
+ * Pothen-Sun algorithm, the relative indices of every A_s inside its parent
+ * clique, and the level schedules, and uploads the index arrays to the current
+ * device.  Returns MFB_EINVAL for malformed CCS, MFB_ENOTCHORDAL when the
+ * pattern is not filled, MFB_ENOMEM / MFB_EHIP on allocation failure. */
+mfb_status_t mfb_plan_symbolic(int64_t n, const int64_t* colptr_host, const int32_t* rowind_host,
+                               uint32_t flags, mfb_plan_t* out);
+
+/* Sizes, workspace requirements and canonical flop counts of a plan. */
+mfb_status_t mfb_plan_info(mfb_plan_t plan, mfb_plan_info_t* out_host);
+
+/* The supernode partition and clique tree (Section 6.2-6.3), for inspection.
+ *   snode_of_host  int32[n]: supernode of every column (0-based, clique-tree
+ *                  postorder numbering), may be NULL.
+ *   sparent_host   int32[nsuper]: parent supernode, -1 for roots, may be NULL.
+ *   srep_host      int32[nsuper]: representative vertex (min N_s), may be NULL. */
+mfb_status_t mfb_plan_supernodes(mfb_plan_t plan, int32_t* snode_of_host, int32_t* sparent_host,
+                                 int32_t* srep_host);
+
+/* Frees the plan and its device arrays.  No factor handle may still use it. */
+void mfb_plan_destroy(mfb_plan_t plan);
+
+/* Numeric state for one X on one plan.
+ *   workspace_dev  device buffer of at least plan_info.factor_workspace_bytes,
+ *                  256-byte aligned; owned by the caller, used until
+ *                  mfb_factor_destroy.  It holds the Cholesky factor, the
+ *                  cached projected inverse and the per-supernode S_AA blocks.
+ * Returns MFB_EINVAL for a short or misaligned buffer. */
+mfb_status_t mfb_factor_create(mfb_plan_t plan, void* workspace_dev, size_t workspace_bytes,
+                               mfb_factor_t* out);
+
+/* Frees the handle (never the caller's memory). */
+void mfb_factor_destroy(mfb_factor_t f);
+
+/* Algorithm 7.1: factor X = L D L^T (x_dev: nnz doubles, read only).
+ * Invalidates the cached projected inverse.  A pivot block that is not
+ * positive definite sets MFB_ENOTPD (see mfb_get_status). */
+mfb_status_t mfb_factor(mfb_factor_t f, const double* x_dev, void* stream);
+
+/* log det X = sum over supernodes of log det D_NN (Section 1.1, f = -logdet),
+ * written as one double to out_dev.  Requires a factor (mfb_factor or
+ * mfb_completion); for a completion it is log det X-hat, and
+ * f_*(S) = logdet - n. */
+mfb_status_t mfb_logdet(mfb_factor_t f, double* out_dev, void* stream);
+
+/* Algorithm 7.2: S = P(X^-1) (eq. e-sn-gradient-1/2) written to s_dev
+ * (nnz doubles).  The result is also cached in the handle for hessian and
+ * inv_hessian.  s_dev may be NULL to fill the cache only. */
+mfb_status_t mfb_projected_inverse(mfb_factor_t f, double* s_dev, void* stream);
+
+/* Hessian of f at X applied to k matrices (Section 5.2):
+ *   t_r = P(X^-1 y_r X^-1),  r = 0..k-1.
+ *   y_dev, t_dev: k*nnz doubles each (may not overlap).
+ *   arena_dev: at least k * plan_info.rhs_arena_bytes device bytes,
+ *   256-byte aligned, caller-owned scratch.
+ * Computes the projected inverse first if it is not cached.  k = 0 is a
+ * no-op. */
+mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y_dev, double* t_dev,
+                         void* arena_dev, size_t arena_bytes, void* stream);
+
+/* Inverse Hessian (Section 5.3): y_r = H^-1(t_r), the unique y_r in S^n_V
+ * with P(X^-1 y_r X^-1) = t_r.  Same buffer rules as mfb_hessian.  Uses and
+ * caches (S_AA)^-1 per supernode for the current X. */
+mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t_dev, double* y_dev,
+                             void* arena_dev, size_t arena_bytes, void* stream);
+
+/* Algorithm 7.3: matrix completion.  Given S in S^n_V with a positive definite
+ * completion (s_dev, nnz doubles), replaces the handle's factor by the factor
+ * of X-hat, the X in S^n_V with P(X^-1) = S (eq. e-Xhat-eq); S itself becomes
+ * the cached projected inverse.  Failure (S_AA or a Schur complement not
+ * positive definite) sets MFB_ENOCOMPLETION. */
+mfb_status_t mfb_completion(mfb_factor_t f, const double* s_dev, void* stream);
+
+/* Algorithm 3.2 (block form): values of L D L^T on V, written to x_dev
+ * (nnz doubles).  For a completion this gives X-hat = -grad f_*(S). */
+mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x_dev, void* stream);
+
+/* The scalar factorization X = L D L^T with unit lower L (Section 2): D_jj
+ * in the diagonal slot of column j and L_ij in the strict-lower slots, in
+ * the pattern's CCS order (ldl_dev, nnz doubles).  Unique for positive
+ * definite X, hence independent of the supernode partition. */
+mfb_status_t mfb_factor_export_ldl(mfb_factor_t f, double* ldl_dev, void* stream);
+
+/* Synchronizes the handle's last stream and reports the first numerical
+ * failure since the last mfb_factor / mfb_completion: MFB_OK, MFB_ENOTPD or
+ * MFB_ENOCOMPLETION.  *bad_index_host (may be NULL) receives the failing
+ * column in the user's labels, or -1. */
+mfb_status_t mfb_get_status(mfb_factor_t f, int64_t* bad_index_host);
+
+/* Static description of a status code. */
+const char* mfb_strerror(mfb_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFB_H */

@@ -1,0 +1,476 @@
+// C-ABI entry points: plan upload, workspace layout, level-scheduled
+// launches and status readback.  Every numeric step runs in the kernels of
+// kernels.hip; this file only marshals.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "mfb_internal.h"
+
+#include "kernels.h"
+
+namespace mfb {
+constexpr size_t ALIGN = 256;
+static inline size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Scratch (doubles per workgroup) of each kernel for a level's largest front.
+enum Op { OP_FACTOR, OP_PRODUCT, OP_COMPLETION, OP_VINV, OP_HUP, OP_HDOWN, OP_IHDOWN, OP_IHUP };
+static int64_t slot_doubles(Op op, const Level& L) {
+  const int64_t N = L.maxN, A = L.maxA, J = L.maxJ;
+  switch (op) {
+    case OP_FACTOR: return J * N + N * N;
+    case OP_PRODUCT: return J * N;
+    case OP_COMPLETION: return std::max(2 * A * A, 3 * N * N);
+    case OP_VINV: return 2 * A * A;
+    case OP_HUP: return J * N;
+    case OP_HDOWN: return 2 * A * N + 2 * N * N;
+    case OP_IHDOWN: return 2 * A * N + 3 * N * N;
+    case OP_IHUP: return J * N + A * N;
+  }
+  return 0;
+}
+static int64_t scratch_doubles(Op op, const std::vector<Level>& lv) {
+  int64_t m = 0;
+  for (const auto& L : lv) m = std::max(m, int64_t(L.count) * std::max<int64_t>(1, slot_doubles(op, L)));
+  return m;
+}
+static bool up_op(Op op) {
+  return op == OP_FACTOR || op == OP_PRODUCT || op == OP_VINV || op == OP_HUP || op == OP_IHUP;
+}
+static int64_t plan_scratch(const mfb_plan_s* p, Op op) {
+  return scratch_doubles(op, up_op(op) ? p->up_levels : p->down_levels);
+}
+static int64_t factor_scratch(const mfb_plan_s* p) {
+  return std::max({plan_scratch(p, OP_FACTOR), plan_scratch(p, OP_PRODUCT),
+                   plan_scratch(p, OP_COMPLETION), plan_scratch(p, OP_VINV), int64_t(1)});
+}
+static int64_t rhs_scratch(const mfb_plan_s* p) {
+  return std::max({plan_scratch(p, OP_HUP), plan_scratch(p, OP_HDOWN), plan_scratch(p, OP_IHDOWN),
+                   plan_scratch(p, OP_IHUP), int64_t(1)});
+}
+static size_t factor_bytes(const mfb_plan_s* p) {
+  const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
+  return 3 * up(nnz * 8) + 3 * up(upd * 8) + up(size_t(std::max(1, p->ns)) * 8) + up(8) +
+         up(sizeof(DevStatus)) + up(size_t(factor_scratch(p)) * 8);
+}
+static size_t rhs_bytes(const mfb_plan_s* p) {
+  const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
+  return (upd + nnz + size_t(rhs_scratch(p))) * 8 + 3 * ALIGN;
+}
+}  // namespace mfb
+
+using namespace mfb;
+
+// Uploads the plan's index arrays to the current device (once).
+static mfb_status_t ensure_device(mfb_plan_s* p) {
+  std::lock_guard<std::mutex> g(p->mu);
+  if (p->dmem) return MFB_OK;
+  // all index arrays in one device allocation
+  std::vector<int32_t> all(std::max(1, p->ns));
+  for (int32_t i = 0; i < p->ns; ++i) all[i] = i;
+  std::vector<int32_t> colidx(std::max<int64_t>(1, p->nnz));
+  for (int64_t j = 0; j < p->n; ++j)
+    for (int64_t e = p->colptr_h[j]; e < p->colptr_h[j + 1]; ++e) colidx[e] = int32_t(j);
+  struct Blob {
+    const void* src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Blob> blobs;
+  size_t total = 0;
+  auto add = [&](const void* src, size_t bytes) {
+    blobs.push_back({src, bytes, total});
+    total += up(std::max<size_t>(bytes, 8));
+    return blobs.size() - 1;
+  };
+  auto v32 = [&](const std::vector<int32_t>& v) { return add(v.data(), v.size() * 4); };
+  auto v64 = [&](const std::vector<int64_t>& v) { return add(v.data(), v.size() * 8); };
+  size_t iN = v32(p->N), iJ = v32(p->J), iPar = v32(p->parent), iCp = v32(p->cptr), iCi = v32(p->cidx),
+         iCb = v32(p->colbase), iCol = v64(p->col), iRb = v32(p->relbase), iRel = v32(p->rel),
+         iAr = v64(p->arena), iVl = v32(p->vlabel), iUp = v32(p->up_list), iDn = v32(p->down_list),
+         iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h);
+  void* d = nullptr;
+  if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
+  for (const auto& b : blobs)
+    if (b.bytes && hipMemcpy((char*)d + b.off, b.src, b.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      return MFB_EHIP;
+    }
+  auto at = [&](size_t i) { return (const void*)((char*)d + blobs[i].off); };
+  p->dmem = d;
+  DevPlan& P = p->dev;
+  P.ns = p->ns;
+  P.n = p->n;
+  P.nnz = p->nnz;
+  P.ncol = (const int32_t*)at(iN);
+  P.nrow = (const int32_t*)at(iJ);
+  P.parent = (const int32_t*)at(iPar);
+  P.cptr = (const int32_t*)at(iCp);
+  P.cidx = (const int32_t*)at(iCi);
+  P.colbase = (const int32_t*)at(iCb);
+  P.col = (const int64_t*)at(iCol);
+  P.relbase = (const int32_t*)at(iRb);
+  P.rel = (const int32_t*)at(iRel);
+  P.arena = (const int64_t*)at(iAr);
+  P.vlabel = (const int32_t*)at(iVl);
+  p->d_up_list = (const int32_t*)at(iUp);
+  p->d_down_list = (const int32_t*)at(iDn);
+  p->d_all_list = (const int32_t*)at(iAll);
+  p->d_colidx = (const int32_t*)at(iCidx);
+  p->d_colptr = (const int64_t*)at(iColptr);
+  return MFB_OK;
+}
+
+
+struct mfb_factor_s {
+  mfb_plan_s* plan = nullptr;
+  char* ws = nullptr;
+  double *R = nullptr, *LB = nullptr, *S = nullptr, *Vs = nullptr, *Vi = nullptr, *U = nullptr;
+  double *part = nullptr, *logdet = nullptr, *scratch = nullptr;
+  DevStatus* st = nullptr;
+  bool has_factor = false, s_valid = false, vinv_valid = false;
+  hipStream_t last = nullptr;
+};
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return MFB_EHIP; \
+  } while (0)
+
+static mfb_status_t launched() { return hipGetLastError() == hipSuccess ? MFB_OK : MFB_EHIP; }
+
+extern "C" {
+
+const char* mfb_strerror(mfb_status_t s) {
+  switch (s) {
+    case MFB_OK: return "ok";
+    case MFB_EINVAL: return "invalid argument";
+    case MFB_ENOTCHORDAL: return "pattern is not filled (chordal) in the given order";
+    case MFB_ENOTPD: return "matrix is not positive definite";
+    case MFB_ENOCOMPLETION: return "matrix has no positive definite completion";
+    case MFB_ENOMEM: return "out of memory";
+    case MFB_EHIP: return "HIP runtime error";
+    case MFB_ESTATE: return "call order violated";
+  }
+  return "unknown status";
+}
+
+mfb_status_t mfb_plan_symbolic(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                               uint32_t flags, mfb_plan_t* out) {
+  if (!out) return MFB_EINVAL;
+  *out = nullptr;
+  mfb_plan_s* p = new (std::nothrow) mfb_plan_s();
+  if (!p) return MFB_ENOMEM;
+  mfb_status_t st = build_plan(n, colptr, rowind, flags, p);
+  if (st) {
+    delete p;
+    return st;
+  }
+  p->colptr_h.assign(colptr, colptr + n + 1);
+  *out = p;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_plan_info(mfb_plan_t p, mfb_plan_info_t* o) {
+  if (!p || !o) return MFB_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->n = p->n;
+  o->nnz = p->nnz;
+  o->nsuper = p->ns;
+  o->nlevels_up = int64_t(p->up_levels.size());
+  o->nlevels_down = int64_t(p->down_levels.size());
+  o->max_front = p->max_front;
+  o->max_ncols = p->max_ncols;
+  o->max_nanc = p->max_nanc;
+  o->update_doubles = p->update_doubles;
+  o->factor_workspace_bytes = factor_bytes(p);
+  o->rhs_arena_bytes = rhs_bytes(p);
+  o->flops_factor = p->fl_factor;
+  o->flops_projinv = p->fl_projinv;
+  o->flops_hessian = p->fl_hess;
+  o->flops_inv_hessian = p->fl_invhess;
+  o->flops_inv_hessian_x = p->fl_invhess_x;
+  o->flops_completion = p->fl_completion;
+  o->flops_product = p->fl_product;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_plan_supernodes(mfb_plan_t p, int32_t* snode_of, int32_t* sparent, int32_t* srep) {
+  if (!p) return MFB_EINVAL;
+  if (snode_of) std::copy(p->snode_of.begin(), p->snode_of.end(), snode_of);
+  if (sparent) std::copy(p->parent.begin(), p->parent.end(), sparent);
+  if (srep) std::copy(p->rep.begin(), p->rep.end(), srep);
+  return MFB_OK;
+}
+
+void mfb_plan_destroy(mfb_plan_t p) {
+  if (!p) return;
+  if (p->dmem) (void)hipFree(p->dmem);
+  delete p;
+}
+
+mfb_status_t mfb_factor_create(mfb_plan_t p, void* ws, size_t bytes, mfb_factor_t* out) {
+  if (!p || !out) return MFB_EINVAL;
+  *out = nullptr;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0 || bytes < factor_bytes(p)) return MFB_EINVAL;
+  if (mfb_status_t st = ensure_device(p)) return st;
+  mfb_factor_s* f = new (std::nothrow) mfb_factor_s();
+  if (!f) return MFB_ENOMEM;
+  f->plan = p;
+  f->ws = (char*)ws;
+  const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
+  char* c = f->ws;
+  auto take = [&](size_t b) {
+    char* r = c;
+    c += up(b);
+    return r;
+  };
+  f->R = (double*)take(nnz * 8);
+  f->LB = (double*)take(nnz * 8);
+  f->S = (double*)take(nnz * 8);
+  f->Vs = (double*)take(upd * 8);
+  f->Vi = (double*)take(upd * 8);
+  f->U = (double*)take(upd * 8);
+  f->part = (double*)take(size_t(std::max(1, p->ns)) * 8);
+  f->logdet = (double*)take(8);
+  f->st = (DevStatus*)take(sizeof(DevStatus));
+  f->scratch = (double*)take(size_t(factor_scratch(p)) * 8);
+  *out = f;
+  return MFB_OK;
+}
+
+void mfb_factor_destroy(mfb_factor_t f) { delete f; }
+
+static mfb_status_t run_levels(mfb_factor_s* f, const std::vector<Level>& lv, const int32_t* dlist,
+                               hipStream_t s, int k, Op op,
+                               void (*launch)(mfb_factor_s*, const int32_t*, dim3, hipStream_t,
+                                              int64_t, void*),
+                               void* ctx) {
+  for (const auto& L : lv) {
+    if (L.count == 0) continue;
+    dim3 grid(unsigned(L.count), unsigned(k));
+    launch(f, dlist + L.begin, grid, s, std::max<int64_t>(1, slot_doubles(op, L)), ctx);
+    if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+  }
+  return MFB_OK;
+}
+
+mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
+  if (!f || (!x && f->plan->nnz)) return MFB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  k_reset_status<<<1, 64, 0, s>>>(f->st);
+  struct Ctx { const double* x; } ctx{x};
+  mfb_status_t st = run_levels(
+      f, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_FACTOR,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        k_factor<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U, f->part,
+                                  f->st, f->scratch, slot);
+      },
+      &ctx);
+  if (st) return st;
+  f->has_factor = true;
+  f->s_valid = false;
+  f->vinv_valid = false;
+  return launched();
+}
+
+mfb_status_t mfb_logdet(mfb_factor_t f, double* out, void* stream) {
+  if (!f || !out) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  k_logdet<<<1, NT_LAUNCH, 0, s>>>(f->part, f->plan->ns, out);
+  return launched();
+}
+
+static mfb_status_t ensure_projinv(mfb_factor_s* f, hipStream_t s) {
+  if (f->s_valid) return MFB_OK;
+  mfb_status_t st = run_levels(
+      f, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_FACTOR,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void*) {
+        k_projinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
+      },
+      nullptr);
+  if (st) return st;
+  f->s_valid = true;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_projected_inverse(mfb_factor_t f, double* s_out, void* stream) {
+  if (!f) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  f->s_valid = false;  // recompute on request
+  mfb_status_t st = ensure_projinv(f, s);
+  if (st) return st;
+  if (s_out && f->plan->nnz)
+    HIPCHK(hipMemcpyAsync(s_out, f->S, size_t(f->plan->nnz) * 8, hipMemcpyDeviceToDevice, s));
+  return launched();
+}
+
+struct RhsArena {
+  double *Ua, *Kt, *scr;
+  int64_t upd;
+};
+static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, RhsArena* a) {
+  const mfb_plan_s* p = f->plan;
+  if (!arena || (reinterpret_cast<uintptr_t>(arena) % ALIGN) != 0) return MFB_EINVAL;
+  if (bytes < size_t(k) * rhs_bytes(p)) return MFB_EINVAL;
+  const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
+  char* c = (char*)arena;
+  a->upd = int64_t(upd);
+  a->Ua = (double*)c;
+  c += up(size_t(k) * upd * 8);
+  a->Kt = (double*)c;
+  c += up(size_t(k) * nnz * 8);
+  a->scr = (double*)c;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, void* arena,
+                         size_t bytes, void* stream) {
+  if (!f || k < 0) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!y || !t) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  RhsArena a;
+  mfb_status_t st = carve(f, k, arena, bytes, &a);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  if ((st = ensure_projinv(f, s))) return st;
+  struct Ctx { const double* y; double* t; RhsArena a; } ctx{y, t, a};
+  st = run_levels(
+      f, f->plan->up_levels, f->plan->d_up_list, s, k, OP_HUP,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        Ctx* x = (Ctx*)c;
+        k_hess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua, x->a.upd,
+                                   x->a.scr, slot);
+      },
+      &ctx);
+  if (st) return st;
+  st = run_levels(
+      f, f->plan->down_levels, f->plan->d_down_list, s, k, OP_HDOWN,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        Ctx* x = (Ctx*)c;
+        k_hess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
+                                     x->a.upd, x->a.scr, slot);
+      },
+      &ctx);
+  if (st) return st;
+  return launched();
+}
+
+static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
+  if (f->vinv_valid) return MFB_OK;
+  mfb_status_t st = run_levels(
+      f, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_VINV,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void*) {
+        k_vinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->Vs, f->Vi, f->st, f->scratch, slot);
+      },
+      nullptr);
+  if (st) return st;
+  f->vinv_valid = true;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double* y, void* arena,
+                             size_t bytes, void* stream) {
+  if (!f || k < 0) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!y || !t) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  RhsArena a;
+  mfb_status_t st = carve(f, k, arena, bytes, &a);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  if ((st = ensure_projinv(f, s))) return st;
+  if ((st = ensure_vinv(f, s))) return st;
+  struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
+  st = run_levels(
+      f, f->plan->down_levels, f->plan->d_down_list, s, k, OP_IHDOWN,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        Ctx* x = (Ctx*)c;
+        k_ihess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
+                                      x->a.Ua, x->a.upd, x->a.scr, slot);
+      },
+      &ctx);
+  if (st) return st;
+  st = run_levels(
+      f, f->plan->up_levels, f->plan->d_up_list, s, k, OP_IHUP,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        Ctx* x = (Ctx*)c;
+        k_ihess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua, x->a.upd,
+                                    x->a.scr, slot);
+      },
+      &ctx);
+  if (st) return st;
+  return launched();
+}
+
+mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
+  if (!f || (!sin && f->plan->nnz)) return MFB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  k_reset_status<<<1, 64, 0, s>>>(f->st);
+  struct Ctx { const double* s; } ctx{sin};
+  mfb_status_t st = run_levels(
+      f, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_COMPLETION,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        k_completion<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
+                                      f->Vi, f->part, f->st, f->scratch, slot);
+      },
+      &ctx);
+  if (st) return st;
+  f->has_factor = true;
+  f->s_valid = true;
+  f->vinv_valid = true;
+  return launched();
+}
+
+mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
+  if (!f || (!x && f->plan->nnz)) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  struct Ctx { double* x; } ctx{x};
+  mfb_status_t st = run_levels(
+      f, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_PRODUCT,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        k_product<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U, f->scratch, slot);
+      },
+      &ctx);
+  if (st) return st;
+  return launched();
+}
+
+mfb_status_t mfb_factor_export_ldl(mfb_factor_t f, double* out, void* stream) {
+  if (!f || (!out && f->plan->nnz)) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  const int64_t nnz = f->plan->nnz;
+  if (nnz == 0) return MFB_OK;
+  const int blocks = int(std::min<int64_t>((nnz + NT_LAUNCH - 1) / NT_LAUNCH, 4096));
+  k_export_ldl<<<blocks, NT_LAUNCH, 0, s>>>(f->R, f->plan->d_colptr, f->plan->d_colidx, nnz, out);
+  return launched();
+}
+
+mfb_status_t mfb_get_status(mfb_factor_t f, int64_t* bad) {
+  if (!f) return MFB_EINVAL;
+  if (bad) *bad = -1;
+  if (hipStreamSynchronize(f->last) != hipSuccess) return MFB_EHIP;
+  DevStatus h{};
+  if (hipMemcpy(&h, f->st, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return MFB_EHIP;
+  if (h.code == 0) return MFB_OK;
+  if (bad && h.bad != ~0ull) *bad = int64_t(h.bad);
+  return h.code;
+}
+
+}  // extern "C"

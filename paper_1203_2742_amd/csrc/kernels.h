@@ -1,0 +1,37 @@
+// Kernel entry points of kernels.hip (launched from api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mfb_internal.h"
+
+namespace mfb {
+constexpr int NT_LAUNCH = 256;  // threads per workgroup of every sweep kernel
+
+struct DevStatus {
+  int code;
+  int pad;
+  unsigned long long bad;  // smallest failing user column
+};
+
+__global__ void k_factor(DevPlan, const int32_t*, const double*, double*, double*, double*,
+                         double*, DevStatus*, double*, int64_t);
+__global__ void k_projinv(DevPlan, const int32_t*, const double*, double*, double*);
+__global__ void k_hess_up(DevPlan, const int32_t*, const double*, const double*, double*, double*,
+                          int64_t, double*, int64_t);
+__global__ void k_hess_down(DevPlan, const int32_t*, const double*, const double*, const double*,
+                            double*, double*, int64_t, double*, int64_t);
+__global__ void k_ihess_down(DevPlan, const int32_t*, const double*, const double*, const double*,
+                             const double*, double*, double*, int64_t, double*, int64_t);
+__global__ void k_ihess_up(DevPlan, const int32_t*, const double*, const double*, double*, double*,
+                           int64_t, double*, int64_t);
+__global__ void k_completion(DevPlan, const int32_t*, const double*, double*, double*, double*,
+                             double*, double*, double*, DevStatus*, double*, int64_t);
+__global__ void k_vinv(DevPlan, const int32_t*, const double*, double*, DevStatus*, double*,
+                       int64_t);
+__global__ void k_product(DevPlan, const int32_t*, const double*, double*, double*, double*,
+                          int64_t);
+__global__ void k_logdet(const double*, int, double*);
+__global__ void k_export_ldl(const double*, const int64_t*, const int32_t*, int64_t, double*);
+__global__ void k_reset_status(DevStatus*);
+
+}  // namespace mfb

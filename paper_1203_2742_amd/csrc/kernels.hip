@@ -1,0 +1,563 @@
+// Supernodal multifrontal sweeps on gfx950: one workgroup per
+// (supernode, right-hand side) of a level of the clique tree.
+//
+// Factor state per supernode s (N = |N_s|, A = |A_s|), all in the CCS
+// order of the user's pattern (column c of s holds rows J_s[c:]):
+//   R  : the Cholesky panel [C; B] with C = chol(D_NN) and B = L_AN C, i.e.
+//        the scalar Cholesky factor of X (independent of the partition);
+//   LB : [D_NN^-1 (lower); L_AN], the block L D L^T factors of Algorithm 7.1
+//        with the inverse of the pivot block;
+//   S  : the projected inverse P(X^-1), and per supernode the packed block
+//        V_s = S_{A_s A_s} (update matrices of Algorithm 7.2);
+//   Vi : (S_{A_s A_s})^-1, packed, for the inverse Hessian and completion.
+// Update matrices (U, U', V, V') are packed lower-triangular A x A blocks in
+// an arena; children are assembled in a fixed order without atomics.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+#include "wg_dense.h"
+
+namespace mfb {
+
+static_assert(NT == NT_LAUNCH, "launch width");
+
+__device__ void report(DevStatus* st, int code, long long label) {
+  atomicMax(&st->code, code);
+  atomicMin(&st->bad, (unsigned long long)label);
+}
+
+struct SnView {
+  int s, N, A, J;
+  const int64_t* col;  // CCS diagonal offsets of the supernode's columns
+  const int32_t* vl;   // user labels of the supernode's columns
+  __device__ SnView(const DevPlan& P, int s_) : s(s_) {
+    N = P.ncol[s];
+    J = P.nrow[s];
+    A = J - N;
+    col = P.col + P.colbase[s];
+    vl = P.vlabel + P.colbase[s];
+  }
+  // element (r, c), r >= c, of a CCS-ordered array restricted to the panel
+  __device__ __forceinline__ int64_t at(int r, int c) const { return col[c] + (r - c); }
+  // symmetric NN access
+  __device__ __forceinline__ int64_t nn(int i, int j) const { return i >= j ? at(i, j) : at(j, i); }
+  // AN block entry (x in A, c in N)
+  __device__ __forceinline__ int64_t an(int x, int c) const { return col[c] + (N + x - c); }
+};
+
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Extend-add of the children's packed update blocks taken from `ua`.
+// Entries landing in N_s columns go to the panel F (leading dimension J);
+// the others (rows and columns in A_s) go to the packed block Us.  One
+// child at a time (fixed order), so every target is written once per pass.
+__device__ void assemble_children(const DevPlan& P, const SnView& v, const double* ua, double* F,
+                                  double* Us) {
+  for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
+    const int c = P.cidx[t];
+    const int Ac = P.nrow[c] - P.ncol[c];
+    const int32_t* rl = P.rel + P.relbase[c];
+    const double* Uc = ua + P.arena[c];
+    for (int y = wave_id(); y < Ac; y += NT / 64) {
+      const int ry = rl[y];
+      if (ry < v.N) {
+        if (!F) continue;
+        for (int x = y + lane_id(); x < Ac; x += 64)
+          F[rl[x] + (int64_t)ry * v.J] += Uc[pk(x, y, Ac)];
+      } else {
+        if (!Us) continue;
+        for (int x = y + lane_id(); x < Ac; x += 64)
+          Us[pk(rl[x] - v.N, ry - v.N, v.A)] += Uc[pk(x, y, Ac)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// V_s = E^T [S_NN S_AN^T; S_AN V_p] E (eq. e-sn-gradient-2): gather the
+// packed A_s x A_s block from the parent's CCS columns of `src` and the
+// parent's packed block in `arena`, into this supernode's packed block.
+__device__ void extract_from_parent(const DevPlan& P, const SnView& v, const double* src,
+                                    double* arena) {
+  if (v.A == 0) return;
+  const int p = P.parent[v.s];
+  const int Np = P.ncol[p], Ap = P.nrow[p] - Np;
+  const int64_t* colp = P.col + P.colbase[p];
+  const int32_t* rl = P.rel + P.relbase[v.s];
+  const double* Vp = arena + P.arena[p];
+  double* Vo = arena + P.arena[v.s];
+  for (int y = wave_id(); y < v.A; y += NT / 64) {
+    const int ry = rl[y];
+    for (int x = y + lane_id(); x < v.A; x += 64) {
+      const int rx = rl[x];
+      Vo[pk(x, y, v.A)] = ry < Np ? src[colp[ry] + (rx - ry)] : Vp[pk(rx - Np, ry - Np, Ap)];
+    }
+  }
+}
+
+__device__ __forceinline__ void zero_packed(double* U, int A) {
+  const int64_t m = (int64_t)A * (A + 1) / 2;
+  for (int64_t e = threadIdx.x; e < m; e += NT) U[e] = 0.0;
+}
+
+__device__ __forceinline__ double* slot_ptr(double* wsb, int64_t slot) {
+  return wsb + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * slot;
+}
+
+// Inverse of a symmetric positive definite A x A block given by the functor
+// `Vf` (full access), through its Cholesky factor G: V^-1 = G^-T G^-1.  The
+// lower triangle of the result is passed to `out(i, j, value)`.  Scratch: 2 A^2.
+template <class VF, class OUT>
+__device__ void wg_spd_inverse(int A, const VF& Vf, const OUT& out, double* ws, double* sm,
+                               int* fail) {
+  double* G = ws;
+  double* Gi = ws + (int64_t)A * A;
+  for (int64_t e = threadIdx.x; e < (int64_t)A * A; e += NT) {
+    const int i = int(e % A), j = int(e / A);
+    if (i >= j) G[e] = Vf(i, j);
+  }
+  __syncthreads();
+  wg_potrf_panel(G, A, A, A, sm, fail);
+  wg_trtri([&](int i, int j) { return G[i + (int64_t)j * A]; }, A, Gi, A, sm);
+  wg_gemm(
+      A, A, A, [&](int i, int k) { return Gi[k + (int64_t)i * A]; },
+      [&](int k, int j) { return Gi[k + (int64_t)j * A]; }, out, true, sm);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 7.1: supernodal Cholesky factorization (leaf-to-root level).
+// F = [X_NN X_AN^T; X_AN 0] + sum_children E U_c E^T; C = chol(F11);
+// B = F21 C^-T; U_s = F22 - B B^T; L_AN = B C^-1; D^-1 = C^-T C^-1.
+// Scratch per workgroup: J*N + N*N.
+__global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, const double* x,
+                                               double* R, double* LB, double* U, double* part,
+                                               DevStatus* st, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int fail;
+  const SnView v(P, list[blockIdx.x]);
+  double* F = slot_ptr(wsb, slot);
+  double* Ci = F + (int64_t)v.J * v.N;
+  double* Us = U + P.arena[v.s];
+  if (threadIdx.x == 0) fail = -1;
+  for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+    const int r = int(e % v.J), c = int(e / v.J);
+    F[e] = r >= c ? x[v.at(r, c)] : 0.0;
+  }
+  zero_packed(Us, v.A);
+  __syncthreads();
+  assemble_children(P, v, U, F, Us);
+  wg_potrf_panel(F, v.J, v.J, v.N, sm, &fail);
+  // Cholesky panel -> R, log det contribution 2 sum log C_kk
+  double lg = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+    const int r = int(e % v.J), c = int(e / v.J);
+    if (r >= c) R[v.at(r, c)] = F[e];
+  }
+  for (int c = threadIdx.x; c < v.N; c += NT) lg += 2.0 * log(F[c + (int64_t)c * v.J]);
+  lg = wg_sum(lg, sm);
+  if (threadIdx.x == 0) {
+    part[v.s] = lg;
+    if (fail >= 0) report(st, MFB_ENOTPD, v.vl[fail]);
+  }
+  // U_s = F22 - B B^T
+  wg_gemm(
+      v.A, v.A, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
+      [&](int k, int j) { return F[(v.N + j) + (int64_t)k * v.J]; },
+      [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
+  // C^-1
+  wg_trtri([&](int i, int j) { return F[i + (int64_t)j * v.J]; }, v.N, Ci, v.N, sm);
+  // L_AN = B C^-1
+  wg_gemm(
+      v.A, v.N, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
+      [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
+      [&](int i, int j, double acc) { LB[v.an(i, j)] = acc; }, false, sm);
+  // D^-1 = C^-T C^-1 (lower)
+  wg_gemm(
+      v.N, v.N, v.N, [&](int i, int k) { return Ci[k + (int64_t)i * v.N]; },
+      [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
+      [&](int i, int j, double acc) { LB[v.at(i, j)] = acc; }, true, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 7.2: projected inverse (root-to-leaf level).
+// V_s from the parent; S_AN = -V_s L_AN; S_NN = D^-1 - S_AN^T L_AN.
+__global__ void __launch_bounds__(NT) k_projinv(DevPlan P, const int32_t* list, const double* LB,
+                                                double* S, double* Vs) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const SnView v(P, list[blockIdx.x]);
+  extract_from_parent(P, v, S, Vs);
+  __syncthreads();
+  const double* V = Vs + P.arena[v.s];
+  wg_gemm(
+      v.A, v.N, v.A, [&](int i, int k) { return sym_packed(V, i, k, v.A); },
+      [&](int k, int j) { return LB[v.an(k, j)]; },
+      [&](int i, int j, double acc) { S[v.an(i, j)] = -acc; }, false, sm);
+  __syncthreads();
+  wg_gemm(
+      v.N, v.N, v.A, [&](int i, int k) { return S[v.an(k, i)]; },
+      [&](int k, int j) { return LB[v.an(k, j)]; },
+      [&](int i, int j, double acc) { S[v.at(i, j)] = LB[v.at(i, j)] - acc; }, true, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Hessian step 1 (leaf-to-root), block form of Algorithm 5.1 step 1:
+// F' = [Y_NN Y_AN^T; Y_AN 0] + sum E U'_c E^T;
+// K_NN = F'11, K_AN = F'21 - L F'11, U'_s = F'22 - L F'21^T - K_AN L^T.
+// Per RHS r = blockIdx.y.  Scratch: J*N.
+__global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, const double* LB,
+                                                const double* Y, double* Kt, double* Ua,
+                                                int64_t upd, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const SnView v(P, list[blockIdx.x]);
+  const int64_t r = blockIdx.y;
+  const double* y = Y + r * P.nnz;
+  double* K = Kt + r * P.nnz;
+  double* ua = Ua + r * upd;
+  double* Us = ua + P.arena[v.s];
+  double* F = slot_ptr(wsb, slot);
+  for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+    const int rr = int(e % v.J), c = int(e / v.J);
+    F[e] = rr >= c ? y[v.at(rr, c)] : 0.0;
+  }
+  zero_packed(Us, v.A);
+  __syncthreads();
+  assemble_children(P, v, ua, F, Us);
+  for (int64_t e = threadIdx.x; e < (int64_t)v.N * v.N; e += NT) {
+    const int i = int(e % v.N), c = int(e / v.N);
+    if (i >= c) K[v.at(i, c)] = F[i + (int64_t)c * v.J];
+  }
+  auto F11 = [&](int i, int j) { return i >= j ? F[i + (int64_t)j * v.J] : F[j + (int64_t)i * v.J]; };
+  wg_gemm(
+      v.A, v.N, v.N, [&](int i, int k) { return LB[v.an(i, k)]; }, [&](int k, int j) { return F11(k, j); },
+      [&](int i, int j, double acc) { K[v.an(i, j)] = F[(v.N + i) + (int64_t)j * v.J] - acc; }, false,
+      sm);
+  __syncthreads();
+  const int N = v.N;
+  wg_gemm(
+      v.A, v.A, 2 * N,
+      [&](int i, int k) { return k < N ? LB[v.an(i, k)] : K[v.an(i, k - N)]; },
+      [&](int k, int j) { return k < N ? F[(N + j) + (int64_t)k * v.J] : LB[v.an(j, k - N)]; },
+      [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
+}
+
+// Hessian steps 2 and 3 (root-to-leaf), block form of Algorithm 5.1 with
+// the V_j recursion of its modified step 2 (here V_s is cached):
+// M_NN = D^-1 K_NN D^-1, M_AN = V_s K_AN D^-1, T_AN = M_AN - V' L,
+// T_NN = M_NN - L^T T_AN - M_AN^T L, V'_c = E^T [T_NN T_AN^T; T_AN V'] E.
+// Scratch: 2AN + 2N^2.
+__global__ void __launch_bounds__(NT) k_hess_down(DevPlan P, const int32_t* list, const double* LB,
+                                                  const double* Vs, const double* Kt, double* T,
+                                                  double* Va, int64_t upd, double* wsb,
+                                                  int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const SnView v(P, list[blockIdx.x]);
+  const int64_t r = blockIdx.y;
+  const double* K = Kt + r * P.nnz;
+  double* t = T + r * P.nnz;
+  double* va = Va + r * upd;
+  const int N = v.N, A = v.A;
+  double* Z = slot_ptr(wsb, slot);
+  double* W = Z + (int64_t)A * N;
+  double* MA = W + (int64_t)N * N;
+  double* MN = MA + (int64_t)A * N;
+  extract_from_parent(P, v, t, va);
+  auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
+  wg_gemm(
+      A, N, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv,
+      [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
+  wg_gemm(
+      N, N, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv,
+      [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
+  __syncthreads();
+  const double* V = Vs + P.arena[v.s];
+  wg_gemm(
+      A, N, A, [&](int i, int k) { return sym_packed(V, i, k, A); },
+      [&](int k, int j) { return Z[k + (int64_t)j * A]; },
+      [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false, sm);
+  wg_gemm(
+      N, N, N, Dinv, [&](int k, int j) { return W[k + (int64_t)j * N]; },
+      [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true, sm);
+  __syncthreads();
+  const double* Vp = va + P.arena[v.s];
+  wg_gemm(
+      A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
+      [&](int k, int j) { return LB[v.an(k, j)]; },
+      [&](int i, int j, double acc) { t[v.an(i, j)] = MA[i + (int64_t)j * A] - acc; }, false, sm);
+  __syncthreads();
+  wg_gemm(
+      N, N, 2 * A,
+      [&](int i, int k) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
+      [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
+      [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; }, true, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse Hessian steps 1 and 2 (root-to-leaf), block form of Algorithm 5.2:
+// V'_s = T_{A_s A_s} from the parent; M_AN = T_AN + V' L;
+// M_NN = T_NN + L^T M_AN + T_AN^T L; K_NN = D M_NN D; K_AN = V_s^-1 M_AN D,
+// with D = C C^T.  Scratch: 2AN + 3N^2.
+__global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* list, const double* R,
+                                                   const double* LB, const double* Vi,
+                                                   const double* T, double* Kt, double* Va,
+                                                   int64_t upd, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const SnView v(P, list[blockIdx.x]);
+  const int64_t r = blockIdx.y;
+  const double* t = T + r * P.nnz;
+  double* K = Kt + r * P.nnz;
+  double* va = Va + r * upd;
+  const int N = v.N, A = v.A;
+  double* MA = slot_ptr(wsb, slot);
+  double* Z = MA + (int64_t)A * N;
+  double* MN = Z + (int64_t)A * N;
+  double* Dm = MN + (int64_t)N * N;
+  double* W = Dm + (int64_t)N * N;
+  extract_from_parent(P, v, t, va);
+  // D = C C^T (full)
+  wg_gemm(
+      N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
+      [&](int k, int j) { return k <= j ? R[v.at(j, k)] : 0.0; },
+      [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false, sm);
+  __syncthreads();
+  const double* Vp = va + P.arena[v.s];
+  wg_gemm(
+      A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
+      [&](int k, int j) { return LB[v.an(k, j)]; },
+      [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false, sm);
+  __syncthreads();
+  wg_gemm(
+      N, N, 2 * A,
+      [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
+      [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
+      [&](int i, int j, double acc) {
+        const double m = t[v.at(i, j)] + acc;
+        MN[i + (int64_t)j * N] = m;
+        MN[j + (int64_t)i * N] = m;
+      },
+      true, sm);
+  __syncthreads();
+  wg_gemm(
+      N, N, N, [&](int i, int k) { return MN[i + (int64_t)k * N]; },
+      [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
+      [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
+  wg_gemm(
+      A, N, N, [&](int i, int k) { return MA[i + (int64_t)k * A]; },
+      [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
+      [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
+  __syncthreads();
+  wg_gemm(
+      N, N, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
+      [&](int k, int j) { return W[k + (int64_t)j * N]; },
+      [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
+  const double* VI = Vi + P.arena[v.s];
+  wg_gemm(
+      A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
+      [&](int k, int j) { return Z[k + (int64_t)j * A]; },
+      [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);
+}
+
+// Inverse Hessian step 3 (leaf-to-root), block form of Algorithm 5.2:
+// G' = sum E U'_c E^T; Y_NN = K_NN - G'11; Y_AN = L K_NN + K_AN - G'21;
+// U'_s = G'22 - L K_NN L^T - L K_AN^T - K_AN L^T.  Scratch: J*N + A*N.
+__global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list, const double* LB,
+                                                 const double* Kt, double* Y, double* Ua,
+                                                 int64_t upd, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const SnView v(P, list[blockIdx.x]);
+  const int64_t r = blockIdx.y;
+  const double* K = Kt + r * P.nnz;
+  double* y = Y + r * P.nnz;
+  double* ua = Ua + r * upd;
+  double* Us = ua + P.arena[v.s];
+  const int N = v.N, A = v.A;
+  double* G = slot_ptr(wsb, slot);
+  double* Q = G + (int64_t)v.J * N;
+  for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
+  zero_packed(Us, A);
+  __syncthreads();
+  assemble_children(P, v, ua, G, Us);
+  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+    const int i = int(e % N), c = int(e / N);
+    if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + (int64_t)c * v.J];
+  }
+  wg_gemm(
+      A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
+      [&](int k, int j) { return K[v.nn(k, j)]; },
+      [&](int i, int j, double acc) {
+        const double q = acc + K[v.an(i, j)];
+        Q[i + (int64_t)j * A] = q;
+        y[v.an(i, j)] = q - G[(N + i) + (int64_t)j * v.J];
+      },
+      false, sm);
+  __syncthreads();
+  wg_gemm(
+      A, A, 2 * N,
+      [&](int i, int k) { return k < N ? Q[i + (int64_t)k * A] : LB[v.an(i, k - N)]; },
+      [&](int k, int j) { return k < N ? LB[v.an(j, k)] : K[v.an(j, k - N)]; },
+      [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 7.3: matrix completion (root-to-leaf level for the V_s gather).
+// V_s = S_{A_s A_s}; L_AN = -V_s^-1 S_AN; D^-1 = S_NN + S_AN^T L_AN;
+// then C = chol(D), B = L_AN C so that the handle holds the factor of X-hat.
+// Also caches S, V_s and V_s^-1.  Scratch: max(2A^2, 3N^2).
+__global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* list, const double* Sin,
+                                                   double* R, double* LB, double* S, double* Vs,
+                                                   double* Vi, double* part, DevStatus* st,
+                                                   double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int fail;
+  const SnView v(P, list[blockIdx.x]);
+  const int N = v.N, A = v.A;
+  double* ws = slot_ptr(wsb, slot);
+  if (threadIdx.x == 0) fail = -1;
+  // cache S (own columns) and gather V_s from the input
+  for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) {
+    const int rr = int(e % v.J), c = int(e / v.J);
+    if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
+  }
+  extract_from_parent(P, v, Sin, Vs);
+  __syncthreads();
+  const double* V = Vs + P.arena[v.s];
+  double* VI = Vi + P.arena[v.s];
+  if (A > 0) {
+    wg_spd_inverse(
+        A, [&](int i, int j) { return sym_packed(V, i, j, A); },
+        [&](int i, int j, double acc) { VI[pk(i, j, A)] = acc; }, ws, sm, &fail);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
+  wg_gemm(
+      A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
+      [&](int k, int j) { return Sin[v.an(k, j)]; },
+      [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false, sm);
+  __syncthreads();
+  double* Dd = ws;
+  double* Gi = ws + (int64_t)N * N;
+  double* Dm = Gi + (int64_t)N * N;
+  wg_gemm(
+      N, N, A, [&](int i, int k) { return Sin[v.an(k, i)]; },
+      [&](int k, int j) { return LB[v.an(k, j)]; },
+      [&](int i, int j, double acc) {
+        const double d = Sin[v.at(i, j)] + acc;
+        LB[v.at(i, j)] = d;
+        Dd[i + (int64_t)j * N] = d;
+      },
+      true, sm);
+  __syncthreads();
+  if (threadIdx.x == 0) fail = -1;
+  __syncthreads();
+  // D = (D^-1)^-1 via its Cholesky factor, then C = chol(D)
+  wg_potrf_panel(Dd, N, N, N, sm, &fail);
+  if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
+  wg_trtri([&](int i, int j) { return Dd[i + (int64_t)j * N]; }, N, Gi, N, sm);
+  wg_gemm(
+      N, N, N, [&](int i, int k) { return Gi[k + (int64_t)i * N]; },
+      [&](int k, int j) { return Gi[k + (int64_t)j * N]; },
+      [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, true, sm);
+  __syncthreads();
+  if (threadIdx.x == 0) fail = -1;
+  __syncthreads();
+  wg_potrf_panel(Dm, N, N, N, sm, &fail);
+  double lg = 0.0;
+  for (int c = threadIdx.x; c < N; c += NT) lg += 2.0 * log(Dm[c + (int64_t)c * N]);
+  lg = wg_sum(lg, sm);
+  if (threadIdx.x == 0) {
+    part[v.s] = lg;
+    if (fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+    const int i = int(e % N), c = int(e / N);
+    if (i >= c) R[v.at(i, c)] = Dm[e];
+  }
+  wg_gemm(
+      A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
+      [&](int k, int j) { return k >= j ? Dm[k + (int64_t)j * N] : 0.0; },
+      [&](int i, int j, double acc) { R[v.an(i, j)] = acc; }, false, sm);
+}
+
+// (S_{A_s A_s})^-1 for every supernode of a level (needs the cached V_s).
+// Scratch: 2A^2.
+__global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, const double* Vs,
+                                             double* Vi, DevStatus* st, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int fail;
+  const SnView v(P, list[blockIdx.x]);
+  if (v.A == 0) return;
+  if (threadIdx.x == 0) fail = -1;
+  __syncthreads();
+  const double* V = Vs + P.arena[v.s];
+  double* VI = Vi + P.arena[v.s];
+  wg_spd_inverse(
+      v.A, [&](int i, int j) { return sym_packed(V, i, j, v.A); },
+      [&](int i, int j, double acc) { VI[pk(i, j, v.A)] = acc; }, slot_ptr(wsb, slot), sm, &fail);
+  if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOTPD, v.vl[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 3.2 in block form (leaf-to-root): with G = sum E U_c E^T,
+// X_NN = C C^T - G11, X_AN = B C^T - G21, U_s = G22 - B B^T.  Scratch: J*N.
+__global__ void __launch_bounds__(NT) k_product(DevPlan P, const int32_t* list, const double* R,
+                                                double* X, double* U, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const SnView v(P, list[blockIdx.x]);
+  const int N = v.N, A = v.A;
+  double* G = slot_ptr(wsb, slot);
+  double* Us = U + P.arena[v.s];
+  for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
+  zero_packed(Us, A);
+  __syncthreads();
+  assemble_children(P, v, U, G, Us);
+  auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
+  wg_gemm(
+      N, N, N, C, [&](int k, int j) { return C(j, k); },
+      [&](int i, int j, double acc) { X[v.at(i, j)] = acc - G[i + (int64_t)j * v.J]; }, true, sm);
+  wg_gemm(
+      A, N, N, [&](int i, int k) { return R[v.an(i, k)]; }, [&](int k, int j) { return C(j, k); },
+      [&](int i, int j, double acc) { X[v.an(i, j)] = acc - G[(N + i) + (int64_t)j * v.J]; }, false,
+      sm);
+  wg_gemm(
+      A, A, N, [&](int i, int k) { return R[v.an(i, k)]; },
+      [&](int k, int j) { return R[v.an(j, k)]; },
+      [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
+}
+
+// ---------------------------------------------------------------------------
+// log det = sum of the per-supernode contributions, fixed-order reduction.
+__global__ void __launch_bounds__(NT) k_logdet(const double* part, int ns, double* out) {
+  __shared__ double sm[NT];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < ns; i += NT) v += part[i];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+// Scalar L D L^T from the Cholesky factor: D_jj = R_jj^2, L_ij = R_ij / R_jj.
+__global__ void __launch_bounds__(NT) k_export_ldl(const double* R, const int64_t* colptr,
+                                                   const int32_t* colidx, int64_t nnz, double* out) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * NT) {
+    const int64_t d = colptr[colidx[e]];
+    const double rd = R[d];
+    out[e] = e == d ? rd * rd : R[e] / rd;
+  }
+}
+
+__global__ void k_reset_status(DevStatus* st) {
+  if (threadIdx.x == 0) {
+    st->code = 0;
+    st->pad = 0;
+    st->bad = ~0ull;
+  }
+}
+
+}  // namespace mfb

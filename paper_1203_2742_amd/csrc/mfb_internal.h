@@ -1,0 +1,73 @@
+// Internal structures shared by the symbolic plan (host) and the kernels.
+#pragma once
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "../../include/mfb.h"
+
+namespace mfb {
+
+// Device view of a plan: plain pointers, passed to kernels by value.
+// Supernodes are numbered in a postorder of the clique tree (children
+// before parents).  For supernode s with N = |N_s|, A = |A_s|, J = N + A:
+//   col[colbase[s] + c] = CCS offset of the diagonal entry of the c-th
+//   column of N_s.  Because V is filled, that CCS column holds exactly the
+//   rows J_s[c:], so panel entry (r, c), r >= c, of any CCS-ordered array
+//   is at col[colbase[s] + c] + (r - c).
+//   rel[relbase[s] + t] = position of A_s[t] inside J_parent(s).
+//   arena[s] = offset (in doubles) of the packed lower triangle of an
+//   A x A symmetric block (update matrices U, V and their derivatives).
+struct DevPlan {
+  int32_t ns;
+  int64_t n, nnz;
+  const int32_t* ncol;      // N
+  const int32_t* nrow;      // J
+  const int32_t* parent;    // -1 for roots
+  const int32_t* cptr;      // children of s: cidx[cptr[s] .. cptr[s+1])
+  const int32_t* cidx;
+  const int32_t* colbase;
+  const int64_t* col;
+  const int32_t* relbase;
+  const int32_t* rel;
+  const int64_t* arena;
+  const int32_t* vlabel;    // user label of the c-th column: vlabel[colbase[s] + c]
+};
+
+struct Level {
+  int32_t begin, count;  // slice of the level's supernode list
+  int32_t maxN, maxA, maxJ;
+};
+
+}  // namespace mfb
+
+struct mfb_plan_s {
+  int64_t n = 0, nnz = 0;
+  uint32_t flags = 0;
+  int32_t ns = 0;
+  std::vector<int32_t> N, J, parent, cptr, cidx, colbase, relbase, rel, rep, vlabel, snode_of;
+  std::vector<int64_t> col, arena;
+  int64_t update_doubles = 0;
+  int32_t max_front = 0, max_ncols = 0, max_nanc = 0;
+  // leaf-to-root schedule: levels by height; root-to-leaf: by depth
+  std::vector<int32_t> up_list, down_list;
+  std::vector<mfb::Level> up_levels, down_levels;
+  double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
+         fl_completion = 0, fl_product = 0;
+  std::vector<int64_t> colptr_h;
+  // device copies (uploaded on first use)
+  std::mutex mu;
+  void* dmem = nullptr;  // one allocation holding every index array
+  mfb::DevPlan dev{};
+  const int32_t* d_up_list = nullptr;
+  const int32_t* d_down_list = nullptr;
+  const int32_t* d_all_list = nullptr;  // 0..ns-1
+  const int64_t* d_colptr = nullptr;    // user colptr (n+1)
+  const int32_t* d_colidx = nullptr;    // column of every CCS entry (nnz)
+};
+
+namespace mfb {
+// Host symbolic analysis (plan.cpp).  Fills everything except device copies.
+mfb_status_t build_plan(int64_t n, const int64_t* colptr, const int32_t* rowind, uint32_t flags,
+                        mfb_plan_s* p);
+}  // namespace mfb

@@ -1,0 +1,252 @@
+// Symbolic analysis on the host: elimination tree, filled-pattern test,
+// supernodes and clique tree (Pothen-Sun), relative indices, level
+// schedules and canonical flop counts.
+//
+// Sections 2 (elimination trees, eqs. e-filled, e-etree-ch), 6.1 (cliques,
+// representative vertices, eq. e-repr-test), 6.2 (supernode partitions,
+// eq. e-new2), 6.3 (clique trees) and Algorithm 6.1 of the paper.
+#include <algorithm>
+#include <cstring>
+
+#include "mfb_internal.h"
+
+namespace mfb {
+
+static mfb_status_t validate(int64_t n, const int64_t* cp, const int32_t* ri) {
+  if (n < 0 || !cp) return MFB_EINVAL;
+  if (n > 0 && !ri) return MFB_EINVAL;
+  if (n >= (int64_t(1) << 31)) return MFB_EINVAL;
+  if (cp[0] != 0) return MFB_EINVAL;
+  for (int64_t j = 0; j < n; ++j) {
+    if (cp[j + 1] <= cp[j]) return MFB_EINVAL;
+    if (ri[cp[j]] != j) return MFB_EINVAL;  // diagonal first
+    for (int64_t p = cp[j] + 1; p < cp[j + 1]; ++p)
+      if (ri[p] <= ri[p - 1] || ri[p] >= n) return MFB_EINVAL;
+  }
+  return MFB_OK;
+}
+
+mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags,
+                        mfb_plan_s* p) {
+  mfb_status_t st = validate(n, cp, ri);
+  if (st) return st;
+  p->n = n;
+  p->nnz = n ? cp[n] : 0;
+  p->flags = flags;
+
+  // Elimination tree: parent(j) = min I_j (the first off-diagonal row).
+  std::vector<int32_t> epar(n), deg(n);
+  for (int64_t j = 0; j < n; ++j) {
+    deg[j] = int32_t(cp[j + 1] - cp[j] - 1);
+    epar[j] = deg[j] > 0 ? ri[cp[j] + 1] : -1;
+  }
+  // Filled test: I_j \ {parent} must lie inside I_parent (eq. e-etree-ch);
+  // applied to every column this is equivalent to eq. e-filled.
+  for (int64_t j = 0; j < n; ++j) {
+    if (epar[j] < 0) continue;
+    int64_t q = cp[epar[j]] + 1, qe = cp[epar[j] + 1];
+    for (int64_t t = cp[j] + 2; t < cp[j + 1]; ++t) {
+      while (q < qe && ri[q] < ri[t]) ++q;
+      if (q == qe || ri[q] != ri[t]) return MFB_ENOTCHORDAL;
+      ++q;
+    }
+  }
+  // Children lists of the elimination tree, ascending.
+  std::vector<int32_t> ehead(n, -1), enext(n, -1);
+  for (int64_t j = n - 1; j >= 0; --j)
+    if (epar[j] >= 0) { enext[j] = ehead[epar[j]]; ehead[epar[j]] = int32_t(j); }
+
+  // Algorithm 6.1 (Pothen-Sun): vertex i is representative iff
+  // |I_i| > |I_j| - 1 for every child j (eq. e-repr-test); otherwise it joins
+  // the supernode of an eligible child (|I_i| = |I_j| - 1).  The choice among
+  // eligible children is free; we take the lowest (or highest) label.
+  const bool tie_last = (flags & MFB_PLAN_TIE_LAST) != 0;
+  std::vector<int32_t> sn_of(n, -1);
+  std::vector<std::vector<int32_t>> members;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t pick = -1;
+    for (int32_t j = ehead[i]; j != -1; j = enext[j]) {
+      if (deg[i] == deg[j] - 1) {
+        if (pick < 0 || tie_last) pick = j;
+        if (!tie_last) break;
+      }
+    }
+    if (pick < 0) {
+      sn_of[i] = int32_t(members.size());
+      members.push_back({int32_t(i)});
+    } else {
+      sn_of[i] = sn_of[pick];
+      members[sn_of[i]].push_back(int32_t(i));
+    }
+  }
+  const int32_t ns = int32_t(members.size());
+  // Clique-tree parent: the supernode holding the first ancestor
+  // min A_s = parent of the last vertex of N_s (Section 6.2).
+  std::vector<int32_t> spar0(ns, -1);
+  for (int32_t s = 0; s < ns; ++s) {
+    int32_t last = members[s].back();
+    if (epar[last] >= 0) spar0[s] = sn_of[epar[last]];
+  }
+  // Postorder of the clique tree; children visited in order of their
+  // representative vertex, roots likewise.
+  std::vector<int32_t> chead(ns, -1), cnext(ns, -1);
+  for (int32_t s = ns - 1; s >= 0; --s)
+    if (spar0[s] >= 0) { cnext[s] = chead[spar0[s]]; chead[spar0[s]] = s; }
+  std::vector<int32_t> post;  // post[k] = old id
+  post.reserve(ns);
+  {
+    std::vector<int32_t> stack;
+    std::vector<int32_t> it(ns, -2);
+    for (int32_t r = 0; r < ns; ++r) {
+      if (spar0[r] >= 0) continue;
+      stack.push_back(r);
+      while (!stack.empty()) {
+        int32_t s = stack.back();
+        if (it[s] == -2) it[s] = chead[s];
+        int32_t c = it[s];
+        if (c != -1) {
+          it[s] = cnext[c];
+          stack.push_back(c);
+        } else {
+          post.push_back(s);
+          stack.pop_back();
+        }
+      }
+    }
+  }
+  if (int32_t(post.size()) != ns) return MFB_EINVAL;
+  std::vector<int32_t> newid(ns);
+  for (int32_t k = 0; k < ns; ++k) newid[post[k]] = k;
+
+  p->ns = ns;
+  p->N.resize(ns);
+  p->J.resize(ns);
+  p->parent.resize(ns);
+  p->rep.resize(ns);
+  p->colbase.resize(ns + 1);
+  p->relbase.resize(ns + 1);
+  p->arena.resize(ns + 1);
+  p->snode_of.resize(n);
+  p->col.resize(n);
+  p->vlabel.resize(n);
+  int64_t cb = 0, rb = 0, ab = 0;
+  p->max_front = p->max_ncols = p->max_nanc = 0;
+  for (int32_t k = 0; k < ns; ++k) {
+    const auto& mem = members[post[k]];
+    const int32_t rep = mem[0];
+    const int32_t Nn = int32_t(mem.size());
+    const int32_t Jn = int32_t(cp[rep + 1] - cp[rep]);
+    const int32_t An = Jn - Nn;
+    if (An < 0) return MFB_ENOTCHORDAL;
+    p->N[k] = Nn;
+    p->J[k] = Jn;
+    p->rep[k] = rep;
+    p->parent[k] = spar0[post[k]] >= 0 ? newid[spar0[post[k]]] : -1;
+    p->colbase[k] = int32_t(cb);
+    p->relbase[k] = int32_t(rb);
+    p->arena[k] = ab;
+    // Column c of the supernode holds rows J_s[c:] (eq. e-new2): check.
+    const int32_t* Js = ri + cp[rep];
+    for (int32_t c = 0; c < Nn; ++c) {
+      const int32_t v = mem[c];
+      if (Js[c] != v) return MFB_ENOTCHORDAL;
+      if (cp[v + 1] - cp[v] != Jn - c) return MFB_ENOTCHORDAL;
+      if (std::memcmp(ri + cp[v], Js + c, sizeof(int32_t) * size_t(Jn - c)) != 0)
+        return MFB_ENOTCHORDAL;
+      p->col[cb + c] = cp[v];
+      p->vlabel[cb + c] = v;
+      p->snode_of[v] = k;
+    }
+    cb += Nn;
+    rb += An;
+    ab += int64_t(An) * (An + 1) / 2;
+    p->max_front = std::max(p->max_front, Jn);
+    p->max_ncols = std::max(p->max_ncols, Nn);
+    p->max_nanc = std::max(p->max_nanc, An);
+  }
+  p->colbase[ns] = int32_t(cb);
+  p->relbase[ns] = int32_t(rb);
+  p->arena[ns] = ab;
+  p->update_doubles = ab;
+
+  // Relative indices: position of A_s[t] in J_parent(s).  A_s lies inside
+  // J_parent (first clique-tree property, Section 6.3).
+  p->rel.resize(rb);
+  for (int32_t k = 0; k < ns; ++k) {
+    const int32_t An = p->J[k] - p->N[k];
+    if (An == 0) {
+      if (p->parent[k] >= 0) return MFB_ENOTCHORDAL;
+      continue;
+    }
+    if (p->parent[k] < 0) return MFB_ENOTCHORDAL;
+    const int32_t* As = ri + cp[p->rep[k]] + p->N[k];
+    const int32_t pr = p->rep[p->parent[k]];
+    const int32_t* Jp = ri + cp[pr];
+    const int32_t Jpn = p->J[p->parent[k]];
+    int32_t q = 0;
+    for (int32_t t = 0; t < An; ++t) {
+      while (q < Jpn && Jp[q] < As[t]) ++q;
+      if (q == Jpn || Jp[q] != As[t]) return MFB_ENOTCHORDAL;
+      p->rel[p->relbase[k] + t] = q++;
+    }
+  }
+  // Children in postorder numbering (ascending = fixed assembly order).
+  p->cptr.assign(ns + 1, 0);
+  for (int32_t k = 0; k < ns; ++k)
+    if (p->parent[k] >= 0) p->cptr[p->parent[k] + 1]++;
+  for (int32_t k = 0; k < ns; ++k) p->cptr[k + 1] += p->cptr[k];
+  p->cidx.assign(std::max(1, p->cptr[ns]), 0);
+  {
+    std::vector<int32_t> fill(p->cptr.begin(), p->cptr.end() - 1);
+    for (int32_t k = 0; k < ns; ++k)
+      if (p->parent[k] >= 0) p->cidx[fill[p->parent[k]]++] = k;
+  }
+  // Level schedules.  Height: leaves 0, parent = 1 + max child (postorder
+  // visits children first).  Depth: roots 0.
+  std::vector<int32_t> h(ns, 0), d(ns, 0);
+  int32_t H = 0, Dm = 0;
+  for (int32_t k = 0; k < ns; ++k)
+    if (p->parent[k] >= 0) h[p->parent[k]] = std::max(h[p->parent[k]], h[k] + 1);
+  for (int32_t k = ns - 1; k >= 0; --k)
+    if (p->parent[k] >= 0) d[k] = d[p->parent[k]] + 1;
+  for (int32_t k = 0; k < ns; ++k) { H = std::max(H, h[k]); Dm = std::max(Dm, d[k]); }
+  auto make_levels = [&](const std::vector<int32_t>& lv, int32_t nl, std::vector<int32_t>& list,
+                         std::vector<Level>& levels) {
+    levels.assign(ns ? nl + 1 : 0, Level{0, 0, 0, 0, 0});
+    list.clear();
+    list.reserve(ns);
+    std::vector<int32_t> cnt(nl + 2, 0);
+    for (int32_t k = 0; k < ns; ++k) cnt[lv[k] + 1]++;
+    for (int32_t l = 0; l <= nl; ++l) cnt[l + 1] += cnt[l];
+    list.assign(ns, 0);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t k = 0; k < ns; ++k) list[fill[lv[k]]++] = k;
+    for (int32_t l = 0; ns && l <= nl; ++l) {
+      Level L{cnt[l], cnt[l + 1] - cnt[l], 0, 0, 0};
+      for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
+        int32_t k = list[t];
+        L.maxN = std::max(L.maxN, p->N[k]);
+        L.maxA = std::max(L.maxA, p->J[k] - p->N[k]);
+        L.maxJ = std::max(L.maxJ, p->J[k]);
+      }
+      levels[l] = L;
+    }
+  };
+  make_levels(h, H, p->up_list, p->up_levels);
+  make_levels(d, Dm, p->down_list, p->down_levels);
+
+  // Canonical algorithmic flop counts per supernode (LAPACK conventions).
+  for (int32_t k = 0; k < ns; ++k) {
+    const double Nn = p->N[k], An = p->J[k] - p->N[k];
+    p->fl_factor += Nn * Nn * Nn / 3 + Nn * Nn * An + Nn * An * An;
+    p->fl_projinv += 2 * Nn * Nn * Nn / 3 + 2 * An * An * Nn + An * Nn * Nn;
+    p->fl_hess += 6 * An * An * Nn + 6 * An * Nn * Nn + 3 * Nn * Nn * Nn;
+    p->fl_invhess += 7 * An * An * Nn + 7 * An * Nn * Nn + 3 * Nn * Nn * Nn;
+    p->fl_invhess_x += An * An * An / 3;
+    p->fl_completion += An * An * An / 3 + 2 * An * An * Nn + An * Nn * Nn + Nn * Nn * Nn;
+    p->fl_product += Nn * Nn * Nn / 3 + Nn * Nn * An + Nn * An * An;
+  }
+  return MFB_OK;
+}
+
+}  // namespace mfb

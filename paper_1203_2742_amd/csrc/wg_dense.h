@@ -1,0 +1,264 @@
+// Workgroup-cooperative dense FP64 building blocks for gfx950.
+//
+// Every routine is called by all 256 threads of a workgroup (uniform
+// control flow) and works on column-major matrices reached through
+// operand functors, so one routine serves panels kept in CCS order,
+// packed symmetric update blocks and per-workgroup scratch alike.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mfb {
+
+constexpr int NT = 256;  // threads per workgroup (4 wavefronts of 64)
+constexpr int TM = 64;   // output tile edge of wg_gemm
+constexpr int KC = 16;   // k-chunk staged through LDS
+constexpr int NB = 32;   // diagonal block of the blocked factorizations
+constexpr int LDD = NB + 1;
+// LDS doubles used by the routines in this file
+constexpr int SMEM_GEMM = 2 * KC * TM;
+constexpr int SMEM_DIAG = 2 * NB * LDD;  // diagonal block and its inverse
+constexpr int SMEM_DOUBLES = SMEM_GEMM + SMEM_DIAG + 8;
+
+// Packed lower storage of a symmetric A x A block, column-major: entry
+// (x, y), x >= y, lives at y*(2A-y-1)/2 + x.
+__device__ __forceinline__ int64_t pk(int x, int y, int A) {
+  return (int64_t)y * (2 * A - y - 1) / 2 + x;
+}
+__device__ __forceinline__ double sym_packed(const double* u, int x, int y, int A) {
+  return x >= y ? u[pk(x, y, A)] : u[pk(y, x, A)];
+}
+
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// C(i, j) <- epi(i, j, sum_k a(i, k) b(k, j)) for 0 <= i < M, 0 <= j < N
+// (only i >= j when `lower`).  64 x 64 output tiles, each thread owning a
+// 4 x 4 register block; k-chunks of 16 are staged through LDS with the
+// next chunk's global loads in flight during the current chunk's FMAs.
+// Every (i, j) is produced by exactly one thread, in a fixed k order.
+template <class FA, class FB, class EPI>
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const FB& fb,
+                                        const EPI& epi, bool lower, double* sm) {
+  double* As = sm;
+  double* Bs = sm + KC * TM;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  constexpr int PER = KC * TM / NT;
+  for (int i0 = 0; i0 < M; i0 += TM) {
+    for (int j0 = 0; j0 < N; j0 += TM) {
+      if (lower && j0 > i0 + TM - 1) continue;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      double ra[PER], rb[PER];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int e = tid + q * NT;
+          const int i = e & (TM - 1), k = e / TM;
+          const int gk = k0 + k;
+          ra[q] = (i0 + i < M && gk < K) ? fa(i0 + i, gk) : 0.0;
+          rb[q] = (j0 + i < N && gk < K) ? fb(gk, j0 + i) : 0.0;
+        }
+      };
+      if (K > 0) fetch(0);
+      for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          As[tid + q * NT] = ra[q];
+          Bs[tid + q * NT] = rb[q];
+        }
+        __syncthreads();
+        if (k0 + KC < K) fetch(k0 + KC);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) av[a] = As[k * TM + tx + 16 * a];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) bv[b] = Bs[k * TM + ty + 16 * b];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
+          if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, acc[a][b]);
+        }
+    }
+  }
+}
+
+// Unblocked Cholesky of an nb x nb (nb <= NB) lower block in LDS (leading
+// dimension LDD) by wavefront 0.  A non-positive pivot is replaced by one
+// (so later arithmetic stays finite) and its index is returned through
+// *fail (first failure, -1 if none).  Call with all threads; includes the
+// closing workgroup barrier.
+__device__ __forceinline__ void diag_chol(double* L, int nb, int* fail) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int k = 0; k < nb; ++k) {
+      double d = L[k + k * LDD];
+      const bool bad = !(d > 0.0);
+      d = bad ? 1.0 : sqrt(d);
+      wave_sync();
+      if (lane == 0) {
+        L[k + k * LDD] = d;
+        if (bad && *fail < 0) *fail = k;
+      }
+      const double inv = 1.0 / d;
+      for (int i = k + 1 + lane; i < nb; i += 64) L[i + k * LDD] *= inv;
+      wave_sync();
+      const int m = nb - k - 1;
+      for (int e = lane; e < m * m; e += 64) {
+        const int i = k + 1 + e % m, j = k + 1 + e / m;
+        if (i >= j) L[i + j * LDD] -= L[i + k * LDD] * L[j + k * LDD];
+      }
+      wave_sync();
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of an nb x nb lower-triangular block L (LDS, LDD) into Li (LDS,
+// LDD; everything outside the lower nb x nb triangle set to zero).  Lane c
+// computes column c by forward substitution; columns are independent.
+__device__ __forceinline__ void diag_trtri(const double* L, double* Li, int nb) {
+  const int c = threadIdx.x;
+  for (int e = threadIdx.x; e < NB * LDD; e += NT) Li[e] = 0.0;
+  __syncthreads();
+  if (c < nb) {
+    for (int i = 0; i < c; ++i) Li[i + c * LDD] = 0.0;
+    Li[c + c * LDD] = 1.0 / L[c + c * LDD];
+    for (int i = c + 1; i < nb; ++i) {
+      double v = 0.0;
+      for (int k = c; k < i; ++k) v = fma(L[i + k * LDD], Li[k + c * LDD], v);
+      Li[i + c * LDD] = -v / L[i + i * LDD];
+    }
+  }
+  __syncthreads();
+}
+
+// Partial Cholesky of a J x N column panel F (leading dimension ld): on
+// return F[0:N, 0:N] holds C = chol(F11) (lower) and F[N:J, 0:N] holds
+// F21 C^-T.  Blocked right-looking with NB-column blocks: the diagonal
+// block is factored and inverted in LDS, the rows below are multiplied by
+// that inverse and the remaining panel columns updated, both with wg_gemm.
+// *fail receives the first failing column (or stays -1).
+__device__ __forceinline__ void wg_potrf_panel(double* F, int ld, int J, int N, double* sm,
+                                               int* fail) {
+  double* Ld = sm + SMEM_GEMM;
+  for (int kb = 0; kb < N; kb += NB) {
+    const int nb = min(NB, N - kb);
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (i >= j) Ld[i + j * LDD] = F[(kb + i) + (int64_t)(kb + j) * ld];
+    }
+    __shared__ int lfail;
+    if (threadIdx.x == 0) lfail = -1;
+    __syncthreads();
+    diag_chol(Ld, nb, &lfail);
+    if (threadIdx.x == 0 && lfail >= 0 && *fail < 0) *fail = kb + lfail;
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (i >= j) F[(kb + i) + (int64_t)(kb + j) * ld] = Ld[i + j * LDD];
+    }
+    // rows below the diagonal block: X <- X C_kk^-T, applied as a product
+    // with the explicit inverse of the diagonal block.  In place is safe:
+    // nb <= TM gives one column tile, and each row tile reads only its own
+    // rows before its epilogue writes them.
+    if (kb + nb < J) {
+      double* Li = Ld + NB * LDD;
+      diag_trtri(Ld, Li, nb);
+      wg_gemm(
+          J - kb - nb, nb, nb, [&](int i, int k) { return F[(kb + nb + i) + (int64_t)(kb + k) * ld]; },
+          [&](int k, int j) { return Li[j + k * LDD]; },
+          [&](int i, int j, double acc) { F[(kb + nb + i) + (int64_t)(kb + j) * ld] = acc; }, false,
+          sm);
+    }
+    __syncthreads();
+    const int r0 = kb + nb;
+    if (r0 < N) {
+      wg_gemm(
+          J - r0, N - r0, nb, [&](int i, int k) { return F[(r0 + i) + (int64_t)(kb + k) * ld]; },
+          [&](int k, int j) { return F[(r0 + j) + (int64_t)(kb + k) * ld]; },
+          [&](int i, int j, double acc) { F[(r0 + i) + (int64_t)(r0 + j) * ld] -= acc; }, true,
+          sm);
+      __syncthreads();
+    }
+  }
+}
+
+// Ci = C^-1 for an N x N lower-triangular C (leading dimensions ldc, ldi),
+// blocked, last diagonal block first: with C = [C11 0; C21 C22],
+// inv(C)21 = -inv(C22) C21 inv(C11).
+template <class CF>
+__device__ __forceinline__ void wg_trtri(const CF& C, int N, double* Ci, int ldi, double* sm) {
+  double* Ld = sm + SMEM_GEMM;
+  double* Li = Ld + NB * LDD;
+  const int nblk = (N + NB - 1) / NB;
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int jb = bk * NB, nb = min(NB, N - jb);
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (i >= j) Ld[i + j * LDD] = C(jb + i, jb + j);
+    }
+    __syncthreads();
+    diag_trtri(Ld, Li, nb);
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      Ci[(jb + i) + (int64_t)(jb + j) * ldi] = i >= j ? Li[i + j * LDD] : 0.0;
+    }
+    const int r0 = jb + nb, m = N - r0;
+    if (m > 0) {
+      // T = inv(C22) C21 into the output block, then right-multiply by -inv(C11)
+      wg_gemm(
+          m, nb, m,
+          [&](int i, int k) { return k <= i ? Ci[(r0 + i) + (int64_t)(r0 + k) * ldi] : 0.0; },
+          [&](int k, int j) { return C(r0 + k, jb + j); },
+          [&](int i, int j, double acc) { Ci[(r0 + i) + (int64_t)(jb + j) * ldi] = acc; }, false,
+          sm);
+      __syncthreads();
+      // block <- -T inv(C11), in place (one column tile, row-local)
+      wg_gemm(
+          m, nb, nb, [&](int i, int k) { return Ci[(r0 + i) + (int64_t)(jb + k) * ldi]; },
+          [&](int k, int j) { return Li[k + j * LDD]; },
+          [&](int i, int j, double acc) { Ci[(r0 + i) + (int64_t)(jb + j) * ldi] = -acc; }, false,
+          sm);
+    }
+    __syncthreads();
+  }
+  // zero the strict upper triangle so Ci can be read as a full matrix
+  for (int e = threadIdx.x; e < N * N; e += NT) {
+    const int i = e % N, j = e / N;
+    if (i < j) Ci[i + (int64_t)j * ldi] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Deterministic workgroup sum of one value per thread.
+__device__ __forceinline__ double wg_sum(double v, double* sm) {
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace mfb
