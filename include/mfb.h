@@ -102,9 +102,10 @@ typedef struct {
  * filled in the given order (I_j \ {parent} within I_parent for every j:
  * eqs. e-filled, e-etree-ch), forms the supernodes and the clique tree by the
  * Pothen-Sun algorithm, the relative indices of every A_s inside its parent
- * clique, and the level schedules, and uploads the index arrays to the current
- * device.  Returns MFB_EINVAL for malformed CCS, MFB_ENOTCHORDAL when the
- * pattern is not filled, MFB_ENOMEM / MFB_EHIP on allocation failure. */
+ * clique, and the level schedules.  Host work only: the index arrays are
+ * uploaded to the current device by the first mfb_factor_create.  Returns
+ * MFB_EINVAL for malformed CCS, MFB_ENOTCHORDAL when the pattern is not
+ * filled, MFB_ENOMEM on allocation failure. */
 mfb_status_t mfb_plan_symbolic(int64_t n, const int64_t* colptr_host, const int32_t* rowind_host,
                                uint32_t flags, mfb_plan_t* out);
 
@@ -191,6 +192,45 @@ mfb_status_t mfb_get_status(mfb_factor_t f, int64_t* bad_index_host);
 
 /* Static description of a status code. */
 const char* mfb_strerror(mfb_status_t s);
+
+/* ---- launch profiling (tracing aid; off by default) -------------------- */
+
+/* Kernel identifiers reported by the profiler. */
+#define MFB_K_FACTOR 0       /* Algorithm 7.1, one leaf-to-root level */
+#define MFB_K_PROJINV 1      /* Algorithm 7.2, one root-to-leaf level */
+#define MFB_K_HESS_UP 2      /* Hessian step 1 (Algorithm 5.1 in block form) */
+#define MFB_K_HESS_DOWN 3    /* Hessian steps 2-3 */
+#define MFB_K_IHESS_DOWN 4   /* inverse Hessian steps 1-2 (Algorithm 5.2) */
+#define MFB_K_IHESS_UP 5     /* inverse Hessian step 3 */
+#define MFB_K_COMPLETION 6   /* Algorithm 7.3 */
+#define MFB_K_VINV 7         /* (S_AA)^-1 per supernode */
+#define MFB_K_PRODUCT 8      /* Algorithm 3.2 in block form */
+#define MFB_K_COUNT 9
+
+typedef struct {
+  int32_t kernel;   /* MFB_K_* */
+  int32_t level;    /* level index in its schedule */
+  int32_t nsuper;   /* supernodes in the launch */
+  int32_t k;        /* right-hand sides in the launch */
+  double ms;        /* launch duration between HIP events recorded on its stream */
+  double bytes;     /* canonical algorithmic bytes moved by the launch */
+  double flops;     /* canonical algorithmic flops of the launch */
+} mfb_profile_entry_t;
+
+/* Enables (1) or disables (0) profiling on a factor handle.  While enabled,
+ * every kernel launch of the handle is bracketed by two HIP events on its
+ * stream.  Entries accumulate until read. */
+mfb_status_t mfb_profile_enable(mfb_factor_t f, int32_t enable);
+
+/* Synchronizes the recorded events and copies up to `cap` entries (in
+ * launch order) to out_host; *count_host receives the number recorded.  The
+ * recorded list is then cleared.  With out_host NULL only the count is
+ * returned and nothing is cleared. */
+mfb_status_t mfb_profile_read(mfb_factor_t f, mfb_profile_entry_t* out_host, int64_t cap,
+                              int64_t* count_host);
+
+/* Kernel symbol name of an MFB_K_* identifier (as seen by rocprofv3). */
+const char* mfb_kernel_name(int32_t kernel);
 
 #ifdef __cplusplus
 }

@@ -125,8 +125,19 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
 }
 
 
+namespace mfb {
+struct ProfRec {
+  int32_t kernel, level, nsuper, k;
+  double bytes, flops;
+  hipEvent_t e0, e1;
+};
+}  // namespace mfb
+
 struct mfb_factor_s {
   mfb_plan_s* plan = nullptr;
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
   char* ws = nullptr;
   double *R = nullptr, *LB = nullptr, *S = nullptr, *Vs = nullptr, *Vi = nullptr, *U = nullptr;
   double *part = nullptr, *logdet = nullptr, *scratch = nullptr;
@@ -242,18 +253,75 @@ mfb_status_t mfb_factor_create(mfb_plan_t p, void* ws, size_t bytes, mfb_factor_
   return MFB_OK;
 }
 
-void mfb_factor_destroy(mfb_factor_t f) { delete f; }
+void mfb_factor_destroy(mfb_factor_t f) {
+  if (!f) return;
+  for (auto& r : f->recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  for (auto e : f->pool) (void)hipEventDestroy(e);
+  delete f;
+}
 
-static mfb_status_t run_levels(mfb_factor_s* f, const std::vector<Level>& lv, const int32_t* dlist,
+// Canonical algorithmic bytes and flops of one level launch of kernel `kid`
+// with k right-hand sides.  Bytes: every panel entry of the inputs read once
+// and of the outputs written once, factor data shared by all right-hand
+// sides counted once, and each update block produced written once and read
+// once.  Flops: the canonical per-supernode counts split between the two
+// sweeps of an operation.
+static void canonical(int kid, const Level& L, int k, double* bytes, double* flops) {
+  const double p = L.p, u = L.u, K = k;
+  double b = 0, fl = 0;
+  switch (kid) {
+    case MFB_K_FACTOR: b = 2 * p + 2 * u; fl = L.n3 / 3 + L.n2a + L.na2; break;
+    case MFB_K_PROJINV: b = 2 * p + 2 * u; fl = 2 * L.n3 / 3 + 2 * L.na2 + L.n2a; break;
+    case MFB_K_HESS_UP: b = p + K * (2 * p + 2 * u); fl = K * (2 * L.na2 + 2 * L.n2a); break;
+    case MFB_K_HESS_DOWN: b = p + u + K * (2 * p + 2 * u); fl = K * (4 * L.na2 + 4 * L.n2a + 3 * L.n3); break;
+    case MFB_K_IHESS_DOWN: b = 2 * p + u + K * (2 * p + 2 * u); fl = K * (4 * L.na2 + 4 * L.n2a + 3 * L.n3); break;
+    case MFB_K_IHESS_UP: b = p + K * (2 * p + 2 * u); fl = K * (3 * L.na2 + 3 * L.n2a); break;
+    case MFB_K_COMPLETION: b = 4 * p + 3 * u; fl = L.a3 / 3 + 2 * L.na2 + L.n2a + L.n3; break;
+    case MFB_K_VINV: b = 2 * u; fl = L.a3 / 3; break;
+    case MFB_K_PRODUCT: b = 2 * p + 2 * u; fl = L.n3 / 3 + L.n2a + L.na2; break;
+  }
+  *bytes = 8 * b;
+  *flops = fl;
+}
+
+static hipEvent_t pool_event(mfb_factor_s* f) {
+  if (!f->pool.empty()) {
+    hipEvent_t e = f->pool.back();
+    f->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static mfb_status_t run_levels(mfb_factor_s* f, int kid, const std::vector<Level>& lv, const int32_t* dlist,
                                hipStream_t s, int k, Op op,
                                void (*launch)(mfb_factor_s*, const int32_t*, dim3, hipStream_t,
                                               int64_t, void*),
                                void* ctx) {
+  int32_t level = -1;
   for (const auto& L : lv) {
+    ++level;
     if (L.count == 0) continue;
     dim3 grid(unsigned(L.count), unsigned(k));
+    ProfRec rec{kid, level, L.count, k, 0.0, 0.0, nullptr, nullptr};
+    if (f->prof) {
+      canonical(kid, L, k, &rec.bytes, &rec.flops);
+      rec.e0 = pool_event(f);
+      rec.e1 = pool_event(f);
+      if (!rec.e0 || !rec.e1) return MFB_EHIP;
+      if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
+    }
     launch(f, dlist + L.begin, grid, s, std::max<int64_t>(1, slot_doubles(op, L)), ctx);
     if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+    if (f->prof) {
+      if (hipEventRecord(rec.e1, s) != hipSuccess) return MFB_EHIP;
+      f->recs.push_back(rec);
+    }
   }
   return MFB_OK;
 }
@@ -265,7 +333,7 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* x; } ctx{x};
   mfb_status_t st = run_levels(
-      f, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_FACTOR,
+      f, MFB_K_FACTOR, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_FACTOR,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         k_factor<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U, f->part,
                                   f->st, f->scratch, slot);
@@ -290,7 +358,7 @@ mfb_status_t mfb_logdet(mfb_factor_t f, double* out, void* stream) {
 static mfb_status_t ensure_projinv(mfb_factor_s* f, hipStream_t s) {
   if (f->s_valid) return MFB_OK;
   mfb_status_t st = run_levels(
-      f, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_FACTOR,
+      f, MFB_K_PROJINV, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_FACTOR,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void*) {
         k_projinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
       },
@@ -346,7 +414,7 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
   if ((st = ensure_projinv(f, s))) return st;
   struct Ctx { const double* y; double* t; RhsArena a; } ctx{y, t, a};
   st = run_levels(
-      f, f->plan->up_levels, f->plan->d_up_list, s, k, OP_HUP,
+      f, MFB_K_HESS_UP, f->plan->up_levels, f->plan->d_up_list, s, k, OP_HUP,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
         k_hess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua, x->a.upd,
@@ -355,7 +423,7 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
       &ctx);
   if (st) return st;
   st = run_levels(
-      f, f->plan->down_levels, f->plan->d_down_list, s, k, OP_HDOWN,
+      f, MFB_K_HESS_DOWN, f->plan->down_levels, f->plan->d_down_list, s, k, OP_HDOWN,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
         k_hess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
@@ -369,7 +437,7 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
 static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
   if (f->vinv_valid) return MFB_OK;
   mfb_status_t st = run_levels(
-      f, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_VINV,
+      f, MFB_K_VINV, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_VINV,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void*) {
         k_vinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->Vs, f->Vi, f->st, f->scratch, slot);
       },
@@ -394,7 +462,7 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   if ((st = ensure_vinv(f, s))) return st;
   struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
   st = run_levels(
-      f, f->plan->down_levels, f->plan->d_down_list, s, k, OP_IHDOWN,
+      f, MFB_K_IHESS_DOWN, f->plan->down_levels, f->plan->d_down_list, s, k, OP_IHDOWN,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
         k_ihess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
@@ -403,7 +471,7 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
       &ctx);
   if (st) return st;
   st = run_levels(
-      f, f->plan->up_levels, f->plan->d_up_list, s, k, OP_IHUP,
+      f, MFB_K_IHESS_UP, f->plan->up_levels, f->plan->d_up_list, s, k, OP_IHUP,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
         k_ihess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua, x->a.upd,
@@ -421,7 +489,7 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* s; } ctx{sin};
   mfb_status_t st = run_levels(
-      f, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_COMPLETION,
+      f, MFB_K_COMPLETION, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_COMPLETION,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         k_completion<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
                                       f->Vi, f->part, f->st, f->scratch, slot);
@@ -441,7 +509,7 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
   f->last = s;
   struct Ctx { double* x; } ctx{x};
   mfb_status_t st = run_levels(
-      f, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_PRODUCT,
+      f, MFB_K_PRODUCT, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_PRODUCT,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         k_product<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U, f->scratch, slot);
       },
@@ -471,6 +539,40 @@ mfb_status_t mfb_get_status(mfb_factor_t f, int64_t* bad) {
   if (h.code == 0) return MFB_OK;
   if (bad && h.bad != ~0ull) *bad = int64_t(h.bad);
   return h.code;
+}
+
+mfb_status_t mfb_profile_enable(mfb_factor_t f, int32_t enable) {
+  if (!f) return MFB_EINVAL;
+  f->prof = enable != 0;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_profile_read(mfb_factor_t f, mfb_profile_entry_t* out, int64_t cap, int64_t* count) {
+  if (!f || (cap > 0 && !out)) return MFB_EINVAL;
+  if (count) *count = int64_t(f->recs.size());
+  if (!out) return MFB_OK;  // count only
+  int64_t i = 0;
+  mfb_status_t st = MFB_OK;
+  for (auto& r : f->recs) {
+    if (i < cap) {
+      float ms = 0.f;
+      if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+        st = MFB_EHIP;
+      out[i] = mfb_profile_entry_t{r.kernel, r.level, r.nsuper, r.k, double(ms), r.bytes, r.flops};
+    }
+    ++i;
+    f->pool.push_back(r.e0);
+    f->pool.push_back(r.e1);
+  }
+  f->recs.clear();
+  return st;
+}
+
+const char* mfb_kernel_name(int32_t kernel) {
+  static const char* names[MFB_K_COUNT] = {"k_factor", "k_projinv", "k_hess_up", "k_hess_down",
+                                           "k_ihess_down", "k_ihess_up", "k_completion", "k_vinv",
+                                           "k_product"};
+  return (kernel >= 0 && kernel < MFB_K_COUNT) ? names[kernel] : "unknown";
 }
 
 }  // extern "C"

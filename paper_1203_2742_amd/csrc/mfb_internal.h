@@ -37,6 +37,9 @@ struct DevPlan {
 struct Level {
   int32_t begin, count;  // slice of the level's supernode list
   int32_t maxN, maxA, maxJ;
+  // sums over the level's supernodes, for canonical bytes and flops:
+  // panel entries sum_c (J - c), packed update entries A(A+1)/2, N^3, N^2 A, N A^2, A^3
+  double p, u, n3, n2a, na2, a3;
 };
 
 }  // namespace mfb

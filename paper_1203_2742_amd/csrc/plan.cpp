@@ -212,7 +212,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   for (int32_t k = 0; k < ns; ++k) { H = std::max(H, h[k]); Dm = std::max(Dm, d[k]); }
   auto make_levels = [&](const std::vector<int32_t>& lv, int32_t nl, std::vector<int32_t>& list,
                          std::vector<Level>& levels) {
-    levels.assign(ns ? nl + 1 : 0, Level{0, 0, 0, 0, 0});
+    levels.assign(ns ? nl + 1 : 0, Level{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
     list.clear();
     list.reserve(ns);
     std::vector<int32_t> cnt(nl + 2, 0);
@@ -222,12 +222,19 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
     for (int32_t k = 0; k < ns; ++k) list[fill[lv[k]]++] = k;
     for (int32_t l = 0; ns && l <= nl; ++l) {
-      Level L{cnt[l], cnt[l + 1] - cnt[l], 0, 0, 0};
+      Level L{cnt[l], cnt[l + 1] - cnt[l], 0, 0, 0, 0, 0, 0, 0, 0, 0};
       for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
         int32_t k = list[t];
         L.maxN = std::max(L.maxN, p->N[k]);
         L.maxA = std::max(L.maxA, p->J[k] - p->N[k]);
         L.maxJ = std::max(L.maxJ, p->J[k]);
+        const double Nn = p->N[k], Jn = p->J[k], An = Jn - Nn;
+        L.p += Nn * Jn - Nn * (Nn - 1) / 2;
+        L.u += An * (An + 1) / 2;
+        L.n3 += Nn * Nn * Nn;
+        L.n2a += Nn * Nn * An;
+        L.na2 += Nn * An * An;
+        L.a3 += An * An * An;
       }
       levels[l] = L;
     }

@@ -41,6 +41,16 @@ class MfbError(RuntimeError):
         super().__init__(f"{where}: {self.name}" if where else self.name)
 
 
+KERNELS = ("k_factor", "k_projinv", "k_hess_up", "k_hess_down", "k_ihess_down", "k_ihess_up",
+           "k_completion", "k_vinv", "k_product")
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("level", ctypes.c_int32), ("nsuper", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n", "nnz", "nsuper", "nlevels_up", "nlevels_down", "max_front", "max_ncols",
@@ -76,6 +86,9 @@ def _load():
         "mfb_factor_export_ldl": (I32, [P, P, P]),
         "mfb_get_status": (I32, [P, ctypes.POINTER(I64)]),
         "mfb_strerror": (ctypes.c_char_p, [I32]),
+        "mfb_profile_enable": (I32, [P, I32]),
+        "mfb_profile_read": (I32, [P, P, I64, ctypes.POINTER(I64)]),
+        "mfb_kernel_name": (ctypes.c_char_p, [I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -246,6 +259,32 @@ def get_status(f: Factor):
 
 def strerror(code: int) -> str:
     return _lib.mfb_strerror(int(code)).decode()
+
+
+def profile_enable(f: Factor, enable: bool = True):
+    _chk(_lib.mfb_profile_enable(f.handle, 1 if enable else 0), "profile_enable")
+
+
+def profile_read(f: Factor):
+    """Recorded launches as a list of dicts (and clears the record)."""
+    count = ctypes.c_int64(0)
+    _chk(_lib.mfb_profile_read(f.handle, None, 0, ctypes.byref(count)), "profile_read")
+    return _profile_take(f, int(count.value))
+
+
+def _profile_take(f, n):
+    if n == 0:
+        return []
+    buf = (ProfileEntry * n)()
+    count = ctypes.c_int64(0)
+    _chk(_lib.mfb_profile_read(f.handle, ctypes.cast(buf, ctypes.c_void_p), n, ctypes.byref(count)),
+         "profile_read")
+    return [{"kernel": KERNELS[e.kernel], "level": e.level, "nsuper": e.nsuper, "k": e.k,
+             "ms": e.ms, "bytes": e.bytes, "flops": e.flops} for e in buf[:min(n, count.value)]]
+
+
+def kernel_name(kernel: int) -> str:
+    return _lib.mfb_kernel_name(int(kernel)).decode()
 
 
 # ----------------------------------------------------------- convenience
