@@ -32,7 +32,8 @@ METRIC = "Hessian evals/s + FP64 GB/s·GFLOP/s vs plain path; p50/p99 latency, 1
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}.json")
-KERNEL_SOURCES = ["paper_1203_2742_amd/csrc/kernels.hip", "paper_1203_2742_amd/csrc/wg_dense.h"]
+KERNEL_SOURCES = ["paper_1203_2742_amd/csrc/kernels.hip", "paper_1203_2742_amd/csrc/wg_dense.h",
+                  "paper_1203_2742_amd/csrc/reg_front.h"]
 
 
 def kernel_source_hash() -> str:

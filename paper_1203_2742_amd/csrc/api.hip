@@ -91,7 +91,8 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   size_t iN = v32(p->N), iJ = v32(p->J), iPar = v32(p->parent), iCp = v32(p->cptr), iCi = v32(p->cidx),
          iCb = v32(p->colbase), iCol = v64(p->col), iRb = v32(p->relbase), iRel = v32(p->rel),
          iAr = v64(p->arena), iVl = v32(p->vlabel), iUp = v32(p->up_list), iDn = v32(p->down_list),
-         iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h);
+         iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h),
+         iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -121,6 +122,9 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->d_all_list = (const int32_t*)at(iAll);
   p->d_colidx = (const int32_t*)at(iCidx);
   p->d_colptr = (const int64_t*)at(iColptr);
+  p->cs_factor.d_list = (const int32_t*)at(iCf);
+  p->cs_vinv.d_list = (const int32_t*)at(iCv);
+  p->cs_completion.d_list = (const int32_t*)at(iCc);
   return MFB_OK;
 }
 
@@ -326,17 +330,50 @@ static mfb_status_t run_levels(mfb_factor_s* f, int kid, const std::vector<Level
   return MFB_OK;
 }
 
+// As run_levels, over a class-split schedule: one launch per (level,
+// class) segment; register classes get their own kernels.
+static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, hipStream_t s, Op op,
+                                void (*launch)(mfb_factor_s*, int, const int32_t*, dim3, hipStream_t,
+                                               int64_t, void*),
+                                void* ctx) {
+  for (const ClassSeg& g : cs.segs) {
+    const Level& L = g.lv;
+    dim3 grid(unsigned(L.count), 1u);
+    ProfRec rec{kid, g.level, L.count, 1, 0.0, 0.0, nullptr, nullptr};
+    if (f->prof) {
+      canonical(kid, L, 1, &rec.bytes, &rec.flops);
+      rec.e0 = pool_event(f);
+      rec.e1 = pool_event(f);
+      if (!rec.e0 || !rec.e1) return MFB_EHIP;
+      if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
+    }
+    int64_t slot = slot_doubles(op, L);
+    if (g.cls < kRegClasses) slot = op == OP_FACTOR ? int64_t(L.maxJ) * L.maxN : 1;
+    launch(f, g.cls, cs.d_list + L.begin, grid, s, std::max<int64_t>(1, slot), ctx);
+    if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+    if (f->prof) {
+      if (hipEventRecord(rec.e1, s) != hipSuccess) return MFB_EHIP;
+      f->recs.push_back(rec);
+    }
+  }
+  return MFB_OK;
+}
+
 mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
   if (!f || (!x && f->plan->nnz)) return MFB_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* x; } ctx{x};
-  mfb_status_t st = run_levels(
-      f, MFB_K_FACTOR, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_FACTOR,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
-        k_factor<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U, f->part,
-                                  f->st, f->scratch, slot);
+  mfb_status_t st = run_classes(
+      f, MFB_K_FACTOR, f->plan->cs_factor, s, OP_FACTOR,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        if (cls < kRegClasses)
+          launch_factor_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U, f->part,
+                            f->st, f->scratch, slot);
+        else
+          k_factor<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
+                                           f->part, f->st, f->scratch, slot);
       },
       &ctx);
   if (st) return st;
@@ -436,10 +473,13 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
 
 static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
   if (f->vinv_valid) return MFB_OK;
-  mfb_status_t st = run_levels(
-      f, MFB_K_VINV, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_VINV,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void*) {
-        k_vinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->Vs, f->Vi, f->st, f->scratch, slot);
+  mfb_status_t st = run_classes(
+      f, MFB_K_VINV, f->plan->cs_vinv, s, OP_VINV,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void*) {
+        if (cls < kRegClasses)
+          launch_vinv_reg(cls, g, s, f->plan->dev, list, f->Vs, f->Vi, f->st);
+        else
+          k_vinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->Vs, f->Vi, f->st, f->scratch, slot);
       },
       nullptr);
   if (st) return st;
@@ -488,11 +528,15 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   f->last = s;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* s; } ctx{sin};
-  mfb_status_t st = run_levels(
-      f, MFB_K_COMPLETION, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_COMPLETION,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
-        k_completion<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
-                                      f->Vi, f->part, f->st, f->scratch, slot);
+  mfb_status_t st = run_classes(
+      f, MFB_K_COMPLETION, f->plan->cs_completion, s, OP_COMPLETION,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        if (cls < kRegClasses)
+          launch_completion_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
+                                f->Vi, f->part, f->st);
+        else
+          k_completion<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S,
+                                               f->Vs, f->Vi, f->part, f->st, f->scratch, slot);
       },
       &ctx);
   if (st) return st;

@@ -34,4 +34,15 @@ __global__ void k_logdet(const double*, int, double*);
 __global__ void k_export_ldl(const double*, const int64_t*, const int32_t*, int64_t, double*);
 __global__ void k_reset_status(DevStatus*);
 
+// Register-front kernels for fronts of order <= kRegMax[cls] (host
+// launchers; cls selects the workgroup shape).
+void launch_vinv_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                     const double* Vs, double* Vi, DevStatus* st);
+void launch_factor_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                       const double* x, double* R, double* LB, double* U, double* part, DevStatus* st,
+                       double* wsb, int64_t slot);
+void launch_completion_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* Sin, double* R, double* LB, double* S, double* Vs,
+                           double* Vi, double* part, DevStatus* st);
+
 }  // namespace mfb

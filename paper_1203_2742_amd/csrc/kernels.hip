@@ -17,6 +17,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "reg_front.h"
 #include "wg_dense.h"
 
 namespace mfb {
@@ -54,6 +55,7 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // Entries landing in N_s columns go to the panel F (leading dimension J);
 // the others (rows and columns in A_s) go to the packed block Us.  One
 // child at a time (fixed order), so every target is written once per pass.
+template <int NTH = NT>
 __device__ void assemble_children(const DevPlan& P, const SnView& v, const double* ua, double* F,
                                   double* Us) {
   for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
@@ -61,7 +63,7 @@ __device__ void assemble_children(const DevPlan& P, const SnView& v, const doubl
     const int Ac = P.nrow[c] - P.ncol[c];
     const int32_t* rl = P.rel + P.relbase[c];
     const double* Uc = ua + P.arena[c];
-    for (int y = wave_id(); y < Ac; y += NT / 64) {
+    for (int y = wave_id(); y < Ac; y += NTH / 64) {
       const int ry = rl[y];
       if (ry < v.N) {
         if (!F) continue;
@@ -80,6 +82,7 @@ __device__ void assemble_children(const DevPlan& P, const SnView& v, const doubl
 // V_s = E^T [S_NN S_AN^T; S_AN V_p] E (eq. e-sn-gradient-2): gather the
 // packed A_s x A_s block from the parent's CCS columns of `src` and the
 // parent's packed block in `arena`, into this supernode's packed block.
+template <int NTH = NT>
 __device__ void extract_from_parent(const DevPlan& P, const SnView& v, const double* src,
                                     double* arena) {
   if (v.A == 0) return;
@@ -89,7 +92,7 @@ __device__ void extract_from_parent(const DevPlan& P, const SnView& v, const dou
   const int32_t* rl = P.rel + P.relbase[v.s];
   const double* Vp = arena + P.arena[p];
   double* Vo = arena + P.arena[v.s];
-  for (int y = wave_id(); y < v.A; y += NT / 64) {
+  for (int y = wave_id(); y < v.A; y += NTH / 64) {
     const int ry = rl[y];
     for (int x = y + lane_id(); x < v.A; x += 64) {
       const int rx = rl[x];
@@ -98,9 +101,10 @@ __device__ void extract_from_parent(const DevPlan& P, const SnView& v, const dou
   }
 }
 
+template <int NTH = NT>
 __device__ __forceinline__ void zero_packed(double* U, int A) {
   const int64_t m = (int64_t)A * (A + 1) / 2;
-  for (int64_t e = threadIdx.x; e < m; e += NT) U[e] = 0.0;
+  for (int64_t e = threadIdx.x; e < m; e += NTH) U[e] = 0.0;
 }
 
 __device__ __forceinline__ double* slot_ptr(double* wsb, int64_t slot) {
@@ -559,5 +563,196 @@ __global__ void k_reset_status(DevStatus* st) {
     st->bad = ~0ull;
   }
 }
+
+
+// ---------------------------------------------------------------------------
+// Register-front kernels: the whole J x J front (or the A x A block V_s) of a
+// supernode lives in the registers of one workgroup (reg_front.h), so the
+// dense part is a sequence of rank-1 steps with one LDS broadcast and one
+// barrier each.  Used for fronts up to order 192; the blocked kernels above
+// serve larger ones.  Results equal those of the blocked kernels up to
+// rounding.
+
+// (S_{A_s A_s})^-1 by sweeping every pivot of V_s.
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_vinv_reg(DevPlan P, const int32_t* list, const double* Vs,
+                                                     double* Vi, DevStatus* st) {
+  __shared__ double buf[2 * C::MMAX];
+  const SnView v(P, list[blockIdx.x]);
+  const int A = v.A;
+  if (A == 0) return;
+  const double* V = Vs + P.arena[v.s];
+  double* VI = Vi + P.arena[v.s];
+  RegFront<C> M;
+  M.load(A, [&](int i, int j) { return sym_packed(V, i, j, A); });
+  bool bad = false;
+  for (int k = 0; k < A; ++k) bad |= M.sweep(k, A, buf);
+  M.store(
+      A, [](int i, int j) { return i >= j; }, [&](int i, int j, double x) { VI[pk(i, j, A)] = -x; });
+  if (threadIdx.x == 0 && bad) report(st, MFB_ENOTPD, v.vl[0]);
+}
+
+// Algorithm 7.1 on a register front.  After the extend-add, sweeping the N
+// pivots of F = [D_NN X_AN^T; X_AN F22] leaves [-D^-1, .; L_AN, U_s] with
+// L_AN = X_AN D^-1 and U_s = F22 - X_AN D^-1 X_AN^T (the block L D L^T
+// step); the Cholesky panel [C; B] then comes from N right-looking steps
+// on the assembled columns.  Scratch: the J x N assembled panel.
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_factor_reg(DevPlan P, const int32_t* list, const double* x,
+                                                       double* R, double* LB, double* U, double* part,
+                                                       DevStatus* st, double* wsb, int64_t slot) {
+  __shared__ double buf[2 * C::MMAX];
+  const SnView v(P, list[blockIdx.x]);
+  const int N = v.N, A = v.A, J = v.J;
+  double* F = slot_ptr(wsb, slot);
+  double* Us = U + P.arena[v.s];
+  for (int64_t e = threadIdx.x; e < (int64_t)J * N; e += C::NTH) {
+    const int r = int(e % J), c = int(e / J);
+    F[e] = r >= c ? x[v.at(r, c)] : 0.0;
+  }
+  zero_packed<C::NTH>(Us, A);
+  __syncthreads();
+  assemble_children<C::NTH>(P, v, U, F, Us);
+  __syncthreads();
+  RegFront<C> M;
+  M.load(J, [&](int i, int j) {
+    if (j < N) return i >= j ? F[i + (int64_t)j * J] : F[j + (int64_t)i * J];
+    if (i < N) return F[j + (int64_t)i * J];
+    return sym_packed(Us, i - N, j - N, A);
+  });
+  for (int k = 0; k < N; ++k) M.sweep(k, J, buf);
+  M.store(
+      J, [](int i, int j) { return i >= j; },
+      [&](int i, int j, double y) {
+        if (j >= N)
+          Us[pk(i - N, j - N, A)] = y;
+        else
+          LB[v.at(i, j)] = i >= N ? y : -y;
+      });
+  M.load(J, [&](int i, int j) { return (j < N && i >= j) ? F[i + (int64_t)j * J] : 0.0; });
+  double lg = 0.0;
+  int fail = -1;
+  for (int k = 0; k < N; ++k) {
+    double d;
+    if (M.chol(k, J, N, buf, &d) && fail < 0) fail = k;
+    lg += 2.0 * log(d);
+  }
+  M.store(
+      J, [&](int i, int j) { return j < N && i >= j; }, [&](int i, int j, double y) { R[v.at(i, j)] = y; });
+  if (threadIdx.x == 0) {
+    part[v.s] = lg;
+    if (fail >= 0) report(st, MFB_ENOTPD, v.vl[fail]);
+  }
+}
+
+// Algorithm 7.3 on a register front G = S_{J_s J_s} = [S_NN S_AN^T; S_AN V_s].
+// Sweeping the A pivots leaves [D^-1, -L_AN^T; -L_AN, -V_s^-1] with
+// L_AN = -V_s^-1 S_AN and D^-1 = S_NN + S_AN^T L_AN; sweeping the N pivots
+// next turns the first N columns into -[D; L_AN D], and N Cholesky steps on
+// [D; L_AN D] give C = chol(D) and B = L_AN D C^-T = L_AN C.
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_completion_reg(DevPlan P, const int32_t* list,
+                                                           const double* Sin, double* R, double* LB,
+                                                           double* S, double* Vs, double* Vi,
+                                                           double* part, DevStatus* st) {
+  __shared__ double buf[2 * C::MMAX];
+  const SnView v(P, list[blockIdx.x]);
+  const int N = v.N, A = v.A, J = v.J;
+  for (int64_t e = threadIdx.x; e < (int64_t)J * N; e += C::NTH) {
+    const int r = int(e % J), c = int(e / J);
+    if (r >= c) S[v.at(r, c)] = Sin[v.at(r, c)];
+  }
+  extract_from_parent<C::NTH>(P, v, Sin, Vs);
+  __syncthreads();
+  const double* V = Vs + P.arena[v.s];
+  double* VI = Vi + P.arena[v.s];
+  RegFront<C> M;
+  M.load(J, [&](int i, int j) {
+    if (i < N && j < N) return Sin[v.nn(i, j)];
+    if (j < N) return Sin[v.an(i - N, j)];
+    if (i < N) return Sin[v.an(j - N, i)];
+    return sym_packed(V, i - N, j - N, A);
+  });
+  bool badV = false;
+  for (int k = N; k < J; ++k) badV |= M.sweep(k, J, buf);
+  M.store(
+      J, [](int i, int j) { return i >= j; },
+      [&](int i, int j, double y) {
+        if (j >= N)
+          VI[pk(i - N, j - N, A)] = -y;
+        else
+          LB[v.at(i, j)] = i >= N ? -y : y;
+      });
+  if (threadIdx.x == 0 && badV) report(st, MFB_ENOCOMPLETION, v.vl[0]);
+  int fail = -1;
+  for (int k = 0; k < N; ++k)
+    if (M.sweep(k, J, buf) && fail < 0) fail = k;
+  M.negate_columns(N);
+  double lg = 0.0;
+  for (int k = 0; k < N; ++k) {
+    double d;
+    if (M.chol(k, J, N, buf, &d) && fail < 0) fail = k;
+    lg += 2.0 * log(d);
+  }
+  M.store(
+      J, [&](int i, int j) { return j < N && i >= j; }, [&](int i, int j, double y) { R[v.at(i, j)] = y; });
+  if (threadIdx.x == 0) {
+    part[v.s] = lg;
+    if (fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
+  }
+}
+
+// Workgroup shapes of the register classes (front order <= MMAX).
+using RegC0 = RegCfg<16, 16, 1, 1>;
+using RegC1 = RegCfg<16, 16, 2, 2>;
+using RegC2 = RegCfg<16, 16, 4, 4>;
+using RegC3 = RegCfg<16, 16, 8, 8>;
+using RegC4 = RegCfg<16, 32, 12, 6>;
+static_assert(RegC0::MMAX == kRegMax[0] && RegC1::MMAX == kRegMax[1] && RegC2::MMAX == kRegMax[2] &&
+                  RegC3::MMAX == kRegMax[3] && RegC4::MMAX == kRegMax[4] && kRegClasses == 5,
+              "register classes shared with the host");
+
+template <class C>
+static void go_vinv(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Vs,
+                    double* Vi, DevStatus* st) {
+  k_vinv_reg<C><<<g, C::NTH, 0, s>>>(P, list, Vs, Vi, st);
+}
+template <class C>
+static void go_factor(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* x,
+                      double* R, double* LB, double* U, double* part, DevStatus* st, double* wsb,
+                      int64_t slot) {
+  k_factor_reg<C><<<g, C::NTH, 0, s>>>(P, list, x, R, LB, U, part, st, wsb, slot);
+}
+template <class C>
+static void go_completion(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                          const double* Sin, double* R, double* LB, double* S, double* Vs, double* Vi,
+                          double* part, DevStatus* st) {
+  k_completion_reg<C><<<g, C::NTH, 0, s>>>(P, list, Sin, R, LB, S, Vs, Vi, part, st);
+}
+
+#define MFB_REG_SWITCH(fn, ...)                  \
+  switch (cls) {                                 \
+    case 0: fn<RegC0>(__VA_ARGS__); break;       \
+    case 1: fn<RegC1>(__VA_ARGS__); break;       \
+    case 2: fn<RegC2>(__VA_ARGS__); break;       \
+    case 3: fn<RegC3>(__VA_ARGS__); break;       \
+    default: fn<RegC4>(__VA_ARGS__); break;      \
+  }
+
+void launch_vinv_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                     const double* Vs, double* Vi, DevStatus* st) {
+  MFB_REG_SWITCH(go_vinv, g, s, P, list, Vs, Vi, st)
+}
+void launch_factor_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                       const double* x, double* R, double* LB, double* U, double* part, DevStatus* st,
+                       double* wsb, int64_t slot) {
+  MFB_REG_SWITCH(go_factor, g, s, P, list, x, R, LB, U, part, st, wsb, slot)
+}
+void launch_completion_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* Sin, double* R, double* LB, double* S, double* Vs,
+                           double* Vi, double* part, DevStatus* st) {
+  MFB_REG_SWITCH(go_completion, g, s, P, list, Sin, R, LB, S, Vs, Vi, part, st)
+}
+#undef MFB_REG_SWITCH
 
 }  // namespace mfb

@@ -42,6 +42,24 @@ struct Level {
   double p, u, n3, n2a, na2, a3;
 };
 
+// Register-front classes: a front whose order (J for the factor and the
+// completion, A for the inverse of V_s) is at most kRegMax[c] runs the
+// register kernel of class c; larger fronts run the blocked kernels.
+constexpr int kRegClasses = 5;
+constexpr int kRegMax[kRegClasses] = {16, 32, 64, 128, 192};
+
+// A level of a schedule split by class: one launch per segment, largest
+// class first.  cls == kRegClasses marks the blocked kernels.
+struct ClassSeg {
+  Level lv;  // begin/count index the schedule's own list
+  int32_t level, cls;
+};
+struct ClassSched {
+  std::vector<int32_t> list;
+  std::vector<ClassSeg> segs;
+  const int32_t* d_list = nullptr;
+};
+
 }  // namespace mfb
 
 struct mfb_plan_s {
@@ -55,6 +73,9 @@ struct mfb_plan_s {
   // leaf-to-root schedule: levels by height; root-to-leaf: by depth
   std::vector<int32_t> up_list, down_list;
   std::vector<mfb::Level> up_levels, down_levels;
+  // class-split schedules: factor (leaf-to-root, by J), inverse of V_s
+  // (by A) and completion (root-to-leaf, by J)
+  mfb::ClassSched cs_factor, cs_vinv, cs_completion;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;
   std::vector<int64_t> colptr_h;

@@ -242,6 +242,46 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   make_levels(h, H, p->up_list, p->up_levels);
   make_levels(d, Dm, p->down_list, p->down_levels);
 
+  // Class-split copies of the schedules (see ClassSeg).
+  auto make_classes = [&](const std::vector<int32_t>& list, const std::vector<Level>& levels,
+                          bool by_a, ClassSched& cs) {
+    cs.list.clear();
+    cs.segs.clear();
+    cs.list.reserve(ns);
+    auto cls_of = [&](int32_t k) {
+      const int32_t m = by_a ? p->J[k] - p->N[k] : p->J[k];
+      int c = 0;
+      while (c < kRegClasses && m > kRegMax[c]) ++c;
+      return c;
+    };
+    for (int32_t l = 0; l < int32_t(levels.size()); ++l) {
+      const Level& L = levels[l];
+      for (int c = kRegClasses; c >= 0; --c) {
+        Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
+          const int32_t k = list[t];
+          if (cls_of(k) != c) continue;
+          cs.list.push_back(k);
+          S.count++;
+          S.maxN = std::max(S.maxN, p->N[k]);
+          S.maxA = std::max(S.maxA, p->J[k] - p->N[k]);
+          S.maxJ = std::max(S.maxJ, p->J[k]);
+          const double Nn = p->N[k], Jn = p->J[k], An = Jn - Nn;
+          S.p += Nn * Jn - Nn * (Nn - 1) / 2;
+          S.u += An * (An + 1) / 2;
+          S.n3 += Nn * Nn * Nn;
+          S.n2a += Nn * Nn * An;
+          S.na2 += Nn * An * An;
+          S.a3 += An * An * An;
+        }
+        if (S.count) cs.segs.push_back(ClassSeg{S, l, c});
+      }
+    }
+  };
+  make_classes(p->up_list, p->up_levels, false, p->cs_factor);
+  make_classes(p->up_list, p->up_levels, true, p->cs_vinv);
+  make_classes(p->down_list, p->down_levels, false, p->cs_completion);
+
   // Canonical algorithmic flop counts per supernode (LAPACK conventions).
   for (int32_t k = 0; k < ns; ++k) {
     const double Nn = p->N[k], An = p->J[k] - p->N[k];

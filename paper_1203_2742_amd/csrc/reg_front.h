@@ -1,0 +1,207 @@
+// Register-resident symmetric fronts for gfx950.
+//
+// A workgroup of GX * GY threads holds an m x m symmetric matrix (m <= MMAX)
+// entirely in registers: thread (tx, ty) = (t % GX, t / GX) owns the RX x RY
+// entries (tx + GX a, ty + GY b).  Both triangles are kept, so every
+// elimination step is one rank-1 update of the whole register block after a
+// single LDS broadcast of the pivot column, with one workgroup barrier per
+// step.  No step touches global memory: the front is read once and its
+// results written once.
+//
+// Two eliminations are provided:
+//  * sweep (the symmetric Gauss-Jordan "sweep operator"): sweeping pivot k
+//    of M maps M_kk -> -1/M_kk, M_ik -> M_ik / M_kk, M_kj -> M_kj / M_kk and
+//    M_ij -> M_ij - M_ik M_kj / M_kk.  Sweeping a set K of pivots of
+//    [M_KK M_KR; M_RK M_RR] leaves [-M_KK^-1, M_KK^-1 M_KR; M_RK M_KK^-1,
+//    M_RR - M_RK M_KK^-1 M_KR], so sweeping every pivot gives -M^-1.  The
+//    pivots are the successive Schur-complement diagonals, all positive
+//    exactly when the swept block is positive definite.
+//  * right-looking Cholesky on the leading columns: step k divides column k
+//    by sqrt(M_kk) and subtracts the outer product of that column from the
+//    trailing columns j < ncols (all rows).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mfb {
+
+template <int GX_, int GY_, int RX_, int RY_>
+struct RegCfg {
+  static constexpr int GX = GX_, GY = GY_, RX = RX_, RY = RY_;
+  static constexpr int NTH = GX * GY;
+  static constexpr int MMAX = GX * RX;
+  static_assert(GX * RX == GY * RY, "square register front");
+  static_assert(NTH % 64 == 0, "whole wavefronts");
+};
+
+template <class C>
+struct RegFront {
+  double v[C::RX][C::RY];
+  int tx, ty;
+  int phase;  // which half of the broadcast buffer the next step uses
+
+  __device__ __forceinline__ RegFront() : tx(threadIdx.x % C::GX), ty(threadIdx.x / C::GX), phase(0) {}
+  __device__ __forceinline__ int row(int a) const { return tx + C::GX * a; }
+  __device__ __forceinline__ int col(int b) const { return ty + C::GY * b; }
+
+  // v(i, j) = f(i, j) for i, j < m, else 0.
+  template <class F>
+  __device__ __forceinline__ void load(int m, const F& f) {
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) {
+        const int i = row(a), j = col(b);
+        v[a][b] = (i < m && j < m) ? f(i, j) : 0.0;
+      }
+  }
+  // out(i, j, v(i, j)) for every owned entry with pred(i, j) true.
+  template <class PR, class OUT>
+  __device__ __forceinline__ void store(int m, const PR& pred, const OUT& out) const {
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) {
+        const int i = row(a), j = col(b);
+        if (C::GX * a < m && C::GY * b < m && i < m && j < m && pred(i, j)) out(i, j, v[a][b]);
+      }
+  }
+
+  // Writes column k to buf (all MMAX rows; rows >= m hold zeros or values
+  // that never reach an entry inside the front).  Called by every thread:
+  // the register index is selected by uniform branches, the owning lanes
+  // by a divergent one inside.
+  __device__ __forceinline__ void put_column(int k, double* buf) const {
+    const int kb = k / C::GY;
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b)
+      if (b == kb) {
+        if (ty == k % C::GY) {
+#pragma unroll
+          for (int a = 0; a < C::RX; ++a) buf[row(a)] = v[a][b];
+        }
+      }
+  }
+
+  // Half of the broadcast buffer for the next step: consecutive steps (of
+  // either kind) alternate, so one barrier per step suffices.
+  __device__ __forceinline__ double* next_half(double* buf) {
+    double* h = buf + phase * C::MMAX;
+    phase ^= 1;
+    return h;
+  }
+
+  // One sweep of pivot k (0 <= k < m); `buf` is LDS of 2 * MMAX doubles.
+  // Returns true if the pivot is not positive (it is then replaced by one
+  // so the arithmetic stays finite).  The rank-1 update runs over the whole
+  // register block (entries outside the front see zero multipliers), and
+  // the pivot row and column are rewritten afterwards by their owners.
+  __device__ __forceinline__ bool sweep(int k, int m, double* buf) {
+    double* bk = next_half(buf);
+    put_column(k, bk);
+    __syncthreads();
+    double p = bk[k];
+    const bool bad = !(p > 0.0);
+    if (bad) p = 1.0;
+    const double r = 1.0 / p;
+    double ci[C::RX], cj[C::RY];
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a) ci[a] = row(a) < m ? bk[row(a)] : 0.0;
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) cj[b] = col(b) < m ? bk[col(b)] * r : 0.0;
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) v[a][b] = fma(-ci[a], cj[b], v[a][b]);
+    // row k: M_kj / M_kk; column k: M_ik / M_kk; pivot: -1 / M_kk
+    const int ka = k / C::GX, kb = k / C::GY;
+    const bool own_r = tx == k % C::GX, own_c = ty == k % C::GY;
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+      if (a == ka) {
+        if (own_r) {
+#pragma unroll
+          for (int b = 0; b < C::RY; ++b) v[a][b] = cj[b];
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b)
+      if (b == kb) {
+        if (own_c) {
+#pragma unroll
+          for (int a = 0; a < C::RX; ++a) v[a][b] = ci[a] * r;
+        }
+#pragma unroll
+        for (int a = 0; a < C::RX; ++a)
+          if (a == ka) {
+            if (own_r && own_c) v[a][b] = -r;
+          }
+      }
+    return bad;
+  }
+
+  // One right-looking Cholesky step on column k (< ncols <= m): on return
+  // column k holds sqrt(M_kk) at row k and M_ik / sqrt(M_kk) below, and the
+  // columns k < j < ncols are updated.  Same buffer protocol and failure
+  // convention as sweep().  Entries above the diagonal are left stale.
+  __device__ __forceinline__ bool chol(int k, int m, int ncols, double* buf, double* diag) {
+    double* bk = next_half(buf);
+    put_column(k, bk);
+    __syncthreads();
+    const double p = bk[k];
+    const bool bad = !(p > 0.0);
+    const double d = bad ? 1.0 : sqrt(p);
+    const double r = 1.0 / d;
+    *diag = d;
+    double li[C::RX], lj[C::RY];
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a) li[a] = (row(a) > k && row(a) < m) ? bk[row(a)] * r : 0.0;
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) lj[b] = (col(b) > k && col(b) < ncols) ? bk[col(b)] * r : 0.0;
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b)
+        if (C::GY * b < ncols) v[a][b] = fma(-li[a], lj[b], v[a][b]);
+    const int kb = k / C::GY;
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b)
+      if (b == kb) {
+        if (ty == k % C::GY) {
+#pragma unroll
+          for (int a = 0; a < C::RX; ++a) {
+            const int i = row(a);
+            v[a][b] = i > k ? li[a] : (i == k ? d : v[a][b]);
+          }
+        }
+      }
+    return bad;
+  }
+
+  // Negates the entries in columns j < ncols.
+  __device__ __forceinline__ void negate_columns(int ncols) {
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b)
+        if (col(b) < ncols) v[a][b] = -v[a][b];
+  }
+};
+
+// Deterministic sum over the NTH threads of a workgroup (sm: NTH doubles).
+template <int NTH>
+__device__ __forceinline__ double block_sum(double x, double* sm) {
+  sm[threadIdx.x] = x;
+  __syncthreads();
+#pragma unroll
+  for (int s = NTH / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace mfb

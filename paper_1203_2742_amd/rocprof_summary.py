@@ -25,8 +25,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 
-def short(name: str) -> str:
+def symbol(name: str) -> str:
     return name.split("(")[0].replace("mfb::", "").replace("void ", "")
+
+
+def short(name: str) -> str:
+    """Operation a kernel symbol serves: the register-front variants
+    (k_<op>_reg<shape>) and the blocked kernel k_<op> count as one."""
+    return symbol(name).split("<")[0].replace("_reg", "")
 
 
 def read_counter(d, calib_pat):
@@ -62,14 +68,27 @@ def main():
 
     stats = glob.glob(os.path.join(args.trace, "*kernel_stats.csv"))[0]
     rows = [r for r in csv.DictReader(open(stats)) if "mfb::" in r["Name"]]
+    agg = {}
+    for r in rows:
+        a = agg.setdefault(short(r["Name"]), {"calls": 0, "total": 0.0, "min": float("inf"), "max": 0.0, "pct": 0.0})
+        a["calls"] += int(r["Calls"])
+        a["total"] += float(r["TotalDurationNs"])
+        a["min"] = min(a["min"], float(r["MinNs"]))
+        a["max"] = max(a["max"], float(r["MaxNs"]))
+        a["pct"] += float(r["Percentage"])
     lines = [f"# Kernel profile: {args.workload}", "", "Commands:", "", "```", args.command.strip(), "```",
-             "", "## rocprofv3 --kernel-trace --stats", "",
+             "", "## rocprofv3 --kernel-trace --stats, per operation", "",
+             "Register-front variants and the blocked kernel of one operation are summed.", "",
              "| kernel | calls | total ms | avg us | min us | max us | % of time |",
              "|---|---|---|---|---|---|---|"]
-    for r in rows:
-        lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
-                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
-                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["total"]):
+        lines.append(f"| {k} | {a['calls']} | {a['total'] / 1e6:.3f} | {a['total'] / a['calls'] / 1e3:.2f} | "
+                     f"{a['min'] / 1e3:.2f} | {a['max'] / 1e3:.2f} | {a['pct']:.2f} |")
+    lines += ["", "## per kernel symbol", "",
+              "| symbol | calls | total ms | avg us |", "|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| {symbol(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} |")
     traffic = {}
     if args.fetch and args.write:
         fa, fc = read_counter(args.fetch, args.calib_kernel)

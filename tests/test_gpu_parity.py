@@ -60,6 +60,9 @@ CASES = {
     "chordal150": lambda: P.random_chordal(150, 0.03, 2),
     "tree300": lambda: P.random_tree_pattern(300, 4),
     "arrow_small": lambda: P.block_arrow([5, 70, 1, 33, 97], 40),
+    # fronts of order 63, 65, 80, 160 and 210: every register class and the
+    # blocked kernels in one tree
+    "arrow_mixed": lambda: P.block_arrow([5, 150, 20, 100, 3], 60),
     "grid2d_24": lambda: get_config("grid2d_24"),
     "grid3d_8": lambda: get_config("grid3d_8"),
     "grid2d_128": lambda: get_config("grid2d_128"),
