@@ -332,23 +332,23 @@ static mfb_status_t run_levels(mfb_factor_s* f, int kid, const std::vector<Level
 
 // As run_levels, over a class-split schedule: one launch per (level,
 // class) segment; register classes get their own kernels.
-static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, hipStream_t s, Op op,
+static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, hipStream_t s, int k,
+                                Op op,
                                 void (*launch)(mfb_factor_s*, int, const int32_t*, dim3, hipStream_t,
                                                int64_t, void*),
                                 void* ctx) {
   for (const ClassSeg& g : cs.segs) {
     const Level& L = g.lv;
-    dim3 grid(unsigned(L.count), 1u);
-    ProfRec rec{kid, g.level, L.count, 1, 0.0, 0.0, nullptr, nullptr};
+    dim3 grid(unsigned(L.count), unsigned(k));
+    ProfRec rec{kid, g.level, L.count, k, 0.0, 0.0, nullptr, nullptr};
     if (f->prof) {
-      canonical(kid, L, 1, &rec.bytes, &rec.flops);
+      canonical(kid, L, k, &rec.bytes, &rec.flops);
       rec.e0 = pool_event(f);
       rec.e1 = pool_event(f);
       if (!rec.e0 || !rec.e1) return MFB_EHIP;
       if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
     }
-    int64_t slot = slot_doubles(op, L);
-    if (g.cls < kRegClasses) slot = op == OP_FACTOR ? int64_t(L.maxJ) * L.maxN : 1;
+    const int64_t slot = g.cls < kRegClasses ? 1 : slot_doubles(op, L);
     launch(f, g.cls, cs.d_list + L.begin, grid, s, std::max<int64_t>(1, slot), ctx);
     if (hipGetLastError() != hipSuccess) return MFB_EHIP;
     if (f->prof) {
@@ -366,11 +366,11 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* x; } ctx{x};
   mfb_status_t st = run_classes(
-      f, MFB_K_FACTOR, f->plan->cs_factor, s, OP_FACTOR,
+      f, MFB_K_FACTOR, f->plan->cs_factor, s, 1, OP_FACTOR,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         if (cls < kRegClasses)
           launch_factor_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U, f->part,
-                            f->st, f->scratch, slot);
+                            f->st);
         else
           k_factor<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
                                            f->part, f->st, f->scratch, slot);
@@ -450,12 +450,15 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
   f->last = s;
   if ((st = ensure_projinv(f, s))) return st;
   struct Ctx { const double* y; double* t; RhsArena a; } ctx{y, t, a};
-  st = run_levels(
-      f, MFB_K_HESS_UP, f->plan->up_levels, f->plan->d_up_list, s, k, OP_HUP,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+  st = run_classes(
+      f, MFB_K_HESS_UP, f->plan->cs_factor, s, k, OP_HUP,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
-        k_hess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua, x->a.upd,
-                                   x->a.scr, slot);
+        if (cls < kRegClasses)
+          launch_hess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua, x->a.upd);
+        else
+          k_hess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua,
+                                            x->a.upd, x->a.scr, slot);
       },
       &ctx);
   if (st) return st;
@@ -474,7 +477,7 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
 static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
   if (f->vinv_valid) return MFB_OK;
   mfb_status_t st = run_classes(
-      f, MFB_K_VINV, f->plan->cs_vinv, s, OP_VINV,
+      f, MFB_K_VINV, f->plan->cs_vinv, s, 1, OP_VINV,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void*) {
         if (cls < kRegClasses)
           launch_vinv_reg(cls, g, s, f->plan->dev, list, f->Vs, f->Vi, f->st);
@@ -510,12 +513,15 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
       },
       &ctx);
   if (st) return st;
-  st = run_levels(
-      f, MFB_K_IHESS_UP, f->plan->up_levels, f->plan->d_up_list, s, k, OP_IHUP,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+  st = run_classes(
+      f, MFB_K_IHESS_UP, f->plan->cs_factor, s, k, OP_IHUP,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
-        k_ihess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua, x->a.upd,
-                                    x->a.scr, slot);
+        if (cls < kRegClasses)
+          launch_ihess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua, x->a.upd);
+        else
+          k_ihess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
+                                             x->a.upd, x->a.scr, slot);
       },
       &ctx);
   if (st) return st;
@@ -529,7 +535,7 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* s; } ctx{sin};
   mfb_status_t st = run_classes(
-      f, MFB_K_COMPLETION, f->plan->cs_completion, s, OP_COMPLETION,
+      f, MFB_K_COMPLETION, f->plan->cs_completion, s, 1, OP_COMPLETION,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         if (cls < kRegClasses)
           launch_completion_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
@@ -552,10 +558,14 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
   struct Ctx { double* x; } ctx{x};
-  mfb_status_t st = run_levels(
-      f, MFB_K_PRODUCT, f->plan->up_levels, f->plan->d_up_list, s, 1, OP_PRODUCT,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
-        k_product<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U, f->scratch, slot);
+  mfb_status_t st = run_classes(
+      f, MFB_K_PRODUCT, f->plan->cs_factor, s, 1, OP_PRODUCT,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        if (cls < kRegClasses)
+          launch_product_reg(cls, g, s, f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U);
+        else
+          k_product<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U, f->scratch,
+                                            slot);
       },
       &ctx);
   if (st) return st;

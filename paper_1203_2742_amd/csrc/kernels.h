@@ -39,10 +39,15 @@ __global__ void k_reset_status(DevStatus*);
 void launch_vinv_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                      const double* Vs, double* Vi, DevStatus* st);
 void launch_factor_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
-                       const double* x, double* R, double* LB, double* U, double* part, DevStatus* st,
-                       double* wsb, int64_t slot);
+                       const double* x, double* R, double* LB, double* U, double* part, DevStatus* st);
 void launch_completion_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                            const double* Sin, double* R, double* LB, double* S, double* Vs,
                            double* Vi, double* part, DevStatus* st);
+void launch_hess_up_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                        const double* LB, const double* Y, double* Kt, double* Ua, int64_t upd);
+void launch_ihess_up_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                         const double* LB, const double* Kt, double* Y, double* Ua, int64_t upd);
+void launch_product_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                        const double* R, double* X, double* U);
 
 }  // namespace mfb

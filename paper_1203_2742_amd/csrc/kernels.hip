@@ -568,10 +568,186 @@ __global__ void k_reset_status(DevStatus* st) {
 // ---------------------------------------------------------------------------
 // Register-front kernels: the whole J x J front (or the A x A block V_s) of a
 // supernode lives in the registers of one workgroup (reg_front.h), so the
-// dense part is a sequence of rank-1 steps with one LDS broadcast and one
-// barrier each.  Used for fronts up to order 192; the blocked kernels above
-// serve larger ones.  Results equal those of the blocked kernels up to
-// rounding.
+// dense part is a sequence of rank-1 or rank-2 steps with one LDS broadcast
+// and one barrier each.  Fronts are read from and written to HBM once, with
+// branch-free gathers (every address is computed, invalid lanes read a
+// valid dummy address and discard the value).  Used for fronts up to order
+// 192; the blocked kernels above serve larger ones.
+
+// Columns of L_AN staged per LDS pass by the congruence kernels.
+constexpr int KCL = 8;
+
+// CCS offsets of the panel entries a thread owns: entry (i, j) with
+// min(i, j) < N lives at col[min] + |i - j|.  Columns are clamped to N - 1
+// for rows/columns outside the panel (their offsets are never used).
+template <class C>
+struct PanelIdx {
+  int64_t cr[C::RX], cc[C::RY];
+  __device__ __forceinline__ PanelIdx(const RegFront<C>& M, const SnView& v) {
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a) cr[a] = v.col[min(M.row(a), v.N - 1)];
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) cc[b] = v.col[min(M.col(b), v.N - 1)];
+  }
+  __device__ __forceinline__ int64_t off(int a, int b, int i, int j) const {
+    return i >= j ? cc[b] + (i - j) : cr[a] + (j - i);
+  }
+};
+
+// Loads the panel part (min(i, j) < N) of the front from the CCS array src;
+// the A x A block is zero.
+template <class C>
+__device__ __forceinline__ void load_panel(RegFront<C>& M, const SnView& v, const double* src) {
+  const PanelIdx<C> ix(M, v);
+#pragma unroll
+  for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) {
+      const int i = M.row(a), j = M.col(b);
+      const bool ok = i < v.J && j < v.J && min(i, j) < v.N;
+      const double x = src[ok ? ix.off(a, b, i, j) : 0];
+      M.v[a][b] = ok ? x : 0.0;
+    }
+}
+
+// Stores the lower panel entries (j < N, i >= j) through out(offset, value)
+// and the lower A x A entries through outa(packed index, value).
+template <class C, class OP, class OA>
+__device__ __forceinline__ void store_front(const RegFront<C>& M, const SnView& v, const OP& out,
+                                            const OA& outa) {
+  const PanelIdx<C> ix(M, v);
+  const int N = v.N, A = v.A;
+  M.store_ab(
+      v.J, [](int i, int j) { return i >= j; },
+      [&](int a, int b, int i, int j, double x) {
+        if (j < N)
+          out(ix.cc[b] + (i - j), x);
+        else
+          outa(pk(i - N, j - N, A), x);
+      });
+}
+
+// Stores the lower panel entries with j < ncols through out(offset, value).
+template <class C, class OP>
+__device__ __forceinline__ void store_panel(const RegFront<C>& M, const SnView& v, int ncols, const OP& out) {
+  const PanelIdx<C> ix(M, v);
+  M.store_ab(
+      v.J, [&](int i, int j) { return j < ncols && i >= j; },
+      [&](int a, int b, int i, int j, double x) { out(ix.cc[b] + (i - j), x); });
+}
+
+// A x A block <- V_s = E^T [S_NN S_AN^T; S_AN V_p] E gathered from the
+// parent's CCS columns of `src` and its packed block in `arena`
+// (eq. e-sn-gradient-2).  No-op for A = 0.
+template <class C>
+__device__ __forceinline__ void gather_parent(RegFront<C>& M, const DevPlan& P, const SnView& v,
+                                              const double* src, const double* arena) {
+  if (v.A == 0) return;
+  const int N = v.N, J = v.J;
+  const int p = P.parent[v.s];
+  const int Np = P.ncol[p], Ap = P.nrow[p] - Np;
+  const int64_t* colp = P.col + P.colbase[p];
+  const int32_t* rl = P.rel + P.relbase[v.s];
+  const double* Vp = arena + P.arena[p];
+  int rr[C::RX], rc[C::RY];
+  int64_t cpr[C::RX], cpc[C::RY];
+#pragma unroll
+  for (int a = 0; a < C::RX; ++a) {
+    const int i = M.row(a);
+    rr[a] = (i >= N && i < J) ? rl[i - N] : 0;
+    cpr[a] = colp[min(rr[a], Np - 1)];
+  }
+#pragma unroll
+  for (int b = 0; b < C::RY; ++b) {
+    const int j = M.col(b);
+    rc[b] = (j >= N && j < J) ? rl[j - N] : 0;
+    cpc[b] = colp[min(rc[b], Np - 1)];
+  }
+#pragma unroll
+  for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) {
+      const int i = M.row(a), j = M.col(b);
+      const bool in = i >= N && j >= N && i < J && j < J;
+      const int hi = max(rr[a], rc[b]), lo = min(rr[a], rc[b]);
+      const bool pan = lo < Np;
+      const int64_t op = rr[a] >= rc[b] ? cpc[b] + (rr[a] - rc[b]) : cpr[a] + (rc[b] - rr[a]);
+      const double* q = !in ? src : (pan ? src + op : Vp + pk(hi - Np, lo - Np, Ap));
+      const double x = *q;
+      if (in) M.v[a][b] = x;
+    }
+}
+
+// Front += sg * sum over children c of E_c U_c E_c^T, with the children's
+// packed blocks taken from `ua`; one child at a time through an inverse
+// relative-index map in LDS (`inv`, MMAX ints).
+template <class C>
+__device__ __forceinline__ void gather_children(RegFront<C>& M, const DevPlan& P, const SnView& v,
+                                                const double* ua, int* inv, double sg) {
+  for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
+    const int c = P.cidx[t];
+    const int Ac = P.nrow[c] - P.ncol[c];
+    const int32_t* rl = P.rel + P.relbase[c];
+    const double* Uc = ua + P.arena[c];
+    for (int i = threadIdx.x; i < C::MMAX; i += C::NTH) inv[i] = -1;
+    __syncthreads();
+    for (int x = threadIdx.x; x < Ac; x += C::NTH) inv[rl[x]] = x;
+    __syncthreads();
+    int xi[C::RX], yj[C::RY];
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a) xi[a] = inv[M.row(a)];
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) yj[b] = inv[M.col(b)];
+    __syncthreads();
+    // rows in groups of GR, so the loads in flight stay within the
+    // registers the front leaves free
+    constexpr int GR = C::RX * C::RY > 32 ? (32 + C::RY - 1) / C::RY : C::RX;
+#pragma unroll
+    for (int a0 = 0; a0 < C::RX; a0 += GR) {
+      double t[GR][C::RY];
+#pragma unroll
+      for (int g = 0; g < GR; ++g)
+#pragma unroll
+        for (int b = 0; b < C::RY; ++b) {
+          const int a = a0 + g < C::RX ? a0 + g : C::RX - 1;
+          const bool ok = a0 + g < C::RX && xi[a] >= 0 && yj[b] >= 0;
+          t[g][b] = Uc[ok ? pk(max(xi[a], yj[b]), min(xi[a], yj[b]), Ac) : 0];
+          t[g][b] = ok ? sg * t[g][b] : 0.0;
+        }
+#pragma unroll
+      for (int g = 0; g < GR; ++g)
+#pragma unroll
+        for (int b = 0; b < C::RY; ++b)
+          if (a0 + g < C::RX) M.v[a0 + g][b] += t[g][b];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Columns k0 .. k0 + kc - 1 of [0; L_AN] (rows 0 .. MMAX-1, zero outside
+// A_s) of supernode s into LDS: Ls[i + t MMAX] = l_{k0+t}(i).
+template <class C, int KC>
+__device__ __forceinline__ void stage_lan(const SnView& v, const double* LB, int k0, double* Ls) {
+  for (int e = threadIdx.x; e < C::MMAX * KC; e += C::NTH) {
+    const int i = e % C::MMAX, t = e / C::MMAX, kk = k0 + t;
+    const bool ok = kk < v.N && i >= v.N && i < v.J;
+    const double x = LB[ok ? v.at(i, kk) : 0];
+    Ls[e] = ok ? x : 0.0;
+  }
+}
+
+// N congruence steps with the columns of [0; L_AN], staged KC at a time.
+template <class C, int KC>
+__device__ __forceinline__ void congruences(RegFront<C>& M, const SnView& v, const double* LB, double sg,
+                                            double* buf, double* Ls) {
+  for (int k0 = 0; k0 < v.N; k0 += KC) {
+    stage_lan<C, KC>(v, LB, k0, Ls);
+    __syncthreads();
+    const int kc = min(KC, v.N - k0);
+    for (int t = 0; t < kc; ++t) M.congruence(k0 + t, sg, buf, Ls + t * C::MMAX);
+    __syncthreads();
+  }
+}
 
 // (S_{A_s A_s})^-1 by sweeping every pivot of V_s.
 template <class C>
@@ -584,9 +760,17 @@ __global__ void __launch_bounds__(C::NTH) k_vinv_reg(DevPlan P, const int32_t* l
   const double* V = Vs + P.arena[v.s];
   double* VI = Vi + P.arena[v.s];
   RegFront<C> M;
-  M.load(A, [&](int i, int j) { return sym_packed(V, i, j, A); });
+#pragma unroll
+  for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) {
+      const int i = M.row(a), j = M.col(b);
+      const bool ok = i < A && j < A;
+      const double x = V[ok ? pk(max(i, j), min(i, j), A) : 0];
+      M.v[a][b] = ok ? x : 0.0;
+    }
   bool bad = false;
-  for (int k = 0; k < A; ++k) bad |= M.sweep(k, A, buf);
+  for (int k = 0; k < A; ++k) bad |= M.sweep(k, buf);
   M.store(
       A, [](int i, int j) { return i >= j; }, [&](int i, int j, double x) { VI[pk(i, j, A)] = -x; });
   if (threadIdx.x == 0 && bad) report(st, MFB_ENOTPD, v.vl[0]);
@@ -596,49 +780,43 @@ __global__ void __launch_bounds__(C::NTH) k_vinv_reg(DevPlan P, const int32_t* l
 // pivots of F = [D_NN X_AN^T; X_AN F22] leaves [-D^-1, .; L_AN, U_s] with
 // L_AN = X_AN D^-1 and U_s = F22 - X_AN D^-1 X_AN^T (the block L D L^T
 // step); the Cholesky panel [C; B] then comes from N right-looking steps
-// on the assembled columns.  Scratch: the J x N assembled panel.
+// on the assembled columns, which are parked in R in between.
 template <class C>
 __global__ void __launch_bounds__(C::NTH) k_factor_reg(DevPlan P, const int32_t* list, const double* x,
                                                        double* R, double* LB, double* U, double* part,
-                                                       DevStatus* st, double* wsb, int64_t slot) {
-  __shared__ double buf[2 * C::MMAX];
+                                                       DevStatus* st) {
+  __shared__ double buf[4 * C::MMAX];
+  __shared__ int inv[C::MMAX];
   const SnView v(P, list[blockIdx.x]);
   const int N = v.N, A = v.A, J = v.J;
-  double* F = slot_ptr(wsb, slot);
   double* Us = U + P.arena[v.s];
-  for (int64_t e = threadIdx.x; e < (int64_t)J * N; e += C::NTH) {
-    const int r = int(e % J), c = int(e / J);
-    F[e] = r >= c ? x[v.at(r, c)] : 0.0;
-  }
-  zero_packed<C::NTH>(Us, A);
-  __syncthreads();
-  assemble_children<C::NTH>(P, v, U, F, Us);
-  __syncthreads();
   RegFront<C> M;
-  M.load(J, [&](int i, int j) {
-    if (j < N) return i >= j ? F[i + (int64_t)j * J] : F[j + (int64_t)i * J];
-    if (i < N) return F[j + (int64_t)i * J];
-    return sym_packed(Us, i - N, j - N, A);
-  });
-  for (int k = 0; k < N; ++k) M.sweep(k, J, buf);
-  M.store(
-      J, [](int i, int j) { return i >= j; },
-      [&](int i, int j, double y) {
-        if (j >= N)
-          Us[pk(i - N, j - N, A)] = y;
-        else
-          LB[v.at(i, j)] = i >= N ? y : -y;
-      });
-  M.load(J, [&](int i, int j) { return (j < N && i >= j) ? F[i + (int64_t)j * J] : 0.0; });
+  load_panel(M, v, x);
+  gather_children(M, P, v, U, inv, 1.0);
+  store_front(M, v, [&](int64_t o, double y) { R[o] = y; }, [](int64_t, double) {});
+  for (int k = 0; k < N; ++k) M.sweep(k, buf);
+  {
+    const PanelIdx<C> ix(M, v);
+    // panel: -D^-1 (N x N, sign flipped on the way out) and L_AN
+    M.store_ab(
+        J, [](int i, int j) { return i >= j; },
+        [&](int a, int b, int i, int j, double y) {
+          if (j < N)
+            LB[ix.cc[b] + (i - j)] = i >= N ? y : -y;
+          else
+            Us[pk(i - N, j - N, A)] = y;
+        });
+  }
+  __syncthreads();
+  load_panel(M, v, R);
   double lg = 0.0;
   int fail = -1;
   for (int k = 0; k < N; ++k) {
     double d;
-    if (M.chol(k, J, N, buf, &d) && fail < 0) fail = k;
+    if (M.chol(k, N, buf, &d) && fail < 0) fail = k;
     lg += 2.0 * log(d);
   }
-  M.store(
-      J, [&](int i, int j) { return j < N && i >= j; }, [&](int i, int j, double y) { R[v.at(i, j)] = y; });
+  store_panel(M, v, N, [&](int64_t o, double y) { R[o] = y; });
   if (threadIdx.x == 0) {
     part[v.s] = lg;
     if (fail >= 0) report(st, MFB_ENOTPD, v.vl[fail]);
@@ -655,51 +833,135 @@ __global__ void __launch_bounds__(C::NTH) k_completion_reg(DevPlan P, const int3
                                                            const double* Sin, double* R, double* LB,
                                                            double* S, double* Vs, double* Vi,
                                                            double* part, DevStatus* st) {
-  __shared__ double buf[2 * C::MMAX];
+  __shared__ double buf[4 * C::MMAX];
   const SnView v(P, list[blockIdx.x]);
   const int N = v.N, A = v.A, J = v.J;
-  for (int64_t e = threadIdx.x; e < (int64_t)J * N; e += C::NTH) {
-    const int r = int(e % J), c = int(e / J);
-    if (r >= c) S[v.at(r, c)] = Sin[v.at(r, c)];
-  }
-  extract_from_parent<C::NTH>(P, v, Sin, Vs);
-  __syncthreads();
-  const double* V = Vs + P.arena[v.s];
+  double* VS = Vs + P.arena[v.s];
   double* VI = Vi + P.arena[v.s];
   RegFront<C> M;
-  M.load(J, [&](int i, int j) {
-    if (i < N && j < N) return Sin[v.nn(i, j)];
-    if (j < N) return Sin[v.an(i - N, j)];
-    if (i < N) return Sin[v.an(j - N, i)];
-    return sym_packed(V, i - N, j - N, A);
-  });
+  load_panel(M, v, Sin);
+  gather_parent(M, P, v, Sin, Vs);
+  // cache S (own columns) and V_s
+  store_front(M, v, [&](int64_t o, double y) { S[o] = y; }, [&](int64_t e, double y) { VS[e] = y; });
   bool badV = false;
-  for (int k = N; k < J; ++k) badV |= M.sweep(k, J, buf);
-  M.store(
-      J, [](int i, int j) { return i >= j; },
-      [&](int i, int j, double y) {
-        if (j >= N)
-          VI[pk(i - N, j - N, A)] = -y;
-        else
-          LB[v.at(i, j)] = i >= N ? -y : y;
-      });
+  for (int k = N; k < J; ++k) badV |= M.sweep(k, buf);
+  {
+    // L_AN = -(swept AN block), D^-1 = swept N x N block, V_s^-1 = -(swept A x A block)
+    const PanelIdx<C> ix(M, v);
+    M.store_ab(
+        J, [](int i, int j) { return i >= j; },
+        [&](int a, int b, int i, int j, double y) {
+          if (j < N)
+            LB[ix.cc[b] + (i - j)] = i >= N ? -y : y;
+          else
+            VI[pk(i - N, j - N, A)] = -y;
+        });
+  }
   if (threadIdx.x == 0 && badV) report(st, MFB_ENOCOMPLETION, v.vl[0]);
   int fail = -1;
   for (int k = 0; k < N; ++k)
-    if (M.sweep(k, J, buf) && fail < 0) fail = k;
+    if (M.sweep(k, buf) && fail < 0) fail = k;
   M.negate_columns(N);
   double lg = 0.0;
   for (int k = 0; k < N; ++k) {
     double d;
-    if (M.chol(k, J, N, buf, &d) && fail < 0) fail = k;
+    if (M.chol(k, N, buf, &d) && fail < 0) fail = k;
     lg += 2.0 * log(d);
   }
-  M.store(
-      J, [&](int i, int j) { return j < N && i >= j; }, [&](int i, int j, double y) { R[v.at(i, j)] = y; });
+  store_panel(M, v, N, [&](int64_t o, double y) { R[o] = y; });
   if (threadIdx.x == 0) {
     part[v.s] = lg;
     if (fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
   }
+}
+
+// Hessian step 1 (leaf-to-root) on a register front: with E = [I 0; L I],
+// E^-1 F' E^-T = [K_NN K_AN^T; K_AN U'_s] for F' = [Y_NN Y_AN^T; Y_AN 0] +
+// sum E_c U'_c E_c^T (the block formulas K_AN = F'21 - L F'11 and
+// U'_s = F'22 - L F'12 - K_AN L^T), applied as N congruence steps.
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_hess_up_reg(DevPlan P, const int32_t* list, const double* LB,
+                                                        const double* Y, double* Kt, double* Ua,
+                                                        int64_t upd) {
+  __shared__ double buf[2 * C::MMAX];
+  __shared__ int inv[C::MMAX];
+  __shared__ double Ls[C::MMAX * KCL];
+  const SnView v(P, list[blockIdx.x]);
+  const int64_t r = blockIdx.y;
+  const double* y = Y + r * P.nnz;
+  double* K = Kt + r * P.nnz;
+  double* ua = Ua + r * upd;
+  double* Us = ua + P.arena[v.s];
+  RegFront<C> M;
+  load_panel(M, v, y);
+  gather_children(M, P, v, ua, inv, 1.0);
+  congruences<C, KCL>(M, v, LB, -1.0, buf, Ls);
+  store_front(M, v, [&](int64_t o, double x) { K[o] = x; }, [&](int64_t e, double x) { Us[e] = x; });
+}
+
+// Inverse Hessian step 3 (leaf-to-root) on a register front:
+// E [K_NN K_AN^T; K_AN 0] E^T - G' = [Y_NN Y_AN^T; Y_AN -U'_s] with
+// G' = sum E_c U'_c E_c^T (Y_AN = L K_NN + K_AN - G'21, U'_s = G'22 -
+// L K_NN L^T - L K_AN^T - K_AN L^T), applied as N congruence steps.
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_ihess_up_reg(DevPlan P, const int32_t* list, const double* LB,
+                                                         const double* Kt, double* Y, double* Ua,
+                                                         int64_t upd) {
+  __shared__ double buf[2 * C::MMAX];
+  __shared__ int inv[C::MMAX];
+  __shared__ double Ls[C::MMAX * KCL];
+  const SnView v(P, list[blockIdx.x]);
+  const int64_t r = blockIdx.y;
+  const double* K = Kt + r * P.nnz;
+  double* y = Y + r * P.nnz;
+  double* ua = Ua + r * upd;
+  double* Us = ua + P.arena[v.s];
+  RegFront<C> M;
+  load_panel(M, v, K);
+  congruences<C, KCL>(M, v, LB, 1.0, buf, Ls);
+  gather_children(M, P, v, ua, inv, -1.0);
+  store_front(M, v, [&](int64_t o, double x) { y[o] = x; }, [&](int64_t e, double x) { Us[e] = -x; });
+}
+
+// Algorithm 3.2 in block form on a register front: R R^T - G =
+// [X_NN X_AN^T; X_AN -U_s] for the Cholesky panel R = [C; B] and
+// G = sum E_c U_c E_c^T, with R R^T accumulated from R's columns staged
+// through LDS in chunks of KC.
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_product_reg(DevPlan P, const int32_t* list, const double* R,
+                                                        double* X, double* U) {
+  constexpr int KC = 16;
+  __shared__ int inv[C::MMAX];
+  __shared__ double Rs[C::MMAX * KC];
+  const SnView v(P, list[blockIdx.x]);
+  const int N = v.N, J = v.J;
+  double* Us = U + P.arena[v.s];
+  RegFront<C> M;
+  M.zero();
+  for (int k0 = 0; k0 < N; k0 += KC) {
+    const int kc = min(KC, N - k0);
+    for (int e = threadIdx.x; e < C::MMAX * KC; e += C::NTH) {
+      const int i = e % C::MMAX, t = e / C::MMAX, k = k0 + t;
+      const bool ok = t < kc && i >= k && i < J;
+      const double x = R[ok ? v.at(i, k) : 0];
+      Rs[e] = ok ? x : 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < kc; ++t) {
+      double ri[C::RX], rj[C::RY];
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a) ri[a] = Rs[M.row(a) + t * C::MMAX];
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) rj[b] = Rs[M.col(b) + t * C::MMAX];
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+        for (int b = 0; b < C::RY; ++b) M.v[a][b] = fma(ri[a], rj[b], M.v[a][b]);
+    }
+    __syncthreads();
+  }
+  gather_children(M, P, v, U, inv, -1.0);
+  store_front(M, v, [&](int64_t o, double x) { X[o] = x; }, [&](int64_t e, double x) { Us[e] = -x; });
 }
 
 // Workgroup shapes of the register classes (front order <= MMAX).
@@ -719,15 +981,29 @@ static void go_vinv(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list
 }
 template <class C>
 static void go_factor(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* x,
-                      double* R, double* LB, double* U, double* part, DevStatus* st, double* wsb,
-                      int64_t slot) {
-  k_factor_reg<C><<<g, C::NTH, 0, s>>>(P, list, x, R, LB, U, part, st, wsb, slot);
+                      double* R, double* LB, double* U, double* part, DevStatus* st) {
+  k_factor_reg<C><<<g, C::NTH, 0, s>>>(P, list, x, R, LB, U, part, st);
 }
 template <class C>
 static void go_completion(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
                           const double* Sin, double* R, double* LB, double* S, double* Vs, double* Vi,
                           double* part, DevStatus* st) {
   k_completion_reg<C><<<g, C::NTH, 0, s>>>(P, list, Sin, R, LB, S, Vs, Vi, part, st);
+}
+template <class C>
+static void go_hess_up(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* LB,
+                       const double* Y, double* Kt, double* Ua, int64_t upd) {
+  k_hess_up_reg<C><<<g, C::NTH, 0, s>>>(P, list, LB, Y, Kt, Ua, upd);
+}
+template <class C>
+static void go_ihess_up(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* LB,
+                        const double* Kt, double* Y, double* Ua, int64_t upd) {
+  k_ihess_up_reg<C><<<g, C::NTH, 0, s>>>(P, list, LB, Kt, Y, Ua, upd);
+}
+template <class C>
+static void go_product(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
+                       double* X, double* U) {
+  k_product_reg<C><<<g, C::NTH, 0, s>>>(P, list, R, X, U);
 }
 
 #define MFB_REG_SWITCH(fn, ...)                  \
@@ -744,14 +1020,25 @@ void launch_vinv_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int
   MFB_REG_SWITCH(go_vinv, g, s, P, list, Vs, Vi, st)
 }
 void launch_factor_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
-                       const double* x, double* R, double* LB, double* U, double* part, DevStatus* st,
-                       double* wsb, int64_t slot) {
-  MFB_REG_SWITCH(go_factor, g, s, P, list, x, R, LB, U, part, st, wsb, slot)
+                       const double* x, double* R, double* LB, double* U, double* part, DevStatus* st) {
+  MFB_REG_SWITCH(go_factor, g, s, P, list, x, R, LB, U, part, st)
 }
 void launch_completion_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
                            const double* Sin, double* R, double* LB, double* S, double* Vs,
                            double* Vi, double* part, DevStatus* st) {
   MFB_REG_SWITCH(go_completion, g, s, P, list, Sin, R, LB, S, Vs, Vi, part, st)
+}
+void launch_hess_up_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                        const double* LB, const double* Y, double* Kt, double* Ua, int64_t upd) {
+  MFB_REG_SWITCH(go_hess_up, g, s, P, list, LB, Y, Kt, Ua, upd)
+}
+void launch_ihess_up_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                         const double* LB, const double* Kt, double* Y, double* Ua, int64_t upd) {
+  MFB_REG_SWITCH(go_ihess_up, g, s, P, list, LB, Kt, Y, Ua, upd)
+}
+void launch_product_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                        const double* R, double* X, double* U) {
+  MFB_REG_SWITCH(go_product, g, s, P, list, R, X, U)
 }
 #undef MFB_REG_SWITCH
 

@@ -67,6 +67,23 @@ struct RegFront {
         if (C::GX * a < m && C::GY * b < m && i < m && j < m && pred(i, j)) out(i, j, v[a][b]);
       }
   }
+  // As store(), with the register coordinates passed on: out(a, b, i, j, value).
+  template <class PR, class OUT>
+  __device__ __forceinline__ void store_ab(int m, const PR& pred, const OUT& out) const {
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) {
+        const int i = row(a), j = col(b);
+        if (C::GX * a < m && C::GY * b < m && i < m && j < m && pred(i, j)) out(a, b, i, j, v[a][b]);
+      }
+  }
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) v[a][b] = 0.0;
+  }
 
   // Writes column k to buf (all MMAX rows; rows >= m hold zeros or values
   // that never reach an entry inside the front).  Called by every thread:
@@ -92,12 +109,16 @@ struct RegFront {
     return h;
   }
 
+  // Entries outside the m x m front are zero and stay zero: every step
+  // below reads the broadcast column without bounds checks, relying on the
+  // zero rows that put_column() copies out of those registers.
+
   // One sweep of pivot k (0 <= k < m); `buf` is LDS of 2 * MMAX doubles.
   // Returns true if the pivot is not positive (it is then replaced by one
   // so the arithmetic stays finite).  The rank-1 update runs over the whole
-  // register block (entries outside the front see zero multipliers), and
-  // the pivot row and column are rewritten afterwards by their owners.
-  __device__ __forceinline__ bool sweep(int k, int m, double* buf) {
+  // register block, and the pivot row and column are rewritten afterwards
+  // by their owners.
+  __device__ __forceinline__ bool sweep(int k, double* buf) {
     double* bk = next_half(buf);
     put_column(k, bk);
     __syncthreads();
@@ -107,9 +128,9 @@ struct RegFront {
     const double r = 1.0 / p;
     double ci[C::RX], cj[C::RY];
 #pragma unroll
-    for (int a = 0; a < C::RX; ++a) ci[a] = row(a) < m ? bk[row(a)] : 0.0;
+    for (int a = 0; a < C::RX; ++a) ci[a] = bk[row(a)];
 #pragma unroll
-    for (int b = 0; b < C::RY; ++b) cj[b] = col(b) < m ? bk[col(b)] * r : 0.0;
+    for (int b = 0; b < C::RY; ++b) cj[b] = bk[col(b)] * r;
 #pragma unroll
     for (int a = 0; a < C::RX; ++a)
 #pragma unroll
@@ -141,13 +162,28 @@ struct RegFront {
     return bad;
   }
 
-  // One right-looking Cholesky step on column k (< ncols <= m): on return
-  // column k holds sqrt(M_kk) at row k and M_ik / sqrt(M_kk) below, and the
-  // columns k < j < ncols are updated.  Same buffer protocol and failure
-  // convention as sweep().  Entries above the diagonal are left stale.
-  __device__ __forceinline__ bool chol(int k, int m, int ncols, double* buf, double* diag) {
+  // One right-looking Cholesky step on column k < ncols: on return column
+  // k holds sqrt(M_kk) at row k and M_ik / sqrt(M_kk) below, and the
+  // columns k < j < ncols are updated.  `buf` is LDS of 4 * MMAX doubles:
+  // the column goes to one half and, cut at row ncols, to the other (the
+  // multipliers of the columns), so columns from ncols on are untouched.
+  // Same failure convention as sweep(); entries above the diagonal are
+  // left stale.
+  __device__ __forceinline__ bool chol(int k, int ncols, double* buf, double* diag) {
     double* bk = next_half(buf);
-    put_column(k, bk);
+    double* bc = bk + 2 * C::MMAX;
+    const int kb = k / C::GY;
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b)
+      if (b == kb) {
+        if (ty == k % C::GY) {
+#pragma unroll
+          for (int a = 0; a < C::RX; ++a) {
+            bk[row(a)] = v[a][b];
+            bc[row(a)] = row(a) < ncols ? v[a][b] : 0.0;
+          }
+        }
+      }
     __syncthreads();
     const double p = bk[k];
     const bool bad = !(p > 0.0);
@@ -156,15 +192,13 @@ struct RegFront {
     *diag = d;
     double li[C::RX], lj[C::RY];
 #pragma unroll
-    for (int a = 0; a < C::RX; ++a) li[a] = (row(a) > k && row(a) < m) ? bk[row(a)] * r : 0.0;
+    for (int a = 0; a < C::RX; ++a) li[a] = row(a) > k ? bk[row(a)] * r : 0.0;
 #pragma unroll
-    for (int b = 0; b < C::RY; ++b) lj[b] = (col(b) > k && col(b) < ncols) ? bk[col(b)] * r : 0.0;
+    for (int b = 0; b < C::RY; ++b) lj[b] = col(b) > k ? bc[col(b)] * r : 0.0;
 #pragma unroll
     for (int a = 0; a < C::RX; ++a)
 #pragma unroll
-      for (int b = 0; b < C::RY; ++b)
-        if (C::GY * b < ncols) v[a][b] = fma(-li[a], lj[b], v[a][b]);
-    const int kb = k / C::GY;
+      for (int b = 0; b < C::RY; ++b) v[a][b] = fma(-li[a], lj[b], v[a][b]);
 #pragma unroll
     for (int b = 0; b < C::RY; ++b)
       if (b == kb) {
@@ -177,6 +211,43 @@ struct RegFront {
         }
       }
     return bad;
+  }
+
+  // Congruence with the elementary matrix I + sg l e_k^T (sg = +-1), where
+  // l vanishes on the rows and columns of the pivots (k among them):
+  // M <- (I + sg l e_k^T) M (I + sg e_k l^T)
+  //    = M + l w^T + w l^T,  w = sg M e_k + (M_kk / 2) l.
+  // Factors for different pivots commute (e_k^T l = 0), so applying them one
+  // pivot at a time to the current M gives the product over all pivots.
+  // `lcol` holds l for every row index below MMAX (LDS, zero where l is).
+  __device__ __forceinline__ void congruence(int k, double sg, double* buf, const double* lcol) {
+    double* bk = next_half(buf);
+    put_column(k, bk);
+    __syncthreads();
+    const double h = 0.5 * bk[k];
+    // two rank-1 passes, so only one pair of vectors is live at a time
+    {
+      double li[C::RX], wj[C::RY];
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a) li[a] = lcol[row(a)];
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) wj[b] = fma(h, lcol[col(b)], sg * bk[col(b)]);
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+        for (int b = 0; b < C::RY; ++b) v[a][b] = fma(li[a], wj[b], v[a][b]);
+    }
+    {
+      double wi[C::RX], lj[C::RY];
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a) wi[a] = fma(h, lcol[row(a)], sg * bk[row(a)]);
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) lj[b] = lcol[col(b)];
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+        for (int b = 0; b < C::RY; ++b) v[a][b] = fma(wi[a], lj[b], v[a][b]);
+    }
   }
 
   // Negates the entries in columns j < ncols.
