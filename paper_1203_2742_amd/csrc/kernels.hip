@@ -574,28 +574,27 @@ __global__ void k_reset_status(DevStatus* st) {
 // valid dummy address and discard the value).  Used for fronts up to order
 // 192; the blocked kernels above serve larger ones.
 
-// Columns of L_AN staged per LDS pass by the congruence kernels.
+// Columns of L_AN (or of the Cholesky panel) staged per LDS pass.
 constexpr int KCL = 8;
 
-// CCS offsets of the panel entries a thread owns: entry (i, j) with
-// min(i, j) < N lives at col[min] + |i - j|.  Columns are clamped to N - 1
-// for rows/columns outside the panel (their offsets are never used).
+// Only the lower triangle of a register front is read or written: the
+// elimination steps never read entries above the diagonal (reg_front.h),
+// so those registers start at zero and are left stale.
+
+// CCS offsets of the lower panel entries a thread owns: entry (i, j),
+// i >= j, j < N, lives at col[j] + (i - j).  Columns are clamped to N - 1
+// for columns outside the panel (their offsets are never used).
 template <class C>
 struct PanelIdx {
-  int64_t cr[C::RX], cc[C::RY];
+  int64_t cc[C::RY];
   __device__ __forceinline__ PanelIdx(const RegFront<C>& M, const SnView& v) {
-#pragma unroll
-    for (int a = 0; a < C::RX; ++a) cr[a] = v.col[min(M.row(a), v.N - 1)];
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) cc[b] = v.col[min(M.col(b), v.N - 1)];
   }
-  __device__ __forceinline__ int64_t off(int a, int b, int i, int j) const {
-    return i >= j ? cc[b] + (i - j) : cr[a] + (j - i);
-  }
 };
 
-// Loads the panel part (min(i, j) < N) of the front from the CCS array src;
-// the A x A block is zero.
+// Loads the lower panel part (j < N) of the front from the CCS array src;
+// everything else is zero.
 template <class C>
 __device__ __forceinline__ void load_panel(RegFront<C>& M, const SnView& v, const double* src) {
   const PanelIdx<C> ix(M, v);
@@ -603,23 +602,25 @@ __device__ __forceinline__ void load_panel(RegFront<C>& M, const SnView& v, cons
   for (int a = 0; a < C::RX; ++a)
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) {
+      M.v[a][b] = 0.0;
+      if (C::upper(a, b)) continue;
       const int i = M.row(a), j = M.col(b);
-      const bool ok = i < v.J && j < v.J && min(i, j) < v.N;
-      const double x = src[ok ? ix.off(a, b, i, j) : 0];
+      const bool ok = i < v.J && j < v.N && i >= j;
+      const double x = src[ok ? ix.cc[b] + (i - j) : 0];
       M.v[a][b] = ok ? x : 0.0;
     }
 }
 
-// Stores the lower panel entries (j < N, i >= j) through out(offset, value)
-// and the lower A x A entries through outa(packed index, value).
+// Stores the lower panel entries (j < N) through out(offset, value) and
+// the lower A x A entries through outa(packed index, value).
 template <class C, class OP, class OA>
 __device__ __forceinline__ void store_front(const RegFront<C>& M, const SnView& v, const OP& out,
                                             const OA& outa) {
   const PanelIdx<C> ix(M, v);
   const int N = v.N, A = v.A;
-  M.store_ab(
-      v.J, [](int i, int j) { return i >= j; },
-      [&](int a, int b, int i, int j, double x) {
+  M.store_lower(
+      v.J, [](int, int) { return true; },
+      [&](int, int b, int i, int j, double x) {
         if (j < N)
           out(ix.cc[b] + (i - j), x);
         else
@@ -627,18 +628,10 @@ __device__ __forceinline__ void store_front(const RegFront<C>& M, const SnView& 
       });
 }
 
-// Stores the lower panel entries with j < ncols through out(offset, value).
-template <class C, class OP>
-__device__ __forceinline__ void store_panel(const RegFront<C>& M, const SnView& v, int ncols, const OP& out) {
-  const PanelIdx<C> ix(M, v);
-  M.store_ab(
-      v.J, [&](int i, int j) { return j < ncols && i >= j; },
-      [&](int a, int b, int i, int j, double x) { out(ix.cc[b] + (i - j), x); });
-}
-
-// A x A block <- V_s = E^T [S_NN S_AN^T; S_AN V_p] E gathered from the
-// parent's CCS columns of `src` and its packed block in `arena`
-// (eq. e-sn-gradient-2).  No-op for A = 0.
+// Lower A x A block <- V_s = E^T [S_NN S_AN^T; S_AN V_p] E gathered from
+// the parent's CCS columns of `src` and its packed block in `arena`
+// (eq. e-sn-gradient-2).  Relative indices increase, so i >= j maps to a
+// lower entry of the parent's front.  No-op for A = 0.
 template <class C>
 __device__ __forceinline__ void gather_parent(RegFront<C>& M, const DevPlan& P, const SnView& v,
                                               const double* src, const double* arena) {
@@ -650,12 +643,11 @@ __device__ __forceinline__ void gather_parent(RegFront<C>& M, const DevPlan& P, 
   const int32_t* rl = P.rel + P.relbase[v.s];
   const double* Vp = arena + P.arena[p];
   int rr[C::RX], rc[C::RY];
-  int64_t cpr[C::RX], cpc[C::RY];
+  int64_t cpc[C::RY];
 #pragma unroll
   for (int a = 0; a < C::RX; ++a) {
     const int i = M.row(a);
     rr[a] = (i >= N && i < J) ? rl[i - N] : 0;
-    cpr[a] = colp[min(rr[a], Np - 1)];
   }
 #pragma unroll
   for (int b = 0; b < C::RY; ++b) {
@@ -667,20 +659,20 @@ __device__ __forceinline__ void gather_parent(RegFront<C>& M, const DevPlan& P, 
   for (int a = 0; a < C::RX; ++a)
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) {
+      if (C::upper(a, b)) continue;
       const int i = M.row(a), j = M.col(b);
-      const bool in = i >= N && j >= N && i < J && j < J;
-      const int hi = max(rr[a], rc[b]), lo = min(rr[a], rc[b]);
-      const bool pan = lo < Np;
-      const int64_t op = rr[a] >= rc[b] ? cpc[b] + (rr[a] - rc[b]) : cpr[a] + (rc[b] - rr[a]);
-      const double* q = !in ? src : (pan ? src + op : Vp + pk(hi - Np, lo - Np, Ap));
+      const bool in = j >= N && i < J && i >= j;
+      const double* q = !in ? src
+                            : (rc[b] < Np ? src + cpc[b] + (rr[a] - rc[b])
+                                          : Vp + pk(rr[a] - Np, rc[b] - Np, Ap));
       const double x = *q;
       if (in) M.v[a][b] = x;
     }
 }
 
-// Front += sg * sum over children c of E_c U_c E_c^T, with the children's
-// packed blocks taken from `ua`; one child at a time through an inverse
-// relative-index map in LDS (`inv`, MMAX ints).
+// Front += sg * sum over children c of E_c U_c E_c^T (lower triangle),
+// with the children's packed blocks taken from `ua`; one child at a time
+// through an inverse relative-index map in LDS (`inv`, MMAX ints).
 template <class C>
 __device__ __forceinline__ void gather_children(RegFront<C>& M, const DevPlan& P, const SnView& v,
                                                 const double* ua, int* inv, double sg) {
@@ -704,56 +696,83 @@ __device__ __forceinline__ void gather_children(RegFront<C>& M, const DevPlan& P
     constexpr int GR = C::RX * C::RY > 32 ? (32 + C::RY - 1) / C::RY : C::RX;
 #pragma unroll
     for (int a0 = 0; a0 < C::RX; a0 += GR) {
-      double t[GR][C::RY];
+      double tv[GR][C::RY];
 #pragma unroll
       for (int g = 0; g < GR; ++g)
 #pragma unroll
         for (int b = 0; b < C::RY; ++b) {
           const int a = a0 + g < C::RX ? a0 + g : C::RX - 1;
-          const bool ok = a0 + g < C::RX && xi[a] >= 0 && yj[b] >= 0;
-          t[g][b] = Uc[ok ? pk(max(xi[a], yj[b]), min(xi[a], yj[b]), Ac) : 0];
-          t[g][b] = ok ? sg * t[g][b] : 0.0;
+          const bool ok = a0 + g < C::RX && !C::upper(a, b) && xi[a] >= yj[b] && yj[b] >= 0;
+          const double x = Uc[ok ? pk(xi[a], yj[b], Ac) : 0];
+          tv[g][b] = ok ? sg * x : 0.0;
         }
 #pragma unroll
       for (int g = 0; g < GR; ++g)
 #pragma unroll
         for (int b = 0; b < C::RY; ++b)
-          if (a0 + g < C::RX) M.v[a0 + g][b] += t[g][b];
+          if (a0 + g < C::RX && !C::upper(a0 + g, b)) M.v[a0 + g][b] += tv[g][b];
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-// Columns k0 .. k0 + kc - 1 of [0; L_AN] (rows 0 .. MMAX-1, zero outside
-// A_s) of supernode s into LDS: Ls[i + t MMAX] = l_{k0+t}(i).
-template <class C, int KC>
-__device__ __forceinline__ void stage_lan(const SnView& v, const double* LB, int k0, double* Ls) {
-  for (int e = threadIdx.x; e < C::MMAX * KC; e += C::NTH) {
-    const int i = e % C::MMAX, t = e / C::MMAX, kk = k0 + t;
-    const bool ok = kk < v.N && i >= v.N && i < v.J;
-    const double x = LB[ok ? v.at(i, kk) : 0];
-    Ls[e] = ok ? x : 0.0;
+// Columns k0 .. k0 + KCL - 1 of the N columns given by val(i, k) for
+// rows i below MMAX (zero where val is not taken) into LDS:
+// Ls[i + t MMAX] = val(i, k0 + t).
+template <class C, class VF>
+__device__ __forceinline__ void stage_columns(int N, int k0, double* Ls, const VF& val) {
+  for (int e = threadIdx.x; e < C::MMAX * KCL; e += C::NTH) {
+    const int i = e % C::MMAX, t = e / C::MMAX;
+    Ls[e] = k0 + t < N ? val(i, k0 + t) : 0.0;
   }
 }
 
-// N congruence steps with the columns of [0; L_AN], staged KC at a time.
-template <class C, int KC>
+// N congruence steps with the columns of [0; L_AN], staged KCL at a time.
+template <class C>
 __device__ __forceinline__ void congruences(RegFront<C>& M, const SnView& v, const double* LB, double sg,
                                             double* buf, double* Ls) {
-  for (int k0 = 0; k0 < v.N; k0 += KC) {
-    stage_lan<C, KC>(v, LB, k0, Ls);
-    __syncthreads();
-    const int kc = min(KC, v.N - k0);
-    for (int t = 0; t < kc; ++t) M.congruence(k0 + t, sg, buf, Ls + t * C::MMAX);
-    __syncthreads();
+  M.template congruences<KCL>(v.N, sg, buf, Ls, [&](int k0, double* ls) {
+    stage_columns<C>(v.N, k0, ls, [&](int i, int kk) {
+      const bool ok = i >= v.N && i < v.J;
+      const double x = LB[ok ? v.at(i, kk) : 0];
+      return ok ? x : 0.0;
+    });
+  });
+}
+
+// Column k of the Cholesky factor from the broadcast column of the sweep
+// of pivot k (rows k .. J-1 of `bk`, pivot p): R[col[k] + i - k] =
+// bk[i] / sqrt(p), one row per thread.
+__device__ __forceinline__ void put_chol_column(const SnView& v, int k, const double* bk, double p,
+                                                const int64_t* colc, double* R) {
+  const int i = k + threadIdx.x;
+  if (i < v.J) R[colc[k] + (i - k)] = bk[i] * fast_rsqrt(p);
+}
+
+// sum_{k < n} log piv[k] (LDS), by the first wavefront in a fixed order;
+// the result is valid in thread 0.  Call with all threads after a barrier
+// that published piv.
+__device__ __forceinline__ double sum_log_pivots(const double* piv, int n) {
+  double s = 0.0;
+  if (threadIdx.x < 64) {
+    for (int k = threadIdx.x; k < n; k += 64) s += log(piv[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   }
+  return s;
+}
+
+// Column offsets of the supernode's panel into LDS (colc[c] = col[c]).
+template <class C>
+__device__ __forceinline__ void stage_col(const SnView& v, int64_t* colc) {
+  for (int c = threadIdx.x; c < v.N; c += C::NTH) colc[c] = v.col[c];
 }
 
 // (S_{A_s A_s})^-1 by sweeping every pivot of V_s.
 template <class C>
 __global__ void __launch_bounds__(C::NTH) k_vinv_reg(DevPlan P, const int32_t* list, const double* Vs,
                                                      double* Vi, DevStatus* st) {
-  __shared__ double buf[2 * C::MMAX];
+  __shared__ double buf[4 * C::MMAX];
   const SnView v(P, list[blockIdx.x]);
   const int A = v.A;
   if (A == 0) return;
@@ -764,111 +783,106 @@ __global__ void __launch_bounds__(C::NTH) k_vinv_reg(DevPlan P, const int32_t* l
   for (int a = 0; a < C::RX; ++a)
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) {
+      M.v[a][b] = 0.0;
+      if (C::upper(a, b)) continue;
       const int i = M.row(a), j = M.col(b);
-      const bool ok = i < A && j < A;
-      const double x = V[ok ? pk(max(i, j), min(i, j), A) : 0];
+      const bool ok = i < A && i >= j;
+      const double x = V[ok ? pk(i, j, A) : 0];
       M.v[a][b] = ok ? x : 0.0;
     }
-  bool bad = false;
-  for (int k = 0; k < A; ++k) bad |= M.sweep(k, buf);
-  M.store(
-      A, [](int i, int j) { return i >= j; }, [&](int i, int j, double x) { VI[pk(i, j, A)] = -x; });
+  const bool bad = M.sweeps(0, A, buf) >= 0;
+  M.store_lower(
+      A, [](int, int) { return true; }, [&](int, int, int i, int j, double x) { VI[pk(i, j, A)] = -x; });
   if (threadIdx.x == 0 && bad) report(st, MFB_ENOTPD, v.vl[0]);
 }
 
 // Algorithm 7.1 on a register front.  After the extend-add, sweeping the N
 // pivots of F = [D_NN X_AN^T; X_AN F22] leaves [-D^-1, .; L_AN, U_s] with
 // L_AN = X_AN D^-1 and U_s = F22 - X_AN D^-1 X_AN^T (the block L D L^T
-// step); the Cholesky panel [C; B] then comes from N right-looking steps
-// on the assembled columns, which are parked in R in between.
+// step), and the column broadcast before each pivot gives the Cholesky
+// panel [C; B] and log det D_NN = sum of log pivots.
 template <class C>
 __global__ void __launch_bounds__(C::NTH) k_factor_reg(DevPlan P, const int32_t* list, const double* x,
                                                        double* R, double* LB, double* U, double* part,
                                                        DevStatus* st) {
   __shared__ double buf[4 * C::MMAX];
   __shared__ int inv[C::MMAX];
+  __shared__ int64_t colc[C::MMAX];
+  __shared__ double piv[C::MMAX];
   const SnView v(P, list[blockIdx.x]);
-  const int N = v.N, A = v.A, J = v.J;
+  const int N = v.N, A = v.A;
   double* Us = U + P.arena[v.s];
+  stage_col<C>(v, colc);
   RegFront<C> M;
   load_panel(M, v, x);
   gather_children(M, P, v, U, inv, 1.0);
-  store_front(M, v, [&](int64_t o, double y) { R[o] = y; }, [](int64_t, double) {});
-  for (int k = 0; k < N; ++k) M.sweep(k, buf);
-  {
-    const PanelIdx<C> ix(M, v);
-    // panel: -D^-1 (N x N, sign flipped on the way out) and L_AN
-    M.store_ab(
-        J, [](int i, int j) { return i >= j; },
-        [&](int a, int b, int i, int j, double y) {
-          if (j < N)
-            LB[ix.cc[b] + (i - j)] = i >= N ? y : -y;
-          else
-            Us[pk(i - N, j - N, A)] = y;
-        });
-  }
+  const int fail = M.sweeps(0, N, buf, [&](const double* bk, double p, int k) {
+    put_chol_column(v, k, bk, p, colc, R);
+    if (threadIdx.x == 0) piv[k] = p;
+  });
+  store_front(
+      M, v,
+      [&](int64_t o, double y) {
+        // N x N block: -D^-1 (sign flipped here); A x N block: L_AN
+        LB[o] = y;
+      },
+      [&](int64_t e, double y) { Us[e] = y; });
+  M.store_lower(
+      N, [](int, int) { return true; },
+      [&](int, int b, int i, int j, double y) { LB[colc[j] + (i - j)] = -y; });
   __syncthreads();
-  load_panel(M, v, R);
-  double lg = 0.0;
-  int fail = -1;
-  for (int k = 0; k < N; ++k) {
-    double d;
-    if (M.chol(k, N, buf, &d) && fail < 0) fail = k;
-    lg += 2.0 * log(d);
-  }
-  store_panel(M, v, N, [&](int64_t o, double y) { R[o] = y; });
+  const double lg = sum_log_pivots(piv, N);
   if (threadIdx.x == 0) {
     part[v.s] = lg;
     if (fail >= 0) report(st, MFB_ENOTPD, v.vl[fail]);
   }
+  (void)A;
 }
 
 // Algorithm 7.3 on a register front G = S_{J_s J_s} = [S_NN S_AN^T; S_AN V_s].
 // Sweeping the A pivots leaves [D^-1, -L_AN^T; -L_AN, -V_s^-1] with
 // L_AN = -V_s^-1 S_AN and D^-1 = S_NN + S_AN^T L_AN; sweeping the N pivots
-// next turns the first N columns into -[D; L_AN D], and N Cholesky steps on
-// [D; L_AN D] give C = chol(D) and B = L_AN D C^-T = L_AN C.
+// next turns the first N columns into -[D; L_AN D].  A last sweep of the N
+// pivots of [D; L_AN D] broadcasts the columns of its Cholesky panel,
+// C = chol(D) and B = L_AN D C^-T = L_AN C, and log det D.
 template <class C>
 __global__ void __launch_bounds__(C::NTH) k_completion_reg(DevPlan P, const int32_t* list,
                                                            const double* Sin, double* R, double* LB,
                                                            double* S, double* Vs, double* Vi,
                                                            double* part, DevStatus* st) {
   __shared__ double buf[4 * C::MMAX];
+  __shared__ int64_t colc[C::MMAX];
+  __shared__ double piv[C::MMAX];
   const SnView v(P, list[blockIdx.x]);
   const int N = v.N, A = v.A, J = v.J;
   double* VS = Vs + P.arena[v.s];
   double* VI = Vi + P.arena[v.s];
+  stage_col<C>(v, colc);
   RegFront<C> M;
   load_panel(M, v, Sin);
   gather_parent(M, P, v, Sin, Vs);
   // cache S (own columns) and V_s
   store_front(M, v, [&](int64_t o, double y) { S[o] = y; }, [&](int64_t e, double y) { VS[e] = y; });
-  bool badV = false;
-  for (int k = N; k < J; ++k) badV |= M.sweep(k, buf);
-  {
-    // L_AN = -(swept AN block), D^-1 = swept N x N block, V_s^-1 = -(swept A x A block)
-    const PanelIdx<C> ix(M, v);
-    M.store_ab(
-        J, [](int i, int j) { return i >= j; },
-        [&](int a, int b, int i, int j, double y) {
-          if (j < N)
-            LB[ix.cc[b] + (i - j)] = i >= N ? -y : y;
-          else
-            VI[pk(i - N, j - N, A)] = -y;
-        });
-  }
+  const bool badV = M.sweeps(N, J, buf) >= 0;
+  // L_AN = -(swept A x N block), D^-1 = swept N x N block, V_s^-1 = -(swept A x A block)
+  M.store_lower(
+      J, [](int, int) { return true; },
+      [&](int, int, int i, int j, double y) {
+        if (j < N)
+          LB[colc[j] + (i - j)] = i >= N ? -y : y;
+        else
+          VI[pk(i - N, j - N, A)] = -y;
+      });
   if (threadIdx.x == 0 && badV) report(st, MFB_ENOCOMPLETION, v.vl[0]);
-  int fail = -1;
-  for (int k = 0; k < N; ++k)
-    if (M.sweep(k, buf) && fail < 0) fail = k;
+  int fail = M.sweeps(0, N, buf);
   M.negate_columns(N);
-  double lg = 0.0;
-  for (int k = 0; k < N; ++k) {
-    double d;
-    if (M.chol(k, N, buf, &d) && fail < 0) fail = k;
-    lg += 2.0 * log(d);
-  }
-  store_panel(M, v, N, [&](int64_t o, double y) { R[o] = y; });
+  const int fail2 = M.sweeps(0, N, buf, [&](const double* bk, double p, int k) {
+    put_chol_column(v, k, bk, p, colc, R);
+    if (threadIdx.x == 0) piv[k] = p;
+  });
+  if (fail < 0) fail = fail2;
+  __syncthreads();
+  const double lg = sum_log_pivots(piv, N);
   if (threadIdx.x == 0) {
     part[v.s] = lg;
     if (fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
@@ -883,7 +897,7 @@ template <class C>
 __global__ void __launch_bounds__(C::NTH) k_hess_up_reg(DevPlan P, const int32_t* list, const double* LB,
                                                         const double* Y, double* Kt, double* Ua,
                                                         int64_t upd) {
-  __shared__ double buf[2 * C::MMAX];
+  __shared__ double buf[4 * C::MMAX];
   __shared__ int inv[C::MMAX];
   __shared__ double Ls[C::MMAX * KCL];
   const SnView v(P, list[blockIdx.x]);
@@ -895,7 +909,7 @@ __global__ void __launch_bounds__(C::NTH) k_hess_up_reg(DevPlan P, const int32_t
   RegFront<C> M;
   load_panel(M, v, y);
   gather_children(M, P, v, ua, inv, 1.0);
-  congruences<C, KCL>(M, v, LB, -1.0, buf, Ls);
+  congruences<C>(M, v, LB, -1.0, buf, Ls);
   store_front(M, v, [&](int64_t o, double x) { K[o] = x; }, [&](int64_t e, double x) { Us[e] = x; });
 }
 
@@ -907,7 +921,7 @@ template <class C>
 __global__ void __launch_bounds__(C::NTH) k_ihess_up_reg(DevPlan P, const int32_t* list, const double* LB,
                                                          const double* Kt, double* Y, double* Ua,
                                                          int64_t upd) {
-  __shared__ double buf[2 * C::MMAX];
+  __shared__ double buf[4 * C::MMAX];
   __shared__ int inv[C::MMAX];
   __shared__ double Ls[C::MMAX * KCL];
   const SnView v(P, list[blockIdx.x]);
@@ -918,7 +932,7 @@ __global__ void __launch_bounds__(C::NTH) k_ihess_up_reg(DevPlan P, const int32_
   double* Us = ua + P.arena[v.s];
   RegFront<C> M;
   load_panel(M, v, K);
-  congruences<C, KCL>(M, v, LB, 1.0, buf, Ls);
+  congruences<C>(M, v, LB, 1.0, buf, Ls);
   gather_children(M, P, v, ua, inv, -1.0);
   store_front(M, v, [&](int64_t o, double x) { y[o] = x; }, [&](int64_t e, double x) { Us[e] = -x; });
 }
@@ -926,38 +940,26 @@ __global__ void __launch_bounds__(C::NTH) k_ihess_up_reg(DevPlan P, const int32_
 // Algorithm 3.2 in block form on a register front: R R^T - G =
 // [X_NN X_AN^T; X_AN -U_s] for the Cholesky panel R = [C; B] and
 // G = sum E_c U_c E_c^T, with R R^T accumulated from R's columns staged
-// through LDS in chunks of KC.
+// through LDS KCL at a time.
 template <class C>
 __global__ void __launch_bounds__(C::NTH) k_product_reg(DevPlan P, const int32_t* list, const double* R,
                                                         double* X, double* U) {
-  constexpr int KC = 16;
   __shared__ int inv[C::MMAX];
-  __shared__ double Rs[C::MMAX * KC];
+  __shared__ double Rs[C::MMAX * KCL];
   const SnView v(P, list[blockIdx.x]);
   const int N = v.N, J = v.J;
   double* Us = U + P.arena[v.s];
   RegFront<C> M;
   M.zero();
-  for (int k0 = 0; k0 < N; k0 += KC) {
-    const int kc = min(KC, N - k0);
-    for (int e = threadIdx.x; e < C::MMAX * KC; e += C::NTH) {
-      const int i = e % C::MMAX, t = e / C::MMAX, k = k0 + t;
-      const bool ok = t < kc && i >= k && i < J;
+  for (int k0 = 0; k0 < N; k0 += KCL) {
+    stage_columns<C>(N, k0, Rs, [&](int i, int k) {
+      const bool ok = i >= k && i < J;
       const double x = R[ok ? v.at(i, k) : 0];
-      Rs[e] = ok ? x : 0.0;
-    }
+      return ok ? x : 0.0;
+    });
     __syncthreads();
-    for (int t = 0; t < kc; ++t) {
-      double ri[C::RX], rj[C::RY];
-#pragma unroll
-      for (int a = 0; a < C::RX; ++a) ri[a] = Rs[M.row(a) + t * C::MMAX];
-#pragma unroll
-      for (int b = 0; b < C::RY; ++b) rj[b] = Rs[M.col(b) + t * C::MMAX];
-#pragma unroll
-      for (int a = 0; a < C::RX; ++a)
-#pragma unroll
-        for (int b = 0; b < C::RY; ++b) M.v[a][b] = fma(ri[a], rj[b], M.v[a][b]);
-    }
+    const int kc = min(KCL, N - k0);
+    for (int t = 0; t < kc; ++t) M.rank1(Rs + t * C::MMAX);
     __syncthreads();
   }
   gather_children(M, P, v, U, inv, -1.0);

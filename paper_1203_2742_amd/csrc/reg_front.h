@@ -1,24 +1,28 @@
 // Register-resident symmetric fronts for gfx950.
 //
 // A workgroup of GX * GY threads holds an m x m symmetric matrix (m <= MMAX)
-// entirely in registers: thread (tx, ty) = (t % GX, t / GX) owns the RX x RY
-// entries (tx + GX a, ty + GY b).  Both triangles are kept, so every
-// elimination step is one rank-1 update of the whole register block after a
-// single LDS broadcast of the pivot column, with one workgroup barrier per
-// step.  No step touches global memory: the front is read once and its
-// results written once.
+// in registers: thread (tx, ty) = (t % GX, t / GX) owns the RX x RY entries
+// (tx + GX a, ty + GY b).  Register blocks (a, b) lying wholly above the
+// diagonal (every row index of the block below every column index) are
+// never computed; all other blocks hold correct values, so the lower
+// triangle and the diagonal are always exact.  Every elimination step is
+// one rank-1 or rank-2 update of the register block after a single LDS
+// broadcast of the pivot column, with one workgroup barrier per step.  No
+// step touches global memory: the front is read once and its results
+// written once.
 //
-// Two eliminations are provided:
+// Eliminations:
 //  * sweep (the symmetric Gauss-Jordan "sweep operator"): sweeping pivot k
 //    of M maps M_kk -> -1/M_kk, M_ik -> M_ik / M_kk, M_kj -> M_kj / M_kk and
 //    M_ij -> M_ij - M_ik M_kj / M_kk.  Sweeping a set K of pivots of
 //    [M_KK M_KR; M_RK M_RR] leaves [-M_KK^-1, M_KK^-1 M_KR; M_RK M_KK^-1,
-//    M_RR - M_RK M_KK^-1 M_KR], so sweeping every pivot gives -M^-1.  The
-//    pivots are the successive Schur-complement diagonals, all positive
-//    exactly when the swept block is positive definite.
-//  * right-looking Cholesky on the leading columns: step k divides column k
-//    by sqrt(M_kk) and subtracts the outer product of that column from the
-//    trailing columns j < ncols (all rows).
+//    M_RR - M_RK M_KK^-1 M_KR], so sweeping every pivot gives -M^-1.  Just
+//    before pivot k is swept (pivots swept in increasing order), column k
+//    restricted to the rows >= k is the first column of the Schur
+//    complement, i.e. d_k [1; l_k] of the scalar L D L^T factorization, so
+//    the broadcast column also yields column k of the Cholesky factor.
+//  * congruence with I + sg l e_k^T for a vector l that vanishes on the
+//    pivot rows (the block L D L^T transforms of the Hessian sweeps).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -33,6 +37,33 @@ struct RegCfg {
   static constexpr int MMAX = GX * RX;
   static_assert(GX * RX == GY * RY, "square register front");
   static_assert(NTH % 64 == 0, "whole wavefronts");
+  static_assert(NTH >= MMAX, "one thread per row of a broadcast column");
+  // register block (a, b) lies wholly above the diagonal
+  static constexpr bool upper(int a, int b) { return GX * a + GX - 1 < GY * b; }
+};
+
+// 1 / p for p > 0: the hardware reciprocal refined by two Newton steps
+// (each squares the relative error), short enough to sit on the
+// per-step critical path.
+__device__ __forceinline__ double fast_rcp(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return r;
+}
+
+// 1 / sqrt(p) for p > 0: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double fast_rsqrt(double p) {
+  double y = __builtin_amdgcn_rsq(p);
+  const double h = 0.5 * p;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+template <int V>
+struct ic {
+  static constexpr int value = V;
 };
 
 template <class C>
@@ -45,172 +76,132 @@ struct RegFront {
   __device__ __forceinline__ int row(int a) const { return tx + C::GX * a; }
   __device__ __forceinline__ int col(int b) const { return ty + C::GY * b; }
 
-  // v(i, j) = f(i, j) for i, j < m, else 0.
-  template <class F>
-  __device__ __forceinline__ void load(int m, const F& f) {
-#pragma unroll
-    for (int a = 0; a < C::RX; ++a)
-#pragma unroll
-      for (int b = 0; b < C::RY; ++b) {
-        const int i = row(a), j = col(b);
-        v[a][b] = (i < m && j < m) ? f(i, j) : 0.0;
-      }
-  }
-  // out(i, j, v(i, j)) for every owned entry with pred(i, j) true.
-  template <class PR, class OUT>
-  __device__ __forceinline__ void store(int m, const PR& pred, const OUT& out) const {
-#pragma unroll
-    for (int a = 0; a < C::RX; ++a)
-#pragma unroll
-      for (int b = 0; b < C::RY; ++b) {
-        const int i = row(a), j = col(b);
-        if (C::GX * a < m && C::GY * b < m && i < m && j < m && pred(i, j)) out(i, j, v[a][b]);
-      }
-  }
-  // As store(), with the register coordinates passed on: out(a, b, i, j, value).
-  template <class PR, class OUT>
-  __device__ __forceinline__ void store_ab(int m, const PR& pred, const OUT& out) const {
-#pragma unroll
-    for (int a = 0; a < C::RX; ++a)
-#pragma unroll
-      for (int b = 0; b < C::RY; ++b) {
-        const int i = row(a), j = col(b);
-        if (C::GX * a < m && C::GY * b < m && i < m && j < m && pred(i, j)) out(a, b, i, j, v[a][b]);
-      }
-  }
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int a = 0; a < C::RX; ++a)
 #pragma unroll
       for (int b = 0; b < C::RY; ++b) v[a][b] = 0.0;
   }
-
-  // Writes column k to buf (all MMAX rows; rows >= m hold zeros or values
-  // that never reach an entry inside the front).  Called by every thread:
-  // the register index is selected by uniform branches, the owning lanes
-  // by a divergent one inside.
-  __device__ __forceinline__ void put_column(int k, double* buf) const {
-    const int kb = k / C::GY;
+  // out(a, b, i, j, v(i, j)) for every owned lower entry (i >= j) of the
+  // m x m front with pred(i, j) true.
+  template <class PR, class OUT>
+  __device__ __forceinline__ void store_lower(int m, const PR& pred, const OUT& out) const {
 #pragma unroll
-    for (int b = 0; b < C::RY; ++b)
-      if (b == kb) {
-        if (ty == k % C::GY) {
+    for (int a = 0; a < C::RX; ++a)
 #pragma unroll
-          for (int a = 0; a < C::RX; ++a) buf[row(a)] = v[a][b];
-        }
+      for (int b = 0; b < C::RY; ++b) {
+        if (C::upper(a, b)) continue;
+        const int i = row(a), j = col(b);
+        if (C::GX * a < m && C::GY * b < m && i < m && i >= j && pred(i, j)) out(a, b, i, j, v[a][b]);
       }
   }
 
-  // Half of the broadcast buffer for the next step: consecutive steps (of
-  // either kind) alternate, so one barrier per step suffices.
+  // Broadcast buffer for the next step (2 MMAX doubles out of `buf`, which
+  // holds 4 MMAX): consecutive steps (of either kind) alternate halves, so
+  // one barrier per step suffices.
   __device__ __forceinline__ double* next_half(double* buf) {
-    double* h = buf + phase * C::MMAX;
+    double* h = buf + phase * 2 * C::MMAX;
     phase ^= 1;
     return h;
   }
 
   // Entries outside the m x m front are zero and stay zero: every step
   // below reads the broadcast column without bounds checks, relying on the
-  // zero rows that put_column() copies out of those registers.
+  // zero rows that the broadcast copies out of those registers.
+  //
+  // Steps are instantiated per register row block KA of the pivot
+  // (k in [GX KA, GX KA + GX)), so the pivot's row block KA and column
+  // block KB = GX KA / GY are compile-time constants and no step selects a
+  // register by a runtime index.
 
-  // One sweep of pivot k (0 <= k < m); `buf` is LDS of 2 * MMAX doubles.
-  // Returns true if the pivot is not positive (it is then replaced by one
-  // so the arithmetic stays finite).  The rank-1 update runs over the whole
-  // register block, and the pivot row and column are rewritten afterwards
-  // by their owners.
-  __device__ __forceinline__ bool sweep(int k, double* buf) {
+  // Broadcast of column k of the symmetric matrix: the owners of column k
+  // write their rows to bk[0 .. MMAX), the owners of row k their columns to
+  // bk[MMAX .. 2 MMAX).  Entry i of column k is then bk[i] for i >= k (a
+  // lower entry of column k) and bk[MMAX + i] for i < k (a lower entry of
+  // row k); in(...) picks the part, which is known at compile time except
+  // in the pivot's own block.
+  template <int KA>
+  __device__ __forceinline__ void put_column(int k, double* bk) const {
+    constexpr int KB = (C::GX * KA) / C::GY;
+    if (ty == k - C::GY * KB) {
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a) bk[row(a)] = C::upper(a, KB) ? 0.0 : v[a][KB];
+    }
+    if (tx == k - C::GX * KA) {
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) bk[C::MMAX + col(b)] = C::upper(KA, b) ? 0.0 : v[KA][b];
+    }
+  }
+  template <int KA>
+  __device__ __forceinline__ double in_row(const double* bk, int a, int k) const {
+    if (a < KA) return bk[C::MMAX + row(a)];
+    if (a > KA) return bk[row(a)];
+    return bk[row(a) < k ? C::MMAX + row(a) : row(a)];
+  }
+  template <int KA>
+  __device__ __forceinline__ double in_col(const double* bk, int b, int k) const {
+    constexpr int KB = (C::GX * KA) / C::GY;
+    if (b < KB) return bk[C::MMAX + col(b)];
+    if (b > KB) return bk[col(b)];
+    return bk[col(b) < k ? C::MMAX + col(b) : col(b)];
+  }
+
+  // One sweep of pivot k (in row block KA).  After the barrier,
+  // ext(column, pivot, k) sees the broadcast column (before this step's
+  // update; entries i >= k at column[i]).  Returns true if the pivot is not
+  // positive (it is then replaced by one so the arithmetic stays finite).
+  // The rank-1 update runs over the whole register block, and the pivot
+  // row and column are rewritten afterwards by their owners.
+  template <int KA, class EX>
+  __device__ __forceinline__ bool sweep_step(int k, double* buf, const EX& ext) {
+    constexpr int KB = (C::GX * KA) / C::GY;
     double* bk = next_half(buf);
-    put_column(k, bk);
+    put_column<KA>(k, bk);
     __syncthreads();
     double p = bk[k];
     const bool bad = !(p > 0.0);
     if (bad) p = 1.0;
-    const double r = 1.0 / p;
+    ext(static_cast<const double*>(bk), p, k);
+    const double r = fast_rcp(p);
     double ci[C::RX], cj[C::RY];
 #pragma unroll
-    for (int a = 0; a < C::RX; ++a) ci[a] = bk[row(a)];
+    for (int a = 0; a < C::RX; ++a) ci[a] = in_row<KA>(bk, a, k);
 #pragma unroll
-    for (int b = 0; b < C::RY; ++b) cj[b] = bk[col(b)] * r;
+    for (int b = 0; b < C::RY; ++b) cj[b] = in_col<KA>(bk, b, k) * r;
 #pragma unroll
     for (int a = 0; a < C::RX; ++a)
 #pragma unroll
-      for (int b = 0; b < C::RY; ++b) v[a][b] = fma(-ci[a], cj[b], v[a][b]);
+      for (int b = 0; b < C::RY; ++b)
+        if (!C::upper(a, b)) v[a][b] = fma(-ci[a], cj[b], v[a][b]);
     // row k: M_kj / M_kk; column k: M_ik / M_kk; pivot: -1 / M_kk
-    const int ka = k / C::GX, kb = k / C::GY;
-    const bool own_r = tx == k % C::GX, own_c = ty == k % C::GY;
+    const bool own_r = tx == k - C::GX * KA, own_c = ty == k - C::GY * KB;
+    if (own_r) {
 #pragma unroll
-    for (int a = 0; a < C::RX; ++a)
-      if (a == ka) {
-        if (own_r) {
+      for (int b = 0; b < C::RY; ++b) v[KA][b] = cj[b];
+    }
+    if (own_c) {
 #pragma unroll
-          for (int b = 0; b < C::RY; ++b) v[a][b] = cj[b];
-        }
-      }
-#pragma unroll
-    for (int b = 0; b < C::RY; ++b)
-      if (b == kb) {
-        if (own_c) {
-#pragma unroll
-          for (int a = 0; a < C::RX; ++a) v[a][b] = ci[a] * r;
-        }
-#pragma unroll
-        for (int a = 0; a < C::RX; ++a)
-          if (a == ka) {
-            if (own_r && own_c) v[a][b] = -r;
-          }
-      }
+      for (int a = 0; a < C::RX; ++a) v[a][KB] = ci[a] * r;
+    }
+    if (own_r && own_c) v[KA][KB] = -r;
     return bad;
   }
 
-  // One right-looking Cholesky step on column k < ncols: on return column
-  // k holds sqrt(M_kk) at row k and M_ik / sqrt(M_kk) below, and the
-  // columns k < j < ncols are updated.  `buf` is LDS of 4 * MMAX doubles:
-  // the column goes to one half and, cut at row ncols, to the other (the
-  // multipliers of the columns), so columns from ncols on are untouched.
-  // Same failure convention as sweep(); entries above the diagonal are
-  // left stale.
-  __device__ __forceinline__ bool chol(int k, int ncols, double* buf, double* diag) {
-    double* bk = next_half(buf);
-    double* bc = bk + 2 * C::MMAX;
-    const int kb = k / C::GY;
-#pragma unroll
-    for (int b = 0; b < C::RY; ++b)
-      if (b == kb) {
-        if (ty == k % C::GY) {
-#pragma unroll
-          for (int a = 0; a < C::RX; ++a) {
-            bk[row(a)] = v[a][b];
-            bc[row(a)] = row(a) < ncols ? v[a][b] : 0.0;
-          }
-        }
-      }
-    __syncthreads();
-    const double p = bk[k];
-    const bool bad = !(p > 0.0);
-    const double d = bad ? 1.0 : sqrt(p);
-    const double r = 1.0 / d;
-    *diag = d;
-    double li[C::RX], lj[C::RY];
-#pragma unroll
-    for (int a = 0; a < C::RX; ++a) li[a] = row(a) > k ? bk[row(a)] * r : 0.0;
-#pragma unroll
-    for (int b = 0; b < C::RY; ++b) lj[b] = col(b) > k ? bc[col(b)] * r : 0.0;
-#pragma unroll
-    for (int a = 0; a < C::RX; ++a)
-#pragma unroll
-      for (int b = 0; b < C::RY; ++b) v[a][b] = fma(-li[a], lj[b], v[a][b]);
-#pragma unroll
-    for (int b = 0; b < C::RY; ++b)
-      if (b == kb) {
-        if (ty == k % C::GY) {
-#pragma unroll
-          for (int a = 0; a < C::RX; ++a) {
-            const int i = row(a);
-            v[a][b] = i > k ? li[a] : (i == k ? d : v[a][b]);
-          }
-        }
-      }
-    return bad;
+  // Sweeps the pivots kbeg .. kend-1 in increasing order, calling
+  // ext(column, pivot, k) at each (see sweep_step).  Returns the first pivot
+  // that was not positive, or -1.
+  template <class EX>
+  __device__ __forceinline__ int sweeps(int kbeg, int kend, double* buf, const EX& ext) {
+    int fail = -1;
+    blocks(kbeg, kend, [&](auto ka, int lo, int hi) {
+      constexpr int KA = decltype(ka)::value;
+      for (int k = lo; k < hi; ++k)
+        if (sweep_step<KA>(k, buf, ext) && fail < 0) fail = k;
+    });
+    return fail;
+  }
+  __device__ __forceinline__ int sweeps(int kbeg, int kend, double* buf) {
+    return sweeps(kbeg, kend, buf, [](const double*, double, int) {});
   }
 
   // Congruence with the elementary matrix I + sg l e_k^T (sg = +-1), where
@@ -220,9 +211,10 @@ struct RegFront {
   // Factors for different pivots commute (e_k^T l = 0), so applying them one
   // pivot at a time to the current M gives the product over all pivots.
   // `lcol` holds l for every row index below MMAX (LDS, zero where l is).
-  __device__ __forceinline__ void congruence(int k, double sg, double* buf, const double* lcol) {
+  template <int KA>
+  __device__ __forceinline__ void congruence_step(int k, double sg, double* buf, const double* lcol) {
     double* bk = next_half(buf);
-    put_column(k, bk);
+    put_column<KA>(k, bk);
     __syncthreads();
     const double h = 0.5 * bk[k];
     // two rank-1 passes, so only one pair of vectors is live at a time
@@ -231,23 +223,70 @@ struct RegFront {
 #pragma unroll
       for (int a = 0; a < C::RX; ++a) li[a] = lcol[row(a)];
 #pragma unroll
-      for (int b = 0; b < C::RY; ++b) wj[b] = fma(h, lcol[col(b)], sg * bk[col(b)]);
+      for (int b = 0; b < C::RY; ++b) wj[b] = fma(h, lcol[col(b)], sg * in_col<KA>(bk, b, k));
 #pragma unroll
       for (int a = 0; a < C::RX; ++a)
 #pragma unroll
-        for (int b = 0; b < C::RY; ++b) v[a][b] = fma(li[a], wj[b], v[a][b]);
+        for (int b = 0; b < C::RY; ++b)
+          if (!C::upper(a, b)) v[a][b] = fma(li[a], wj[b], v[a][b]);
     }
     {
       double wi[C::RX], lj[C::RY];
 #pragma unroll
-      for (int a = 0; a < C::RX; ++a) wi[a] = fma(h, lcol[row(a)], sg * bk[row(a)]);
+      for (int a = 0; a < C::RX; ++a) wi[a] = fma(h, lcol[row(a)], sg * in_row<KA>(bk, a, k));
 #pragma unroll
       for (int b = 0; b < C::RY; ++b) lj[b] = lcol[col(b)];
 #pragma unroll
       for (int a = 0; a < C::RX; ++a)
 #pragma unroll
-        for (int b = 0; b < C::RY; ++b) v[a][b] = fma(wi[a], lj[b], v[a][b]);
+        for (int b = 0; b < C::RY; ++b)
+          if (!C::upper(a, b)) v[a][b] = fma(wi[a], lj[b], v[a][b]);
     }
+  }
+
+  // Congruence steps for the pivots 0 .. n-1.  The vectors l come in LDS
+  // chunks of KC pivots: stage(k0, ls) fills ls[i + t MMAX] = l_{k0+t}(i)
+  // (every thread takes part; KC divides GX, so chunks never straddle a
+  // register row block).
+  template <int KC, class ST>
+  __device__ __forceinline__ void congruences(int n, double sg, double* buf, double* ls, const ST& stage) {
+    static_assert(C::GX % KC == 0, "chunks inside one row block");
+    blocks(0, n, [&](auto ka, int lo, int hi) {
+      constexpr int KA = decltype(ka)::value;
+      for (int k0 = lo; k0 < hi; k0 += KC) {
+        stage(k0, ls);
+        __syncthreads();
+        const int kc = min(KC, hi - k0);
+        for (int t = 0; t < kc; ++t) congruence_step<KA>(k0 + t, sg, buf, ls + t * C::MMAX);
+        __syncthreads();
+      }
+    });
+  }
+
+  // f(ic<KA>, lo, hi) for every register row block KA meeting [kbeg, kend),
+  // with [lo, hi) its part of the range, in increasing order.
+  template <int KA = 0, class F>
+  __device__ __forceinline__ static void blocks(int kbeg, int kend, const F& f) {
+    if constexpr (KA < C::RX) {
+      const int lo = max(kbeg, C::GX * KA), hi = min(kend, C::GX * (KA + 1));
+      if (lo < hi) f(ic<KA>{}, lo, hi);
+      blocks<KA + 1>(kbeg, kend, f);
+    }
+  }
+
+  // Rank-1 update M += x x^T with x read from LDS (x[i] for every row
+  // index below MMAX).
+  __device__ __forceinline__ void rank1(const double* x) {
+    double xi[C::RX], xj[C::RY];
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a) xi[a] = x[row(a)];
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) xj[b] = x[col(b)];
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b)
+        if (!C::upper(a, b)) v[a][b] = fma(xi[a], xj[b], v[a][b]);
   }
 
   // Negates the entries in columns j < ncols.
@@ -259,20 +298,5 @@ struct RegFront {
         if (col(b) < ncols) v[a][b] = -v[a][b];
   }
 };
-
-// Deterministic sum over the NTH threads of a workgroup (sm: NTH doubles).
-template <int NTH>
-__device__ __forceinline__ double block_sum(double x, double* sm) {
-  sm[threadIdx.x] = x;
-  __syncthreads();
-#pragma unroll
-  for (int s = NTH / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = sm[0];
-  __syncthreads();
-  return r;
-}
 
 }  // namespace mfb
