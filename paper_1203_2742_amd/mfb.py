@@ -144,7 +144,7 @@ class Plan:
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
-        if h:
+        if h and _lib is not None:  # the module may already be torn down at exit
             _lib.mfb_plan_destroy(h)
 
 
@@ -186,7 +186,7 @@ class Factor:
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
-        if h:
+        if h and _lib is not None:  # the module may already be torn down at exit
             _lib.mfb_factor_destroy(h)
 
 
