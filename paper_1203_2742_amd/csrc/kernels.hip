@@ -54,27 +54,39 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // Extend-add of the children's packed update blocks taken from `ua`.
 // Entries landing in N_s columns go to the panel F (leading dimension J);
 // the others (rows and columns in A_s) go to the packed block Us.  One
-// child at a time (fixed order), so every target is written once per pass.
+// child at a time (fixed order), so every target is written once per pass;
+// a child's entries are spread over the whole workgroup (flat index over
+// its A_c x A_c square, lower entries taken), with its relative indices
+// staged in LDS (`sm`: at least 2048 doubles) when they fit.
 template <int NTH = NT>
-__device__ void assemble_children(const DevPlan& P, const SnView& v, const double* ua, double* F,
-                                  double* Us) {
+__device__ __forceinline__ void assemble_children(const DevPlan& P, const SnView& v, const double* ua,
+                                                  double* F, double* Us, double* sm) {
+  int* srl = reinterpret_cast<int*>(sm);
+  constexpr int CAP = 4096;
   for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
     const int c = P.cidx[t];
     const int Ac = P.nrow[c] - P.ncol[c];
     const int32_t* rl = P.rel + P.relbase[c];
     const double* Uc = ua + P.arena[c];
-    for (int y = wave_id(); y < Ac; y += NTH / 64) {
-      const int ry = rl[y];
-      if (ry < v.N) {
-        if (!F) continue;
-        for (int x = y + lane_id(); x < Ac; x += 64)
-          F[rl[x] + (int64_t)ry * v.J] += Uc[pk(x, y, Ac)];
-      } else {
-        if (!Us) continue;
-        for (int x = y + lane_id(); x < Ac; x += 64)
-          Us[pk(rl[x] - v.N, ry - v.N, v.A)] += Uc[pk(x, y, Ac)];
+    const bool st = Ac <= CAP;
+    if (st)
+      for (int i = threadIdx.x; i < Ac; i += NTH) srl[i] = rl[i];
+    __syncthreads();
+    auto pass = [&](const auto& R) {
+      const int64_t m = (int64_t)Ac * Ac;
+#pragma unroll 4
+      for (int64_t e = threadIdx.x; e < m; e += NTH) {
+        const int y = int(e / Ac), x = int(e - (int64_t)y * Ac);
+        if (x < y) continue;
+        const int rx = R(x), ry = R(y);
+        double* q = ry < v.N ? F + (rx + (int64_t)ry * v.J) : Us + pk(rx - v.N, ry - v.N, v.A);
+        *q += Uc[pk(x, y, Ac)];
       }
-    }
+    };
+    if (st)
+      pass([&](int i) { return srl[i]; });
+    else
+      pass([&](int i) { return rl[i]; });
     __syncthreads();
   }
 }
@@ -82,23 +94,44 @@ __device__ void assemble_children(const DevPlan& P, const SnView& v, const doubl
 // V_s = E^T [S_NN S_AN^T; S_AN V_p] E (eq. e-sn-gradient-2): gather the
 // packed A_s x A_s block from the parent's CCS columns of `src` and the
 // parent's packed block in `arena`, into this supernode's packed block.
+// Entries are spread over the whole workgroup (flat index over the A x A
+// square, lower entries taken); the relative indices and the parent's
+// column offsets are staged in LDS (`sm`: at least 4096 doubles) when they
+// fit.  Ends with a barrier.
 template <int NTH = NT>
-__device__ void extract_from_parent(const DevPlan& P, const SnView& v, const double* src,
-                                    double* arena) {
+__device__ __forceinline__ void extract_from_parent(const DevPlan& P, const SnView& v, const double* src,
+                                                    double* arena, double* sm) {
   if (v.A == 0) return;
+  const int A = v.A;
   const int p = P.parent[v.s];
   const int Np = P.ncol[p], Ap = P.nrow[p] - Np;
   const int64_t* colp = P.col + P.colbase[p];
   const int32_t* rl = P.rel + P.relbase[v.s];
   const double* Vp = arena + P.arena[p];
   double* Vo = arena + P.arena[v.s];
-  for (int y = wave_id(); y < v.A; y += NTH / 64) {
-    const int ry = rl[y];
-    for (int x = y + lane_id(); x < v.A; x += 64) {
-      const int rx = rl[x];
-      Vo[pk(x, y, v.A)] = ry < Np ? src[colp[ry] + (rx - ry)] : Vp[pk(rx - Np, ry - Np, Ap)];
-    }
+  int* srl = reinterpret_cast<int*>(sm);
+  int64_t* scp = reinterpret_cast<int64_t*>(sm + 2048);
+  const bool st = A <= 4096 && Np <= 2048;
+  if (st) {
+    for (int i = threadIdx.x; i < A; i += NTH) srl[i] = rl[i];
+    for (int i = threadIdx.x; i < Np; i += NTH) scp[i] = colp[i];
   }
+  __syncthreads();
+  auto pass = [&](const auto& R, const auto& CP) {
+    const int64_t m = (int64_t)A * A;
+#pragma unroll 4
+    for (int64_t e = threadIdx.x; e < m; e += NTH) {
+      const int y = int(e / A), x = int(e - (int64_t)y * A);
+      if (x < y) continue;
+      const int rx = R(x), ry = R(y);
+      Vo[pk(x, y, A)] = ry < Np ? src[CP(ry) + (rx - ry)] : Vp[pk(rx - Np, ry - Np, Ap)];
+    }
+  };
+  if (st)
+    pass([&](int i) { return srl[i]; }, [&](int i) { return scp[i]; });
+  else
+    pass([&](int i) { return rl[i]; }, [&](int i) { return colp[i]; });
+  __syncthreads();
 }
 
 template <int NTH = NT>
@@ -153,7 +186,7 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
   }
   zero_packed(Us, v.A);
   __syncthreads();
-  assemble_children(P, v, U, F, Us);
+  assemble_children(P, v, U, F, Us, sm);
   wg_potrf_panel(F, v.J, v.J, v.N, sm, &fail);
   // Cholesky panel -> R, log det contribution 2 sum log C_kk
   double lg = 0.0;
@@ -193,7 +226,7 @@ __global__ void __launch_bounds__(NT) k_projinv(DevPlan P, const int32_t* list, 
                                                 double* S, double* Vs) {
   __shared__ double sm[SMEM_DOUBLES];
   const SnView v(P, list[blockIdx.x]);
-  extract_from_parent(P, v, S, Vs);
+  extract_from_parent(P, v, S, Vs, sm);
   __syncthreads();
   const double* V = Vs + P.arena[v.s];
   wg_gemm(
@@ -229,7 +262,7 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
   }
   zero_packed(Us, v.A);
   __syncthreads();
-  assemble_children(P, v, ua, F, Us);
+  assemble_children(P, v, ua, F, Us, sm);
   for (int64_t e = threadIdx.x; e < (int64_t)v.N * v.N; e += NT) {
     const int i = int(e % v.N), c = int(e / v.N);
     if (i >= c) K[v.at(i, c)] = F[i + (int64_t)c * v.J];
@@ -268,7 +301,7 @@ __global__ void __launch_bounds__(NT) k_hess_down(DevPlan P, const int32_t* list
   double* W = Z + (int64_t)A * N;
   double* MA = W + (int64_t)N * N;
   double* MN = MA + (int64_t)A * N;
-  extract_from_parent(P, v, t, va);
+  extract_from_parent(P, v, t, va, sm);
   auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
   wg_gemm(
       A, N, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv,
@@ -320,7 +353,7 @@ __global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* lis
   double* MN = Z + (int64_t)A * N;
   double* Dm = MN + (int64_t)N * N;
   double* W = Dm + (int64_t)N * N;
-  extract_from_parent(P, v, t, va);
+  extract_from_parent(P, v, t, va, sm);
   // D = C C^T (full)
   wg_gemm(
       N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
@@ -383,7 +416,7 @@ __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list,
   for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
   zero_packed(Us, A);
   __syncthreads();
-  assemble_children(P, v, ua, G, Us);
+  assemble_children(P, v, ua, G, Us, sm);
   for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
     const int i = int(e % N), c = int(e / N);
     if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + (int64_t)c * v.J];
@@ -425,7 +458,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
     const int rr = int(e % v.J), c = int(e / v.J);
     if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
   }
-  extract_from_parent(P, v, Sin, Vs);
+  extract_from_parent(P, v, Sin, Vs, sm);
   __syncthreads();
   const double* V = Vs + P.arena[v.s];
   double* VI = Vi + P.arena[v.s];
@@ -516,7 +549,7 @@ __global__ void __launch_bounds__(NT) k_product(DevPlan P, const int32_t* list, 
   for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
   zero_packed(Us, A);
   __syncthreads();
-  assemble_children(P, v, U, G, Us);
+  assemble_children(P, v, U, G, Us, sm);
   auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
   wg_gemm(
       N, N, N, C, [&](int k, int j) { return C(j, k); },
