@@ -92,7 +92,8 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iCb = v32(p->colbase), iCol = v64(p->col), iRb = v32(p->relbase), iRel = v32(p->rel),
          iAr = v64(p->arena), iVl = v32(p->vlabel), iUp = v32(p->up_list), iDn = v32(p->down_list),
          iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h),
-         iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list);
+         iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list),
+         iCd = v32(p->cs_down.list);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -125,6 +126,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_factor.d_list = (const int32_t*)at(iCf);
   p->cs_vinv.d_list = (const int32_t*)at(iCv);
   p->cs_completion.d_list = (const int32_t*)at(iCc);
+  p->cs_down.d_list = (const int32_t*)at(iCd);
   return MFB_OK;
 }
 
@@ -348,7 +350,10 @@ static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, 
       if (!rec.e0 || !rec.e1) return MFB_EHIP;
       if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
     }
-    const int64_t slot = g.cls < kRegClasses ? 1 : slot_doubles(op, L);
+    // register kernels use workgroup scratch only for the down sweeps'
+    // intermediate products
+    const bool reg_scratch = op == OP_HDOWN || op == OP_IHDOWN;
+    const int64_t slot = g.cls < kRegClasses && !reg_scratch ? 1 : slot_doubles(op, L);
     launch(f, g.cls, cs.d_list + L.begin, grid, s, std::max<int64_t>(1, slot), ctx);
     if (hipGetLastError() != hipSuccess) return MFB_EHIP;
     if (f->prof) {
@@ -394,10 +399,13 @@ mfb_status_t mfb_logdet(mfb_factor_t f, double* out, void* stream) {
 
 static mfb_status_t ensure_projinv(mfb_factor_s* f, hipStream_t s) {
   if (f->s_valid) return MFB_OK;
-  mfb_status_t st = run_levels(
-      f, MFB_K_PROJINV, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_FACTOR,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void*) {
-        k_projinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
+  mfb_status_t st = run_classes(
+      f, MFB_K_PROJINV, f->plan->cs_down, s, 1, OP_FACTOR,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t, void*) {
+        if (cls < kRegClasses)
+          launch_projinv_reg(cls, g, s, f->plan->dev, list, f->LB, f->S, f->Vs);
+        else
+          k_projinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
       },
       nullptr);
   if (st) return st;
@@ -462,12 +470,16 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
       },
       &ctx);
   if (st) return st;
-  st = run_levels(
-      f, MFB_K_HESS_DOWN, f->plan->down_levels, f->plan->d_down_list, s, k, OP_HDOWN,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+  st = run_classes(
+      f, MFB_K_HESS_DOWN, f->plan->cs_down, s, k, OP_HDOWN,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
-        k_hess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
-                                     x->a.upd, x->a.scr, slot);
+        if (cls < kRegClasses)
+          launch_hess_down_reg(cls, g, s, f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
+                               x->a.upd, x->a.scr, slot);
+        else
+          k_hess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
+                                              x->a.upd, x->a.scr, slot);
       },
       &ctx);
   if (st) return st;
@@ -504,12 +516,16 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   if ((st = ensure_projinv(f, s))) return st;
   if ((st = ensure_vinv(f, s))) return st;
   struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
-  st = run_levels(
-      f, MFB_K_IHESS_DOWN, f->plan->down_levels, f->plan->d_down_list, s, k, OP_IHDOWN,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+  st = run_classes(
+      f, MFB_K_IHESS_DOWN, f->plan->cs_down, s, k, OP_IHDOWN,
+      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
-        k_ihess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
-                                      x->a.Ua, x->a.upd, x->a.scr, slot);
+        if (cls < kRegClasses)
+          launch_ihess_down_reg(cls, g, s, f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
+                                x->a.Ua, x->a.upd, x->a.scr, slot);
+        else
+          k_ihess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
+                                               x->a.Ua, x->a.upd, x->a.scr, slot);
       },
       &ctx);
   if (st) return st;

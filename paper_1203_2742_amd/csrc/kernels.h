@@ -49,5 +49,13 @@ void launch_ihess_up_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, co
                          const double* LB, const double* Kt, double* Y, double* Ua, int64_t upd);
 void launch_product_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const double* R, double* X, double* U);
+void launch_projinv_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                        const double* LB, double* S, double* Vs);
+void launch_hess_down_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                          const double* LB, const double* Vs, const double* Kt, double* T, double* Va,
+                          int64_t upd, double* wsb, int64_t slot);
+void launch_ihess_down_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* R, const double* LB, const double* Vi, const double* T,
+                           double* Kt, double* Va, int64_t upd, double* wsb, int64_t slot);
 
 }  // namespace mfb

@@ -620,7 +620,8 @@ constexpr int KCL = 8;
 template <class C>
 struct PanelIdx {
   int64_t cc[C::RY];
-  __device__ __forceinline__ PanelIdx(const RegFront<C>& M, const SnView& v) {
+  template <bool LO>
+  __device__ __forceinline__ PanelIdx(const RegFront<C, LO>& M, const SnView& v) {
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) cc[b] = v.col[min(M.col(b), v.N - 1)];
   }
@@ -628,15 +629,15 @@ struct PanelIdx {
 
 // Loads the lower panel part (j < N) of the front from the CCS array src;
 // everything else is zero.
-template <class C>
-__device__ __forceinline__ void load_panel(RegFront<C>& M, const SnView& v, const double* src) {
+template <class C, bool LO>
+__device__ __forceinline__ void load_panel(RegFront<C, LO>& M, const SnView& v, const double* src) {
   const PanelIdx<C> ix(M, v);
 #pragma unroll
   for (int a = 0; a < C::RX; ++a)
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) {
       M.v[a][b] = 0.0;
-      if (C::upper(a, b)) continue;
+      if (M.skip(a, b)) continue;
       const int i = M.row(a), j = M.col(b);
       const bool ok = i < v.J && j < v.N && i >= j;
       const double x = src[ok ? ix.cc[b] + (i - j) : 0];
@@ -646,8 +647,8 @@ __device__ __forceinline__ void load_panel(RegFront<C>& M, const SnView& v, cons
 
 // Stores the lower panel entries (j < N) through out(offset, value) and
 // the lower A x A entries through outa(packed index, value).
-template <class C, class OP, class OA>
-__device__ __forceinline__ void store_front(const RegFront<C>& M, const SnView& v, const OP& out,
+template <class C, bool LO, class OP, class OA>
+__device__ __forceinline__ void store_front(const RegFront<C, LO>& M, const SnView& v, const OP& out,
                                             const OA& outa) {
   const PanelIdx<C> ix(M, v);
   const int N = v.N, A = v.A;
@@ -665,8 +666,8 @@ __device__ __forceinline__ void store_front(const RegFront<C>& M, const SnView& 
 // the parent's CCS columns of `src` and its packed block in `arena`
 // (eq. e-sn-gradient-2).  Relative indices increase, so i >= j maps to a
 // lower entry of the parent's front.  No-op for A = 0.
-template <class C>
-__device__ __forceinline__ void gather_parent(RegFront<C>& M, const DevPlan& P, const SnView& v,
+template <class C, bool LO>
+__device__ __forceinline__ void gather_parent(RegFront<C, LO>& M, const DevPlan& P, const SnView& v,
                                               const double* src, const double* arena) {
   if (v.A == 0) return;
   const int N = v.N, J = v.J;
@@ -692,7 +693,7 @@ __device__ __forceinline__ void gather_parent(RegFront<C>& M, const DevPlan& P, 
   for (int a = 0; a < C::RX; ++a)
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) {
-      if (C::upper(a, b)) continue;
+      if (M.skip(a, b)) continue;
       const int i = M.row(a), j = M.col(b);
       const bool in = j >= N && i < J && i >= j;
       const double* q = !in ? src
@@ -706,8 +707,8 @@ __device__ __forceinline__ void gather_parent(RegFront<C>& M, const DevPlan& P, 
 // Front += sg * sum over children c of E_c U_c E_c^T (lower triangle),
 // with the children's packed blocks taken from `ua`; one child at a time
 // through an inverse relative-index map in LDS (`inv`, MMAX ints).
-template <class C>
-__device__ __forceinline__ void gather_children(RegFront<C>& M, const DevPlan& P, const SnView& v,
+template <class C, bool LO>
+__device__ __forceinline__ void gather_children(RegFront<C, LO>& M, const DevPlan& P, const SnView& v,
                                                 const double* ua, int* inv, double sg) {
   for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
     const int c = P.cidx[t];
@@ -735,7 +736,7 @@ __device__ __forceinline__ void gather_children(RegFront<C>& M, const DevPlan& P
 #pragma unroll
         for (int b = 0; b < C::RY; ++b) {
           const int a = a0 + g < C::RX ? a0 + g : C::RX - 1;
-          const bool ok = a0 + g < C::RX && !C::upper(a, b) && xi[a] >= yj[b] && yj[b] >= 0;
+          const bool ok = a0 + g < C::RX && !M.skip(a, b) && xi[a] >= yj[b] && yj[b] >= 0;
           const double x = Uc[ok ? pk(xi[a], yj[b], Ac) : 0];
           tv[g][b] = ok ? sg * x : 0.0;
         }
@@ -743,7 +744,7 @@ __device__ __forceinline__ void gather_children(RegFront<C>& M, const DevPlan& P
       for (int g = 0; g < GR; ++g)
 #pragma unroll
         for (int b = 0; b < C::RY; ++b)
-          if (a0 + g < C::RX && !C::upper(a0 + g, b)) M.v[a0 + g][b] += tv[g][b];
+          if (a0 + g < C::RX && !M.skip(a0 + g, b)) M.v[a0 + g][b] += tv[g][b];
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -761,8 +762,8 @@ __device__ __forceinline__ void stage_columns(int N, int k0, double* Ls, const V
 }
 
 // N congruence steps with the columns of [0; L_AN], staged KCL at a time.
-template <class C>
-__device__ __forceinline__ void congruences(RegFront<C>& M, const SnView& v, const double* LB, double sg,
+template <class C, bool LO>
+__device__ __forceinline__ void congruences(RegFront<C, LO>& M, const SnView& v, const double* LB, double sg,
                                             double* buf, double* Ls) {
   M.template congruences<KCL>(v.N, sg, buf, Ls, [&](int k0, double* ls) {
     stage_columns<C>(v.N, k0, ls, [&](int i, int kk) {
@@ -817,7 +818,7 @@ __global__ void __launch_bounds__(C::NTH) k_vinv_reg(DevPlan P, const int32_t* l
 #pragma unroll
     for (int b = 0; b < C::RY; ++b) {
       M.v[a][b] = 0.0;
-      if (C::upper(a, b)) continue;
+      if (M.skip(a, b)) continue;
       const int i = M.row(a), j = M.col(b);
       const bool ok = i < A && i >= j;
       const double x = V[ok ? pk(i, j, A) : 0];
@@ -999,6 +1000,291 @@ __global__ void __launch_bounds__(C::NTH) k_product_reg(DevPlan P, const int32_t
   store_front(M, v, [&](int64_t o, double x) { X[o] = x; }, [&](int64_t e, double x) { Us[e] = -x; });
 }
 
+// Panel addressing of SnView with the column offsets staged in LDS, so an
+// operand fetch needs no dependent global load.
+struct LdsPanel {
+  const int64_t* colc;
+  int N;
+  __device__ __forceinline__ int64_t at(int r, int c) const { return colc[c] + (r - c); }
+  __device__ __forceinline__ int64_t nn(int i, int j) const { return i >= j ? at(i, j) : at(j, i); }
+  __device__ __forceinline__ int64_t an(int x, int c) const { return colc[c] + (N + x - c); }
+};
+
+// Chunk width of the staged operands of reg_gemm.
+constexpr int KG = 8;
+
+// M(i, j) += sum_{x < K} fa(i, x) fb(x, j) for i < nr, j < nc.  fa and fb
+// return zero outside the wanted block, so the FMAs run over the whole
+// register block: branches around register blocks outside nr x nc cost
+// more than the FMAs they save.  Operands are staged through LDS KG columns of fa and KG rows of
+// fb at a time (As, Bs: 2 MMAX KG doubles each, double-buffered), with the
+// next chunk's global loads in flight during the current chunk's FMAs; one
+// barrier per chunk.  Ends with a barrier.
+template <class C, bool LO, class FA, class FB>
+__device__ __forceinline__ void reg_gemm(RegFront<C, LO>& M, int K, int nr, int nc, double* As, double* Bs,
+                                         const FA& fa, const FB& fb) {
+  constexpr int CH = C::MMAX * KG;
+  constexpr int PER = (CH + C::NTH - 1) / C::NTH;
+  const int nch = (K + KG - 1) / KG;
+  if (nch == 0) return;
+  double ra[PER], rb[PER];
+  auto fetch = [&](int x0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * C::NTH;
+      const int i = e % C::MMAX, x = x0 + e / C::MMAX;
+      const bool ok = e < CH && x < K;
+      ra[q] = ok ? fa(i, x) : 0.0;
+      rb[q] = ok ? fb(x, i) : 0.0;
+    }
+  };
+  auto put = [&](int h) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * C::NTH;
+      if (e < CH) {
+        As[h * CH + e] = ra[q];
+        Bs[h * CH + e] = rb[q];
+      }
+    }
+  };
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) fetch((c + 1) * KG);
+    const double* as = As + (c & 1) * CH;
+    const double* bs = Bs + (c & 1) * CH;
+#pragma unroll 4
+    for (int t = 0; t < KG; ++t) {
+      double ai[C::RX], bj[C::RY];
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a) ai[a] = as[M.row(a) + t * C::MMAX];
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) bj[b] = bs[M.col(b) + t * C::MMAX];
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+        for (int b = 0; b < C::RY; ++b)
+          if (!M.skip(a, b)) M.v[a][b] = fma(ai[a], bj[b], M.v[a][b]);
+      // one k-step's operands live at a time (the other wavefronts of the
+      // SIMD hide the LDS latency)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (c + 1 < nch) put((c + 1) & 1);
+    __syncthreads();
+  }
+}
+
+// Algorithm 7.2 on a register front (root-to-leaf): V_s gathered from the
+// parent (and cached), then S_AN = -V_s L_AN and S_NN = D^-1 - S_AN^T L_AN
+// as two register GEMMs over A.
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_projinv_reg(DevPlan P, const int32_t* list, const double* LB,
+                                                        double* S, double* Vs) {
+  __shared__ double As[2 * C::MMAX * KG], Bs[2 * C::MMAX * KG];
+  __shared__ int64_t colc[C::MMAX];
+  const SnView v(P, list[blockIdx.x]);
+  const int N = v.N, A = v.A, J = v.J;
+  stage_col<C>(v, colc);
+  __syncthreads();
+  const LdsPanel pn{colc, N};
+  const double* V = Vs + P.arena[v.s];
+  RegFront<C> M;
+  M.zero();
+  gather_parent(M, P, v, S, Vs);
+  store_front(M, v, [](int64_t, double) {}, [&](int64_t e, double y) { Vs[P.arena[v.s] + e] = y; });
+  __syncthreads();
+  M.zero();
+  reg_gemm(
+      M, A, J, N, As, Bs,
+      [&](int i, int x) { return i >= N && i < J ? sym_packed(V, i - N, x, A) : 0.0; },
+      [&](int x, int j) { return j < N ? LB[pn.an(x, j)] : 0.0; });
+  store_front(M, v, [&](int64_t o, double y) { S[o] = -y; }, [](int64_t, double) {});
+  __syncthreads();
+  M.zero();
+  reg_gemm(
+      M, A, N, N, As, Bs, [&](int i, int x) { return i < N ? LB[pn.an(x, i)] : 0.0; },
+      [&](int x, int j) { return j < N ? S[pn.an(x, j)] : 0.0; });
+  M.store_lower(
+      N, [](int, int) { return true; },
+      [&](int, int, int i, int j, double y) { S[pn.at(i, j)] = LB[pn.at(i, j)] - y; });
+}
+
+// Hessian steps 2 and 3 (root-to-leaf) on a register front: with
+// Z = [K_NN; K_AN] D^-1, [M_NN; M_AN] = blkdiag(D^-1, V_s) Z, then
+// T_AN = M_AN - V' L and T_NN = M_NN - M_AN^T L - L^T T_AN, where
+// V'_s = T_{A_s A_s} is gathered from the parent (and cached for the
+// children).  Four register GEMMs; Z and M_AN pass through the
+// workgroup's scratch (J N + A N doubles).
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_hess_down_reg(DevPlan P, const int32_t* list, const double* LB,
+                                                          const double* Vs, const double* Kt, double* T,
+                                                          double* Va, int64_t upd, double* wsb,
+                                                          int64_t slot) {
+  __shared__ double As[2 * C::MMAX * KG], Bs[2 * C::MMAX * KG];
+  __shared__ int64_t colc[C::MMAX];
+  const SnView v(P, list[blockIdx.x]);
+  stage_col<C>(v, colc);
+  __syncthreads();
+  const LdsPanel pn{colc, v.N};
+  const int64_t r = blockIdx.y;
+  const double* K = Kt + r * P.nnz;
+  double* t = T + r * P.nnz;
+  double* va = Va + r * upd;
+  const int N = v.N, A = v.A, J = v.J;
+  double* Z = slot_ptr(wsb, slot);      // J x N
+  double* MA = Z + (int64_t)J * N;      // A x N
+  const double* V = Vs + P.arena[v.s];
+  const double* Vp = va + P.arena[v.s];
+  auto Dinv = [&](int i, int j) { return LB[pn.nn(i, j)]; };
+  {
+    RegFront<C> G;
+    G.zero();
+    gather_parent(G, P, v, t, va);
+    store_front(G, v, [](int64_t, double) {}, [&](int64_t e, double y) { va[P.arena[v.s] + e] = y; });
+  }
+  RegFront<C, false> M;  // general J x N products (Z is not symmetric)
+  M.zero();
+  reg_gemm(
+      M, N, J, N, As, Bs,
+      [&](int i, int x) { return i < J ? (i >= N ? K[pn.an(i - N, x)] : K[pn.nn(i, x)]) : 0.0; },
+      [&](int x, int j) { return j < N ? Dinv(x, j) : 0.0; });
+  M.store_all(
+      J, [&](int, int j) { return j < N; }, [&](int, int, int i, int j, double y) { Z[i + (int64_t)j * J] = y; });
+  __syncthreads();
+  M.zero();
+  reg_gemm(
+      M, J, J, N, As, Bs,
+      [&](int i, int x) {
+        if (i < N && x < N) return Dinv(i, x);
+        if (i >= N && i < J && x >= N) return sym_packed(V, i - N, x - N, A);
+        return 0.0;
+      },
+      [&](int x, int j) { return j < N ? Z[x + (int64_t)j * J] : 0.0; });
+  M.store_lower(
+      J, [&](int i, int j) { return j < N && i >= N; },
+      [&](int, int, int i, int j, double y) { MA[(i - N) + (int64_t)j * A] = y; });
+  reg_gemm(
+      M, A, J, N, As, Bs, [&](int i, int x) { return i >= N && i < J ? -sym_packed(Vp, i - N, x, A) : 0.0; },
+      [&](int x, int j) { return j < N ? LB[pn.an(x, j)] : 0.0; });
+  M.store_lower(
+      J, [&](int i, int j) { return j < N && i >= N; },
+      [&](int, int, int i, int j, double y) { t[pn.at(i, j)] = y; });
+  __syncthreads();
+  reg_gemm(
+      M, 2 * A, N, N, As, Bs,
+      [&](int i, int x) {
+        if (i >= N) return 0.0;
+        return x < A ? -MA[x + (int64_t)i * A] : -LB[pn.an(x - A, i)];
+      },
+      [&](int x, int j) {
+        if (j >= N) return 0.0;
+        return x < A ? LB[pn.an(x, j)] : t[pn.an(x - A, j)];
+      });
+  M.store_lower(
+      N, [](int, int) { return true; }, [&](int, int, int i, int j, double y) { t[pn.at(i, j)] = y; });
+}
+
+// Inverse Hessian steps 1 and 2 (root-to-leaf) on a register front:
+// V'_s = T_{A_s A_s} from the parent (cached for the children);
+// M_AN = T_AN + V' L, M_NN = T_NN + L^T M_AN + T_AN^T L; with D = C C^T,
+// [W; Z] = [M_NN; M_AN] D and [K_NN; K_AN] = blkdiag(D, V_s^-1) [W; Z].
+// Five register GEMMs; D, M_NN, M_AN and [W; Z] pass through the
+// workgroup's scratch (3 N^2 + 2 A N doubles).
+template <class C>
+__global__ void __launch_bounds__(C::NTH) k_ihess_down_reg(DevPlan P, const int32_t* list, const double* R,
+                                                           const double* LB, const double* Vi,
+                                                           const double* T, double* Kt, double* Va,
+                                                           int64_t upd, double* wsb, int64_t slot) {
+  __shared__ double As[2 * C::MMAX * KG], Bs[2 * C::MMAX * KG];
+  __shared__ int64_t colc[C::MMAX];
+  const SnView v(P, list[blockIdx.x]);
+  stage_col<C>(v, colc);
+  __syncthreads();
+  const LdsPanel pn{colc, v.N};
+  const int64_t r = blockIdx.y;
+  const double* t = T + r * P.nnz;
+  double* K = Kt + r * P.nnz;
+  double* va = Va + r * upd;
+  const int N = v.N, A = v.A, J = v.J;
+  double* Dm = slot_ptr(wsb, slot);     // N x N
+  double* MN = Dm + (int64_t)N * N;     // N x N
+  double* MA = MN + (int64_t)N * N;     // A x N
+  double* WZ = MA + (int64_t)A * N;     // J x N
+  const double* Vp = va + P.arena[v.s];
+  const double* VI = Vi + P.arena[v.s];
+  {
+    RegFront<C> G;
+    G.zero();
+    gather_parent(G, P, v, t, va);
+    store_front(G, v, [](int64_t, double) {}, [&](int64_t e, double y) { va[P.arena[v.s] + e] = y; });
+  }
+  RegFront<C, false> M;  // general J x N products ([W; Z] is not symmetric)
+  // D = C C^T
+  M.zero();
+  reg_gemm(
+      M, N, N, N, As, Bs, [&](int i, int x) { return i < N && x <= i ? R[pn.at(i, x)] : 0.0; },
+      [&](int x, int j) { return j < N && x <= j ? R[pn.at(j, x)] : 0.0; });
+  M.store_lower(
+      N, [](int, int) { return true; },
+      [&](int, int, int i, int j, double y) {
+        Dm[i + (int64_t)j * N] = y;
+        Dm[j + (int64_t)i * N] = y;
+      });
+  // M_AN = T_AN + V' L
+  M.zero();
+  load_panel(M, v, t);
+  reg_gemm(
+      M, A, J, N, As, Bs, [&](int i, int x) { return i >= N && i < J ? sym_packed(Vp, i - N, x, A) : 0.0; },
+      [&](int x, int j) { return j < N ? LB[pn.an(x, j)] : 0.0; });
+  M.store_lower(
+      J, [&](int i, int j) { return j < N && i >= N; },
+      [&](int, int, int i, int j, double y) { MA[(i - N) + (int64_t)j * A] = y; });
+  __syncthreads();
+  // M_NN = T_NN + L^T M_AN + T_AN^T L (rows < N of the registers still hold T_NN)
+  reg_gemm(
+      M, 2 * A, N, N, As, Bs,
+      [&](int i, int x) {
+        if (i >= N) return 0.0;
+        return x < A ? LB[pn.an(x, i)] : t[pn.an(x - A, i)];
+      },
+      [&](int x, int j) {
+        if (j >= N) return 0.0;
+        return x < A ? MA[x + (int64_t)j * A] : LB[pn.an(x - A, j)];
+      });
+  M.store_lower(
+      N, [](int, int) { return true; },
+      [&](int, int, int i, int j, double y) {
+        MN[i + (int64_t)j * N] = y;
+        MN[j + (int64_t)i * N] = y;
+      });
+  __syncthreads();
+  // [W; Z] = [M_NN; M_AN] D
+  M.zero();
+  reg_gemm(
+      M, N, J, N, As, Bs,
+      [&](int i, int x) {
+        if (i >= J) return 0.0;
+        return i < N ? MN[i + (int64_t)x * N] : MA[(i - N) + (int64_t)x * A];
+      },
+      [&](int x, int j) { return j < N ? Dm[x + (int64_t)j * N] : 0.0; });
+  M.store_all(
+      J, [&](int, int j) { return j < N; }, [&](int, int, int i, int j, double y) { WZ[i + (int64_t)j * J] = y; });
+  __syncthreads();
+  // [K_NN; K_AN] = blkdiag(D, V^-1) [W; Z]
+  M.zero();
+  reg_gemm(
+      M, J, J, N, As, Bs,
+      [&](int i, int x) {
+        if (i < N && x < N) return Dm[i + (int64_t)x * N];
+        if (i >= N && i < J && x >= N) return sym_packed(VI, i - N, x - N, A);
+        return 0.0;
+      },
+      [&](int x, int j) { return j < N ? WZ[x + (int64_t)j * J] : 0.0; });
+  store_front(M, v, [&](int64_t o, double y) { K[o] = y; }, [](int64_t, double) {});
+}
+
 // Workgroup shapes of the register classes (front order <= MMAX).
 using RegC0 = RegCfg<16, 16, 1, 1>;
 using RegC1 = RegCfg<16, 16, 2, 2>;
@@ -1041,6 +1327,24 @@ static void go_product(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* l
   k_product_reg<C><<<g, C::NTH, 0, s>>>(P, list, R, X, U);
 }
 
+template <class C>
+static void go_projinv(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* LB,
+                       double* S, double* Vs) {
+  k_projinv_reg<C><<<g, C::NTH, 0, s>>>(P, list, LB, S, Vs);
+}
+template <class C>
+static void go_hess_down(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* LB,
+                         const double* Vs, const double* Kt, double* T, double* Va, int64_t upd,
+                         double* wsb, int64_t slot) {
+  k_hess_down_reg<C><<<g, C::NTH, 0, s>>>(P, list, LB, Vs, Kt, T, Va, upd, wsb, slot);
+}
+template <class C>
+static void go_ihess_down(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
+                          const double* LB, const double* Vi, const double* T, double* Kt, double* Va,
+                          int64_t upd, double* wsb, int64_t slot) {
+  k_ihess_down_reg<C><<<g, C::NTH, 0, s>>>(P, list, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
+}
+
 #define MFB_REG_SWITCH(fn, ...)                  \
   switch (cls) {                                 \
     case 0: fn<RegC0>(__VA_ARGS__); break;       \
@@ -1074,6 +1378,20 @@ void launch_ihess_up_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const
 void launch_product_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const double* R, double* X, double* U) {
   MFB_REG_SWITCH(go_product, g, s, P, list, R, X, U)
+}
+void launch_projinv_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                        const double* LB, double* S, double* Vs) {
+  MFB_REG_SWITCH(go_projinv, g, s, P, list, LB, S, Vs)
+}
+void launch_hess_down_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                          const double* LB, const double* Vs, const double* Kt, double* T, double* Va,
+                          int64_t upd, double* wsb, int64_t slot) {
+  MFB_REG_SWITCH(go_hess_down, g, s, P, list, LB, Vs, Kt, T, Va, upd, wsb, slot)
+}
+void launch_ihess_down_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* R, const double* LB, const double* Vi, const double* T,
+                           double* Kt, double* Va, int64_t upd, double* wsb, int64_t slot) {
+  MFB_REG_SWITCH(go_ihess_down, g, s, P, list, R, LB, Vi, T, Kt, Va, upd, wsb, slot)
 }
 #undef MFB_REG_SWITCH
 

@@ -47,6 +47,9 @@ struct Level {
 // register kernel of class c; larger fronts run the blocked kernels.
 constexpr int kRegClasses = 5;
 constexpr int kRegMax[kRegClasses] = {16, 32, 64, 128, 192};
+// Largest front order for which the projected inverse and the Hessian
+// down-sweeps use the register kernels on a level of non-root fronts.
+constexpr int kDownRegMaxJ = 32;
 
 // A level of a schedule split by class: one launch per segment, largest
 // class first.  cls == kRegClasses marks the blocked kernels.
@@ -74,8 +77,10 @@ struct mfb_plan_s {
   std::vector<int32_t> up_list, down_list;
   std::vector<mfb::Level> up_levels, down_levels;
   // class-split schedules: factor (leaf-to-root, by J), inverse of V_s
-  // (by A) and completion (root-to-leaf, by J)
-  mfb::ClassSched cs_factor, cs_vinv, cs_completion;
+  // (by A), completion (root-to-leaf, by J) and the other root-to-leaf
+  // sweeps (by J on the levels that take the register kernels, blocked
+  // elsewhere)
+  mfb::ClassSched cs_factor, cs_vinv, cs_completion, cs_down;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;
   std::vector<int64_t> colptr_h;

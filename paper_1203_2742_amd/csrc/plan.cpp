@@ -243,8 +243,21 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   make_levels(d, Dm, p->down_list, p->down_levels);
 
   // Class-split copies of the schedules (see ClassSeg).
+  // The down-sweep register kernels stage the parent block in chunks and
+  // step through A columns one at a time: they beat the blocked kernels
+  // on levels of small fronts (every J <= kDownRegMaxJ) and on levels of
+  // roots (every A = 0), and lose elsewhere, most of all where a level
+  // mixes classes whose launches then run one after another.
+  auto down_reg_level = [&](const std::vector<int32_t>& list, const Level& L) {
+    bool small = true, roots = true;
+    for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
+      small = small && p->J[list[t]] <= kDownRegMaxJ;
+      roots = roots && p->J[list[t]] == p->N[list[t]];
+    }
+    return small || roots;
+  };
   auto make_classes = [&](const std::vector<int32_t>& list, const std::vector<Level>& levels,
-                          bool by_a, ClassSched& cs) {
+                          bool by_a, bool down, ClassSched& cs) {
     cs.list.clear();
     cs.segs.clear();
     cs.list.reserve(ns);
@@ -256,11 +269,12 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     };
     for (int32_t l = 0; l < int32_t(levels.size()); ++l) {
       const Level& L = levels[l];
+      const bool blocked_only = down && !down_reg_level(list, L);
       for (int c = kRegClasses; c >= 0; --c) {
         Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
           const int32_t k = list[t];
-          if (cls_of(k) != c) continue;
+          if ((blocked_only ? kRegClasses : cls_of(k)) != c) continue;
           cs.list.push_back(k);
           S.count++;
           S.maxN = std::max(S.maxN, p->N[k]);
@@ -278,9 +292,10 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
       }
     }
   };
-  make_classes(p->up_list, p->up_levels, false, p->cs_factor);
-  make_classes(p->up_list, p->up_levels, true, p->cs_vinv);
-  make_classes(p->down_list, p->down_levels, false, p->cs_completion);
+  make_classes(p->up_list, p->up_levels, false, false, p->cs_factor);
+  make_classes(p->up_list, p->up_levels, true, false, p->cs_vinv);
+  make_classes(p->down_list, p->down_levels, false, false, p->cs_completion);
+  make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
 
   // Canonical algorithmic flop counts per supernode (LAPACK conventions).
   for (int32_t k = 0; k < ns; ++k) {

@@ -66,8 +66,12 @@ struct ic {
   static constexpr int value = V;
 };
 
-template <class C>
+// LO: keep only the register blocks not wholly above the diagonal (a
+// symmetric front); otherwise every block (a general m x m tile).
+template <class C, bool LO = true>
 struct RegFront {
+  // register block (a, b) is not stored
+  static constexpr bool skip(int a, int b) { return LO && C::upper(a, b); }
   double v[C::RX][C::RY];
   int tx, ty;
   int phase;  // which half of the broadcast buffer the next step uses
@@ -90,9 +94,23 @@ struct RegFront {
     for (int a = 0; a < C::RX; ++a)
 #pragma unroll
       for (int b = 0; b < C::RY; ++b) {
-        if (C::upper(a, b)) continue;
+        if (skip(a, b)) continue;
         const int i = row(a), j = col(b);
         if (C::GX * a < m && C::GY * b < m && i < m && i >= j && pred(i, j)) out(a, b, i, j, v[a][b]);
+      }
+  }
+
+  // out(a, b, i, j, v(i, j)) for every stored entry of the m x m tile with
+  // pred(i, j) true.
+  template <class PR, class OUT>
+  __device__ __forceinline__ void store_all(int m, const PR& pred, const OUT& out) const {
+#pragma unroll
+    for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) {
+        if (skip(a, b)) continue;
+        const int i = row(a), j = col(b);
+        if (C::GX * a < m && C::GY * b < m && i < m && j < m && pred(i, j)) out(a, b, i, j, v[a][b]);
       }
   }
 
@@ -125,11 +143,11 @@ struct RegFront {
     constexpr int KB = (C::GX * KA) / C::GY;
     if (ty == k - C::GY * KB) {
 #pragma unroll
-      for (int a = 0; a < C::RX; ++a) bk[row(a)] = C::upper(a, KB) ? 0.0 : v[a][KB];
+      for (int a = 0; a < C::RX; ++a) bk[row(a)] = skip(a, KB) ? 0.0 : v[a][KB];
     }
     if (tx == k - C::GX * KA) {
 #pragma unroll
-      for (int b = 0; b < C::RY; ++b) bk[C::MMAX + col(b)] = C::upper(KA, b) ? 0.0 : v[KA][b];
+      for (int b = 0; b < C::RY; ++b) bk[C::MMAX + col(b)] = skip(KA, b) ? 0.0 : v[KA][b];
     }
   }
   template <int KA>
@@ -172,7 +190,7 @@ struct RegFront {
     for (int a = 0; a < C::RX; ++a)
 #pragma unroll
       for (int b = 0; b < C::RY; ++b)
-        if (!C::upper(a, b)) v[a][b] = fma(-ci[a], cj[b], v[a][b]);
+        if (!skip(a, b)) v[a][b] = fma(-ci[a], cj[b], v[a][b]);
     // row k: M_kj / M_kk; column k: M_ik / M_kk; pivot: -1 / M_kk
     const bool own_r = tx == k - C::GX * KA, own_c = ty == k - C::GY * KB;
     if (own_r) {
@@ -228,7 +246,7 @@ struct RegFront {
       for (int a = 0; a < C::RX; ++a)
 #pragma unroll
         for (int b = 0; b < C::RY; ++b)
-          if (!C::upper(a, b)) v[a][b] = fma(li[a], wj[b], v[a][b]);
+          if (!skip(a, b)) v[a][b] = fma(li[a], wj[b], v[a][b]);
     }
     {
       double wi[C::RX], lj[C::RY];
@@ -240,7 +258,7 @@ struct RegFront {
       for (int a = 0; a < C::RX; ++a)
 #pragma unroll
         for (int b = 0; b < C::RY; ++b)
-          if (!C::upper(a, b)) v[a][b] = fma(wi[a], lj[b], v[a][b]);
+          if (!skip(a, b)) v[a][b] = fma(wi[a], lj[b], v[a][b]);
     }
   }
 
@@ -286,7 +304,7 @@ struct RegFront {
     for (int a = 0; a < C::RX; ++a)
 #pragma unroll
       for (int b = 0; b < C::RY; ++b)
-        if (!C::upper(a, b)) v[a][b] = fma(xi[a], xj[b], v[a][b]);
+        if (!skip(a, b)) v[a][b] = fma(xi[a], xj[b], v[a][b]);
   }
 
   // Negates the entries in columns j < ncols.
