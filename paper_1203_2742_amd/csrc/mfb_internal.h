@@ -42,17 +42,19 @@ struct Level {
   double p, u, n3, n2a, na2, a3;
 };
 
-// Register-front classes: a front whose order (J for the factor and the
-// completion, A for the inverse of V_s) is at most kRegMax[c] runs the
-// register kernel of class c; larger fronts run the blocked kernels.
+// Register-front classes: the register kernel of class c takes fronts of
+// order (J for the factor and the completion, A for the inverse of V_s)
+// at most kRegMax[c]; larger fronts run the blocked kernels.
 constexpr int kRegClasses = 5;
 constexpr int kRegMax[kRegClasses] = {16, 32, 64, 128, 192};
-// Largest front order for which the projected inverse and the Hessian
+// Largest front order for which the Hessian and inverse-Hessian
 // down-sweeps use the register kernels on a level of non-root fronts.
-constexpr int kDownRegMaxJ = 32;
+constexpr int kDownRegMaxJ = 64;
 
-// A level of a schedule split by class: one launch per segment, largest
-// class first.  cls == kRegClasses marks the blocked kernels.
+// A level of a schedule split by class: at most two launches, the blocked
+// kernels (cls == kRegClasses) on the fronts no register class holds,
+// then one register class, the largest any other front of the level
+// needs.
 struct ClassSeg {
   Level lv;  // begin/count index the schedule's own list
   int32_t level, cls;
@@ -77,9 +79,9 @@ struct mfb_plan_s {
   std::vector<int32_t> up_list, down_list;
   std::vector<mfb::Level> up_levels, down_levels;
   // class-split schedules: factor (leaf-to-root, by J), inverse of V_s
-  // (by A), completion (root-to-leaf, by J) and the other root-to-leaf
-  // sweeps (by J on the levels that take the register kernels, blocked
-  // elsewhere)
+  // (by A), completion and projected inverse (root-to-leaf, by J) and the
+  // Hessian down-sweeps (by J on the levels that take the register
+  // kernels, blocked elsewhere)
   mfb::ClassSched cs_factor, cs_vinv, cs_completion, cs_down;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;

@@ -242,12 +242,18 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   make_levels(h, H, p->up_list, p->up_levels);
   make_levels(d, Dm, p->down_list, p->down_levels);
 
-  // Class-split copies of the schedules (see ClassSeg).
-  // The down-sweep register kernels stage the parent block in chunks and
-  // step through A columns one at a time: they beat the blocked kernels
-  // on levels of small fronts (every J <= kDownRegMaxJ) and on levels of
-  // roots (every A = 0), and lose elsewhere, most of all where a level
-  // mixes classes whose launches then run one after another.
+  // Class-split copies of the schedules (see ClassSeg).  A register
+  // kernel of class c takes any front of order <= kRegMax[c], so all the
+  // register fronts of a level go into one launch at the largest class
+  // they need: small fronts then run beside the large ones instead of in
+  // launches of their own after them.
+  //
+  // The Hessian down-sweep register kernels stage their operands in chunks
+  // and step through A (or J) columns one at a time, with most of the
+  // register front idle when N is small: they beat the blocked kernels on
+  // levels of small fronts (every J <= kDownRegMaxJ) and on levels of roots
+  // (every A = 0), and lose elsewhere.  The projected inverse runs its
+  // register kernel wherever a front fits.
   auto down_reg_level = [&](const std::vector<int32_t>& list, const Level& L) {
     bool small = true, roots = true;
     for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
@@ -261,7 +267,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     cs.list.clear();
     cs.segs.clear();
     cs.list.reserve(ns);
-    auto cls_of = [&](int32_t k) {
+    auto fit_class = [&](int32_t k) {  // smallest class that holds the front, or kRegClasses
       const int32_t m = by_a ? p->J[k] - p->N[k] : p->J[k];
       int c = 0;
       while (c < kRegClasses && m > kRegMax[c]) ++c;
@@ -269,12 +275,18 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     };
     for (int32_t l = 0; l < int32_t(levels.size()); ++l) {
       const Level& L = levels[l];
-      const bool blocked_only = down && !down_reg_level(list, L);
-      for (int c = kRegClasses; c >= 0; --c) {
+      const bool reg_ok = !down || down_reg_level(list, L);
+      int lvcls = 0;
+      for (int32_t t = L.begin; t < L.begin + L.count; ++t)
+        if (fit_class(list[t]) < kRegClasses) lvcls = std::max(lvcls, fit_class(list[t]));
+      auto class_of = [&](int32_t k) {
+        return reg_ok && fit_class(k) < kRegClasses ? lvcls : kRegClasses;
+      };
+      for (int c : {kRegClasses, lvcls}) {
         Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
           const int32_t k = list[t];
-          if ((blocked_only ? kRegClasses : cls_of(k)) != c) continue;
+          if (class_of(k) != c) continue;
           cs.list.push_back(k);
           S.count++;
           S.maxN = std::max(S.maxN, p->N[k]);
