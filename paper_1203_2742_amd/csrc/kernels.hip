@@ -66,21 +66,45 @@ __device__ __forceinline__ void assemble_children(const DevPlan& P, const SnView
   for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
     const int c = P.cidx[t];
     const int Ac = P.nrow[c] - P.ncol[c];
+    if (Ac == 0) continue;  // (a child always has ancestors)
     const int32_t* rl = P.rel + P.relbase[c];
     const double* Uc = ua + P.arena[c];
     const bool st = Ac <= CAP;
     if (st)
       for (int i = threadIdx.x; i < Ac; i += NTH) srl[i] = rl[i];
     __syncthreads();
+    // flat walk of the Ac x Ac square as in extract_from_parent, BATCH
+    // entries per round; the targets of one child are distinct
     auto pass = [&](const auto& R) {
-      const int64_t m = (int64_t)Ac * Ac;
-#pragma unroll 4
-      for (int64_t e = threadIdx.x; e < m; e += NTH) {
-        const int y = int(e / Ac), x = int(e - (int64_t)y * Ac);
-        if (x < y) continue;
-        const int rx = R(x), ry = R(y);
-        double* q = ry < v.N ? F + (rx + (int64_t)ry * v.J) : Us + pk(rx - v.N, ry - v.N, v.A);
-        *q += Uc[pk(x, y, Ac)];
+      constexpr int BATCH = 4;
+      const int dy = NTH / Ac, dx = NTH - dy * Ac;
+      int y = int(threadIdx.x) / Ac, x = int(threadIdx.x) - y * Ac;
+      while (y < Ac) {
+        double* q[BATCH];
+        const double* u_[BATCH];
+        bool ok[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+          ok[u] = y < Ac && x >= y;
+          const int rx = ok[u] ? R(x) : 0, ry = ok[u] ? R(y) : 0;
+          q[u] = !ok[u] ? F : ry < v.N ? F + (rx + (int64_t)ry * v.J) : Us + pk(rx - v.N, ry - v.N, v.A);
+          u_[u] = ok[u] ? Uc + pk(x, y, Ac) : Uc;
+          x += dx;
+          y += dy;
+          if (x >= Ac) {
+            x -= Ac;
+            ++y;
+          }
+        }
+        double a[BATCH], b[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+          a[u] = *q[u];
+          b[u] = *u_[u];
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+          if (ok[u]) *q[u] = a[u] + b[u];
       }
     };
     if (st)
@@ -117,14 +141,35 @@ __device__ __forceinline__ void extract_from_parent(const DevPlan& P, const SnVi
     for (int i = threadIdx.x; i < Np; i += NTH) scp[i] = colp[i];
   }
   __syncthreads();
+  // Each thread walks the flat index tid, tid + NTH, ... of the A x A
+  // square as (x, y) = (e mod A, e div A), stepped without divisions, and
+  // issues BATCH loads (masked entries load a valid dummy) before storing.
   auto pass = [&](const auto& R, const auto& CP) {
-    const int64_t m = (int64_t)A * A;
-#pragma unroll 4
-    for (int64_t e = threadIdx.x; e < m; e += NTH) {
-      const int y = int(e / A), x = int(e - (int64_t)y * A);
-      if (x < y) continue;
-      const int rx = R(x), ry = R(y);
-      Vo[pk(x, y, A)] = ry < Np ? src[CP(ry) + (rx - ry)] : Vp[pk(rx - Np, ry - Np, Ap)];
+    constexpr int BATCH = 8;
+    const int dy = NTH / A, dx = NTH - dy * A;
+    int y = int(threadIdx.x) / A, x = int(threadIdx.x) - y * A;
+    while (y < A) {
+      const double* q[BATCH];
+      int64_t o[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const bool ok = y < A && x >= y;
+        const int rx = ok ? R(x) : 0, ry = ok ? R(y) : 0;
+        q[u] = !ok ? src : ry < Np ? src + CP(ry) + (rx - ry) : Vp + pk(rx - Np, ry - Np, Ap);
+        o[u] = ok ? pk(x, y, A) : -1;
+        x += dx;
+        y += dy;
+        if (x >= A) {
+          x -= A;
+          ++y;
+        }
+      }
+      double val[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) val[u] = *q[u];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u)
+        if (o[u] >= 0) Vo[o[u]] = val[u];
     }
   };
   if (st)
@@ -142,6 +187,22 @@ __device__ __forceinline__ void zero_packed(double* U, int A) {
 
 __device__ __forceinline__ double* slot_ptr(double* wsb, int64_t slot) {
   return wsb + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * slot;
+}
+
+// Runs body(v) with the supernode's column offsets copied to LDS (`colc`)
+// when N <= kColCache, so every CCS address is formed without a dependent
+// global load, else with the offsets read from global memory.
+constexpr int kColCache = 512;
+template <class BODY>
+__device__ __forceinline__ void with_staged_cols(SnView v, int64_t* colc, const BODY& body) {
+  if (v.N <= kColCache) {
+    for (int i = threadIdx.x; i < v.N; i += NT) colc[i] = v.col[i];
+    __syncthreads();
+    v.col = colc;
+    body(v);
+  } else {
+    body(v);
+  }
 }
 
 // Inverse of a symmetric positive definite A x A block given by the functor
@@ -174,49 +235,51 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
                                                double* R, double* LB, double* U, double* part,
                                                DevStatus* st, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
   __shared__ int fail;
-  const SnView v(P, list[blockIdx.x]);
-  double* F = slot_ptr(wsb, slot);
-  double* Ci = F + (int64_t)v.J * v.N;
-  double* Us = U + P.arena[v.s];
-  if (threadIdx.x == 0) fail = -1;
-  for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
-    const int r = int(e % v.J), c = int(e / v.J);
-    F[e] = r >= c ? x[v.at(r, c)] : 0.0;
-  }
-  zero_packed(Us, v.A);
-  __syncthreads();
-  assemble_children(P, v, U, F, Us, sm);
-  wg_potrf_panel(F, v.J, v.J, v.N, sm, &fail);
-  // Cholesky panel -> R, log det contribution 2 sum log C_kk
-  double lg = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
-    const int r = int(e % v.J), c = int(e / v.J);
-    if (r >= c) R[v.at(r, c)] = F[e];
-  }
-  for (int c = threadIdx.x; c < v.N; c += NT) lg += 2.0 * log(F[c + (int64_t)c * v.J]);
-  lg = wg_sum(lg, sm);
-  if (threadIdx.x == 0) {
-    part[v.s] = lg;
-    if (fail >= 0) report(st, MFB_ENOTPD, v.vl[fail]);
-  }
-  // U_s = F22 - B B^T
-  wg_gemm(
-      v.A, v.A, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
-      [&](int k, int j) { return F[(v.N + j) + (int64_t)k * v.J]; },
-      [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
-  // C^-1
-  wg_trtri([&](int i, int j) { return F[i + (int64_t)j * v.J]; }, v.N, Ci, v.N, sm);
-  // L_AN = B C^-1
-  wg_gemm(
-      v.A, v.N, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
-      [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
-      [&](int i, int j, double acc) { LB[v.an(i, j)] = acc; }, false, sm);
-  // D^-1 = C^-T C^-1 (lower)
-  wg_gemm(
-      v.N, v.N, v.N, [&](int i, int k) { return Ci[k + (int64_t)i * v.N]; },
-      [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
-      [&](int i, int j, double acc) { LB[v.at(i, j)] = acc; }, true, sm);
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    double* F = slot_ptr(wsb, slot);
+    double* Ci = F + (int64_t)v.J * v.N;
+    double* Us = U + P.arena[v.s];
+    if (threadIdx.x == 0) fail = -1;
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+      const int r = int(e % v.J), c = int(e / v.J);
+      F[e] = r >= c ? x[v.at(r, c)] : 0.0;
+    }
+    zero_packed(Us, v.A);
+    __syncthreads();
+    assemble_children(P, v, U, F, Us, sm);
+    wg_potrf_panel(F, v.J, v.J, v.N, sm, &fail);
+    // Cholesky panel -> R, log det contribution 2 sum log C_kk
+    double lg = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+      const int r = int(e % v.J), c = int(e / v.J);
+      if (r >= c) R[v.at(r, c)] = F[e];
+    }
+    for (int c = threadIdx.x; c < v.N; c += NT) lg += 2.0 * log(F[c + (int64_t)c * v.J]);
+    lg = wg_sum(lg, sm);
+    if (threadIdx.x == 0) {
+      part[v.s] = lg;
+      if (fail >= 0) report(st, MFB_ENOTPD, v.vl[fail]);
+    }
+    // U_s = F22 - B B^T
+    wg_gemm(
+        v.A, v.A, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
+        [&](int k, int j) { return F[(v.N + j) + (int64_t)k * v.J]; },
+        [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
+    // C^-1
+    wg_trtri([&](int i, int j) { return F[i + (int64_t)j * v.J]; }, v.N, Ci, v.N, sm);
+    // L_AN = B C^-1
+    wg_gemm(
+        v.A, v.N, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
+        [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
+        [&](int i, int j, double acc) { LB[v.an(i, j)] = acc; }, false, sm);
+    // D^-1 = C^-T C^-1 (lower)
+    wg_gemm(
+        v.N, v.N, v.N, [&](int i, int k) { return Ci[k + (int64_t)i * v.N]; },
+        [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
+        [&](int i, int j, double acc) { LB[v.at(i, j)] = acc; }, true, sm);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -225,19 +288,21 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
 __global__ void __launch_bounds__(NT) k_projinv(DevPlan P, const int32_t* list, const double* LB,
                                                 double* S, double* Vs) {
   __shared__ double sm[SMEM_DOUBLES];
-  const SnView v(P, list[blockIdx.x]);
-  extract_from_parent(P, v, S, Vs, sm);
-  __syncthreads();
-  const double* V = Vs + P.arena[v.s];
-  wg_gemm(
-      v.A, v.N, v.A, [&](int i, int k) { return sym_packed(V, i, k, v.A); },
-      [&](int k, int j) { return LB[v.an(k, j)]; },
-      [&](int i, int j, double acc) { S[v.an(i, j)] = -acc; }, false, sm);
-  __syncthreads();
-  wg_gemm(
-      v.N, v.N, v.A, [&](int i, int k) { return S[v.an(k, i)]; },
-      [&](int k, int j) { return LB[v.an(k, j)]; },
-      [&](int i, int j, double acc) { S[v.at(i, j)] = LB[v.at(i, j)] - acc; }, true, sm);
+  __shared__ int64_t colc[kColCache];
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    extract_from_parent(P, v, S, Vs, sm);
+    __syncthreads();
+    const double* V = Vs + P.arena[v.s];
+    wg_gemm(
+        v.A, v.N, v.A, [&](int i, int k) { return sym_packed(V, i, k, v.A); },
+        [&](int k, int j) { return LB[v.an(k, j)]; },
+        [&](int i, int j, double acc) { S[v.an(i, j)] = -acc; }, false, sm);
+    __syncthreads();
+    wg_gemm(
+        v.N, v.N, v.A, [&](int i, int k) { return S[v.an(k, i)]; },
+        [&](int k, int j) { return LB[v.an(k, j)]; },
+        [&](int i, int j, double acc) { S[v.at(i, j)] = LB[v.at(i, j)] - acc; }, true, sm);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -249,36 +314,38 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
                                                 const double* Y, double* Kt, double* Ua,
                                                 int64_t upd, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
-  const SnView v(P, list[blockIdx.x]);
-  const int64_t r = blockIdx.y;
-  const double* y = Y + r * P.nnz;
-  double* K = Kt + r * P.nnz;
-  double* ua = Ua + r * upd;
-  double* Us = ua + P.arena[v.s];
-  double* F = slot_ptr(wsb, slot);
-  for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
-    const int rr = int(e % v.J), c = int(e / v.J);
-    F[e] = rr >= c ? y[v.at(rr, c)] : 0.0;
-  }
-  zero_packed(Us, v.A);
-  __syncthreads();
-  assemble_children(P, v, ua, F, Us, sm);
-  for (int64_t e = threadIdx.x; e < (int64_t)v.N * v.N; e += NT) {
-    const int i = int(e % v.N), c = int(e / v.N);
-    if (i >= c) K[v.at(i, c)] = F[i + (int64_t)c * v.J];
-  }
-  auto F11 = [&](int i, int j) { return i >= j ? F[i + (int64_t)j * v.J] : F[j + (int64_t)i * v.J]; };
-  wg_gemm(
-      v.A, v.N, v.N, [&](int i, int k) { return LB[v.an(i, k)]; }, [&](int k, int j) { return F11(k, j); },
-      [&](int i, int j, double acc) { K[v.an(i, j)] = F[(v.N + i) + (int64_t)j * v.J] - acc; }, false,
-      sm);
-  __syncthreads();
-  const int N = v.N;
-  wg_gemm(
-      v.A, v.A, 2 * N,
-      [&](int i, int k) { return k < N ? LB[v.an(i, k)] : K[v.an(i, k - N)]; },
-      [&](int k, int j) { return k < N ? F[(N + j) + (int64_t)k * v.J] : LB[v.an(j, k - N)]; },
-      [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
+  __shared__ int64_t colc[kColCache];
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int64_t r = blockIdx.y;
+    const double* y = Y + r * P.nnz;
+    double* K = Kt + r * P.nnz;
+    double* ua = Ua + r * upd;
+    double* Us = ua + P.arena[v.s];
+    double* F = slot_ptr(wsb, slot);
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+      const int rr = int(e % v.J), c = int(e / v.J);
+      F[e] = rr >= c ? y[v.at(rr, c)] : 0.0;
+    }
+    zero_packed(Us, v.A);
+    __syncthreads();
+    assemble_children(P, v, ua, F, Us, sm);
+    for (int64_t e = threadIdx.x; e < (int64_t)v.N * v.N; e += NT) {
+      const int i = int(e % v.N), c = int(e / v.N);
+      if (i >= c) K[v.at(i, c)] = F[i + (int64_t)c * v.J];
+    }
+    auto F11 = [&](int i, int j) { return i >= j ? F[i + (int64_t)j * v.J] : F[j + (int64_t)i * v.J]; };
+    wg_gemm(
+        v.A, v.N, v.N, [&](int i, int k) { return LB[v.an(i, k)]; }, [&](int k, int j) { return F11(k, j); },
+        [&](int i, int j, double acc) { K[v.an(i, j)] = F[(v.N + i) + (int64_t)j * v.J] - acc; }, false,
+        sm);
+    __syncthreads();
+    const int N = v.N;
+    wg_gemm(
+        v.A, v.A, 2 * N,
+        [&](int i, int k) { return k < N ? LB[v.an(i, k)] : K[v.an(i, k - N)]; },
+        [&](int k, int j) { return k < N ? F[(N + j) + (int64_t)k * v.J] : LB[v.an(j, k - N)]; },
+        [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
+  });
 }
 
 // Hessian steps 2 and 3 (root-to-leaf), block form of Algorithm 5.1 with
@@ -291,45 +358,47 @@ __global__ void __launch_bounds__(NT) k_hess_down(DevPlan P, const int32_t* list
                                                   double* Va, int64_t upd, double* wsb,
                                                   int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
-  const SnView v(P, list[blockIdx.x]);
-  const int64_t r = blockIdx.y;
-  const double* K = Kt + r * P.nnz;
-  double* t = T + r * P.nnz;
-  double* va = Va + r * upd;
-  const int N = v.N, A = v.A;
-  double* Z = slot_ptr(wsb, slot);
-  double* W = Z + (int64_t)A * N;
-  double* MA = W + (int64_t)N * N;
-  double* MN = MA + (int64_t)A * N;
-  extract_from_parent(P, v, t, va, sm);
-  auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
-  wg_gemm(
-      A, N, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv,
-      [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
-  wg_gemm(
-      N, N, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv,
-      [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
-  __syncthreads();
-  const double* V = Vs + P.arena[v.s];
-  wg_gemm(
-      A, N, A, [&](int i, int k) { return sym_packed(V, i, k, A); },
-      [&](int k, int j) { return Z[k + (int64_t)j * A]; },
-      [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false, sm);
-  wg_gemm(
-      N, N, N, Dinv, [&](int k, int j) { return W[k + (int64_t)j * N]; },
-      [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true, sm);
-  __syncthreads();
-  const double* Vp = va + P.arena[v.s];
-  wg_gemm(
-      A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
-      [&](int k, int j) { return LB[v.an(k, j)]; },
-      [&](int i, int j, double acc) { t[v.an(i, j)] = MA[i + (int64_t)j * A] - acc; }, false, sm);
-  __syncthreads();
-  wg_gemm(
-      N, N, 2 * A,
-      [&](int i, int k) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
-      [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
-      [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; }, true, sm);
+  __shared__ int64_t colc[kColCache];
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int64_t r = blockIdx.y;
+    const double* K = Kt + r * P.nnz;
+    double* t = T + r * P.nnz;
+    double* va = Va + r * upd;
+    const int N = v.N, A = v.A;
+    double* Z = slot_ptr(wsb, slot);
+    double* W = Z + (int64_t)A * N;
+    double* MA = W + (int64_t)N * N;
+    double* MN = MA + (int64_t)A * N;
+    extract_from_parent(P, v, t, va, sm);
+    auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
+    wg_gemm(
+        A, N, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv,
+        [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
+    wg_gemm(
+        N, N, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv,
+        [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
+    __syncthreads();
+    const double* V = Vs + P.arena[v.s];
+    wg_gemm(
+        A, N, A, [&](int i, int k) { return sym_packed(V, i, k, A); },
+        [&](int k, int j) { return Z[k + (int64_t)j * A]; },
+        [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false, sm);
+    wg_gemm(
+        N, N, N, Dinv, [&](int k, int j) { return W[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true, sm);
+    __syncthreads();
+    const double* Vp = va + P.arena[v.s];
+    wg_gemm(
+        A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
+        [&](int k, int j) { return LB[v.an(k, j)]; },
+        [&](int i, int j, double acc) { t[v.an(i, j)] = MA[i + (int64_t)j * A] - acc; }, false, sm);
+    __syncthreads();
+    wg_gemm(
+        N, N, 2 * A,
+        [&](int i, int k) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
+        [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
+        [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; }, true, sm);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -342,59 +411,61 @@ __global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* lis
                                                    const double* T, double* Kt, double* Va,
                                                    int64_t upd, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
-  const SnView v(P, list[blockIdx.x]);
-  const int64_t r = blockIdx.y;
-  const double* t = T + r * P.nnz;
-  double* K = Kt + r * P.nnz;
-  double* va = Va + r * upd;
-  const int N = v.N, A = v.A;
-  double* MA = slot_ptr(wsb, slot);
-  double* Z = MA + (int64_t)A * N;
-  double* MN = Z + (int64_t)A * N;
-  double* Dm = MN + (int64_t)N * N;
-  double* W = Dm + (int64_t)N * N;
-  extract_from_parent(P, v, t, va, sm);
-  // D = C C^T (full)
-  wg_gemm(
-      N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
-      [&](int k, int j) { return k <= j ? R[v.at(j, k)] : 0.0; },
-      [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false, sm);
-  __syncthreads();
-  const double* Vp = va + P.arena[v.s];
-  wg_gemm(
-      A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
-      [&](int k, int j) { return LB[v.an(k, j)]; },
-      [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false, sm);
-  __syncthreads();
-  wg_gemm(
-      N, N, 2 * A,
-      [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
-      [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
-      [&](int i, int j, double acc) {
-        const double m = t[v.at(i, j)] + acc;
-        MN[i + (int64_t)j * N] = m;
-        MN[j + (int64_t)i * N] = m;
-      },
-      true, sm);
-  __syncthreads();
-  wg_gemm(
-      N, N, N, [&](int i, int k) { return MN[i + (int64_t)k * N]; },
-      [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
-      [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
-  wg_gemm(
-      A, N, N, [&](int i, int k) { return MA[i + (int64_t)k * A]; },
-      [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
-      [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
-  __syncthreads();
-  wg_gemm(
-      N, N, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
-      [&](int k, int j) { return W[k + (int64_t)j * N]; },
-      [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
-  const double* VI = Vi + P.arena[v.s];
-  wg_gemm(
-      A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
-      [&](int k, int j) { return Z[k + (int64_t)j * A]; },
-      [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);
+  __shared__ int64_t colc[kColCache];
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int64_t r = blockIdx.y;
+    const double* t = T + r * P.nnz;
+    double* K = Kt + r * P.nnz;
+    double* va = Va + r * upd;
+    const int N = v.N, A = v.A;
+    double* MA = slot_ptr(wsb, slot);
+    double* Z = MA + (int64_t)A * N;
+    double* MN = Z + (int64_t)A * N;
+    double* Dm = MN + (int64_t)N * N;
+    double* W = Dm + (int64_t)N * N;
+    extract_from_parent(P, v, t, va, sm);
+    // D = C C^T (full)
+    wg_gemm(
+        N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
+        [&](int k, int j) { return k <= j ? R[v.at(j, k)] : 0.0; },
+        [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false, sm);
+    __syncthreads();
+    const double* Vp = va + P.arena[v.s];
+    wg_gemm(
+        A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
+        [&](int k, int j) { return LB[v.an(k, j)]; },
+        [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false, sm);
+    __syncthreads();
+    wg_gemm(
+        N, N, 2 * A,
+        [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
+        [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
+        [&](int i, int j, double acc) {
+          const double m = t[v.at(i, j)] + acc;
+          MN[i + (int64_t)j * N] = m;
+          MN[j + (int64_t)i * N] = m;
+        },
+        true, sm);
+    __syncthreads();
+    wg_gemm(
+        N, N, N, [&](int i, int k) { return MN[i + (int64_t)k * N]; },
+        [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
+    wg_gemm(
+        A, N, N, [&](int i, int k) { return MA[i + (int64_t)k * A]; },
+        [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
+    __syncthreads();
+    wg_gemm(
+        N, N, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
+        [&](int k, int j) { return W[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
+    const double* VI = Vi + P.arena[v.s];
+    wg_gemm(
+        A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
+        [&](int k, int j) { return Z[k + (int64_t)j * A]; },
+        [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);
+  });
 }
 
 // Inverse Hessian step 3 (leaf-to-root), block form of Algorithm 5.2:
@@ -404,38 +475,40 @@ __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list,
                                                  const double* Kt, double* Y, double* Ua,
                                                  int64_t upd, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
-  const SnView v(P, list[blockIdx.x]);
-  const int64_t r = blockIdx.y;
-  const double* K = Kt + r * P.nnz;
-  double* y = Y + r * P.nnz;
-  double* ua = Ua + r * upd;
-  double* Us = ua + P.arena[v.s];
-  const int N = v.N, A = v.A;
-  double* G = slot_ptr(wsb, slot);
-  double* Q = G + (int64_t)v.J * N;
-  for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
-  zero_packed(Us, A);
-  __syncthreads();
-  assemble_children(P, v, ua, G, Us, sm);
-  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
-    const int i = int(e % N), c = int(e / N);
-    if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + (int64_t)c * v.J];
-  }
-  wg_gemm(
-      A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
-      [&](int k, int j) { return K[v.nn(k, j)]; },
-      [&](int i, int j, double acc) {
-        const double q = acc + K[v.an(i, j)];
-        Q[i + (int64_t)j * A] = q;
-        y[v.an(i, j)] = q - G[(N + i) + (int64_t)j * v.J];
-      },
-      false, sm);
-  __syncthreads();
-  wg_gemm(
-      A, A, 2 * N,
-      [&](int i, int k) { return k < N ? Q[i + (int64_t)k * A] : LB[v.an(i, k - N)]; },
-      [&](int k, int j) { return k < N ? LB[v.an(j, k)] : K[v.an(j, k - N)]; },
-      [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
+  __shared__ int64_t colc[kColCache];
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int64_t r = blockIdx.y;
+    const double* K = Kt + r * P.nnz;
+    double* y = Y + r * P.nnz;
+    double* ua = Ua + r * upd;
+    double* Us = ua + P.arena[v.s];
+    const int N = v.N, A = v.A;
+    double* G = slot_ptr(wsb, slot);
+    double* Q = G + (int64_t)v.J * N;
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
+    zero_packed(Us, A);
+    __syncthreads();
+    assemble_children(P, v, ua, G, Us, sm);
+    for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+      const int i = int(e % N), c = int(e / N);
+      if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + (int64_t)c * v.J];
+    }
+    wg_gemm(
+        A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
+        [&](int k, int j) { return K[v.nn(k, j)]; },
+        [&](int i, int j, double acc) {
+          const double q = acc + K[v.an(i, j)];
+          Q[i + (int64_t)j * A] = q;
+          y[v.an(i, j)] = q - G[(N + i) + (int64_t)j * v.J];
+        },
+        false, sm);
+    __syncthreads();
+    wg_gemm(
+        A, A, 2 * N,
+        [&](int i, int k) { return k < N ? Q[i + (int64_t)k * A] : LB[v.an(i, k - N)]; },
+        [&](int k, int j) { return k < N ? LB[v.an(j, k)] : K[v.an(j, k - N)]; },
+        [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -448,74 +521,76 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
                                                    double* Vi, double* part, DevStatus* st,
                                                    double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
   __shared__ int fail;
-  const SnView v(P, list[blockIdx.x]);
-  const int N = v.N, A = v.A;
-  double* ws = slot_ptr(wsb, slot);
-  if (threadIdx.x == 0) fail = -1;
-  // cache S (own columns) and gather V_s from the input
-  for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) {
-    const int rr = int(e % v.J), c = int(e / v.J);
-    if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
-  }
-  extract_from_parent(P, v, Sin, Vs, sm);
-  __syncthreads();
-  const double* V = Vs + P.arena[v.s];
-  double* VI = Vi + P.arena[v.s];
-  if (A > 0) {
-    wg_spd_inverse(
-        A, [&](int i, int j) { return sym_packed(V, i, j, A); },
-        [&](int i, int j, double acc) { VI[pk(i, j, A)] = acc; }, ws, sm, &fail);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
-  wg_gemm(
-      A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
-      [&](int k, int j) { return Sin[v.an(k, j)]; },
-      [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false, sm);
-  __syncthreads();
-  double* Dd = ws;
-  double* Gi = ws + (int64_t)N * N;
-  double* Dm = Gi + (int64_t)N * N;
-  wg_gemm(
-      N, N, A, [&](int i, int k) { return Sin[v.an(k, i)]; },
-      [&](int k, int j) { return LB[v.an(k, j)]; },
-      [&](int i, int j, double acc) {
-        const double d = Sin[v.at(i, j)] + acc;
-        LB[v.at(i, j)] = d;
-        Dd[i + (int64_t)j * N] = d;
-      },
-      true, sm);
-  __syncthreads();
-  if (threadIdx.x == 0) fail = -1;
-  __syncthreads();
-  // D = (D^-1)^-1 via its Cholesky factor, then C = chol(D)
-  wg_potrf_panel(Dd, N, N, N, sm, &fail);
-  if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
-  wg_trtri([&](int i, int j) { return Dd[i + (int64_t)j * N]; }, N, Gi, N, sm);
-  wg_gemm(
-      N, N, N, [&](int i, int k) { return Gi[k + (int64_t)i * N]; },
-      [&](int k, int j) { return Gi[k + (int64_t)j * N]; },
-      [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, true, sm);
-  __syncthreads();
-  if (threadIdx.x == 0) fail = -1;
-  __syncthreads();
-  wg_potrf_panel(Dm, N, N, N, sm, &fail);
-  double lg = 0.0;
-  for (int c = threadIdx.x; c < N; c += NT) lg += 2.0 * log(Dm[c + (int64_t)c * N]);
-  lg = wg_sum(lg, sm);
-  if (threadIdx.x == 0) {
-    part[v.s] = lg;
-    if (fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
-    const int i = int(e % N), c = int(e / N);
-    if (i >= c) R[v.at(i, c)] = Dm[e];
-  }
-  wg_gemm(
-      A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
-      [&](int k, int j) { return k >= j ? Dm[k + (int64_t)j * N] : 0.0; },
-      [&](int i, int j, double acc) { R[v.an(i, j)] = acc; }, false, sm);
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N, A = v.A;
+    double* ws = slot_ptr(wsb, slot);
+    if (threadIdx.x == 0) fail = -1;
+    // cache S (own columns) and gather V_s from the input
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) {
+      const int rr = int(e % v.J), c = int(e / v.J);
+      if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
+    }
+    extract_from_parent(P, v, Sin, Vs, sm);
+    __syncthreads();
+    const double* V = Vs + P.arena[v.s];
+    double* VI = Vi + P.arena[v.s];
+    if (A > 0) {
+      wg_spd_inverse(
+          A, [&](int i, int j) { return sym_packed(V, i, j, A); },
+          [&](int i, int j, double acc) { VI[pk(i, j, A)] = acc; }, ws, sm, &fail);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
+    wg_gemm(
+        A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
+        [&](int k, int j) { return Sin[v.an(k, j)]; },
+        [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false, sm);
+    __syncthreads();
+    double* Dd = ws;
+    double* Gi = ws + (int64_t)N * N;
+    double* Dm = Gi + (int64_t)N * N;
+    wg_gemm(
+        N, N, A, [&](int i, int k) { return Sin[v.an(k, i)]; },
+        [&](int k, int j) { return LB[v.an(k, j)]; },
+        [&](int i, int j, double acc) {
+          const double d = Sin[v.at(i, j)] + acc;
+          LB[v.at(i, j)] = d;
+          Dd[i + (int64_t)j * N] = d;
+        },
+        true, sm);
+    __syncthreads();
+    if (threadIdx.x == 0) fail = -1;
+    __syncthreads();
+    // D = (D^-1)^-1 via its Cholesky factor, then C = chol(D)
+    wg_potrf_panel(Dd, N, N, N, sm, &fail);
+    if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
+    wg_trtri([&](int i, int j) { return Dd[i + (int64_t)j * N]; }, N, Gi, N, sm);
+    wg_gemm(
+        N, N, N, [&](int i, int k) { return Gi[k + (int64_t)i * N]; },
+        [&](int k, int j) { return Gi[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, true, sm);
+    __syncthreads();
+    if (threadIdx.x == 0) fail = -1;
+    __syncthreads();
+    wg_potrf_panel(Dm, N, N, N, sm, &fail);
+    double lg = 0.0;
+    for (int c = threadIdx.x; c < N; c += NT) lg += 2.0 * log(Dm[c + (int64_t)c * N]);
+    lg = wg_sum(lg, sm);
+    if (threadIdx.x == 0) {
+      part[v.s] = lg;
+      if (fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
+    }
+    for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+      const int i = int(e % N), c = int(e / N);
+      if (i >= c) R[v.at(i, c)] = Dm[e];
+    }
+    wg_gemm(
+        A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
+        [&](int k, int j) { return k >= j ? Dm[k + (int64_t)j * N] : 0.0; },
+        [&](int i, int j, double acc) { R[v.an(i, j)] = acc; }, false, sm);
+  });
 }
 
 // (S_{A_s A_s})^-1 for every supernode of a level (needs the cached V_s).
@@ -523,17 +598,19 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
 __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, const double* Vs,
                                              double* Vi, DevStatus* st, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
   __shared__ int fail;
-  const SnView v(P, list[blockIdx.x]);
-  if (v.A == 0) return;
-  if (threadIdx.x == 0) fail = -1;
-  __syncthreads();
-  const double* V = Vs + P.arena[v.s];
-  double* VI = Vi + P.arena[v.s];
-  wg_spd_inverse(
-      v.A, [&](int i, int j) { return sym_packed(V, i, j, v.A); },
-      [&](int i, int j, double acc) { VI[pk(i, j, v.A)] = acc; }, slot_ptr(wsb, slot), sm, &fail);
-  if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOTPD, v.vl[0]);
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    if (v.A == 0) return;
+    if (threadIdx.x == 0) fail = -1;
+    __syncthreads();
+    const double* V = Vs + P.arena[v.s];
+    double* VI = Vi + P.arena[v.s];
+    wg_spd_inverse(
+        v.A, [&](int i, int j) { return sym_packed(V, i, j, v.A); },
+        [&](int i, int j, double acc) { VI[pk(i, j, v.A)] = acc; }, slot_ptr(wsb, slot), sm, &fail);
+    if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOTPD, v.vl[0]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -542,26 +619,28 @@ __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, con
 __global__ void __launch_bounds__(NT) k_product(DevPlan P, const int32_t* list, const double* R,
                                                 double* X, double* U, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
-  const SnView v(P, list[blockIdx.x]);
-  const int N = v.N, A = v.A;
-  double* G = slot_ptr(wsb, slot);
-  double* Us = U + P.arena[v.s];
-  for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
-  zero_packed(Us, A);
-  __syncthreads();
-  assemble_children(P, v, U, G, Us, sm);
-  auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
-  wg_gemm(
-      N, N, N, C, [&](int k, int j) { return C(j, k); },
-      [&](int i, int j, double acc) { X[v.at(i, j)] = acc - G[i + (int64_t)j * v.J]; }, true, sm);
-  wg_gemm(
-      A, N, N, [&](int i, int k) { return R[v.an(i, k)]; }, [&](int k, int j) { return C(j, k); },
-      [&](int i, int j, double acc) { X[v.an(i, j)] = acc - G[(N + i) + (int64_t)j * v.J]; }, false,
-      sm);
-  wg_gemm(
-      A, A, N, [&](int i, int k) { return R[v.an(i, k)]; },
-      [&](int k, int j) { return R[v.an(j, k)]; },
-      [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
+  __shared__ int64_t colc[kColCache];
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N, A = v.A;
+    double* G = slot_ptr(wsb, slot);
+    double* Us = U + P.arena[v.s];
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
+    zero_packed(Us, A);
+    __syncthreads();
+    assemble_children(P, v, U, G, Us, sm);
+    auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
+    wg_gemm(
+        N, N, N, C, [&](int k, int j) { return C(j, k); },
+        [&](int i, int j, double acc) { X[v.at(i, j)] = acc - G[i + (int64_t)j * v.J]; }, true, sm);
+    wg_gemm(
+        A, N, N, [&](int i, int k) { return R[v.an(i, k)]; }, [&](int k, int j) { return C(j, k); },
+        [&](int i, int j, double acc) { X[v.an(i, j)] = acc - G[(N + i) + (int64_t)j * v.J]; }, false,
+        sm);
+    wg_gemm(
+        A, A, N, [&](int i, int k) { return R[v.an(i, k)]; },
+        [&](int k, int j) { return R[v.an(j, k)]; },
+        [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
+  });
 }
 
 // ---------------------------------------------------------------------------
