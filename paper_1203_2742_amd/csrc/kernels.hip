@@ -220,7 +220,7 @@ __device__ void wg_spd_inverse(int A, const VF& Vf, const OUT& out, double* ws, 
   __syncthreads();
   wg_potrf_panel(G, A, A, A, sm, fail);
   wg_trtri([&](int i, int j) { return G[i + (int64_t)j * A]; }, A, Gi, A, sm);
-  wg_gemm(
+  wg_gemm<true, true>(
       A, A, A, [&](int i, int k) { return Gi[k + (int64_t)i * A]; },
       [&](int k, int j) { return Gi[k + (int64_t)j * A]; }, out, true, sm);
   __syncthreads();
@@ -270,12 +270,12 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
     // C^-1
     wg_trtri([&](int i, int j) { return F[i + (int64_t)j * v.J]; }, v.N, Ci, v.N, sm);
     // L_AN = B C^-1
-    wg_gemm(
+    wg_gemm<false, true>(
         v.A, v.N, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
         [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
         [&](int i, int j, double acc) { LB[v.an(i, j)] = acc; }, false, sm);
     // D^-1 = C^-T C^-1 (lower)
-    wg_gemm(
+    wg_gemm<true, true>(
         v.N, v.N, v.N, [&](int i, int k) { return Ci[k + (int64_t)i * v.N]; },
         [&](int k, int j) { return Ci[k + (int64_t)j * v.N]; },
         [&](int i, int j, double acc) { LB[v.at(i, j)] = acc; }, true, sm);
@@ -293,12 +293,12 @@ __global__ void __launch_bounds__(NT) k_projinv(DevPlan P, const int32_t* list, 
     extract_from_parent(P, v, S, Vs, sm);
     __syncthreads();
     const double* V = Vs + P.arena[v.s];
-    wg_gemm(
+    wg_gemm<false, true>(
         v.A, v.N, v.A, [&](int i, int k) { return sym_packed(V, i, k, v.A); },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { S[v.an(i, j)] = -acc; }, false, sm);
     __syncthreads();
-    wg_gemm(
+    wg_gemm<true, true>(
         v.N, v.N, v.A, [&](int i, int k) { return S[v.an(k, i)]; },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { S[v.at(i, j)] = LB[v.at(i, j)] - acc; }, true, sm);
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
       if (i >= c) K[v.at(i, c)] = F[i + (int64_t)c * v.J];
     }
     auto F11 = [&](int i, int j) { return i >= j ? F[i + (int64_t)j * v.J] : F[j + (int64_t)i * v.J]; };
-    wg_gemm(
+    wg_gemm<false, true>(
         v.A, v.N, v.N, [&](int i, int k) { return LB[v.an(i, k)]; }, [&](int k, int j) { return F11(k, j); },
         [&](int i, int j, double acc) { K[v.an(i, j)] = F[(v.N + i) + (int64_t)j * v.J] - acc; }, false,
         sm);
@@ -371,29 +371,29 @@ __global__ void __launch_bounds__(NT) k_hess_down(DevPlan P, const int32_t* list
     double* MN = MA + (int64_t)A * N;
     extract_from_parent(P, v, t, va, sm);
     auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv,
         [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
-    wg_gemm(
+    wg_gemm<false, true>(
         N, N, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv,
         [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
     __syncthreads();
     const double* V = Vs + P.arena[v.s];
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(V, i, k, A); },
         [&](int k, int j) { return Z[k + (int64_t)j * A]; },
         [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false, sm);
-    wg_gemm(
+    wg_gemm<false, true>(
         N, N, N, Dinv, [&](int k, int j) { return W[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true, sm);
     __syncthreads();
     const double* Vp = va + P.arena[v.s];
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { t[v.an(i, j)] = MA[i + (int64_t)j * A] - acc; }, false, sm);
     __syncthreads();
-    wg_gemm(
+    wg_gemm<true, true>(
         N, N, 2 * A,
         [&](int i, int k) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
         [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
@@ -431,12 +431,12 @@ __global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* lis
         [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false, sm);
     __syncthreads();
     const double* Vp = va + P.arena[v.s];
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false, sm);
     __syncthreads();
-    wg_gemm(
+    wg_gemm<true, true>(
         N, N, 2 * A,
         [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
         [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
@@ -447,21 +447,21 @@ __global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* lis
         },
         true, sm);
     __syncthreads();
-    wg_gemm(
+    wg_gemm<false, true>(
         N, N, N, [&](int i, int k) { return MN[i + (int64_t)k * N]; },
         [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, N, [&](int i, int k) { return MA[i + (int64_t)k * A]; },
         [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
     __syncthreads();
-    wg_gemm(
+    wg_gemm<false, true>(
         N, N, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
         [&](int k, int j) { return W[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
     const double* VI = Vi + P.arena[v.s];
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
         [&](int k, int j) { return Z[k + (int64_t)j * A]; },
         [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);
@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list,
       const int i = int(e % N), c = int(e / N);
       if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + (int64_t)c * v.J];
     }
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
         [&](int k, int j) { return K[v.nn(k, j)]; },
         [&](int i, int j, double acc) {
@@ -543,7 +543,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
     }
     __syncthreads();
     if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
         [&](int k, int j) { return Sin[v.an(k, j)]; },
         [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false, sm);
@@ -551,7 +551,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
     double* Dd = ws;
     double* Gi = ws + (int64_t)N * N;
     double* Dm = Gi + (int64_t)N * N;
-    wg_gemm(
+    wg_gemm<true, true>(
         N, N, A, [&](int i, int k) { return Sin[v.an(k, i)]; },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) {
@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
     wg_potrf_panel(Dd, N, N, N, sm, &fail);
     if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
     wg_trtri([&](int i, int j) { return Dd[i + (int64_t)j * N]; }, N, Gi, N, sm);
-    wg_gemm(
+    wg_gemm<true, true>(
         N, N, N, [&](int i, int k) { return Gi[k + (int64_t)i * N]; },
         [&](int k, int j) { return Gi[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, true, sm);
@@ -586,7 +586,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
       const int i = int(e % N), c = int(e / N);
       if (i >= c) R[v.at(i, c)] = Dm[e];
     }
-    wg_gemm(
+    wg_gemm<false, true>(
         A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
         [&](int k, int j) { return k >= j ? Dm[k + (int64_t)j * N] : 0.0; },
         [&](int i, int j, double acc) { R[v.an(i, j)] = acc; }, false, sm);

@@ -17,7 +17,8 @@ constexpr int KC = 16;   // k-chunk staged through LDS
 constexpr int NB = 32;   // diagonal block of the blocked factorizations
 constexpr int LDD = NB + 1;
 // LDS doubles used by the routines in this file
-constexpr int SMEM_GEMM = 2 * KC * TM;
+constexpr int LDS_TM = TM + 1;  // padded row of a staged k-chunk (no bank conflicts on k-major stores)
+constexpr int SMEM_GEMM = 2 * KC * LDS_TM;
 constexpr int SMEM_DIAG = 2 * NB * LDD;  // diagonal block and its inverse
 constexpr int SMEM_DOUBLES = SMEM_GEMM + SMEM_DIAG + 8;
 
@@ -40,14 +41,28 @@ __device__ __forceinline__ void wave_sync() {
 // (only i >= j when `lower`).  64 x 64 output tiles, each thread owning a
 // 4 x 4 register block; k-chunks of 16 are staged through LDS with the
 // next chunk's global loads in flight during the current chunk's FMAs.
-// Every (i, j) is produced by exactly one thread, in a fixed k order.
-template <class FA, class FB, class EPI>
+// AK (BK) makes consecutive lanes fetch consecutive k of a(i, .) (of
+// b(., j)), for operands stored contiguously along k; otherwise they fetch
+// consecutive i (j).  Every (i, j) is produced by exactly one thread, in a
+// fixed k order.
+template <bool AK = false, bool BK = false, class FA, class FB, class EPI>
 __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const FB& fb,
                                         const EPI& epi, bool lower, double* sm) {
   double* As = sm;
-  double* Bs = sm + KC * TM;
+  double* Bs = sm + KC * LDS_TM;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   constexpr int PER = KC * TM / NT;
+  // (row or column, k) of the q-th staged element of a thread
+  auto slot_a = [&](int q, int& i, int& k) {
+    const int e = tid + q * NT;
+    i = AK ? e / KC : e & (TM - 1);
+    k = AK ? e & (KC - 1) : e / TM;
+  };
+  auto slot_b = [&](int q, int& j, int& k) {
+    const int e = tid + q * NT;
+    j = BK ? e / KC : e & (TM - 1);
+    k = BK ? e & (KC - 1) : e / TM;
+  };
   for (int i0 = 0; i0 < M; i0 += TM) {
     for (int j0 = 0; j0 < N; j0 += TM) {
       if (lower && j0 > i0 + TM - 1) continue;
@@ -60,33 +75,42 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const
       auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-          const int e = tid + q * NT;
-          const int i = e & (TM - 1), k = e / TM;
-          const int gk = k0 + k;
-          ra[q] = (i0 + i < M && gk < K) ? fa(i0 + i, gk) : 0.0;
-          rb[q] = (j0 + i < N && gk < K) ? fb(gk, j0 + i) : 0.0;
+          int i, ka, j, kb;
+          slot_a(q, i, ka);
+          slot_b(q, j, kb);
+          ra[q] = (i0 + i < M && k0 + ka < K) ? fa(i0 + i, k0 + ka) : 0.0;
+          rb[q] = (j0 + j < N && k0 + kb < K) ? fb(k0 + kb, j0 + j) : 0.0;
         }
       };
       if (K > 0) fetch(0);
       for (int k0 = 0; k0 < K; k0 += KC) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-          As[tid + q * NT] = ra[q];
-          Bs[tid + q * NT] = rb[q];
+          int i, ka, j, kb;
+          slot_a(q, i, ka);
+          slot_b(q, j, kb);
+          As[ka * LDS_TM + i] = ra[q];
+          Bs[kb * LDS_TM + j] = rb[q];
         }
         __syncthreads();
         if (k0 + KC < K) fetch(k0 + KC);
+        // software-pipelined: step k + 1's LDS reads are in flight during
+        // step k's FMAs (one wave per SIMD cannot hide LDS latency otherwise)
+        double av[2][4], bv[2][4];
+        auto lds_step = [&](int k, double* a_, double* b_) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a) a_[a] = As[k * LDS_TM + tx + 16 * a];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) b_[b] = Bs[k * LDS_TM + ty + 16 * b];
+        };
+        lds_step(0, av[0], bv[0]);
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-          double av[4], bv[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) av[a] = As[k * TM + tx + 16 * a];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) bv[b] = Bs[k * TM + ty + 16 * b];
+          if (k + 1 < KC) lds_step(k + 1, av[(k + 1) & 1], bv[(k + 1) & 1]);
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[k & 1][a], bv[k & 1][b], acc[a][b]);
         }
         __syncthreads();
       }
@@ -224,7 +248,7 @@ __device__ __forceinline__ void wg_trtri(const CF& C, int N, double* Ci, int ldi
     const int r0 = jb + nb, m = N - r0;
     if (m > 0) {
       // T = inv(C22) C21 into the output block, then right-multiply by -inv(C11)
-      wg_gemm(
+      wg_gemm<false, true>(
           m, nb, m,
           [&](int i, int k) { return k <= i ? Ci[(r0 + i) + (int64_t)(r0 + k) * ldi] : 0.0; },
           [&](int k, int j) { return C(r0 + k, jb + j); },
