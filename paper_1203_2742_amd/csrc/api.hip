@@ -478,7 +478,7 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
           launch_hess_down_reg(cls, g, s, f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                x->a.upd, x->a.scr, slot);
         else
-          k_hess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
+          k_hess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                               x->a.upd, x->a.scr, slot);
       },
       &ctx);
@@ -524,7 +524,7 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
           launch_ihess_down_reg(cls, g, s, f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
                                 x->a.Ua, x->a.upd, x->a.scr, slot);
         else
-          k_ihess_down<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
+          k_ihess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
                                                x->a.Ua, x->a.upd, x->a.scr, slot);
       },
       &ctx);

@@ -5,7 +5,10 @@
 #include "mfb_internal.h"
 
 namespace mfb {
-constexpr int NT_LAUNCH = 256;  // threads per workgroup of every sweep kernel
+constexpr int NT_LAUNCH = 256;  // threads per workgroup of the blocked sweep kernels
+// except the Hessian down-sweeps: two teams of NT_LAUNCH splitting every
+// product's k range
+constexpr int NT_DOWN = 512;
 
 struct DevStatus {
   int code;

@@ -193,10 +193,10 @@ __device__ __forceinline__ double* slot_ptr(double* wsb, int64_t slot) {
 // when N <= kColCache, so every CCS address is formed without a dependent
 // global load, else with the offsets read from global memory.
 constexpr int kColCache = 512;
-template <class BODY>
+template <int NTH = NT, class BODY>
 __device__ __forceinline__ void with_staged_cols(SnView v, int64_t* colc, const BODY& body) {
   if (v.N <= kColCache) {
-    for (int i = threadIdx.x; i < v.N; i += NT) colc[i] = v.col[i];
+    for (int i = threadIdx.x; i < v.N; i += NTH) colc[i] = v.col[i];
     __syncthreads();
     v.col = colc;
     body(v);
@@ -353,13 +353,13 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
 // M_NN = D^-1 K_NN D^-1, M_AN = V_s K_AN D^-1, T_AN = M_AN - V' L,
 // T_NN = M_NN - L^T T_AN - M_AN^T L, V'_c = E^T [T_NN T_AN^T; T_AN V'] E.
 // Scratch: 2AN + 2N^2.
-__global__ void __launch_bounds__(NT) k_hess_down(DevPlan P, const int32_t* list, const double* LB,
+__global__ void __launch_bounds__(NT_DOWN) k_hess_down(DevPlan P, const int32_t* list, const double* LB,
                                                   const double* Vs, const double* Kt, double* T,
                                                   double* Va, int64_t upd, double* wsb,
                                                   int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
-  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+  with_staged_cols<NT_DOWN>(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
     const int64_t r = blockIdx.y;
     const double* K = Kt + r * P.nnz;
     double* t = T + r * P.nnz;
@@ -369,31 +369,31 @@ __global__ void __launch_bounds__(NT) k_hess_down(DevPlan P, const int32_t* list
     double* W = Z + (int64_t)A * N;
     double* MA = W + (int64_t)N * N;
     double* MN = MA + (int64_t)A * N;
-    extract_from_parent(P, v, t, va, sm);
+    extract_from_parent<NT_DOWN>(P, v, t, va, sm);
     auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         A, N, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv,
         [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         N, N, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv,
         [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
     __syncthreads();
     const double* V = Vs + P.arena[v.s];
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(V, i, k, A); },
         [&](int k, int j) { return Z[k + (int64_t)j * A]; },
         [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false, sm);
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         N, N, N, Dinv, [&](int k, int j) { return W[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true, sm);
     __syncthreads();
     const double* Vp = va + P.arena[v.s];
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { t[v.an(i, j)] = MA[i + (int64_t)j * A] - acc; }, false, sm);
     __syncthreads();
-    wg_gemm<true, true>(
+    wg_gemm_split<NT_DOWN, true, true>(
         N, N, 2 * A,
         [&](int i, int k) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
         [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
@@ -406,13 +406,13 @@ __global__ void __launch_bounds__(NT) k_hess_down(DevPlan P, const int32_t* list
 // V'_s = T_{A_s A_s} from the parent; M_AN = T_AN + V' L;
 // M_NN = T_NN + L^T M_AN + T_AN^T L; K_NN = D M_NN D; K_AN = V_s^-1 M_AN D,
 // with D = C C^T.  Scratch: 2AN + 3N^2.
-__global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* list, const double* R,
+__global__ void __launch_bounds__(NT_DOWN) k_ihess_down(DevPlan P, const int32_t* list, const double* R,
                                                    const double* LB, const double* Vi,
                                                    const double* T, double* Kt, double* Va,
                                                    int64_t upd, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
-  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+  with_staged_cols<NT_DOWN>(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
     const int64_t r = blockIdx.y;
     const double* t = T + r * P.nnz;
     double* K = Kt + r * P.nnz;
@@ -423,20 +423,20 @@ __global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* lis
     double* MN = Z + (int64_t)A * N;
     double* Dm = MN + (int64_t)N * N;
     double* W = Dm + (int64_t)N * N;
-    extract_from_parent(P, v, t, va, sm);
+    extract_from_parent<NT_DOWN>(P, v, t, va, sm);
     // D = C C^T (full)
-    wg_gemm(
+    wg_gemm_split<NT_DOWN>(
         N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
         [&](int k, int j) { return k <= j ? R[v.at(j, k)] : 0.0; },
         [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false, sm);
     __syncthreads();
     const double* Vp = va + P.arena[v.s];
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false, sm);
     __syncthreads();
-    wg_gemm<true, true>(
+    wg_gemm_split<NT_DOWN, true, true>(
         N, N, 2 * A,
         [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
         [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
@@ -447,21 +447,21 @@ __global__ void __launch_bounds__(NT) k_ihess_down(DevPlan P, const int32_t* lis
         },
         true, sm);
     __syncthreads();
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         N, N, N, [&](int i, int k) { return MN[i + (int64_t)k * N]; },
         [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         A, N, N, [&](int i, int k) { return MA[i + (int64_t)k * A]; },
         [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
     __syncthreads();
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         N, N, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
         [&](int k, int j) { return W[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
     const double* VI = Vi + P.arena[v.s];
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
         [&](int k, int j) { return Z[k + (int64_t)j * A]; },
         [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);

@@ -125,6 +125,116 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const
   }
 }
 
+// wg_gemm for a workgroup of NTH = TEAMS * NT threads: the teams of NT
+// threads share every output tile and take its k-chunks in turn (team t
+// the chunks t, t + TEAMS, ...), each staging its own chunk in LDS; the
+// partial tiles are then added through LDS in team order, so the result
+// does not depend on timing.  At most one tile per front is in flight, so
+// this doubles the waves per SIMD on fronts too few to fill the chip.
+// Staging: TEAMS * 2 * KC * LDS_TM doubles at sm; the reduction reuses
+// them ((TEAMS - 1) * TM * TM doubles).
+template <int NTH, bool AK = false, bool BK = false, class FA, class FB, class EPI>
+__device__ __forceinline__ void wg_gemm_split(int M, int N, int K, const FA& fa, const FB& fb,
+                                              const EPI& epi, bool lower, double* sm) {
+  constexpr int TEAMS = NTH / NT;
+  static_assert(TEAMS * NT == NTH && TEAMS >= 1, "whole teams");
+  static_assert((TEAMS - 1) * TM * TM <= TEAMS * 2 * KC * LDS_TM || TEAMS == 1, "reduction fits the staging");
+  const int team = threadIdx.x / NT, tid = threadIdx.x - team * NT, tx = tid & 15, ty = tid >> 4;
+  double* As = sm + team * 2 * KC * LDS_TM;
+  double* Bs = As + KC * LDS_TM;
+  constexpr int PER = KC * TM / NT;
+  auto slot_a = [&](int q, int& i, int& k) {
+    const int e = tid + q * NT;
+    i = AK ? e / KC : e & (TM - 1);
+    k = AK ? e & (KC - 1) : e / TM;
+  };
+  auto slot_b = [&](int q, int& j, int& k) {
+    const int e = tid + q * NT;
+    j = BK ? e / KC : e & (TM - 1);
+    k = BK ? e & (KC - 1) : e / TM;
+  };
+  const int rounds = ((K + KC - 1) / KC + TEAMS - 1) / TEAMS;
+  for (int i0 = 0; i0 < M; i0 += TM) {
+    for (int j0 = 0; j0 < N; j0 += TM) {
+      if (lower && j0 > i0 + TM - 1) continue;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      double ra[PER], rb[PER];
+      auto fetch = [&](int r) {
+        const int k0 = (r * TEAMS + team) * KC;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          int i, ka, j, kb;
+          slot_a(q, i, ka);
+          slot_b(q, j, kb);
+          ra[q] = (i0 + i < M && k0 + ka < K) ? fa(i0 + i, k0 + ka) : 0.0;
+          rb[q] = (j0 + j < N && k0 + kb < K) ? fb(k0 + kb, j0 + j) : 0.0;
+        }
+      };
+      if (rounds > 0) fetch(0);
+      for (int r = 0; r < rounds; ++r) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          int i, ka, j, kb;
+          slot_a(q, i, ka);
+          slot_b(q, j, kb);
+          As[ka * LDS_TM + i] = ra[q];
+          Bs[kb * LDS_TM + j] = rb[q];
+        }
+        __syncthreads();
+        if (r + 1 < rounds) fetch(r + 1);
+        double av[2][4], bv[2][4];
+        auto lds_step = [&](int k, double* a_, double* b_) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a) a_[a] = As[k * LDS_TM + tx + 16 * a];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) b_[b] = Bs[k * LDS_TM + ty + 16 * b];
+        };
+        lds_step(0, av[0], bv[0]);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          if (k + 1 < KC) lds_step(k + 1, av[(k + 1) & 1], bv[(k + 1) & 1]);
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[k & 1][a], bv[k & 1][b], acc[a][b]);
+        }
+        __syncthreads();
+      }
+      if (TEAMS > 1) {
+        // teams 1.. park their partial tiles, team 0 adds them in order
+        if (team > 0) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) sm[(team - 1) * TM * TM + (a * 4 + b) * NT + tid] = acc[a][b];
+        }
+        __syncthreads();
+        if (team == 0) {
+          for (int t = 1; t < TEAMS; ++t)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) acc[a][b] += sm[(t - 1) * TM * TM + (a * 4 + b) * NT + tid];
+        }
+      }
+      if (team == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
+            if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, acc[a][b]);
+          }
+      }
+      if (TEAMS > 1) __syncthreads();  // the next tile's staging overwrites the partials
+    }
+  }
+}
+
 // Unblocked Cholesky of an nb x nb (nb <= NB) lower block in LDS (leading
 // dimension LDD) by wavefront 0.  A non-positive pivot is replaced by one
 // (so later arithmetic stays finite) and its index is returned through
