@@ -840,17 +840,26 @@ __device__ __forceinline__ void stage_columns(int N, int k0, double* Ls, const V
   }
 }
 
-// N congruence steps with the columns of [0; L_AN], staged KCL at a time.
+// The N congruences with the columns of [0; L_AN] (staged KCL at a time):
+// fronts of order above 64 take them in blocks of KCL (two barriers per
+// block; the extra small solve per block does not pay on smaller fronts),
+// smaller ones one step at a time.  `lds` holds kCongLds<C> doubles.
+template <class C>
+constexpr int kCongLds = C::MMAX > 64 ? 6 * KCL * C::MMAX : (4 + KCL) * C::MMAX;
 template <class C, bool LO>
 __device__ __forceinline__ void congruences(RegFront<C, LO>& M, const SnView& v, const double* LB, double sg,
-                                            double* buf, double* Ls) {
-  M.template congruences<KCL>(v.N, sg, buf, Ls, [&](int k0, double* ls) {
+                                            double* lds) {
+  auto stage = [&](int k0, double* ls) {
     stage_columns<C>(v.N, k0, ls, [&](int i, int kk) {
       const bool ok = i >= v.N && i < v.J;
       const double x = LB[ok ? v.at(i, kk) : 0];
       return ok ? x : 0.0;
     });
-  });
+  };
+  if constexpr (C::MMAX > 64)
+    M.template congruences_blocked<KCL>(v.N, sg, lds, stage);
+  else
+    M.template congruences<KCL>(v.N, sg, lds, lds + 4 * C::MMAX, stage);
 }
 
 // Column k of the Cholesky factor from the broadcast column of the sweep
@@ -1010,9 +1019,8 @@ template <class C>
 __global__ void __launch_bounds__(C::NTH) k_hess_up_reg(DevPlan P, const int32_t* list, const double* LB,
                                                         const double* Y, double* Kt, double* Ua,
                                                         int64_t upd) {
-  __shared__ double buf[4 * C::MMAX];
+  __shared__ double lds[kCongLds<C>];
   __shared__ int inv[C::MMAX];
-  __shared__ double Ls[C::MMAX * KCL];
   const SnView v(P, list[blockIdx.x]);
   const int64_t r = blockIdx.y;
   const double* y = Y + r * P.nnz;
@@ -1022,7 +1030,7 @@ __global__ void __launch_bounds__(C::NTH) k_hess_up_reg(DevPlan P, const int32_t
   RegFront<C> M;
   load_panel(M, v, y);
   gather_children(M, P, v, ua, inv, 1.0);
-  congruences<C>(M, v, LB, -1.0, buf, Ls);
+  congruences<C>(M, v, LB, -1.0, lds);
   store_front(M, v, [&](int64_t o, double x) { K[o] = x; }, [&](int64_t e, double x) { Us[e] = x; });
 }
 
@@ -1034,9 +1042,8 @@ template <class C>
 __global__ void __launch_bounds__(C::NTH) k_ihess_up_reg(DevPlan P, const int32_t* list, const double* LB,
                                                          const double* Kt, double* Y, double* Ua,
                                                          int64_t upd) {
-  __shared__ double buf[4 * C::MMAX];
+  __shared__ double lds[kCongLds<C>];
   __shared__ int inv[C::MMAX];
-  __shared__ double Ls[C::MMAX * KCL];
   const SnView v(P, list[blockIdx.x]);
   const int64_t r = blockIdx.y;
   const double* K = Kt + r * P.nnz;
@@ -1045,7 +1052,7 @@ __global__ void __launch_bounds__(C::NTH) k_ihess_up_reg(DevPlan P, const int32_
   double* Us = ua + P.arena[v.s];
   RegFront<C> M;
   load_panel(M, v, K);
-  congruences<C>(M, v, LB, 1.0, buf, Ls);
+  congruences<C>(M, v, LB, 1.0, lds);
   gather_children(M, P, v, ua, inv, -1.0);
   store_front(M, v, [&](int64_t o, double x) { y[o] = x; }, [&](int64_t e, double x) { Us[e] = -x; });
 }

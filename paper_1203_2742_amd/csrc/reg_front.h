@@ -281,6 +281,119 @@ struct RegFront {
     });
   }
 
+  // Columns k0 .. k0 + kc - 1 (all in row block KA) of the symmetric matrix
+  // into cols[t MMAX + i], whole: entry i of column k is taken from (i, k)
+  // by the owners of column k when i >= k and from (k, i) by the owners of
+  // row k when i < k, both lower entries and hence exact.
+  template <int KA>
+  __device__ __forceinline__ void put_columns(int k0, int kc, double* cols) const {
+    constexpr int KB = (C::GX * KA) / C::GY;
+    const int tc = col(KB) - k0;
+    if (tc >= 0 && tc < kc) {
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a)
+        if (!skip(a, KB) && row(a) >= col(KB)) cols[tc * C::MMAX + row(a)] = v[a][KB];
+    }
+    const int tr = row(KA) - k0;
+    if (tr >= 0 && tr < kc) {
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b)
+        if (!skip(KA, b) && col(b) < row(KA)) cols[tr * C::MMAX + col(b)] = v[KA][b];
+    }
+  }
+
+  // v += sgn sum_{t < kc} p_t q_t^T over the stored register blocks, with
+  // p_t(i) = pp[t MMAX + i] and q_t(j) = qq[t MMAX + j] in LDS (rows below
+  // MMAX; kc <= KC).  Step t + 1's operands are loaded while step t's FMAs
+  // run, and no further (the scheduling barrier keeps the live operands to
+  // two steps' worth).
+  template <int KC>
+  __device__ __forceinline__ void rank_updates(int kc, const double* pp, const double* qq, double sgn) {
+    double p[2][C::RX], q[2][C::RY];
+    auto load = [&](int t, double* pt, double* qt) {
+#pragma unroll
+      for (int a = 0; a < C::RX; ++a) pt[a] = pp[t * C::MMAX + row(a)];
+#pragma unroll
+      for (int b = 0; b < C::RY; ++b) qt[b] = sgn * qq[t * C::MMAX + col(b)];
+    };
+    load(0, p[0], q[0]);
+#pragma unroll
+    for (int t = 0; t < KC; ++t) {
+      if (t + 1 < KC) load(t + 1, p[(t + 1) & 1], q[(t + 1) & 1]);
+      if (t < kc) {
+#pragma unroll
+        for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+          for (int b = 0; b < C::RY; ++b)
+            if (!skip(a, b)) v[a][b] = fma(p[t & 1][a], q[t & 1][b], v[a][b]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // Congruence with the elementary matrices I + sg l_k e_k^T (sg = +-1) of
+  // the kc <= KC pivots k = k0 .. k0 + kc - 1 of row block KA, where every
+  // l_k vanishes on the pivot rows.  The factors commute (e_k^T l_j = 0), so
+  // with L = [l_k] and E = [e_k] their product is I + sg L E^T and
+  //   M <- (I + sg L E^T) M (I + sg E L^T) = M + L W^T + W L^T,
+  //   W = sg M E + (1/2) L M_EE,
+  // one rank-2kc update after a single broadcast of the kc columns M E:
+  // two barriers for kc pivots.  ls[t MMAX + i] = l_{k0+t}(i) (LDS, every
+  // row index below MMAX, written before the call); cols and W take KC MMAX
+  // doubles each.
+  template <int KA, int KC>
+  __device__ __forceinline__ void congruence_block(int k0, int kc, double sg, double* cols, double* W,
+                                                   const double* ls) {
+    put_columns<KA>(k0, kc, cols);
+    __syncthreads();
+    if (threadIdx.x < C::MMAX) {
+      const int r = threadIdx.x;
+      double hl[KC];
+#pragma unroll
+      for (int u = 0; u < KC; ++u) hl[u] = u < kc ? 0.5 * ls[u * C::MMAX + r] : 0.0;
+#pragma unroll
+      for (int t = 0; t < KC; ++t) {
+        if (t < kc) {
+          double w = sg * cols[t * C::MMAX + r];
+#pragma unroll
+          for (int u = 0; u < KC; ++u)
+            if (u < kc) w = fma(hl[u], cols[t * C::MMAX + k0 + u], w);
+          W[t * C::MMAX + r] = w;
+        }
+      }
+    }
+    __syncthreads();
+    rank_updates<KC>(kc, ls, W, 1.0);
+    rank_updates<KC>(kc, W, ls, 1.0);
+  }
+
+  // Half of a 6 KC MMAX double buffer for the next blocked step (halves
+  // alternate with `phase`).
+  template <int KC>
+  __device__ __forceinline__ double* next_block_half(double* bufs) {
+    double* h = bufs + phase * 3 * KC * C::MMAX;
+    phase ^= 1;
+    return h;
+  }
+
+  // Congruence blocks for the pivots 0 .. n-1, KC at a time (KC divides GX,
+  // so a block never straddles a register row block).  stage(k0, ls) fills
+  // ls[i + t MMAX] = l_{k0+t}(i) (every thread takes part).  `bufs` holds
+  // 6 KC MMAX doubles: two halves of (cols, W, ls) used alternately, so a
+  // block's writes never meet the previous block's reads.
+  template <int KC, class ST>
+  __device__ __forceinline__ void congruences_blocked(int n, double sg, double* bufs, const ST& stage) {
+    static_assert(C::GX % KC == 0, "blocks inside one row block");
+    blocks(0, n, [&](auto ka, int lo, int hi) {
+      constexpr int KA = decltype(ka)::value;
+      for (int k0 = lo; k0 < hi; k0 += KC) {
+        double* h = next_block_half<KC>(bufs);
+        stage(k0, h + 2 * KC * C::MMAX);
+        congruence_block<KA, KC>(k0, min(KC, hi - k0), sg, h, h + KC * C::MMAX, h + 2 * KC * C::MMAX);
+      }
+    });
+  }
+
   // f(ic<KA>, lo, hi) for every register row block KA meeting [kbeg, kend),
   // with [lo, hi) its part of the range, in increasing order.
   template <int KA = 0, class F>
