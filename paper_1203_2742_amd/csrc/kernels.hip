@@ -23,6 +23,7 @@
 namespace mfb {
 
 static_assert(NT == NT_LAUNCH, "launch width");
+static_assert(SMEM_DOUBLES >= (NT_DOWN / NT) * 2 * KC * LDS_TM, "team GEMM staging fits the workgroup scratch");
 
 __device__ void report(DevStatus* st, int code, long long label) {
   atomicMax(&st->code, code);

@@ -37,10 +37,61 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// FP64 matrix-core tile: each wavefront of a 256-thread team owns a 32 x 32
+// quadrant (wr, wc) of the 64 x 64 output tile as 2 x 2 blocks of 16 x 16,
+// accumulated by v_mfma_f64_16x16x4f64.  Lane layout of that instruction
+// (checked on the device): lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16) of the 16 x 4 and 4 x 16 operands and holds
+// D(l / 16 + 4 v, l % 16) in accumulator element v.
+typedef double v4d __attribute__((ext_vector_type(4)));
+struct MfmaTile {
+  v4d acc[2][2];
+  int wr, wc, lr, lk;  // quadrant origin; lane's row in a block and k in a step
+  __device__ __forceinline__ explicit MfmaTile(int tid) {
+    const int w = tid >> 6, l = tid & 63;
+    wr = (w >> 1) * 32;
+    wc = (w & 1) * 32;
+    lr = l & 15;
+    lk = l >> 4;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  // the KC k-steps of one staged chunk (As, Bs: [k][LDS_TM]); step s + 1's
+  // operands are read while step s's products run
+  __device__ __forceinline__ void chunk(const double* As, const double* Bs) {
+    double fa[2][2], fb[2][2];
+    auto load = [&](int s, double* a_, double* b_) {
+      const int k = 4 * s + lk;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a_[q] = As[k * LDS_TM + wr + 16 * q + lr];
+        b_[q] = Bs[k * LDS_TM + wc + 16 * q + lr];
+      }
+    };
+    load(0, fa[0], fb[0]);
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      if (s + 1 < KC / 4) load(s + 1, fa[(s + 1) & 1], fb[(s + 1) & 1]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s & 1][a], fb[s & 1][b], acc[a][b], 0, 0, 0);
+    }
+  }
+  // element e (0..15) of this lane: block (e >> 3, (e >> 2) & 1), entry e & 3
+  __device__ __forceinline__ double get(int e) const { return acc[e >> 3][(e >> 2) & 1][e & 3]; }
+  __device__ __forceinline__ void add(int e, double x) { acc[e >> 3][(e >> 2) & 1][e & 3] += x; }
+  __device__ __forceinline__ int row_of(int e) const { return wr + 16 * (e >> 3) + lk + 4 * (e & 3); }
+  __device__ __forceinline__ int col_of(int e) const { return wc + 16 * ((e >> 2) & 1) + lr; }
+};
+
 // C(i, j) <- epi(i, j, sum_k a(i, k) b(k, j)) for 0 <= i < M, 0 <= j < N
-// (only i >= j when `lower`).  64 x 64 output tiles, each thread owning a
-// 4 x 4 register block; k-chunks of 16 are staged through LDS with the
-// next chunk's global loads in flight during the current chunk's FMAs.
+// (only i >= j when `lower`).  64 x 64 output tiles on the FP64 matrix
+// cores (MfmaTile); k-chunks of 16 are staged through LDS with the next
+// chunk's global loads in flight during the current chunk's products.
 // AK (BK) makes consecutive lanes fetch consecutive k of a(i, .) (of
 // b(., j)), for operands stored contiguously along k; otherwise they fetch
 // consecutive i (j).  Every (i, j) is produced by exactly one thread, in a
@@ -50,9 +101,8 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const
                                         const EPI& epi, bool lower, double* sm) {
   double* As = sm;
   double* Bs = sm + KC * LDS_TM;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x;
   constexpr int PER = KC * TM / NT;
-  // (row or column, k) of the q-th staged element of a thread
   auto slot_a = [&](int q, int& i, int& k) {
     const int e = tid + q * NT;
     i = AK ? e / KC : e & (TM - 1);
@@ -66,11 +116,7 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const
   for (int i0 = 0; i0 < M; i0 += TM) {
     for (int j0 = 0; j0 < N; j0 += TM) {
       if (lower && j0 > i0 + TM - 1) continue;
-      double acc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      MfmaTile T(tid);
       double ra[PER], rb[PER];
       auto fetch = [&](int k0) {
 #pragma unroll
@@ -94,33 +140,14 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const
         }
         __syncthreads();
         if (k0 + KC < K) fetch(k0 + KC);
-        // software-pipelined: step k + 1's LDS reads are in flight during
-        // step k's FMAs (one wave per SIMD cannot hide LDS latency otherwise)
-        double av[2][4], bv[2][4];
-        auto lds_step = [&](int k, double* a_, double* b_) {
-#pragma unroll
-          for (int a = 0; a < 4; ++a) a_[a] = As[k * LDS_TM + tx + 16 * a];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) b_[b] = Bs[k * LDS_TM + ty + 16 * b];
-        };
-        lds_step(0, av[0], bv[0]);
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-          if (k + 1 < KC) lds_step(k + 1, av[(k + 1) & 1], bv[(k + 1) & 1]);
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[k & 1][a], bv[k & 1][b], acc[a][b]);
-        }
+        T.chunk(As, Bs);
         __syncthreads();
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
-          if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, acc[a][b]);
-        }
+      for (int e = 0; e < 16; ++e) {
+        const int gi = i0 + T.row_of(e), gj = j0 + T.col_of(e);
+        if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, T.get(e));
+      }
     }
   }
 }
@@ -139,7 +166,7 @@ __device__ __forceinline__ void wg_gemm_split(int M, int N, int K, const FA& fa,
   constexpr int TEAMS = NTH / NT;
   static_assert(TEAMS * NT == NTH && TEAMS >= 1, "whole teams");
   static_assert((TEAMS - 1) * TM * TM <= TEAMS * 2 * KC * LDS_TM || TEAMS == 1, "reduction fits the staging");
-  const int team = threadIdx.x / NT, tid = threadIdx.x - team * NT, tx = tid & 15, ty = tid >> 4;
+  const int team = threadIdx.x / NT, tid = threadIdx.x - team * NT;
   double* As = sm + team * 2 * KC * LDS_TM;
   double* Bs = As + KC * LDS_TM;
   constexpr int PER = KC * TM / NT;
@@ -157,11 +184,7 @@ __device__ __forceinline__ void wg_gemm_split(int M, int N, int K, const FA& fa,
   for (int i0 = 0; i0 < M; i0 += TM) {
     for (int j0 = 0; j0 < N; j0 += TM) {
       if (lower && j0 > i0 + TM - 1) continue;
-      double acc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      MfmaTile T(tid);
       double ra[PER], rb[PER];
       auto fetch = [&](int r) {
         const int k0 = (r * TEAMS + team) * KC;
@@ -186,49 +209,28 @@ __device__ __forceinline__ void wg_gemm_split(int M, int N, int K, const FA& fa,
         }
         __syncthreads();
         if (r + 1 < rounds) fetch(r + 1);
-        double av[2][4], bv[2][4];
-        auto lds_step = [&](int k, double* a_, double* b_) {
-#pragma unroll
-          for (int a = 0; a < 4; ++a) a_[a] = As[k * LDS_TM + tx + 16 * a];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) b_[b] = Bs[k * LDS_TM + ty + 16 * b];
-        };
-        lds_step(0, av[0], bv[0]);
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-          if (k + 1 < KC) lds_step(k + 1, av[(k + 1) & 1], bv[(k + 1) & 1]);
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[k & 1][a], bv[k & 1][b], acc[a][b]);
-        }
+        T.chunk(As, Bs);
         __syncthreads();
       }
       if (TEAMS > 1) {
         // teams 1.. park their partial tiles, team 0 adds them in order
         if (team > 0) {
 #pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) sm[(team - 1) * TM * TM + (a * 4 + b) * NT + tid] = acc[a][b];
+          for (int e = 0; e < 16; ++e) sm[(team - 1) * TM * TM + e * NT + tid] = T.get(e);
         }
         __syncthreads();
         if (team == 0) {
           for (int t = 1; t < TEAMS; ++t)
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-              for (int b = 0; b < 4; ++b) acc[a][b] += sm[(t - 1) * TM * TM + (a * 4 + b) * NT + tid];
+            for (int e = 0; e < 16; ++e) T.add(e, sm[(t - 1) * TM * TM + e * NT + tid]);
         }
       }
       if (team == 0) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
-            if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, acc[a][b]);
-          }
+        for (int e = 0; e < 16; ++e) {
+          const int gi = i0 + T.row_of(e), gj = j0 + T.col_of(e);
+          if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, T.get(e));
+        }
       }
       if (TEAMS > 1) __syncthreads();  // the next tile's staging overwrites the partials
     }
