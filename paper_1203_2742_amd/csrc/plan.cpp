@@ -305,7 +305,49 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     }
   };
   make_classes(p->up_list, p->up_levels, false, false, p->cs_factor);
-  make_classes(p->up_list, p->up_levels, true, false, p->cs_vinv);
+  // The inverses of V_s depend on nothing but V_s: the register fronts run
+  // in one launch per class over all supernodes (longest first), not level
+  // by level; fronts beyond the register classes keep per-level launches,
+  // which bound their workgroup scratch as for the other sweeps.
+  {
+    ClassSched& cs = p->cs_vinv;
+    cs.list.clear();
+    cs.segs.clear();
+    cs.list.reserve(ns);
+    auto fit_a = [&](int32_t k) {
+      int c = 0;
+      while (c < kRegClasses && p->J[k] - p->N[k] > kRegMax[c]) ++c;
+      return c;
+    };
+    auto add_front = [&](Level& S, int32_t k) {
+      cs.list.push_back(k);
+      S.count++;
+      S.maxN = std::max(S.maxN, p->N[k]);
+      S.maxA = std::max(S.maxA, p->J[k] - p->N[k]);
+      S.maxJ = std::max(S.maxJ, p->J[k]);
+      const double An = p->J[k] - p->N[k];
+      S.u += An * (An + 1) / 2;
+      S.a3 += An * An * An;
+    };
+    for (int c = kRegClasses - 1; c >= 0; --c) {
+      std::vector<int32_t> fr;
+      for (int32_t k = 0; k < ns; ++k)
+        if (p->J[k] > p->N[k] && fit_a(k) == c) fr.push_back(k);
+      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) {
+        return p->J[x] - p->N[x] > p->J[y] - p->N[y];
+      });
+      Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int32_t k : fr) add_front(S, k);
+      if (S.count) cs.segs.push_back(ClassSeg{S, -1, c});
+    }
+    for (int32_t l = 0; l < int32_t(p->up_levels.size()); ++l) {
+      const Level& L = p->up_levels[l];
+      Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int32_t t = L.begin; t < L.begin + L.count; ++t)
+        if (fit_a(p->up_list[t]) == kRegClasses) add_front(S, p->up_list[t]);
+      if (S.count) cs.segs.push_back(ClassSeg{S, l, kRegClasses});
+    }
+  }
   make_classes(p->down_list, p->down_levels, false, false, p->cs_completion);
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
 
