@@ -205,7 +205,8 @@ const char* mfb_strerror(mfb_status_t s);
 #define MFB_K_COMPLETION 6   /* Algorithm 7.3 */
 #define MFB_K_VINV 7         /* (S_AA)^-1 per supernode */
 #define MFB_K_PRODUCT 8      /* Algorithm 3.2 in block form */
-#define MFB_K_COUNT 9
+#define MFB_K_GATHER_V 9     /* completion's gather of S_AA blocks, one root-to-leaf level */
+#define MFB_K_COUNT 10
 
 typedef struct {
   int32_t kernel;   /* MFB_K_* */

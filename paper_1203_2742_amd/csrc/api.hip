@@ -93,7 +93,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iAr = v64(p->arena), iVl = v32(p->vlabel), iUp = v32(p->up_list), iDn = v32(p->down_list),
          iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h),
          iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list),
-         iCd = v32(p->cs_down.list);
+         iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -127,6 +127,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_vinv.d_list = (const int32_t*)at(iCv);
   p->cs_completion.d_list = (const int32_t*)at(iCc);
   p->cs_down.d_list = (const int32_t*)at(iCd);
+  p->cs_compl_flat.d_list = (const int32_t*)at(iCx);
   return MFB_OK;
 }
 
@@ -288,6 +289,7 @@ static void canonical(int kid, const Level& L, int k, double* bytes, double* flo
     case MFB_K_COMPLETION: b = 4 * p + 3 * u; fl = L.a3 / 3 + 2 * L.na2 + L.n2a + L.n3; break;
     case MFB_K_VINV: b = 2 * u; fl = L.a3 / 3; break;
     case MFB_K_PRODUCT: b = 2 * p + 2 * u; fl = L.n3 / 3 + L.n2a + L.na2; break;
+    case MFB_K_GATHER_V: b = 2 * u; fl = 0; break;
   }
   *bytes = 8 * b;
   *flops = fl;
@@ -550,8 +552,17 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   f->last = s;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* s; } ctx{sin};
-  mfb_status_t st = run_classes(
-      f, MFB_K_COMPLETION, f->plan->cs_completion, s, 1, OP_COMPLETION,
+  // V_s = S_{A_s A_s} for every supernode (root-to-leaf gathers), then the
+  // fronts' sweeps, which need nothing but their own S and V_s
+  mfb_status_t st = run_levels(
+      f, MFB_K_GATHER_V, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_COMPLETION,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void* c) {
+        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->Vs);
+      },
+      &ctx);
+  if (st) return st;
+  st = run_classes(
+      f, MFB_K_COMPLETION, f->plan->cs_compl_flat, s, 1, OP_COMPLETION,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         if (cls < kRegClasses)
           launch_completion_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
@@ -641,7 +652,7 @@ mfb_status_t mfb_profile_read(mfb_factor_t f, mfb_profile_entry_t* out, int64_t 
 const char* mfb_kernel_name(int32_t kernel) {
   static const char* names[MFB_K_COUNT] = {"k_factor", "k_projinv", "k_hess_up", "k_hess_down",
                                            "k_ihess_down", "k_ihess_up", "k_completion", "k_vinv",
-                                           "k_product"};
+                                           "k_product", "k_gather_v"};
   return (kernel >= 0 && kernel < MFB_K_COUNT) ? names[kernel] : "unknown";
 }
 

@@ -513,10 +513,10 @@ __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list,
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 7.3: matrix completion (root-to-leaf level for the V_s gather).
-// V_s = S_{A_s A_s}; L_AN = -V_s^-1 S_AN; D^-1 = S_NN + S_AN^T L_AN;
-// then C = chol(D), B = L_AN C so that the handle holds the factor of X-hat.
-// Also caches S, V_s and V_s^-1.  Scratch: max(2A^2, 3N^2).
+// Algorithm 7.3: matrix completion of one front, with V_s = S_{A_s A_s}
+// already gathered (k_gather_v): L_AN = -V_s^-1 S_AN; D^-1 = S_NN +
+// S_AN^T L_AN; then C = chol(D), B = L_AN C so that the handle holds the
+// factor of X-hat.  Also caches S and V_s^-1.  Scratch: max(2A^2, 3N^2).
 __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* list, const double* Sin,
                                                    double* R, double* LB, double* S, double* Vs,
                                                    double* Vi, double* part, DevStatus* st,
@@ -533,8 +533,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
       const int rr = int(e % v.J), c = int(e / v.J);
       if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
     }
-    extract_from_parent(P, v, Sin, Vs, sm);
-    __syncthreads();
+    __syncthreads();  // (V_s was gathered by k_gather_v)
     const double* V = Vs + P.arena[v.s];
     double* VI = Vi + P.arena[v.s];
     if (A > 0) {
@@ -612,6 +611,16 @@ __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, con
         [&](int i, int j, double acc) { VI[pk(i, j, v.A)] = acc; }, slot_ptr(wsb, slot), sm, &fail);
     if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOTPD, v.vl[0]);
   });
+}
+
+// The completion's gather pass (root-to-leaf level): V_s = S_{A_s A_s} into
+// the packed arena, from the parent's CCS columns of S and the parent's
+// packed block (eq. e-sn-gradient-2 applied to S itself).  With every V_s
+// in place the completion's sweeps depend on nothing but their own front.
+__global__ void __launch_bounds__(NT) k_gather_v(DevPlan P, const int32_t* list, const double* Sin,
+                                                 double* Vs) {
+  __shared__ double sm[SMEM_DOUBLES];
+  extract_from_parent(P, SnView(P, list[blockIdx.x]), Sin, Vs, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -780,6 +789,23 @@ __device__ __forceinline__ void gather_parent(RegFront<C, LO>& M, const DevPlan&
                             : (rc[b] < Np ? src + cpc[b] + (rr[a] - rc[b])
                                           : Vp + pk(rr[a] - Np, rc[b] - Np, Ap));
       const double x = *q;
+      if (in) M.v[a][b] = x;
+    }
+}
+
+// The A x A block of the front from this supernode's packed lower block U
+// (entries (i, j), N <= j <= i < J).
+template <class C, bool LO>
+__device__ __forceinline__ void load_packed_block(RegFront<C, LO>& M, const SnView& v, const double* U) {
+  const int N = v.N, J = v.J, A = v.A;
+#pragma unroll
+  for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) {
+      if (M.skip(a, b)) continue;
+      const int i = M.row(a), j = M.col(b);
+      const bool in = j >= N && i < J && i >= j;
+      const double x = U[in ? pk(i - N, j - N, A) : 0];
       if (in) M.v[a][b] = x;
     }
 }
@@ -983,9 +1009,9 @@ __global__ void __launch_bounds__(C::NTH) k_completion_reg(DevPlan P, const int3
   stage_col<C>(v, colc);
   RegFront<C> M;
   load_panel(M, v, Sin);
-  gather_parent(M, P, v, Sin, Vs);
-  // cache S (own columns) and V_s
-  store_front(M, v, [&](int64_t o, double y) { S[o] = y; }, [&](int64_t e, double y) { VS[e] = y; });
+  load_packed_block(M, v, VS);  // V_s, gathered by k_gather_v
+  // cache S (own columns)
+  store_front(M, v, [&](int64_t o, double y) { S[o] = y; }, [](int64_t, double) {});
   const bool badV = M.sweeps(N, J, buf) >= 0;
   // L_AN = -(swept A x N block), D^-1 = swept N x N block, V_s^-1 = -(swept A x A block)
   M.store_lower(

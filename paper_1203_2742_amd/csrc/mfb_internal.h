@@ -83,6 +83,8 @@ struct mfb_plan_s {
   // Hessian down-sweeps (by J on the levels that take the register
   // kernels, blocked elsewhere)
   mfb::ClassSched cs_factor, cs_vinv, cs_completion, cs_down;
+  // the completion's sweeps, one launch per class over all supernodes
+  mfb::ClassSched cs_compl_flat;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;
   std::vector<int64_t> colptr_h;

@@ -305,49 +305,60 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     }
   };
   make_classes(p->up_list, p->up_levels, false, false, p->cs_factor);
-  // The inverses of V_s depend on nothing but V_s: the register fronts run
-  // in one launch per class over all supernodes (longest first), not level
-  // by level; fronts beyond the register classes keep per-level launches,
-  // which bound their workgroup scratch as for the other sweeps.
-  {
-    ClassSched& cs = p->cs_vinv;
+  // Schedules for work with no dependence between fronts: the register
+  // fronts run in one launch per class over all supernodes (longest first)
+  // instead of level by level; fronts beyond the register classes keep
+  // per-level launches, which bound their workgroup scratch as for the
+  // other sweeps.  by_a: order A (the inverse of V_s, roots skipped), else J.
+  auto make_flat = [&](bool by_a, const std::vector<int32_t>& list, const std::vector<Level>& levels,
+                       ClassSched& cs) {
     cs.list.clear();
     cs.segs.clear();
     cs.list.reserve(ns);
-    auto fit_a = [&](int32_t k) {
+    auto order = [&](int32_t k) { return by_a ? p->J[k] - p->N[k] : p->J[k]; };
+    auto fit = [&](int32_t k) {
       int c = 0;
-      while (c < kRegClasses && p->J[k] - p->N[k] > kRegMax[c]) ++c;
+      while (c < kRegClasses && order(k) > kRegMax[c]) ++c;
       return c;
     };
+    auto wanted = [&](int32_t k) { return !by_a || p->J[k] > p->N[k]; };
     auto add_front = [&](Level& S, int32_t k) {
       cs.list.push_back(k);
       S.count++;
       S.maxN = std::max(S.maxN, p->N[k]);
       S.maxA = std::max(S.maxA, p->J[k] - p->N[k]);
       S.maxJ = std::max(S.maxJ, p->J[k]);
-      const double An = p->J[k] - p->N[k];
+      const double Nn = p->N[k], Jn = p->J[k], An = Jn - Nn;
+      S.p += Nn * Jn - Nn * (Nn - 1) / 2;
       S.u += An * (An + 1) / 2;
+      S.n3 += Nn * Nn * Nn;
+      S.n2a += Nn * Nn * An;
+      S.na2 += Nn * An * An;
       S.a3 += An * An * An;
     };
     for (int c = kRegClasses - 1; c >= 0; --c) {
       std::vector<int32_t> fr;
       for (int32_t k = 0; k < ns; ++k)
-        if (p->J[k] > p->N[k] && fit_a(k) == c) fr.push_back(k);
-      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) {
-        return p->J[x] - p->N[x] > p->J[y] - p->N[y];
-      });
+        if (wanted(k) && fit(k) == c) fr.push_back(k);
+      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) { return order(x) > order(y); });
       Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       for (int32_t k : fr) add_front(S, k);
       if (S.count) cs.segs.push_back(ClassSeg{S, -1, c});
     }
-    for (int32_t l = 0; l < int32_t(p->up_levels.size()); ++l) {
-      const Level& L = p->up_levels[l];
+    for (int32_t l = 0; l < int32_t(levels.size()); ++l) {
+      const Level& L = levels[l];
       Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       for (int32_t t = L.begin; t < L.begin + L.count; ++t)
-        if (fit_a(p->up_list[t]) == kRegClasses) add_front(S, p->up_list[t]);
+        if (wanted(list[t]) && fit(list[t]) == kRegClasses) add_front(S, list[t]);
       if (S.count) cs.segs.push_back(ClassSeg{S, l, kRegClasses});
     }
-  }
+  };
+  // V_s^-1 needs only V_s; the completion's sweeps need only S and V_s,
+  // which a level-scheduled gather pass puts in place beforehand.
+  // (the blocked segments follow the level lists the workgroup scratch is
+  // sized over: leaf-to-root for V_s^-1, root-to-leaf for the completion)
+  make_flat(true, p->up_list, p->up_levels, p->cs_vinv);
+  make_flat(false, p->down_list, p->down_levels, p->cs_compl_flat);
   make_classes(p->down_list, p->down_levels, false, false, p->cs_completion);
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
 
