@@ -16,22 +16,6 @@ namespace mfb {
 constexpr size_t ALIGN = 256;
 static inline size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
-// Scratch (doubles per workgroup) of each kernel for a level's largest front.
-enum Op { OP_FACTOR, OP_PRODUCT, OP_COMPLETION, OP_VINV, OP_HUP, OP_HDOWN, OP_IHDOWN, OP_IHUP };
-static int64_t slot_doubles(Op op, const Level& L) {
-  const int64_t N = L.maxN, A = L.maxA, J = L.maxJ;
-  switch (op) {
-    case OP_FACTOR: return J * N + N * N;
-    case OP_PRODUCT: return J * N;
-    case OP_COMPLETION: return std::max(2 * A * A, 3 * N * N);
-    case OP_VINV: return 2 * A * A;
-    case OP_HUP: return J * N;
-    case OP_HDOWN: return 2 * A * N + 2 * N * N;
-    case OP_IHDOWN: return 2 * A * N + 3 * N * N;
-    case OP_IHUP: return J * N + A * N;
-  }
-  return 0;
-}
 static int64_t scratch_doubles(Op op, const std::vector<Level>& lv) {
   int64_t m = 0;
   for (const auto& L : lv) m = std::max(m, int64_t(L.count) * std::max<int64_t>(1, slot_doubles(op, L)));
@@ -48,8 +32,11 @@ static int64_t factor_scratch(const mfb_plan_s* p) {
                    plan_scratch(p, OP_COMPLETION), plan_scratch(p, OP_VINV), int64_t(1)});
 }
 static int64_t rhs_scratch(const mfb_plan_s* p) {
-  return std::max({plan_scratch(p, OP_HUP), plan_scratch(p, OP_HDOWN), plan_scratch(p, OP_IHDOWN),
-                   plan_scratch(p, OP_IHUP), int64_t(1)});
+  int64_t flat = 0;
+  for (const ClassSeg& g : p->cs_ihd_flat.segs)
+    flat = std::max(flat, int64_t(g.lv.count) * std::max<int64_t>(1, slot_doubles(OP_IHDOWN, g.lv)));
+  return std::max({plan_scratch(p, OP_HUP), plan_scratch(p, OP_HDOWN), flat, plan_scratch(p, OP_IHUP),
+                   int64_t(1)});
 }
 static size_t factor_bytes(const mfb_plan_s* p) {
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
@@ -93,7 +80,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iAr = v64(p->arena), iVl = v32(p->vlabel), iUp = v32(p->up_list), iDn = v32(p->down_list),
          iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h),
          iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list),
-         iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list);
+         iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -128,6 +115,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_completion.d_list = (const int32_t*)at(iCc);
   p->cs_down.d_list = (const int32_t*)at(iCd);
   p->cs_compl_flat.d_list = (const int32_t*)at(iCx);
+  p->cs_ihd_flat.d_list = (const int32_t*)at(iCh);
   return MFB_OK;
 }
 
@@ -518,8 +506,18 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   if ((st = ensure_projinv(f, s))) return st;
   if ((st = ensure_vinv(f, s))) return st;
   struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
+  // V'_s = T_{A_s A_s} for every supernode and right-hand side (root-to-leaf
+  // gathers), then steps 1+2 of all fronts, which are independent
+  st = run_levels(
+      f, MFB_K_GATHER_V, f->plan->down_levels, f->plan->d_down_list, s, k, OP_IHDOWN,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void* c) {
+        Ctx* x = (Ctx*)c;
+        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, x->t, x->a.Ua, f->plan->nnz, x->a.upd);
+      },
+      &ctx);
+  if (st) return st;
   st = run_classes(
-      f, MFB_K_IHESS_DOWN, f->plan->cs_down, s, k, OP_IHDOWN,
+      f, MFB_K_IHESS_DOWN, f->plan->cs_ihd_flat, s, k, OP_IHDOWN,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
         if (cls < kRegClasses)
@@ -557,7 +555,7 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   mfb_status_t st = run_levels(
       f, MFB_K_GATHER_V, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_COMPLETION,
       [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void* c) {
-        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->Vs);
+        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->Vs, 0, 0);
       },
       &ctx);
   if (st) return st;

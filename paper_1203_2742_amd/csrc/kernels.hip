@@ -403,8 +403,8 @@ __global__ void __launch_bounds__(NT_DOWN) k_hess_down(DevPlan P, const int32_t*
 }
 
 // ---------------------------------------------------------------------------
-// Inverse Hessian steps 1 and 2 (root-to-leaf), block form of Algorithm 5.2:
-// V'_s = T_{A_s A_s} from the parent; M_AN = T_AN + V' L;
+// Inverse Hessian steps 1 and 2, block form of Algorithm 5.2, for one
+// front given V'_s = T_{A_s A_s} in the arena; M_AN = T_AN + V' L;
 // M_NN = T_NN + L^T M_AN + T_AN^T L; K_NN = D M_NN D; K_AN = V_s^-1 M_AN D,
 // with D = C C^T.  Scratch: 2AN + 3N^2.
 __global__ void __launch_bounds__(NT_DOWN) k_ihess_down(DevPlan P, const int32_t* list, const double* R,
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(NT_DOWN) k_ihess_down(DevPlan P, const int32_t
     double* MN = Z + (int64_t)A * N;
     double* Dm = MN + (int64_t)N * N;
     double* W = Dm + (int64_t)N * N;
-    extract_from_parent<NT_DOWN>(P, v, t, va, sm);
+    // (V'_s = T_{A_s A_s} is in the arena: k_gather_v)
     // D = C C^T (full)
     wg_gemm_split<NT_DOWN>(
         N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
@@ -613,14 +613,17 @@ __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, con
   });
 }
 
-// The completion's gather pass (root-to-leaf level): V_s = S_{A_s A_s} into
-// the packed arena, from the parent's CCS columns of S and the parent's
-// packed block (eq. e-sn-gradient-2 applied to S itself).  With every V_s
-// in place the completion's sweeps depend on nothing but their own front.
+// Gather pass (root-to-leaf level) of the steps that read a block of their
+// input: V_s = S_{A_s A_s} for the completion, V'_s = T_{A_s A_s} for the
+// inverse Hessian (right-hand side blockIdx.y), into the packed arena, from
+// the parent's CCS columns and the parent's packed block (the extraction of
+// eq. e-sn-gradient-2 applied to the input itself).  With every block in
+// place those steps depend on nothing but their own front.
 __global__ void __launch_bounds__(NT) k_gather_v(DevPlan P, const int32_t* list, const double* Sin,
-                                                 double* Vs) {
+                                                 double* Vs, int64_t src_stride, int64_t arena_stride) {
   __shared__ double sm[SMEM_DOUBLES];
-  extract_from_parent(P, SnView(P, list[blockIdx.x]), Sin, Vs, sm);
+  const int64_t r = blockIdx.y;  // right-hand side
+  extract_from_parent(P, SnView(P, list[blockIdx.x]), Sin + r * src_stride, Vs + r * arena_stride, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1299,8 +1302,8 @@ __global__ void __launch_bounds__(C::NTH) k_hess_down_reg(DevPlan P, const int32
       N, [](int, int) { return true; }, [&](int, int, int i, int j, double y) { t[pn.at(i, j)] = y; });
 }
 
-// Inverse Hessian steps 1 and 2 (root-to-leaf) on a register front:
-// V'_s = T_{A_s A_s} from the parent (cached for the children);
+// Inverse Hessian steps 1 and 2 on a register front (no dependence on
+// other fronts once V'_s = T_{A_s A_s} is in the arena);
 // M_AN = T_AN + V' L, M_NN = T_NN + L^T M_AN + T_AN^T L; with D = C C^T,
 // [W; Z] = [M_NN; M_AN] D and [K_NN; K_AN] = blkdiag(D, V_s^-1) [W; Z].
 // Five register GEMMs; D, M_NN, M_AN and [W; Z] pass through the
@@ -1327,12 +1330,7 @@ __global__ void __launch_bounds__(C::NTH) k_ihess_down_reg(DevPlan P, const int3
   double* WZ = MA + (int64_t)A * N;     // J x N
   const double* Vp = va + P.arena[v.s];
   const double* VI = Vi + P.arena[v.s];
-  {
-    RegFront<C> G;
-    G.zero();
-    gather_parent(G, P, v, t, va);
-    store_front(G, v, [](int64_t, double) {}, [&](int64_t e, double y) { va[P.arena[v.s] + e] = y; });
-  }
+  // V'_s = T_{A_s A_s} is in the arena (k_gather_v)
   RegFront<C, false> M;  // general J x N products ([W; Z] is not symmetric)
   // D = C C^T
   M.zero();

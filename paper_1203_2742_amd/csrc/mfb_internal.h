@@ -1,5 +1,6 @@
 // Internal structures shared by the symbolic plan (host) and the kernels.
 #pragma once
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 #include <vector>
@@ -42,6 +43,22 @@ struct Level {
   double p, u, n3, n2a, na2, a3;
 };
 
+// Scratch (doubles per workgroup) of each kernel for a level's largest front.
+enum Op { OP_FACTOR, OP_PRODUCT, OP_COMPLETION, OP_VINV, OP_HUP, OP_HDOWN, OP_IHDOWN, OP_IHUP };
+inline int64_t slot_doubles(Op op, const Level& L) {
+  const int64_t N = L.maxN, A = L.maxA, J = L.maxJ;
+  switch (op) {
+    case OP_FACTOR: return J * N + N * N;
+    case OP_PRODUCT: return J * N;
+    case OP_COMPLETION: return std::max(2 * A * A, 3 * N * N);
+    case OP_VINV: return 2 * A * A;
+    case OP_HUP: return J * N;
+    case OP_HDOWN: return 2 * A * N + 2 * N * N;
+    case OP_IHDOWN: return 2 * A * N + 3 * N * N;
+    case OP_IHUP: return J * N + A * N;
+  }
+  return 0;
+}
 // Register-front classes: the register kernel of class c takes fronts of
 // order (J for the factor and the completion, A for the inverse of V_s)
 // at most kRegMax[c]; larger fronts run the blocked kernels.
@@ -50,6 +67,9 @@ constexpr int kRegMax[kRegClasses] = {16, 32, 64, 128, 192};
 // Largest front order for which the Hessian and inverse-Hessian
 // down-sweeps use the register kernels on a level of non-root fronts.
 constexpr int kDownRegMaxJ = 64;
+// Largest workgroup scratch (doubles per right-hand side) of one launch of
+// a schedule that runs independent fronts together.
+constexpr int64_t kFlatScratch = int64_t(1) << 22;
 
 // A level of a schedule split by class: at most two launches, the blocked
 // kernels (cls == kRegClasses) on the fronts no register class holds,
@@ -83,8 +103,10 @@ struct mfb_plan_s {
   // Hessian down-sweeps (by J on the levels that take the register
   // kernels, blocked elsewhere)
   mfb::ClassSched cs_factor, cs_vinv, cs_completion, cs_down;
-  // the completion's sweeps, one launch per class over all supernodes
-  mfb::ClassSched cs_compl_flat;
+  // the completion's sweeps, one launch per class over all supernodes;
+  // the inverse Hessian's steps 1+2 likewise, in launches whose workgroup
+  // scratch stays within kFlatScratch doubles per right-hand side
+  mfb::ClassSched cs_compl_flat, cs_ihd_flat;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;
   std::vector<int64_t> colptr_h;

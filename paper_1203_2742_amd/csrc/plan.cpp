@@ -359,6 +359,57 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   // sized over: leaf-to-root for V_s^-1, root-to-leaf for the completion)
   make_flat(true, p->up_list, p->up_levels, p->cs_vinv);
   make_flat(false, p->down_list, p->down_levels, p->cs_compl_flat);
+  // The inverse Hessian's steps 1+2 read T_{A_s A_s}, which a gather pass
+  // puts in place, so its fronts are independent too.  Each front takes the
+  // kernel the root-to-leaf rule gives it (register kernels for J <=
+  // kDownRegMaxJ and for roots, blocked otherwise); fronts of one kind run
+  // together, longest first, in launches of at most kFlatScratch doubles
+  // of workgroup scratch.
+  {
+    ClassSched& cs = p->cs_ihd_flat;
+    cs.list.clear();
+    cs.segs.clear();
+    cs.list.reserve(ns);
+    auto kind = [&](int32_t k) {
+      const bool reg = p->J[k] <= kDownRegMaxJ || p->J[k] == p->N[k];
+      int c = 0;
+      while (c < kRegClasses && p->J[k] > kRegMax[c]) ++c;
+      return reg ? c : kRegClasses;
+    };
+    for (int c = kRegClasses; c >= 0; --c) {
+      std::vector<int32_t> fr;
+      for (int32_t k = 0; k < ns; ++k)
+        if (kind(k) == c) fr.push_back(k);
+      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) { return p->J[x] > p->J[y]; });
+      Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int32_t k : fr) {
+        Level T = S;
+        T.count++;
+        T.maxN = std::max(T.maxN, p->N[k]);
+        T.maxA = std::max(T.maxA, p->J[k] - p->N[k]);
+        T.maxJ = std::max(T.maxJ, p->J[k]);
+        if (S.count && int64_t(T.count) * slot_doubles(OP_IHDOWN, T) > kFlatScratch) {
+          cs.segs.push_back(ClassSeg{S, -1, c});
+          S = Level{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+          T = S;
+          T.count = 1;
+          T.maxN = p->N[k];
+          T.maxA = p->J[k] - p->N[k];
+          T.maxJ = p->J[k];
+        }
+        const double Nn = p->N[k], Jn = p->J[k], An = Jn - Nn;
+        T.p += Nn * Jn - Nn * (Nn - 1) / 2;
+        T.u += An * (An + 1) / 2;
+        T.n3 += Nn * Nn * Nn;
+        T.n2a += Nn * Nn * An;
+        T.na2 += Nn * An * An;
+        T.a3 += An * An * An;
+        cs.list.push_back(k);
+        S = T;
+      }
+      if (S.count) cs.segs.push_back(ClassSeg{S, -1, c});
+    }
+  }
   make_classes(p->down_list, p->down_levels, false, false, p->cs_completion);
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
 
