@@ -72,6 +72,12 @@ typedef struct mfb_factor_s* mfb_factor_t;
 /* Plan flags. */
 #define MFB_PLAN_TIE_LAST 1u  /* Pothen-Sun tie-break: join the highest-labelled
                                  eligible child instead of the lowest */
+#define MFB_PLAN_NO_GATHER_MAP 2u  /* keep no CCS source map of the packed update
+                                      blocks: the completion and the inverse
+                                      Hessian gather their input blocks level by
+                                      level from the parents instead of in one
+                                      launch (plans with more than 2^25 block
+                                      entries never keep the map) */
 
 typedef struct {
   int64_t n;                 /* order of X */

@@ -80,7 +80,8 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iAr = v64(p->arena), iVl = v32(p->vlabel), iUp = v32(p->up_list), iDn = v32(p->down_list),
          iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h),
          iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list),
-         iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list);
+         iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list),
+         iGm = v64(p->gmap);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -116,6 +117,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_down.d_list = (const int32_t*)at(iCd);
   p->cs_compl_flat.d_list = (const int32_t*)at(iCx);
   p->cs_ihd_flat.d_list = (const int32_t*)at(iCh);
+  p->d_gmap = p->gmap.empty() ? nullptr : (const int64_t*)at(iGm);
   return MFB_OK;
 }
 
@@ -277,7 +279,7 @@ static void canonical(int kid, const Level& L, int k, double* bytes, double* flo
     case MFB_K_COMPLETION: b = 4 * p + 3 * u; fl = L.a3 / 3 + 2 * L.na2 + L.n2a + L.n3; break;
     case MFB_K_VINV: b = 2 * u; fl = L.a3 / 3; break;
     case MFB_K_PRODUCT: b = 2 * p + 2 * u; fl = L.n3 / 3 + L.n2a + L.na2; break;
-    case MFB_K_GATHER_V: b = 2 * u; fl = 0; break;
+    case MFB_K_GATHER_V: b = K * 2 * u; fl = 0; break;
   }
   *bytes = 8 * b;
   *flops = fl;
@@ -352,6 +354,35 @@ static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, 
     }
   }
   return MFB_OK;
+}
+
+// Packed A_s x A_s blocks of an input (S for the completion, T for the
+// inverse Hessian, k right-hand sides) into `arena`: one elementwise launch
+// with the plan's source map, else level by level from the parents.
+static mfb_status_t gather_blocks(mfb_factor_s* f, hipStream_t s, int k, const double* src, double* arena,
+                                  int64_t src_stride, int64_t arena_stride) {
+  const mfb_plan_s* p = f->plan;
+  struct Ctx { const double* src; double* arena; int64_t ss, as; } ctx{src, arena, src_stride, arena_stride};
+  if (p->d_gmap) {
+    const std::vector<Level> one{p->all_level};
+    return run_levels(
+        f, MFB_K_GATHER_V, one, p->d_all_list, s, k, OP_COMPLETION,
+        [](mfb_factor_s* f, const int32_t*, dim3 g, hipStream_t s, int64_t, void* c) {
+          Ctx* x = (Ctx*)c;
+          const int64_t n = f->plan->update_doubles;
+          const unsigned blocks = unsigned(std::min<int64_t>(2048, std::max<int64_t>(1, (n + NT_LAUNCH - 1) / NT_LAUNCH)));
+          const dim3 grid(blocks, g.y);
+          k_gather_map<<<grid, NT_LAUNCH, 0, s>>>(f->plan->d_gmap, n, x->src, x->arena, x->ss, x->as);
+        },
+        &ctx);
+  }
+  return run_levels(
+      f, MFB_K_GATHER_V, p->down_levels, p->d_down_list, s, k, OP_COMPLETION,
+      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void* c) {
+        Ctx* x = (Ctx*)c;
+        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, x->src, x->arena, x->ss, x->as);
+      },
+      &ctx);
 }
 
 mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
@@ -508,13 +539,7 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
   // V'_s = T_{A_s A_s} for every supernode and right-hand side (root-to-leaf
   // gathers), then steps 1+2 of all fronts, which are independent
-  st = run_levels(
-      f, MFB_K_GATHER_V, f->plan->down_levels, f->plan->d_down_list, s, k, OP_IHDOWN,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void* c) {
-        Ctx* x = (Ctx*)c;
-        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, x->t, x->a.Ua, f->plan->nnz, x->a.upd);
-      },
-      &ctx);
+  st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd);
   if (st) return st;
   st = run_classes(
       f, MFB_K_IHESS_DOWN, f->plan->cs_ihd_flat, s, k, OP_IHDOWN,
@@ -552,12 +577,7 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   struct Ctx { const double* s; } ctx{sin};
   // V_s = S_{A_s A_s} for every supernode (root-to-leaf gathers), then the
   // fronts' sweeps, which need nothing but their own S and V_s
-  mfb_status_t st = run_levels(
-      f, MFB_K_GATHER_V, f->plan->down_levels, f->plan->d_down_list, s, 1, OP_COMPLETION,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void* c) {
-        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->Vs, 0, 0);
-      },
-      &ctx);
+  mfb_status_t st = gather_blocks(f, s, 1, sin, f->Vs, 0, 0);
   if (st) return st;
   st = run_classes(
       f, MFB_K_COMPLETION, f->plan->cs_compl_flat, s, 1, OP_COMPLETION,

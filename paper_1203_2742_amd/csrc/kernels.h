@@ -32,6 +32,7 @@ __global__ void k_completion(DevPlan, const int32_t*, const double*, double*, do
 __global__ void k_vinv(DevPlan, const int32_t*, const double*, double*, DevStatus*, double*,
                        int64_t);
 __global__ void k_gather_v(DevPlan, const int32_t*, const double*, double*, int64_t, int64_t);
+__global__ void k_gather_map(const int64_t*, int64_t, const double*, double*, int64_t, int64_t);
 __global__ void k_product(DevPlan, const int32_t*, const double*, double*, double*, double*,
                           int64_t);
 __global__ void k_logdet(const double*, int, double*);

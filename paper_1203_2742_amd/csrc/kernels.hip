@@ -626,6 +626,18 @@ __global__ void __launch_bounds__(NT) k_gather_v(DevPlan P, const int32_t* list,
   extract_from_parent(P, SnView(P, list[blockIdx.x]), Sin + r * src_stride, Vs + r * arena_stride, sm);
 }
 
+// The same gather with the plan's source map: arena[e] = src[map[e]] for
+// every packed update-block entry e < n (right-hand side blockIdx.y), one
+// elementwise launch for all supernodes.
+__global__ void __launch_bounds__(NT) k_gather_map(const int64_t* map, int64_t n, const double* src,
+                                                   double* arena, int64_t src_stride, int64_t arena_stride) {
+  const int64_t r = blockIdx.y;
+  const double* sr = src + r * src_stride;
+  double* ar = arena + r * arena_stride;
+  for (int64_t e = int64_t(blockIdx.x) * NT + threadIdx.x; e < n; e += int64_t(gridDim.x) * NT)
+    ar[e] = sr[map[e]];
+}
+
 // ---------------------------------------------------------------------------
 // Algorithm 3.2 in block form (leaf-to-root): with G = sum E U_c E^T,
 // X_NN = C C^T - G11, X_AN = B C^T - G21, U_s = G22 - B B^T.  Scratch: J*N.

@@ -70,6 +70,10 @@ constexpr int kDownRegMaxJ = 64;
 // Largest workgroup scratch (doubles per right-hand side) of one launch of
 // a schedule that runs independent fronts together.
 constexpr int64_t kFlatScratch = int64_t(1) << 22;
+// Largest number of packed update-block entries for which the plan keeps
+// the CCS source offset of every entry (8 bytes each), so that gathering
+// the blocks of an input takes one elementwise launch.
+constexpr int64_t kGatherMapMax = int64_t(1) << 25;
 
 // A level of a schedule split by class: at most two launches, the blocked
 // kernels (cls == kRegClasses) on the fronts no register class holds,
@@ -107,6 +111,12 @@ struct mfb_plan_s {
   // the inverse Hessian's steps 1+2 likewise, in launches whose workgroup
   // scratch stays within kFlatScratch doubles per right-hand side
   mfb::ClassSched cs_compl_flat, cs_ihd_flat;
+  // gmap[e]: CCS offset of the input entry that packed update-block entry e
+  // holds (S_AA or T_AA blocks), empty beyond kGatherMapMax entries;
+  // all_level: every supernode as one level (canonical counts of a gather)
+  std::vector<int64_t> gmap;
+  mfb::Level all_level{};
+  const int64_t* d_gmap = nullptr;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;
   std::vector<int64_t> colptr_h;

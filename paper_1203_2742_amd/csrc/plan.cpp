@@ -413,6 +413,32 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   make_classes(p->down_list, p->down_levels, false, false, p->cs_completion);
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
 
+  // Source offsets of the packed update-block entries: entry (x, y) of
+  // supernode s's A_s x A_s block is S(A_s[x], A_s[y]), which lies in the
+  // parent's CCS columns when A_s[y] is one of the parent's own columns and
+  // in the parent's block otherwise (parents come first in down_list).
+  p->gmap.clear();
+  if (!(flags & MFB_PLAN_NO_GATHER_MAP) && p->update_doubles <= kGatherMapMax) {
+    p->gmap.assign(size_t(p->update_doubles), 0);
+    auto pkh = [](int64_t x, int64_t y, int64_t A) { return y * (2 * A - y - 1) / 2 + x; };
+    for (int32_t t = 0; t < ns; ++t) {
+      const int32_t s = p->down_list[t];
+      const int32_t A = p->J[s] - p->N[s];
+      if (A == 0) continue;
+      const int32_t q = p->parent[s];
+      const int32_t Nq = p->N[q], Aq = p->J[q] - Nq;
+      const int32_t* rl = &p->rel[p->relbase[s]];
+      const int64_t* colq = &p->col[p->colbase[q]];
+      for (int32_t y = 0; y < A; ++y)
+        for (int32_t x = y; x < A; ++x) {
+          const int32_t rx = rl[x], ry = rl[y];
+          p->gmap[p->arena[s] + pkh(x, y, A)] =
+              ry < Nq ? colq[ry] + (rx - ry) : p->gmap[p->arena[q] + pkh(rx - Nq, ry - Nq, Aq)];
+        }
+    }
+  }
+  p->all_level = Level{0, ns, 0, 0, 0, 0, double(p->update_doubles), 0, 0, 0, 0};
+
   // Canonical algorithmic flop counts per supernode (LAPACK conventions).
   for (int32_t k = 0; k < ns; ++k) {
     const double Nn = p->N[k], An = p->J[k] - p->N[k];

@@ -32,6 +32,7 @@ OK, EINVAL, ENOTCHORDAL, ENOTPD, ENOCOMPLETION, ENOMEM, EHIP, ESTATE = range(8)
 NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTCHORDAL", 3: "ENOTPD", 4: "ENOCOMPLETION",
          5: "ENOMEM", 6: "EHIP", 7: "ESTATE"}
 PLAN_TIE_LAST = 1
+PLAN_NO_GATHER_MAP = 2
 
 
 class MfbError(RuntimeError):

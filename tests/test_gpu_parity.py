@@ -151,6 +151,34 @@ def test_completion_recovers_x(case, mfb):
     assert relerr(case.pat, t0, case.t[0]) <= TOL
 
 
+@pytest.mark.parametrize("name", ["arrow_small", "grid2d_24"])
+def test_level_gathers_match_the_map(name, mfb):
+    """The completion and the inverse Hessian read the A_s x A_s blocks of
+    their input either through the plan's source map (one launch) or level
+    by level from the parents (MFB_PLAN_NO_GATHER_MAP, the path of plans too
+    large for the map): the same values land in the same places, so the
+    outputs agree bitwise, and both agree with the oracle."""
+    pat = CASES[name]()
+    x = V.make_x(*pat, seed=0)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    ys = V.make_ys(*pat, 2, seed=5)
+    outs = []
+    for flags in (0, mfb.PLAN_NO_GATHER_MAP):
+        b = mfb.SparseBarrier(pat, flags=flags)
+        b.factor(dev(x))
+        yy = host(b.inv_hessian(dev(ys)))
+        b.completion(dev(s))
+        assert b.status() == (0, -1)
+        outs.append((yy, host(b.export_ldl())))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    want_ldl = oracle.factor(pat, x)
+    assert np.linalg.norm(outs[1][1] - want_ldl) / np.linalg.norm(want_ldl) <= TOL
+    for r in range(2):
+        want = oracle.inv_hessian(pat, ldl, s, ys[r])
+        assert relerr(pat, outs[1][0][r], want) <= TOL
+
+
 def test_completion_of_general_s(mfb):
     pat = P.random_chordal(60, 0.06, 8)
     s = V.project(*pat, V.make_spd_dense(pat[0], 3))
