@@ -421,12 +421,12 @@ mfb_status_t mfb_logdet(mfb_factor_t f, double* out, void* stream) {
 static mfb_status_t ensure_projinv(mfb_factor_s* f, hipStream_t s) {
   if (f->s_valid) return MFB_OK;
   mfb_status_t st = run_classes(
-      f, MFB_K_PROJINV, f->plan->cs_completion, s, 1, OP_FACTOR,
+      f, MFB_K_PROJINV, f->plan->cs_down, s, 1, OP_FACTOR,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t, void*) {
         if (cls < kRegClasses)
           launch_projinv_reg(cls, g, s, f->plan->dev, list, f->LB, f->S, f->Vs);
         else
-          k_projinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
+          k_projinv<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
       },
       nullptr);
   if (st) return st;

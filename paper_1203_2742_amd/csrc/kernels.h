@@ -6,8 +6,8 @@
 
 namespace mfb {
 constexpr int NT_LAUNCH = 256;  // threads per workgroup of the blocked sweep kernels
-// except the Hessian down-sweeps: two teams of NT_LAUNCH splitting every
-// product's k range
+// except the projected inverse and the Hessian down-sweeps: two teams of
+// NT_LAUNCH splitting every product's k range
 constexpr int NT_DOWN = 512;
 
 struct DevStatus {

@@ -286,20 +286,20 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
 // ---------------------------------------------------------------------------
 // Algorithm 7.2: projected inverse (root-to-leaf level).
 // V_s from the parent; S_AN = -V_s L_AN; S_NN = D^-1 - S_AN^T L_AN.
-__global__ void __launch_bounds__(NT) k_projinv(DevPlan P, const int32_t* list, const double* LB,
+__global__ void __launch_bounds__(NT_DOWN) k_projinv(DevPlan P, const int32_t* list, const double* LB,
                                                 double* S, double* Vs) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
-  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
-    extract_from_parent(P, v, S, Vs, sm);
+  with_staged_cols<NT_DOWN>(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    extract_from_parent<NT_DOWN>(P, v, S, Vs, sm);
     __syncthreads();
     const double* V = Vs + P.arena[v.s];
-    wg_gemm<false, true>(
+    wg_gemm_split<NT_DOWN, false, true>(
         v.A, v.N, v.A, [&](int i, int k) { return sym_packed(V, i, k, v.A); },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { S[v.an(i, j)] = -acc; }, false, sm);
     __syncthreads();
-    wg_gemm<true, true>(
+    wg_gemm_split<NT_DOWN, true, true>(
         v.N, v.N, v.A, [&](int i, int k) { return S[v.an(k, i)]; },
         [&](int k, int j) { return LB[v.an(k, j)]; },
         [&](int i, int j, double acc) { S[v.at(i, j)] = LB[v.at(i, j)] - acc; }, true, sm);

@@ -64,8 +64,9 @@ inline int64_t slot_doubles(Op op, const Level& L) {
 // at most kRegMax[c]; larger fronts run the blocked kernels.
 constexpr int kRegClasses = 5;
 constexpr int kRegMax[kRegClasses] = {16, 32, 64, 128, 192};
-// Largest front order for which the Hessian and inverse-Hessian
-// down-sweeps use the register kernels on a level of non-root fronts.
+// Largest front order for which the projected inverse and the Hessian
+// and inverse-Hessian down-sweeps use the register kernels on a level of
+// non-root fronts.
 constexpr int kDownRegMaxJ = 64;
 // Largest workgroup scratch (doubles per right-hand side) of one launch of
 // a schedule that runs independent fronts together.
@@ -103,7 +104,7 @@ struct mfb_plan_s {
   std::vector<int32_t> up_list, down_list;
   std::vector<mfb::Level> up_levels, down_levels;
   // class-split schedules: factor (leaf-to-root, by J), inverse of V_s
-  // (by A), completion and projected inverse (root-to-leaf, by J) and the
+  // (by A), completion (root-to-leaf, by J) and the projected inverse and
   // Hessian down-sweeps (by J on the levels that take the register
   // kernels, blocked elsewhere)
   mfb::ClassSched cs_factor, cs_vinv, cs_completion, cs_down;

@@ -252,8 +252,8 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   // and step through A (or J) columns one at a time, with most of the
   // register front idle when N is small: they beat the blocked kernels on
   // levels of small fronts (every J <= kDownRegMaxJ) and on levels of roots
-  // (every A = 0), and lose elsewhere.  The projected inverse runs its
-  // register kernel wherever a front fits.
+  // (every A = 0), and lose elsewhere; the projected inverse follows the
+  // same rule.
   auto down_reg_level = [&](const std::vector<int32_t>& list, const Level& L) {
     bool small = true, roots = true;
     for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
