@@ -63,6 +63,9 @@ CASES = {
     # fronts of order 63, 65, 80, 160 and 210: every register class and the
     # blocked kernels in one tree
     "arrow_mixed": lambda: P.block_arrow([5, 150, 20, 100, 3], 60),
+    # one dense front with 528 columns: the blocked kernels read the column
+    # offsets from global memory beyond the LDS cache of 512
+    "dense528": lambda: P.block_arrow([520], 8),
     "grid2d_24": lambda: get_config("grid2d_24"),
     "grid3d_8": lambda: get_config("grid3d_8"),
     "grid2d_128": lambda: get_config("grid2d_128"),
