@@ -1,8 +1,8 @@
 """Summarize rocprofv3 CSV output of bench.py runs into profiles/.
 
     python -m paper_1203_2742_amd.rocprof_summary --workload grid2d_128 \\
-        --trace gpurun_out/prof_trace --fetch gpurun_out/prof_fetch \\
-        --write gpurun_out/prof_write --command "<the rocprofv3 command lines>"
+        --trace out/prof_trace --fetch out/prof_fetch \\
+        --write out/prof_write --command "<the rocprofv3 command lines>"
 
 Writes profiles/kernels_<workload>.md (per-kernel duration statistics from
 --kernel-trace --stats, HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE)
