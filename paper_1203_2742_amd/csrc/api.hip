@@ -364,9 +364,8 @@ static mfb_status_t gather_blocks(mfb_factor_s* f, hipStream_t s, int k, const d
   const mfb_plan_s* p = f->plan;
   struct Ctx { const double* src; double* arena; int64_t ss, as; } ctx{src, arena, src_stride, arena_stride};
   if (p->d_gmap) {
-    const std::vector<Level> one{p->all_level};
     return run_levels(
-        f, MFB_K_GATHER_V, one, p->d_all_list, s, k, OP_COMPLETION,
+        f, MFB_K_GATHER_V, p->all_levels, p->d_all_list, s, k, OP_COMPLETION,
         [](mfb_factor_s* f, const int32_t*, dim3 g, hipStream_t s, int64_t, void* c) {
           Ctx* x = (Ctx*)c;
           const int64_t n = f->plan->update_doubles;

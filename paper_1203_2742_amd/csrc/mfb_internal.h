@@ -114,9 +114,9 @@ struct mfb_plan_s {
   mfb::ClassSched cs_compl_flat, cs_ihd_flat;
   // gmap[e]: CCS offset of the input entry that packed update-block entry e
   // holds (S_AA or T_AA blocks), empty beyond kGatherMapMax entries;
-  // all_level: every supernode as one level (canonical counts of a gather)
+  // all_levels: every supernode as one level (canonical counts of a gather)
   std::vector<int64_t> gmap;
-  mfb::Level all_level{};
+  std::vector<mfb::Level> all_levels;
   const int64_t* d_gmap = nullptr;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;

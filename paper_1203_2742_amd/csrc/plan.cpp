@@ -437,7 +437,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
         }
     }
   }
-  p->all_level = Level{0, ns, 0, 0, 0, 0, double(p->update_doubles), 0, 0, 0, 0};
+  p->all_levels.assign(1, Level{0, ns, 0, 0, 0, 0, double(p->update_doubles), 0, 0, 0, 0});
 
   // Canonical algorithmic flop counts per supernode (LAPACK conventions).
   for (int32_t k = 0; k < ns; ++k) {
