@@ -1412,7 +1412,7 @@ __global__ void __launch_bounds__(C::NTH) k_ihess_down_reg(DevPlan P, const int3
 using RegC0 = RegCfg<16, 16, 1, 1>;
 using RegC1 = RegCfg<16, 16, 2, 2>;
 using RegC2 = RegCfg<16, 16, 4, 4>;
-using RegC3 = RegCfg<16, 16, 8, 8>;
+using RegC3 = RegCfg<16, 32, 8, 4>;
 using RegC4 = RegCfg<16, 32, 12, 6>;
 static_assert(RegC0::MMAX == kRegMax[0] && RegC1::MMAX == kRegMax[1] && RegC2::MMAX == kRegMax[2] &&
                   RegC3::MMAX == kRegMax[3] && RegC4::MMAX == kRegMax[4] && kRegClasses == 5,
