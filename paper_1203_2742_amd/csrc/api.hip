@@ -81,7 +81,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h),
          iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list),
          iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list),
-         iGm = v64(p->gmap);
+         iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -118,6 +118,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_compl_flat.d_list = (const int32_t*)at(iCx);
   p->cs_ihd_flat.d_list = (const int32_t*)at(iCh);
   p->d_gmap = p->gmap.empty() ? nullptr : (const int64_t*)at(iGm);
+  p->cs_hdown.d_list = (const int32_t*)at(iHd);
   return MFB_OK;
 }
 
@@ -490,8 +491,31 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
       },
       &ctx);
   if (st) return st;
+  if (f->plan->hd_root >= 0) {
+    // the root front: two tile-parallel products (Hessian steps 2+3 with A = 0)
+    const mfb_plan_s* p = f->plan;
+    const int N = p->N[p->hd_root];
+    const unsigned tiles = unsigned((N + 63) / 64);
+    const int32_t* root = p->d_all_list + p->hd_root;
+    ProfRec rec{MFB_K_HESS_DOWN, 0, 1, k, 0.0, 0.0, nullptr, nullptr};
+    if (f->prof) {
+      canonical(MFB_K_HESS_DOWN, p->down_levels[0], k, &rec.bytes, &rec.flops);
+      rec.e0 = pool_event(f);
+      rec.e1 = pool_event(f);
+      if (!rec.e0 || !rec.e1) return MFB_EHIP;
+      if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
+    }
+    const dim3 grid(tiles, tiles, unsigned(k));
+    k_hess_down_root<0><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->LB, a.Kt, t, a.scr, int64_t(N) * N);
+    k_hess_down_root<1><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->LB, a.Kt, t, a.scr, int64_t(N) * N);
+    if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+    if (f->prof) {
+      if (hipEventRecord(rec.e1, s) != hipSuccess) return MFB_EHIP;
+      f->recs.push_back(rec);
+    }
+  }
   st = run_classes(
-      f, MFB_K_HESS_DOWN, f->plan->cs_down, s, k, OP_HDOWN,
+      f, MFB_K_HESS_DOWN, f->plan->cs_hdown, s, k, OP_HDOWN,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
         if (cls < kRegClasses)

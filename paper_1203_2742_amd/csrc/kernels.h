@@ -32,6 +32,9 @@ __global__ void k_completion(DevPlan, const int32_t*, const double*, double*, do
 __global__ void k_vinv(DevPlan, const int32_t*, const double*, double*, DevStatus*, double*,
                        int64_t);
 __global__ void k_gather_v(DevPlan, const int32_t*, const double*, double*, int64_t, int64_t);
+template <int STAGE>
+__global__ void k_hess_down_root(DevPlan, const int32_t*, const double*, const double*, double*, double*,
+                                 int64_t);
 __global__ void k_gather_map(const int64_t*, int64_t, const double*, double*, int64_t, int64_t);
 __global__ void k_product(DevPlan, const int32_t*, const double*, double*, double*, double*,
                           int64_t);

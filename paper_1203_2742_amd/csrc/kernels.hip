@@ -402,6 +402,41 @@ __global__ void __launch_bounds__(NT_DOWN) k_hess_down(DevPlan P, const int32_t*
   });
 }
 
+// Hessian steps 2+3 of a root front (A = 0, so T_NN = D^-1 K_NN D^-1 and
+// nothing else) with its two products spread over 64 x 64 output tiles, one
+// workgroup each (blockIdx.x, blockIdx.y: tile; blockIdx.z: right-hand
+// side).  STAGE 0: W = K_NN D^-1 into scratch (N x N per right-hand side);
+// STAGE 1: T_NN = D^-1 W, lower tiles.  The supernode is list[0].
+template <int STAGE>
+__global__ void __launch_bounds__(NT) k_hess_down_root(DevPlan P, const int32_t* list, const double* LB,
+                                                       const double* Kt, double* T, double* W,
+                                                       int64_t wstride) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TM;
+  if (STAGE == 1 && j0 > i0) return;  // a tile wholly above the diagonal (the whole workgroup)
+  const int64_t r = blockIdx.z;
+  with_staged_cols(SnView(P, list[0]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N;
+    const double* K = Kt + r * P.nnz;
+    double* t = T + r * P.nnz;
+    double* w = W + r * wstride;
+    auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
+    if (STAGE == 0)
+      tile_gemm<false, true>(
+          i0, j0, N, N, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv,
+          [&](int i, int j, double acc) { w[i + (int64_t)j * N] = acc; }, false, sm);
+    else
+      tile_gemm<false, true>(
+          i0, j0, N, N, N, Dinv, [&](int k, int j) { return w[k + (int64_t)j * N]; },
+          [&](int i, int j, double acc) { t[v.at(i, j)] = acc; }, true, sm);
+  });
+}
+template __global__ void k_hess_down_root<0>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                             double*, int64_t);
+template __global__ void k_hess_down_root<1>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                             double*, int64_t);
+
 // ---------------------------------------------------------------------------
 // Inverse Hessian steps 1 and 2, block form of Algorithm 5.2, for one
 // front given V'_s = T_{A_s A_s} in the arena; M_AN = T_AN + V' L;

@@ -112,6 +112,11 @@ struct mfb_plan_s {
   // the inverse Hessian's steps 1+2 likewise, in launches whose workgroup
   // scratch stays within kFlatScratch doubles per right-hand side
   mfb::ClassSched cs_compl_flat, cs_ihd_flat;
+  // the Hessian down-sweep: cs_down without its root level when that is one
+  // front with A = 0 and N > kDownRegMaxJ (hd_root, else -1), which runs as
+  // tile-parallel products instead
+  mfb::ClassSched cs_hdown;
+  int32_t hd_root = -1;
   // gmap[e]: CCS offset of the input entry that packed update-block entry e
   // holds (S_AA or T_AA blocks), empty beyond kGatherMapMax entries;
   // all_levels: every supernode as one level (canonical counts of a gather)

@@ -412,6 +412,16 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   }
   make_classes(p->down_list, p->down_levels, false, false, p->cs_completion);
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
+  p->cs_hdown = p->cs_down;
+  p->hd_root = -1;
+  if (!p->down_levels.empty() && p->down_levels[0].count == 1) {
+    const int32_t s = p->down_list[p->down_levels[0].begin];
+    if (p->J[s] == p->N[s] && p->N[s] > kDownRegMaxJ) {
+      p->hd_root = s;
+      auto& sg = p->cs_hdown.segs;
+      sg.erase(std::remove_if(sg.begin(), sg.end(), [](const ClassSeg& g) { return g.level == 0; }), sg.end());
+    }
+  }
 
   // Source offsets of the packed update-block entries: entry (x, y) of
   // supernode s's A_s x A_s block is S(A_s[x], A_s[y]), which lies in the

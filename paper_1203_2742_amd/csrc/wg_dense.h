@@ -152,6 +152,59 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const
   }
 }
 
+// One 64 x 64 output tile (i0, j0) of wg_gemm's product by one 256-thread
+// workgroup, for products spread over many workgroups (one tile each).
+template <bool AK = false, bool BK = false, class FA, class FB, class EPI>
+__device__ __forceinline__ void tile_gemm(int i0, int j0, int M, int N, int K, const FA& fa, const FB& fb,
+                                          const EPI& epi, bool lower, double* sm) {
+  double* As = sm;
+  double* Bs = sm + KC * LDS_TM;
+  const int tid = threadIdx.x;
+  constexpr int PER = KC * TM / NT;
+  auto slot_a = [&](int q, int& i, int& k) {
+    const int e = tid + q * NT;
+    i = AK ? e / KC : e & (TM - 1);
+    k = AK ? e & (KC - 1) : e / TM;
+  };
+  auto slot_b = [&](int q, int& j, int& k) {
+    const int e = tid + q * NT;
+    j = BK ? e / KC : e & (TM - 1);
+    k = BK ? e & (KC - 1) : e / TM;
+  };
+  MfmaTile T(tid);
+  double ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, ka, j, kb;
+      slot_a(q, i, ka);
+      slot_b(q, j, kb);
+      ra[q] = (i0 + i < M && k0 + ka < K) ? fa(i0 + i, k0 + ka) : 0.0;
+      rb[q] = (j0 + j < N && k0 + kb < K) ? fb(k0 + kb, j0 + j) : 0.0;
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, ka, j, kb;
+      slot_a(q, i, ka);
+      slot_b(q, j, kb);
+      As[ka * LDS_TM + i] = ra[q];
+      Bs[kb * LDS_TM + j] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + KC < K) fetch(k0 + KC);
+    T.chunk(As, Bs);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int gi = i0 + T.row_of(e), gj = j0 + T.col_of(e);
+    if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, T.get(e));
+  }
+}
+
 // wg_gemm for a workgroup of NTH = TEAMS * NT threads: the teams of NT
 // threads share every output tile and take its k-chunks in turn (team t
 // the chunks t, t + TEAMS, ...), each staging its own chunk in LDS; the
