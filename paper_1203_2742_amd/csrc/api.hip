@@ -35,6 +35,7 @@ static int64_t rhs_scratch(const mfb_plan_s* p) {
   int64_t flat = 0;
   for (const ClassSeg& g : p->cs_ihd_flat.segs)
     flat = std::max(flat, int64_t(g.lv.count) * std::max<int64_t>(1, slot_doubles(OP_IHDOWN, g.lv)));
+  if (p->ihd_root >= 0) flat = std::max(flat, 2 * int64_t(p->N[p->ihd_root]) * p->N[p->ihd_root]);
   return std::max({plan_scratch(p, OP_HUP), plan_scratch(p, OP_HDOWN), flat, plan_scratch(p, OP_IHUP),
                    int64_t(1)});
 }
@@ -564,6 +565,31 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   // gathers), then steps 1+2 of all fronts, which are independent
   st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd);
   if (st) return st;
+  if (f->plan->ihd_root >= 0) {
+    // the root front: three tile-parallel products (steps 1+2 with A = 0)
+    const mfb_plan_s* p = f->plan;
+    const int N = p->N[p->ihd_root];
+    const unsigned tiles = unsigned((N + 63) / 64);
+    const int32_t* root = p->d_all_list + p->ihd_root;
+    ProfRec rec{MFB_K_IHESS_DOWN, 0, 1, k, 0.0, 0.0, nullptr, nullptr};
+    if (f->prof) {
+      canonical(MFB_K_IHESS_DOWN, p->down_levels[0], k, &rec.bytes, &rec.flops);
+      rec.e0 = pool_event(f);
+      rec.e1 = pool_event(f);
+      if (!rec.e0 || !rec.e1) return MFB_EHIP;
+      if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
+    }
+    const dim3 grid(tiles, tiles, unsigned(k));
+    const int64_t ws = 2 * int64_t(N) * N;
+    k_ihess_down_root<0><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
+    k_ihess_down_root<1><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
+    k_ihess_down_root<2><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
+    if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+    if (f->prof) {
+      if (hipEventRecord(rec.e1, s) != hipSuccess) return MFB_EHIP;
+      f->recs.push_back(rec);
+    }
+  }
   st = run_classes(
       f, MFB_K_IHESS_DOWN, f->plan->cs_ihd_flat, s, k, OP_IHDOWN,
       [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {

@@ -35,6 +35,9 @@ __global__ void k_gather_v(DevPlan, const int32_t*, const double*, double*, int6
 template <int STAGE>
 __global__ void k_hess_down_root(DevPlan, const int32_t*, const double*, const double*, double*, double*,
                                  int64_t);
+template <int STAGE>
+__global__ void k_ihess_down_root(DevPlan, const int32_t*, const double*, const double*, double*, double*,
+                                  int64_t);
 __global__ void k_gather_map(const int64_t*, int64_t, const double*, double*, int64_t, int64_t);
 __global__ void k_product(DevPlan, const int32_t*, const double*, double*, double*, double*,
                           int64_t);

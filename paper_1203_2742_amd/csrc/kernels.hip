@@ -437,6 +437,50 @@ template __global__ void k_hess_down_root<0>(DevPlan, const int32_t*, const doub
 template __global__ void k_hess_down_root<1>(DevPlan, const int32_t*, const double*, const double*, double*,
                                              double*, int64_t);
 
+// Inverse Hessian steps 1+2 of a root front (A = 0, so K_NN = D T_NN D with
+// D = C C^T and nothing else), tile-parallel like k_hess_down_root.
+// STAGE 0: D = C C^T into scratch; STAGE 1: W = T_NN D into scratch;
+// STAGE 2: K_NN = D W, lower tiles.  Scratch: 2 N^2 per right-hand side
+// (D, then W).  The supernode is list[0].
+template <int STAGE>
+__global__ void __launch_bounds__(NT) k_ihess_down_root(DevPlan P, const int32_t* list, const double* R,
+                                                        const double* T, double* Kt, double* W,
+                                                        int64_t wstride) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TM;
+  if (STAGE == 2 && j0 > i0) return;  // a tile wholly above the diagonal (the whole workgroup)
+  const int64_t r = blockIdx.z;
+  with_staged_cols(SnView(P, list[0]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N;
+    const double* t = T + r * P.nnz;
+    double* K = Kt + r * P.nnz;
+    double* Dm = W + r * wstride;
+    double* Wm = Dm + (int64_t)N * N;
+    if (STAGE == 0)
+      tile_gemm(
+          i0, j0, N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
+          [&](int k, int j) { return k <= j ? R[v.at(j, k)] : 0.0; },
+          [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false, sm);
+    else if (STAGE == 1)
+      tile_gemm<false, true>(
+          i0, j0, N, N, N, [&](int i, int k) { return t[v.nn(i, k)]; },
+          [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
+          [&](int i, int j, double acc) { Wm[i + (int64_t)j * N] = acc; }, false, sm);
+    else
+      tile_gemm<false, true>(
+          i0, j0, N, N, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
+          [&](int k, int j) { return Wm[k + (int64_t)j * N]; },
+          [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
+  });
+}
+template __global__ void k_ihess_down_root<0>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                              double*, int64_t);
+template __global__ void k_ihess_down_root<1>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                              double*, int64_t);
+template __global__ void k_ihess_down_root<2>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                              double*, int64_t);
+
 // ---------------------------------------------------------------------------
 // Inverse Hessian steps 1 and 2, block form of Algorithm 5.2, for one
 // front given V'_s = T_{A_s A_s} in the arena; M_AN = T_AN + V' L;

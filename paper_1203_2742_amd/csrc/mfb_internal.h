@@ -117,6 +117,9 @@ struct mfb_plan_s {
   // tile-parallel products instead
   mfb::ClassSched cs_hdown;
   int32_t hd_root = -1;
+  // that front when it was also taken out of cs_ihd_flat (the inverse
+  // Hessian's steps 1+2 of it then run tile-parallel too), else -1
+  int32_t ihd_root = -1;
   // gmap[e]: CCS offset of the input entry that packed update-block entry e
   // holds (S_AA or T_AA blocks), empty beyond kGatherMapMax entries;
   // all_levels: every supernode as one level (canonical counts of a gather)

@@ -414,12 +414,23 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
   p->cs_hdown = p->cs_down;
   p->hd_root = -1;
+  p->ihd_root = -1;
   if (!p->down_levels.empty() && p->down_levels[0].count == 1) {
     const int32_t s = p->down_list[p->down_levels[0].begin];
     if (p->J[s] == p->N[s] && p->N[s] > kDownRegMaxJ) {
       p->hd_root = s;
       auto& sg = p->cs_hdown.segs;
       sg.erase(std::remove_if(sg.begin(), sg.end(), [](const ClassSeg& g) { return g.level == 0; }), sg.end());
+      // likewise the inverse Hessian's steps 1+2 for that front (its own
+      // segment of the all-fronts schedule: the only front of its kind there)
+      auto& sh = p->cs_ihd_flat.segs;
+      const size_t before = sh.size();
+      sh.erase(std::remove_if(sh.begin(), sh.end(),
+                              [&](const ClassSeg& g) {
+                                return g.lv.count == 1 && p->cs_ihd_flat.list[g.lv.begin] == s;
+                              }),
+               sh.end());
+      p->ihd_root = sh.size() < before ? s : -1;
     }
   }
 
