@@ -965,11 +965,16 @@ __device__ __forceinline__ void stage_columns(int N, int k0, double* Ls, const V
 // fronts of order above 64 take them in blocks of KCL (two barriers per
 // block; the extra small solve per block does not pay on smaller fronts),
 // smaller ones one step at a time.  `lds` holds kCongLds<C> doubles.
+// With A = 0 (a root front) every l_k is zero and the congruences are the
+// identity, so none is taken; the early return is uniform over the
+// workgroup and leaves no LDS access unfenced (the callers' other steps
+// bracket their own LDS use with barriers).
 template <class C>
 constexpr int kCongLds = C::MMAX > 64 ? 6 * KCL * C::MMAX : (4 + KCL) * C::MMAX;
 template <class C, bool LO>
 __device__ __forceinline__ void congruences(RegFront<C, LO>& M, const SnView& v, const double* LB, double sg,
                                             double* lds) {
+  if (v.A == 0) return;
   auto stage = [&](int k0, double* ls) {
     stage_columns<C>(v.N, k0, ls, [&](int i, int kk) {
       const bool ok = i >= v.N && i < v.J;
