@@ -51,6 +51,20 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+
+def _roots_mixed():
+    sizes = [100, 150, 250]
+    n = sum(sizes) + 40
+    mask = np.zeros((n, n), dtype=bool)
+    o = 0
+    for b in sizes:
+        mask[o:o + b, o:o + b] = True
+        o += b
+    for j in range(o, n):
+        mask[j:min(n, j + 4), j] = True
+    return P.pattern_from_dense_mask(mask)
+
+
 CASES = {
     "fig1": lambda: load_fig1()["pattern"],
     "band200": lambda: get_config("band200"),
@@ -66,6 +80,10 @@ CASES = {
     # one dense front with 528 columns: the blocked kernels read the column
     # offsets from global memory beyond the LDS cache of 512
     "dense528": lambda: P.block_arrow([520], 8),
+    # a forest of roots (A = 0) of orders 100, 150 and 250 beside a band:
+    # root fronts of several register classes and of the blocked kernels on
+    # one level, where the up-sweeps take no congruences
+    "roots_mixed": lambda: _roots_mixed(),
     "grid2d_24": lambda: get_config("grid2d_24"),
     "grid3d_8": lambda: get_config("grid3d_8"),
     "grid2d_128": lambda: get_config("grid2d_128"),
