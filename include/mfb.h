@@ -78,6 +78,10 @@ typedef struct mfb_factor_s* mfb_factor_t;
                                       level from the parents instead of in one
                                       launch (plans with more than 2^25 block
                                       entries never keep the map) */
+#define MFB_PLAN_WIDE_LOW 4u  /* run the tile-parallel wide-front kernels from
+                                 front order 65 instead of 513 (fronts with at
+                                 most 64 columns and a nonempty ancestor set);
+                                 for testing those kernels on small patterns */
 
 typedef struct {
   int64_t n;                 /* order of X */

@@ -27,9 +27,18 @@ static bool up_op(Op op) {
 static int64_t plan_scratch(const mfb_plan_s* p, Op op) {
   return scratch_doubles(op, up_op(op) ? p->up_levels : p->down_levels);
 }
+// Largest workgroup scratch of one launch of a schedule of independent
+// fronts (the blocked segments).
+static int64_t flat_scratch(const ClassSched& cs, Op op) {
+  int64_t m = 0;
+  for (const ClassSeg& g : cs.segs)
+    if (g.cls == kRegClasses) m = std::max(m, int64_t(g.lv.count) * std::max<int64_t>(1, slot_doubles(op, g.lv)));
+  return m;
+}
 static int64_t factor_scratch(const mfb_plan_s* p) {
   return std::max({plan_scratch(p, OP_FACTOR), plan_scratch(p, OP_PRODUCT),
-                   plan_scratch(p, OP_COMPLETION), plan_scratch(p, OP_VINV), int64_t(1)});
+                   flat_scratch(p->cs_compl_flat, OP_COMPLETION), flat_scratch(p->cs_vinv, OP_VINV),
+                   int64_t(1)});
 }
 static int64_t rhs_scratch(const mfb_plan_s* p) {
   int64_t flat = 0;
@@ -80,9 +89,10 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iCb = v32(p->colbase), iCol = v64(p->col), iRb = v32(p->relbase), iRel = v32(p->rel),
          iAr = v64(p->arena), iVl = v32(p->vlabel), iUp = v32(p->up_list), iDn = v32(p->down_list),
          iAll = v32(all), iCidx = v32(colidx), iColptr = v64(p->colptr_h),
-         iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list), iCc = v32(p->cs_completion.list),
+         iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list),
          iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list),
-         iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list);
+         iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
+         iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -114,12 +124,14 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->d_colptr = (const int64_t*)at(iColptr);
   p->cs_factor.d_list = (const int32_t*)at(iCf);
   p->cs_vinv.d_list = (const int32_t*)at(iCv);
-  p->cs_completion.d_list = (const int32_t*)at(iCc);
   p->cs_down.d_list = (const int32_t*)at(iCd);
   p->cs_compl_flat.d_list = (const int32_t*)at(iCx);
   p->cs_ihd_flat.d_list = (const int32_t*)at(iCh);
   p->d_gmap = p->gmap.empty() ? nullptr : (const int64_t*)at(iGm);
   p->cs_hdown.d_list = (const int32_t*)at(iHd);
+  p->cs_factor.d_pre = (const int32_t*)at(iPf);
+  p->cs_down.d_pre = (const int32_t*)at(iPd);
+  p->cs_hdown.d_pre = (const int32_t*)at(iPh);
   return MFB_OK;
 }
 
@@ -328,11 +340,14 @@ static mfb_status_t run_levels(mfb_factor_s* f, int kid, const std::vector<Level
 
 // As run_levels, over a class-split schedule: one launch per (level,
 // class) segment; register classes get their own kernels.
+// The launcher gets the segment: its class (g.cls: a register class,
+// kRegClasses for the blocked kernels, kWide for the wide-front launches),
+// its fronts cs.d_list + g.lv.begin and, for a wide segment, its tile
+// numbering in cs.d_pre.
+typedef void (*SegLaunch)(mfb_factor_s*, const ClassSched&, const ClassSeg&, dim3, hipStream_t, int64_t,
+                          void*);
 static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, hipStream_t s, int k,
-                                Op op,
-                                void (*launch)(mfb_factor_s*, int, const int32_t*, dim3, hipStream_t,
-                                               int64_t, void*),
-                                void* ctx) {
+                                Op op, SegLaunch launch, void* ctx) {
   for (const ClassSeg& g : cs.segs) {
     const Level& L = g.lv;
     dim3 grid(unsigned(L.count), unsigned(k));
@@ -348,7 +363,7 @@ static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, 
     // intermediate products
     const bool reg_scratch = op == OP_HDOWN || op == OP_IHDOWN;
     const int64_t slot = g.cls < kRegClasses && !reg_scratch ? 1 : slot_doubles(op, L);
-    launch(f, g.cls, cs.d_list + L.begin, grid, s, std::max<int64_t>(1, slot), ctx);
+    launch(f, cs, g, grid, s, std::max<int64_t>(1, slot), ctx);
     if (hipGetLastError() != hipSuccess) return MFB_EHIP;
     if (f->prof) {
       if (hipEventRecord(rec.e1, s) != hipSuccess) return MFB_EHIP;
@@ -390,23 +405,31 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
   if (!f || (!x && f->plan->nnz)) return MFB_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
+  // the cached state describes the previous X until this factor is enqueued
+  f->has_factor = f->s_valid = f->vinv_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* x; } ctx{x};
   mfb_status_t st = run_classes(
       f, MFB_K_FACTOR, f->plan->cs_factor, s, 1, OP_FACTOR,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
-        if (cls < kRegClasses)
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
+        if (cls < kRegClasses) {
           launch_factor_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U, f->part,
                             f->st);
-        else
-          k_factor<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
-                                           f->part, f->st, f->scratch, slot);
+        } else if (cls == kWide) {
+          k_factor<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
+                                                 f->part, f->st, f->scratch, slot);
+          launch_wide_update(0, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                             sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+        } else {
+          k_factor<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
+                                                  f->part, f->st, f->scratch, slot);
+        }
       },
       &ctx);
   if (st) return st;
   f->has_factor = true;
-  f->s_valid = false;
-  f->vinv_valid = false;
   return launched();
 }
 
@@ -423,9 +446,14 @@ static mfb_status_t ensure_projinv(mfb_factor_s* f, hipStream_t s) {
   if (f->s_valid) return MFB_OK;
   mfb_status_t st = run_classes(
       f, MFB_K_PROJINV, f->plan->cs_down, s, 1, OP_FACTOR,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t, void*) {
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t, void*) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
         if (cls < kRegClasses)
           launch_projinv_reg(cls, g, s, f->plan->dev, list, f->LB, f->S, f->Vs);
+        else if (cls == kWide)
+          launch_wide_projinv(s, f->plan->dev, list, cs.d_pre + sg.aa_off, cs.d_pre + sg.rt_off, sg.lv.count,
+                              sg.n_aa, sg.n_rt, f->LB, f->S, f->Vs);
         else
           k_projinv<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
       },
@@ -482,13 +510,21 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
   struct Ctx { const double* y; double* t; RhsArena a; } ctx{y, t, a};
   st = run_classes(
       f, MFB_K_HESS_UP, f->plan->cs_factor, s, k, OP_HUP,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
         Ctx* x = (Ctx*)c;
-        if (cls < kRegClasses)
+        if (cls < kRegClasses) {
           launch_hess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua, x->a.upd);
-        else
-          k_hess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua,
-                                            x->a.upd, x->a.scr, slot);
+        } else if (cls == kWide) {
+          k_hess_up<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua,
+                                                  x->a.upd, x->a.scr, slot);
+          launch_wide_update(1, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                             sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+        } else {
+          k_hess_up<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua,
+                                                   x->a.upd, x->a.scr, slot);
+        }
       },
       &ctx);
   if (st) return st;
@@ -517,11 +553,17 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
   }
   st = run_classes(
       f, MFB_K_HESS_DOWN, f->plan->cs_hdown, s, k, OP_HDOWN,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
         Ctx* x = (Ctx*)c;
         if (cls < kRegClasses)
           launch_hess_down_reg(cls, g, s, f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                x->a.upd, x->a.scr, slot);
+        else if (cls == kWide)
+          launch_wide_hess_down(int(g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off, cs.d_pre + sg.rt_off,
+                                sg.lv.count, sg.n_aa, sg.n_rt, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua, x->a.upd,
+                                x->a.scr, slot);
         else
           k_hess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                               x->a.upd, x->a.scr, slot);
@@ -535,7 +577,9 @@ static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
   if (f->vinv_valid) return MFB_OK;
   mfb_status_t st = run_classes(
       f, MFB_K_VINV, f->plan->cs_vinv, s, 1, OP_VINV,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void*) {
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void*) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
         if (cls < kRegClasses)
           launch_vinv_reg(cls, g, s, f->plan->dev, list, f->Vs, f->Vi, f->st);
         else
@@ -592,7 +636,9 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   }
   st = run_classes(
       f, MFB_K_IHESS_DOWN, f->plan->cs_ihd_flat, s, k, OP_IHDOWN,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
         Ctx* x = (Ctx*)c;
         if (cls < kRegClasses)
           launch_ihess_down_reg(cls, g, s, f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
@@ -605,13 +651,21 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   if (st) return st;
   st = run_classes(
       f, MFB_K_IHESS_UP, f->plan->cs_factor, s, k, OP_IHUP,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
         Ctx* x = (Ctx*)c;
-        if (cls < kRegClasses)
+        if (cls < kRegClasses) {
           launch_ihess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua, x->a.upd);
-        else
-          k_ihess_up<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
-                                             x->a.upd, x->a.scr, slot);
+        } else if (cls == kWide) {
+          k_ihess_up<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
+                                                   x->a.upd, x->a.scr, slot);
+          launch_wide_update(2, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                             sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+        } else {
+          k_ihess_up<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
+                                                    x->a.upd, x->a.scr, slot);
+        }
       },
       &ctx);
   if (st) return st;
@@ -622,6 +676,7 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   if (!f || (!sin && f->plan->nnz)) return MFB_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
+  f->has_factor = f->s_valid = f->vinv_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* s; } ctx{sin};
   // V_s = S_{A_s A_s} for every supernode (root-to-leaf gathers), then the
@@ -630,7 +685,9 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   if (st) return st;
   st = run_classes(
       f, MFB_K_COMPLETION, f->plan->cs_compl_flat, s, 1, OP_COMPLETION,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
         if (cls < kRegClasses)
           launch_completion_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
                                 f->Vi, f->part, f->st);
@@ -654,12 +711,20 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
   struct Ctx { double* x; } ctx{x};
   mfb_status_t st = run_classes(
       f, MFB_K_PRODUCT, f->plan->cs_factor, s, 1, OP_PRODUCT,
-      [](mfb_factor_s* f, int cls, const int32_t* list, dim3 g, hipStream_t s, int64_t slot, void* c) {
-        if (cls < kRegClasses)
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
+        if (cls < kRegClasses) {
           launch_product_reg(cls, g, s, f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U);
-        else
-          k_product<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U, f->scratch,
-                                            slot);
+        } else if (cls == kWide) {
+          k_product<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
+                                                  f->scratch, slot);
+          launch_wide_update(0, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                             sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+        } else {
+          k_product<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
+                                                   f->scratch, slot);
+        }
       },
       &ctx);
   if (st) return st;

@@ -17,6 +17,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "front.h"
 #include "reg_front.h"
 #include "wg_dense.h"
 
@@ -25,206 +26,23 @@ namespace mfb {
 static_assert(NT == NT_LAUNCH, "launch width");
 static_assert(SMEM_DOUBLES >= (NT_DOWN / NT) * 2 * KC * LDS_TM, "team GEMM staging fits the workgroup scratch");
 
-__device__ void report(DevStatus* st, int code, long long label) {
-  atomicMax(&st->code, code);
-  atomicMin(&st->bad, (unsigned long long)label);
-}
 
-struct SnView {
-  int s, N, A, J;
-  const int64_t* col;  // CCS diagonal offsets of the supernode's columns
-  const int32_t* vl;   // user labels of the supernode's columns
-  __device__ SnView(const DevPlan& P, int s_) : s(s_) {
-    N = P.ncol[s];
-    J = P.nrow[s];
-    A = J - N;
-    col = P.col + P.colbase[s];
-    vl = P.vlabel + P.colbase[s];
-  }
-  // element (r, c), r >= c, of a CCS-ordered array restricted to the panel
-  __device__ __forceinline__ int64_t at(int r, int c) const { return col[c] + (r - c); }
-  // symmetric NN access
-  __device__ __forceinline__ int64_t nn(int i, int j) const { return i >= j ? at(i, j) : at(j, i); }
-  // AN block entry (x in A, c in N)
-  __device__ __forceinline__ int64_t an(int x, int c) const { return col[c] + (N + x - c); }
+// Lower-triangle accessor of a packed symmetric A x A block.
+struct PackedLower {
+  double* u;
+  int A;
+  __device__ __forceinline__ double& operator()(int i, int j) const { return u[pk(i, j, A)]; }
 };
 
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-
-// Extend-add of the children's packed update blocks taken from `ua`.
-// Entries landing in N_s columns go to the panel F (leading dimension J);
-// the others (rows and columns in A_s) go to the packed block Us.  One
-// child at a time (fixed order), so every target is written once per pass;
-// a child's entries are spread over the whole workgroup (flat index over
-// its A_c x A_c square, lower entries taken), with its relative indices
-// staged in LDS (`sm`: at least 2048 doubles) when they fit.
-template <int NTH = NT>
-__device__ __forceinline__ void assemble_children(const DevPlan& P, const SnView& v, const double* ua,
-                                                  double* F, double* Us, double* sm) {
-  int* srl = reinterpret_cast<int*>(sm);
-  constexpr int CAP = 4096;
-  for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
-    const int c = P.cidx[t];
-    const int Ac = P.nrow[c] - P.ncol[c];
-    if (Ac == 0) continue;  // (a child always has ancestors)
-    const int32_t* rl = P.rel + P.relbase[c];
-    const double* Uc = ua + P.arena[c];
-    const bool st = Ac <= CAP;
-    if (st)
-      for (int i = threadIdx.x; i < Ac; i += NTH) srl[i] = rl[i];
-    __syncthreads();
-    // flat walk of the Ac x Ac square as in extract_from_parent, BATCH
-    // entries per round; the targets of one child are distinct
-    auto pass = [&](const auto& R) {
-      constexpr int BATCH = 4;
-      const int dy = NTH / Ac, dx = NTH - dy * Ac;
-      int y = int(threadIdx.x) / Ac, x = int(threadIdx.x) - y * Ac;
-      while (y < Ac) {
-        double* q[BATCH];
-        const double* u_[BATCH];
-        bool ok[BATCH];
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-          ok[u] = y < Ac && x >= y;
-          const int rx = ok[u] ? R(x) : 0, ry = ok[u] ? R(y) : 0;
-          q[u] = !ok[u] ? F : ry < v.N ? F + (rx + (int64_t)ry * v.J) : Us + pk(rx - v.N, ry - v.N, v.A);
-          u_[u] = ok[u] ? Uc + pk(x, y, Ac) : Uc;
-          x += dx;
-          y += dy;
-          if (x >= Ac) {
-            x -= Ac;
-            ++y;
-          }
-        }
-        double a[BATCH], b[BATCH];
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-          a[u] = *q[u];
-          b[u] = *u_[u];
-        }
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u)
-          if (ok[u]) *q[u] = a[u] + b[u];
-      }
-    };
-    if (st)
-      pass([&](int i) { return srl[i]; });
-    else
-      pass([&](int i) { return rl[i]; });
-    __syncthreads();
-  }
-}
-
-// V_s = E^T [S_NN S_AN^T; S_AN V_p] E (eq. e-sn-gradient-2): gather the
-// packed A_s x A_s block from the parent's CCS columns of `src` and the
-// parent's packed block in `arena`, into this supernode's packed block.
-// Entries are spread over the whole workgroup (flat index over the A x A
-// square, lower entries taken); the relative indices and the parent's
-// column offsets are staged in LDS (`sm`: at least 4096 doubles) when they
-// fit.  Ends with a barrier.
-template <int NTH = NT>
-__device__ __forceinline__ void extract_from_parent(const DevPlan& P, const SnView& v, const double* src,
-                                                    double* arena, double* sm) {
-  if (v.A == 0) return;
-  const int A = v.A;
-  const int p = P.parent[v.s];
-  const int Np = P.ncol[p], Ap = P.nrow[p] - Np;
-  const int64_t* colp = P.col + P.colbase[p];
-  const int32_t* rl = P.rel + P.relbase[v.s];
-  const double* Vp = arena + P.arena[p];
-  double* Vo = arena + P.arena[v.s];
-  int* srl = reinterpret_cast<int*>(sm);
-  int64_t* scp = reinterpret_cast<int64_t*>(sm + 2048);
-  const bool st = A <= 4096 && Np <= 2048;
-  if (st) {
-    for (int i = threadIdx.x; i < A; i += NTH) srl[i] = rl[i];
-    for (int i = threadIdx.x; i < Np; i += NTH) scp[i] = colp[i];
-  }
-  __syncthreads();
-  // Each thread walks the flat index tid, tid + NTH, ... of the A x A
-  // square as (x, y) = (e mod A, e div A), stepped without divisions, and
-  // issues BATCH loads (masked entries load a valid dummy) before storing.
-  auto pass = [&](const auto& R, const auto& CP) {
-    constexpr int BATCH = 8;
-    const int dy = NTH / A, dx = NTH - dy * A;
-    int y = int(threadIdx.x) / A, x = int(threadIdx.x) - y * A;
-    while (y < A) {
-      const double* q[BATCH];
-      int64_t o[BATCH];
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) {
-        const bool ok = y < A && x >= y;
-        const int rx = ok ? R(x) : 0, ry = ok ? R(y) : 0;
-        q[u] = !ok ? src : ry < Np ? src + CP(ry) + (rx - ry) : Vp + pk(rx - Np, ry - Np, Ap);
-        o[u] = ok ? pk(x, y, A) : -1;
-        x += dx;
-        y += dy;
-        if (x >= A) {
-          x -= A;
-          ++y;
-        }
-      }
-      double val[BATCH];
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) val[u] = *q[u];
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u)
-        if (o[u] >= 0) Vo[o[u]] = val[u];
-    }
-  };
-  if (st)
-    pass([&](int i) { return srl[i]; }, [&](int i) { return scp[i]; });
-  else
-    pass([&](int i) { return rl[i]; }, [&](int i) { return colp[i]; });
-  __syncthreads();
-}
-
-template <int NTH = NT>
-__device__ __forceinline__ void zero_packed(double* U, int A) {
+// VI <- C^-1 (lower, packed) for a packed symmetric positive definite
+// A x A block V = C C^T, in place in VI (no scratch): copy V, then the
+// Cholesky factor and its triangular inverse on the packed triangle.
+__device__ __forceinline__ void packed_tri_inverse(const double* V, double* VI, int A, double* sm, int* fail) {
   const int64_t m = (int64_t)A * (A + 1) / 2;
-  for (int64_t e = threadIdx.x; e < m; e += NTH) U[e] = 0.0;
-}
-
-__device__ __forceinline__ double* slot_ptr(double* wsb, int64_t slot) {
-  return wsb + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * slot;
-}
-
-// Runs body(v) with the supernode's column offsets copied to LDS (`colc`)
-// when N <= kColCache, so every CCS address is formed without a dependent
-// global load, else with the offsets read from global memory.
-constexpr int kColCache = 512;
-template <int NTH = NT, class BODY>
-__device__ __forceinline__ void with_staged_cols(SnView v, int64_t* colc, const BODY& body) {
-  if (v.N <= kColCache) {
-    for (int i = threadIdx.x; i < v.N; i += NTH) colc[i] = v.col[i];
-    __syncthreads();
-    v.col = colc;
-    body(v);
-  } else {
-    body(v);
-  }
-}
-
-// Inverse of a symmetric positive definite A x A block given by the functor
-// `Vf` (full access), through its Cholesky factor G: V^-1 = G^-T G^-1.  The
-// lower triangle of the result is passed to `out(i, j, value)`.  Scratch: 2 A^2.
-template <class VF, class OUT>
-__device__ void wg_spd_inverse(int A, const VF& Vf, const OUT& out, double* ws, double* sm,
-                               int* fail) {
-  double* G = ws;
-  double* Gi = ws + (int64_t)A * A;
-  for (int64_t e = threadIdx.x; e < (int64_t)A * A; e += NT) {
-    const int i = int(e % A), j = int(e / A);
-    if (i >= j) G[e] = Vf(i, j);
-  }
+  for (int64_t e = threadIdx.x; e < m; e += NT) VI[e] = V[e];
   __syncthreads();
-  wg_potrf_panel(G, A, A, A, sm, fail);
-  wg_trtri([&](int i, int j) { return G[i + (int64_t)j * A]; }, A, Gi, A, sm);
-  wg_gemm<true, true>(
-      A, A, A, [&](int i, int k) { return Gi[k + (int64_t)i * A]; },
-      [&](int k, int j) { return Gi[k + (int64_t)j * A]; }, out, true, sm);
-  __syncthreads();
+  wg_potrf_acc<true>(PackedLower{VI, A}, A, A, sm, fail);
+  wg_trtri_inplace<true>(PackedLower{VI, A}, A, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,6 +50,9 @@ __device__ void wg_spd_inverse(int A, const VF& Vf, const OUT& out, double* ws, 
 // F = [X_NN X_AN^T; X_AN 0] + sum_children E U_c E^T; C = chol(F11);
 // B = F21 C^-T; U_s = F22 - B B^T; L_AN = B C^-1; D^-1 = C^-T C^-1.
 // Scratch per workgroup: J*N + N*N.
+// PANEL: the front's A x A update block is left to the tile-parallel
+// update kernel (k_wide_update); only the panel columns are assembled.
+template <bool PANEL>
 __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, const double* x,
                                                double* R, double* LB, double* U, double* part,
                                                DevStatus* st, double* wsb, int64_t slot) {
@@ -247,9 +68,12 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
       const int r = int(e % v.J), c = int(e / v.J);
       F[e] = r >= c ? x[v.at(r, c)] : 0.0;
     }
-    zero_packed(Us, v.A);
+    if (!PANEL) zero_packed(Us, v.A);
     __syncthreads();
-    assemble_children(P, v, U, F, Us, sm);
+    if (PANEL)
+      assemble_children_panel(P, v, U, F);
+    else
+      assemble_children(P, v, U, F, Us, sm);
     wg_potrf_panel(F, v.J, v.J, v.N, sm, &fail);
     // Cholesky panel -> R, log det contribution 2 sum log C_kk
     double lg = 0.0;
@@ -264,10 +88,11 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
       if (fail >= 0) report(st, MFB_ENOTPD, v.vl[fail]);
     }
     // U_s = F22 - B B^T
-    wg_gemm(
-        v.A, v.A, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
-        [&](int k, int j) { return F[(v.N + j) + (int64_t)k * v.J]; },
-        [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
+    if (!PANEL)
+      wg_gemm(
+          v.A, v.A, v.N, [&](int i, int k) { return F[(v.N + i) + (int64_t)k * v.J]; },
+          [&](int k, int j) { return F[(v.N + j) + (int64_t)k * v.J]; },
+          [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
     // C^-1
     wg_trtri([&](int i, int j) { return F[i + (int64_t)j * v.J]; }, v.N, Ci, v.N, sm);
     // L_AN = B C^-1
@@ -282,6 +107,10 @@ __global__ void __launch_bounds__(NT) k_factor(DevPlan P, const int32_t* list, c
         [&](int i, int j, double acc) { LB[v.at(i, j)] = acc; }, true, sm);
   });
 }
+template __global__ void k_factor<false>(DevPlan, const int32_t*, const double*, double*, double*, double*,
+                                         double*, DevStatus*, double*, int64_t);
+template __global__ void k_factor<true>(DevPlan, const int32_t*, const double*, double*, double*, double*,
+                                        double*, DevStatus*, double*, int64_t);
 
 // ---------------------------------------------------------------------------
 // Algorithm 7.2: projected inverse (root-to-leaf level).
@@ -311,6 +140,9 @@ __global__ void __launch_bounds__(NT_DOWN) k_projinv(DevPlan P, const int32_t* l
 // F' = [Y_NN Y_AN^T; Y_AN 0] + sum E U'_c E^T;
 // K_NN = F'11, K_AN = F'21 - L F'11, U'_s = F'22 - L F'21^T - K_AN L^T.
 // Per RHS r = blockIdx.y.  Scratch: J*N.
+// PANEL: panel columns only; U'_s is left to k_wide_update, which reads
+// F'21 from this workgroup's scratch slot.
+template <bool PANEL>
 __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, const double* LB,
                                                 const double* Y, double* Kt, double* Ua,
                                                 int64_t upd, double* wsb, int64_t slot) {
@@ -327,9 +159,12 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
       const int rr = int(e % v.J), c = int(e / v.J);
       F[e] = rr >= c ? y[v.at(rr, c)] : 0.0;
     }
-    zero_packed(Us, v.A);
+    if (!PANEL) zero_packed(Us, v.A);
     __syncthreads();
-    assemble_children(P, v, ua, F, Us, sm);
+    if (PANEL)
+      assemble_children_panel(P, v, ua, F);
+    else
+      assemble_children(P, v, ua, F, Us, sm);
     for (int64_t e = threadIdx.x; e < (int64_t)v.N * v.N; e += NT) {
       const int i = int(e % v.N), c = int(e / v.N);
       if (i >= c) K[v.at(i, c)] = F[i + (int64_t)c * v.J];
@@ -339,6 +174,7 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
         v.A, v.N, v.N, [&](int i, int k) { return LB[v.an(i, k)]; }, [&](int k, int j) { return F11(k, j); },
         [&](int i, int j, double acc) { K[v.an(i, j)] = F[(v.N + i) + (int64_t)j * v.J] - acc; }, false,
         sm);
+    if (PANEL) return;
     __syncthreads();
     const int N = v.N;
     wg_gemm(
@@ -348,6 +184,10 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
         [&](int i, int j, double acc) { Us[pk(i, j, v.A)] -= acc; }, true, sm);
   });
 }
+template __global__ void k_hess_up<false>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                          double*, int64_t, double*, int64_t);
+template __global__ void k_hess_up<true>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                         double*, int64_t, double*, int64_t);
 
 // Hessian steps 2 and 3 (root-to-leaf), block form of Algorithm 5.1 with
 // the V_j recursion of its modified step 2 (here V_s is cached):
@@ -541,16 +381,32 @@ __global__ void __launch_bounds__(NT_DOWN) k_ihess_down(DevPlan P, const int32_t
         [&](int k, int j) { return W[k + (int64_t)j * N]; },
         [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
     const double* VI = Vi + P.arena[v.s];
-    wg_gemm_split<NT_DOWN, false, true>(
-        A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
-        [&](int k, int j) { return Z[k + (int64_t)j * A]; },
-        [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);
+    if (A <= kVExplicitMax) {
+      wg_gemm_split<NT_DOWN, false, true>(
+          A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
+          [&](int k, int j) { return Z[k + (int64_t)j * A]; },
+          [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);
+    } else {
+      // V^-1 Z = C_V^-T (C_V^-1 Z), through MA (free once Z is formed)
+      wg_gemm_split<NT_DOWN, false, true>(
+          A, N, A, [&](int i, int k) { return k <= i ? VI[pk(i, k, A)] : 0.0; },
+          [&](int k, int j) { return Z[k + (int64_t)j * A]; },
+          [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false, sm);
+      __syncthreads();
+      wg_gemm_split<NT_DOWN, true, true>(
+          A, N, A, [&](int i, int k) { return k >= i ? VI[pk(k, i, A)] : 0.0; },
+          [&](int k, int j) { return MA[k + (int64_t)j * A]; },
+          [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false, sm);
+    }
   });
 }
 
 // Inverse Hessian step 3 (leaf-to-root), block form of Algorithm 5.2:
 // G' = sum E U'_c E^T; Y_NN = K_NN - G'11; Y_AN = L K_NN + K_AN - G'21;
 // U'_s = G'22 - L K_NN L^T - L K_AN^T - K_AN L^T.  Scratch: J*N + A*N.
+// PANEL: panel columns only; U'_s is left to k_wide_update, which reads Q
+// from this workgroup's scratch slot.
+template <bool PANEL>
 __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list, const double* LB,
                                                  const double* Kt, double* Y, double* Ua,
                                                  int64_t upd, double* wsb, int64_t slot) {
@@ -566,9 +422,12 @@ __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list,
     double* G = slot_ptr(wsb, slot);
     double* Q = G + (int64_t)v.J * N;
     for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
-    zero_packed(Us, A);
+    if (!PANEL) zero_packed(Us, A);
     __syncthreads();
-    assemble_children(P, v, ua, G, Us, sm);
+    if (PANEL)
+      assemble_children_panel(P, v, ua, G);
+    else
+      assemble_children(P, v, ua, G, Us, sm);
     for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
       const int i = int(e % N), c = int(e / N);
       if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + (int64_t)c * v.J];
@@ -582,6 +441,7 @@ __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list,
           y[v.an(i, j)] = q - G[(N + i) + (int64_t)j * v.J];
         },
         false, sm);
+    if (PANEL) return;
     __syncthreads();
     wg_gemm(
         A, A, 2 * N,
@@ -590,12 +450,17 @@ __global__ void __launch_bounds__(NT) k_ihess_up(DevPlan P, const int32_t* list,
         [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
   });
 }
+template __global__ void k_ihess_up<false>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                           double*, int64_t, double*, int64_t);
+template __global__ void k_ihess_up<true>(DevPlan, const int32_t*, const double*, const double*, double*,
+                                          double*, int64_t, double*, int64_t);
 
 // ---------------------------------------------------------------------------
 // Algorithm 7.3: matrix completion of one front, with V_s = S_{A_s A_s}
 // already gathered (k_gather_v): L_AN = -V_s^-1 S_AN; D^-1 = S_NN +
 // S_AN^T L_AN; then C = chol(D), B = L_AN C so that the handle holds the
-// factor of X-hat.  Also caches S and V_s^-1.  Scratch: max(2A^2, 3N^2).
+// factor of X-hat.  Also caches S and the inverse of V_s in its packed
+// block (see kVExplicitMax).  Scratch: 3N^2 + AN.
 __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* list, const double* Sin,
                                                    double* R, double* LB, double* S, double* Vs,
                                                    double* Vi, double* part, DevStatus* st,
@@ -615,26 +480,31 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
     __syncthreads();  // (V_s was gathered by k_gather_v)
     const double* V = Vs + P.arena[v.s];
     double* VI = Vi + P.arena[v.s];
-    if (A > 0) {
-      wg_spd_inverse(
-          A, [&](int i, int j) { return sym_packed(V, i, j, A); },
-          [&](int i, int j, double acc) { VI[pk(i, j, A)] = acc; }, ws, sm, &fail);
-    }
+    const PackedLower Cvi{VI, A};  // C_V^-1 once formed
+    if (A > 0) packed_tri_inverse(V, VI, A, sm, &fail);  // VI <- C_V^-1, V = C_V C_V^T
     __syncthreads();
     if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
-    wg_gemm<false, true>(
-        A, N, A, [&](int i, int k) { return sym_packed(VI, i, k, A); },
-        [&](int k, int j) { return Sin[v.an(k, j)]; },
-        [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false, sm);
-    __syncthreads();
     double* Dd = ws;
     double* Gi = ws + (int64_t)N * N;
     double* Dm = Gi + (int64_t)N * N;
+    double* W = Dm + (int64_t)N * N;
+    // W = C_V^-1 S_AN, L_AN = -C_V^-T W, D^-1 = S_NN - W^T W: the Schur
+    // complement as a difference of Gram products (no explicit V^-1, whose
+    // product with S_AN would cancel against S_NN)
+    wg_gemm<false, true>(
+        A, N, A, [&](int i, int k) { return k <= i ? Cvi(i, k) : 0.0; },
+        [&](int k, int j) { return Sin[v.an(k, j)]; },
+        [&](int i, int j, double acc) { W[i + (int64_t)j * A] = acc; }, false, sm);
+    __syncthreads();
     wg_gemm<true, true>(
-        N, N, A, [&](int i, int k) { return Sin[v.an(k, i)]; },
-        [&](int k, int j) { return LB[v.an(k, j)]; },
+        A, N, A, [&](int i, int k) { return k >= i ? Cvi(k, i) : 0.0; },
+        [&](int k, int j) { return W[k + (int64_t)j * A]; },
+        [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false, sm);
+    wg_gemm<true, true>(
+        N, N, A, [&](int i, int k) { return W[k + (int64_t)i * A]; },
+        [&](int k, int j) { return W[k + (int64_t)j * A]; },
         [&](int i, int j, double acc) {
-          const double d = Sin[v.at(i, j)] + acc;
+          const double d = Sin[v.at(i, j)] - acc;
           LB[v.at(i, j)] = d;
           Dd[i + (int64_t)j * N] = d;
         },
@@ -669,11 +539,17 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
         A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
         [&](int k, int j) { return k >= j ? Dm[k + (int64_t)j * N] : 0.0; },
         [&](int i, int j, double acc) { R[v.an(i, j)] = acc; }, false, sm);
+    // the cached block: V^-1 itself up to kVExplicitMax, C_V^-1 beyond
+    if (A > 0 && A <= kVExplicitMax) {
+      __syncthreads();
+      wg_lauum_inplace(Cvi, A, sm);
+    }
   });
 }
 
-// (S_{A_s A_s})^-1 for every supernode of a level (needs the cached V_s).
-// Scratch: 2A^2.
+// The inverse of S_{A_s A_s} for every supernode in the list (needs the
+// cached V_s), in place in the packed Vi block (no scratch): V^-1 up to
+// order kVExplicitMax, the inverse Cholesky factor C_V^-1 beyond.
 __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, const double* Vs,
                                              double* Vi, DevStatus* st, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
@@ -683,11 +559,12 @@ __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, con
     if (v.A == 0) return;
     if (threadIdx.x == 0) fail = -1;
     __syncthreads();
-    const double* V = Vs + P.arena[v.s];
     double* VI = Vi + P.arena[v.s];
-    wg_spd_inverse(
-        v.A, [&](int i, int j) { return sym_packed(V, i, j, v.A); },
-        [&](int i, int j, double acc) { VI[pk(i, j, v.A)] = acc; }, slot_ptr(wsb, slot), sm, &fail);
+    packed_tri_inverse(Vs + P.arena[v.s], VI, v.A, sm, &fail);
+    if (v.A <= kVExplicitMax) {
+      __syncthreads();
+      wg_lauum_inplace(PackedLower{VI, v.A}, v.A, sm);
+    }
     if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOTPD, v.vl[0]);
   });
 }
@@ -720,6 +597,8 @@ __global__ void __launch_bounds__(NT) k_gather_map(const int64_t* map, int64_t n
 // ---------------------------------------------------------------------------
 // Algorithm 3.2 in block form (leaf-to-root): with G = sum E U_c E^T,
 // X_NN = C C^T - G11, X_AN = B C^T - G21, U_s = G22 - B B^T.  Scratch: J*N.
+// PANEL: panel columns only; U_s is left to k_wide_update.
+template <bool PANEL>
 __global__ void __launch_bounds__(NT) k_product(DevPlan P, const int32_t* list, const double* R,
                                                 double* X, double* U, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
@@ -729,9 +608,12 @@ __global__ void __launch_bounds__(NT) k_product(DevPlan P, const int32_t* list, 
     double* G = slot_ptr(wsb, slot);
     double* Us = U + P.arena[v.s];
     for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) G[e] = 0.0;
-    zero_packed(Us, A);
+    if (!PANEL) zero_packed(Us, A);
     __syncthreads();
-    assemble_children(P, v, U, G, Us, sm);
+    if (PANEL)
+      assemble_children_panel(P, v, U, G);
+    else
+      assemble_children(P, v, U, G, Us, sm);
     auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
     wg_gemm(
         N, N, N, C, [&](int k, int j) { return C(j, k); },
@@ -740,12 +622,17 @@ __global__ void __launch_bounds__(NT) k_product(DevPlan P, const int32_t* list, 
         A, N, N, [&](int i, int k) { return R[v.an(i, k)]; }, [&](int k, int j) { return C(j, k); },
         [&](int i, int j, double acc) { X[v.an(i, j)] = acc - G[(N + i) + (int64_t)j * v.J]; }, false,
         sm);
+    if (PANEL) return;
     wg_gemm(
         A, A, N, [&](int i, int k) { return R[v.an(i, k)]; },
         [&](int k, int j) { return R[v.an(j, k)]; },
         [&](int i, int j, double acc) { Us[pk(i, j, A)] -= acc; }, true, sm);
   });
 }
+template __global__ void k_product<false>(DevPlan, const int32_t*, const double*, double*, double*, double*,
+                                          int64_t);
+template __global__ void k_product<true>(DevPlan, const int32_t*, const double*, double*, double*, double*,
+                                         int64_t);
 
 // ---------------------------------------------------------------------------
 // log det = sum of the per-supernode contributions, fixed-order reduction.

@@ -50,8 +50,8 @@ inline int64_t slot_doubles(Op op, const Level& L) {
   switch (op) {
     case OP_FACTOR: return J * N + N * N;
     case OP_PRODUCT: return J * N;
-    case OP_COMPLETION: return std::max(2 * A * A, 3 * N * N);
-    case OP_VINV: return 2 * A * A;
+    case OP_COMPLETION: return 3 * N * N + A * N;
+    case OP_VINV: return 1;
     case OP_HUP: return J * N;
     case OP_HDOWN: return 2 * A * N + 2 * N * N;
     case OP_IHDOWN: return 2 * A * N + 3 * N * N;
@@ -64,6 +64,13 @@ inline int64_t slot_doubles(Op op, const Level& L) {
 // at most kRegMax[c]; larger fronts run the blocked kernels.
 constexpr int kRegClasses = 5;
 constexpr int kRegMax[kRegClasses] = {16, 32, 64, 128, 192};
+// The cached inverse of V_s = S_{A_s A_s} (inverse Hessian and completion)
+// is held as V_s^-1 itself for A <= kVExplicitMax (the register kernels'
+// sweeps produce it) and as the inverse Cholesky factor C_V^-1 (lower,
+// packed; V_s = C_V C_V^T) beyond, so that the blocked kernels form
+// V_s^-1 B as C_V^-T (C_V^-1 B) and the completion's Schur complement as
+// S_NN - W^T W with W = C_V^-1 S_AN.
+constexpr int kVExplicitMax = kRegMax[kRegClasses - 1];
 // Largest front order for which the projected inverse and the Hessian
 // and inverse-Hessian down-sweeps use the register kernels on a level of
 // non-root fronts.
@@ -76,18 +83,34 @@ constexpr int64_t kFlatScratch = int64_t(1) << 22;
 // the blocks of an input takes one elementwise launch.
 constexpr int64_t kGatherMapMax = int64_t(1) << 25;
 
-// A level of a schedule split by class: at most two launches, the blocked
-// kernels (cls == kRegClasses) on the fronts no register class holds,
-// then one register class, the largest any other front of the level
-// needs.
+// Wide fronts: a large ancestor set and few columns (J > the plan's wide
+// threshold, N <= kWideMaxN, A > 0).  Their A x A and A x N work runs
+// tile-parallel over all wide fronts of a level (wide.hip).
+constexpr int kWideMaxN = 64;
+constexpr int kWideJ = 512;     // default threshold on J
+constexpr int kWideJLow = 64;   // with MFB_PLAN_WIDE_LOW
+constexpr int kWide = kRegClasses + 1;  // class value of a wide segment
+constexpr int kWideTile = 64;
+
+// A level of a schedule split by class: at most three launches (groups of
+// launches for the wide fronts), the wide fronts (cls == kWide), the
+// blocked kernels (cls == kRegClasses) on the other fronts no register
+// class holds, then one register class, the largest any other front of
+// the level needs.  A wide segment also numbers its tiles: pre[aa_off +
+// f] is the first 64 x 64 lower tile of the A x A block of its front f
+// (n_aa in all), pre[rt_off + f] the first 64-row tile of its A rows (n_rt
+// in all).
 struct ClassSeg {
   Level lv;  // begin/count index the schedule's own list
   int32_t level, cls;
+  int32_t aa_off = 0, rt_off = 0, n_aa = 0, n_rt = 0;
 };
 struct ClassSched {
   std::vector<int32_t> list;
   std::vector<ClassSeg> segs;
+  std::vector<int32_t> pre;  // tile prefix arrays of the wide segments
   const int32_t* d_list = nullptr;
+  const int32_t* d_pre = nullptr;
 };
 
 }  // namespace mfb
@@ -96,6 +119,7 @@ struct mfb_plan_s {
   int64_t n = 0, nnz = 0;
   uint32_t flags = 0;
   int32_t ns = 0;
+  int32_t wide_thr = mfb::kWideJ;  // wide fronts: J > wide_thr (see kWideMaxN)
   std::vector<int32_t> N, J, parent, cptr, cidx, colbase, relbase, rel, rep, vlabel, snode_of;
   std::vector<int64_t> col, arena;
   int64_t update_doubles = 0;
@@ -104,10 +128,10 @@ struct mfb_plan_s {
   std::vector<int32_t> up_list, down_list;
   std::vector<mfb::Level> up_levels, down_levels;
   // class-split schedules: factor (leaf-to-root, by J), inverse of V_s
-  // (by A), completion (root-to-leaf, by J) and the projected inverse and
-  // Hessian down-sweeps (by J on the levels that take the register
-  // kernels, blocked elsewhere)
-  mfb::ClassSched cs_factor, cs_vinv, cs_completion, cs_down;
+  // (by A) and the projected inverse and Hessian down-sweeps (by J on the
+  // levels that take the register kernels, blocked elsewhere); wide fronts
+  // in segments of their own in the leaf-to-root and root-to-leaf ones
+  mfb::ClassSched cs_factor, cs_vinv, cs_down;
   // the completion's sweeps, one launch per class over all supernodes;
   // the inverse Hessian's steps 1+2 likewise, in launches whose workgroup
   // scratch stays within kFlatScratch doubles per right-hand side

@@ -254,18 +254,29 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   // levels of small fronts (every J <= kDownRegMaxJ) and on levels of roots
   // (every A = 0), and lose elsewhere; the projected inverse follows the
   // same rule.
-  auto down_reg_level = [&](const std::vector<int32_t>& list, const Level& L) {
+  //
+  // Wide fronts (J above the wide threshold, N <= kWideMaxN, A > 0) of the
+  // level-scheduled sweeps go to a segment of their own (cls == kWide),
+  // launched first on their level, with their tiles numbered: 64 x 64 lower
+  // tiles of the A x A block and 64-row tiles of the A rows.
+  p->wide_thr = (flags & MFB_PLAN_WIDE_LOW) ? kWideJLow : kWideJ;
+  auto is_wide = [&](int32_t k) {
+    return p->J[k] > p->wide_thr && p->N[k] <= kWideMaxN && p->J[k] > p->N[k];
+  };
+  auto down_reg_level = [&](const std::vector<int32_t>& list, const Level& L, bool wide_ok) {
     bool small = true, roots = true;
     for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
+      if (wide_ok && is_wide(list[t])) continue;
       small = small && p->J[list[t]] <= kDownRegMaxJ;
       roots = roots && p->J[list[t]] == p->N[list[t]];
     }
     return small || roots;
   };
   auto make_classes = [&](const std::vector<int32_t>& list, const std::vector<Level>& levels,
-                          bool by_a, bool down, ClassSched& cs) {
+                          bool by_a, bool down, ClassSched& cs, bool wide_ok) {
     cs.list.clear();
     cs.segs.clear();
+    cs.pre.clear();
     cs.list.reserve(ns);
     auto fit_class = [&](int32_t k) {  // smallest class that holds the front, or kRegClasses
       const int32_t m = by_a ? p->J[k] - p->N[k] : p->J[k];
@@ -275,14 +286,16 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     };
     for (int32_t l = 0; l < int32_t(levels.size()); ++l) {
       const Level& L = levels[l];
-      const bool reg_ok = !down || down_reg_level(list, L);
+      const bool reg_ok = !down || down_reg_level(list, L, wide_ok);
       int lvcls = 0;
       for (int32_t t = L.begin; t < L.begin + L.count; ++t)
-        if (fit_class(list[t]) < kRegClasses) lvcls = std::max(lvcls, fit_class(list[t]));
+        if (!(wide_ok && is_wide(list[t])) && fit_class(list[t]) < kRegClasses)
+          lvcls = std::max(lvcls, fit_class(list[t]));
       auto class_of = [&](int32_t k) {
+        if (wide_ok && is_wide(k)) return kWide;
         return reg_ok && fit_class(k) < kRegClasses ? lvcls : kRegClasses;
       };
-      for (int c : {kRegClasses, lvcls}) {
+      for (int c : {kWide, kRegClasses, lvcls}) {
         Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
           const int32_t k = list[t];
@@ -300,18 +313,40 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
           S.na2 += Nn * An * An;
           S.a3 += An * An * An;
         }
-        if (S.count) cs.segs.push_back(ClassSeg{S, l, c});
+        if (!S.count) continue;
+        ClassSeg g{S, l, c};
+        if (c == kWide) {
+          auto tiles = [](int32_t A) { return (A + kWideTile - 1) / kWideTile; };
+          g.aa_off = int32_t(cs.pre.size());
+          int32_t acc = 0;
+          for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
+            cs.pre.push_back(acc);
+            const int32_t nt = tiles(p->J[cs.list[t]] - p->N[cs.list[t]]);
+            acc += nt * (nt + 1) / 2;
+          }
+          cs.pre.push_back(acc);
+          g.n_aa = acc;
+          g.rt_off = int32_t(cs.pre.size());
+          acc = 0;
+          for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
+            cs.pre.push_back(acc);
+            acc += tiles(p->J[cs.list[t]] - p->N[cs.list[t]]);
+          }
+          cs.pre.push_back(acc);
+          g.n_rt = acc;
+        }
+        cs.segs.push_back(g);
       }
     }
   };
-  make_classes(p->up_list, p->up_levels, false, false, p->cs_factor);
+  make_classes(p->up_list, p->up_levels, false, false, p->cs_factor, true);
   // Schedules for work with no dependence between fronts: the register
   // fronts run in one launch per class over all supernodes (longest first)
-  // instead of level by level; fronts beyond the register classes keep
-  // per-level launches, which bound their workgroup scratch as for the
-  // other sweeps.  by_a: order A (the inverse of V_s, roots skipped), else J.
-  auto make_flat = [&](bool by_a, const std::vector<int32_t>& list, const std::vector<Level>& levels,
-                       ClassSched& cs) {
+  // instead of level by level; fronts beyond the register classes run
+  // likewise, longest first, in launches whose workgroup scratch stays
+  // within kFlatScratch doubles (a launch holds at least one front).
+  // by_a: order A (the inverse of V_s, roots skipped), else J.
+  auto make_flat = [&](bool by_a, Op op, ClassSched& cs) {
     cs.list.clear();
     cs.segs.clear();
     cs.list.reserve(ns);
@@ -345,20 +380,31 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
       for (int32_t k : fr) add_front(S, k);
       if (S.count) cs.segs.push_back(ClassSeg{S, -1, c});
     }
-    for (int32_t l = 0; l < int32_t(levels.size()); ++l) {
-      const Level& L = levels[l];
+    {
+      std::vector<int32_t> fr;
+      for (int32_t k = 0; k < ns; ++k)
+        if (wanted(k) && fit(k) == kRegClasses) fr.push_back(k);
+      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) { return order(x) > order(y); });
       Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-      for (int32_t t = L.begin; t < L.begin + L.count; ++t)
-        if (wanted(list[t]) && fit(list[t]) == kRegClasses) add_front(S, list[t]);
-      if (S.count) cs.segs.push_back(ClassSeg{S, l, kRegClasses});
+      for (int32_t k : fr) {
+        Level T = S;
+        T.count++;
+        T.maxN = std::max(T.maxN, p->N[k]);
+        T.maxA = std::max(T.maxA, p->J[k] - p->N[k]);
+        T.maxJ = std::max(T.maxJ, p->J[k]);
+        if (S.count && int64_t(T.count) * slot_doubles(op, T) > kFlatScratch) {
+          cs.segs.push_back(ClassSeg{S, -1, kRegClasses});
+          S = Level{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        }
+        add_front(S, k);
+      }
+      if (S.count) cs.segs.push_back(ClassSeg{S, -1, kRegClasses});
     }
   };
   // V_s^-1 needs only V_s; the completion's sweeps need only S and V_s,
-  // which a level-scheduled gather pass puts in place beforehand.
-  // (the blocked segments follow the level lists the workgroup scratch is
-  // sized over: leaf-to-root for V_s^-1, root-to-leaf for the completion)
-  make_flat(true, p->up_list, p->up_levels, p->cs_vinv);
-  make_flat(false, p->down_list, p->down_levels, p->cs_compl_flat);
+  // which a gather pass puts in place beforehand.
+  make_flat(true, OP_VINV, p->cs_vinv);
+  make_flat(false, OP_COMPLETION, p->cs_compl_flat);
   // The inverse Hessian's steps 1+2 read T_{A_s A_s}, which a gather pass
   // puts in place, so its fronts are independent too.  Each front takes the
   // kernel the root-to-leaf rule gives it (register kernels for J <=
@@ -410,8 +456,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
       if (S.count) cs.segs.push_back(ClassSeg{S, -1, c});
     }
   }
-  make_classes(p->down_list, p->down_levels, false, false, p->cs_completion);
-  make_classes(p->down_list, p->down_levels, false, true, p->cs_down);
+  make_classes(p->down_list, p->down_levels, false, true, p->cs_down, true);
   p->cs_hdown = p->cs_down;
   p->hd_root = -1;
   p->ihd_root = -1;

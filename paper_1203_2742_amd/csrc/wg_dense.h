@@ -152,6 +152,67 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const FA& fa, const
   }
 }
 
+// Accumulates sum_{kb <= k < ke} a(i, k) b(k, j) into the tile T at
+// (i0, j0) (rows i < M, columns j < N; entries outside read as zero), with
+// the operand fetch of wg_gemm (AK, BK).  Several calls with different
+// k ranges and fetch layouts may accumulate into one tile.
+template <bool AK = false, bool BK = false, class FA, class FB>
+__device__ __forceinline__ void tile_mma(MfmaTile& T, int i0, int j0, int M, int N, int kb, int ke,
+                                         const FA& fa, const FB& fb, double* sm) {
+  double* As = sm;
+  double* Bs = sm + KC * LDS_TM;
+  const int tid = threadIdx.x;
+  constexpr int PER = KC * TM / NT;
+  auto slot_a = [&](int q, int& i, int& k) {
+    const int e = tid + q * NT;
+    i = AK ? e / KC : e & (TM - 1);
+    k = AK ? e & (KC - 1) : e / TM;
+  };
+  auto slot_b = [&](int q, int& j, int& k) {
+    const int e = tid + q * NT;
+    j = BK ? e / KC : e & (TM - 1);
+    k = BK ? e & (KC - 1) : e / TM;
+  };
+  double ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, ka, j, kb2;
+      slot_a(q, i, ka);
+      slot_b(q, j, kb2);
+      ra[q] = (i0 + i < M && k0 + ka < ke) ? fa(i0 + i, k0 + ka) : 0.0;
+      rb[q] = (j0 + j < N && k0 + kb2 < ke) ? fb(k0 + kb2, j0 + j) : 0.0;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, ka, j, kb2;
+      slot_a(q, i, ka);
+      slot_b(q, j, kb2);
+      As[ka * LDS_TM + i] = ra[q];
+      Bs[kb2 * LDS_TM + j] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + KC < ke) fetch(k0 + KC);
+    T.chunk(As, Bs);
+    __syncthreads();
+  }
+}
+
+// Passes the entries (i, j) of tile T at (i0, j0) with i < M, j < N (and
+// i >= j when `lower`) to epi(i, j, value).
+template <class EPI>
+__device__ __forceinline__ void tile_store(const MfmaTile& T, int i0, int j0, int M, int N, const EPI& epi,
+                                           bool lower) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int gi = i0 + T.row_of(e), gj = j0 + T.col_of(e);
+    if (gi < M && gj < N && (!lower || gi >= gj)) epi(gi, gj, T.get(e));
+  }
+}
+
 // One 64 x 64 output tile (i0, j0) of wg_gemm's product by one 256-thread
 // workgroup, for products spread over many workgroups (one tile each).
 template <bool AK = false, bool BK = false, class FA, class FB, class EPI>
@@ -340,51 +401,141 @@ __device__ __forceinline__ void diag_trtri(const double* L, double* Li, int nb) 
   __syncthreads();
 }
 
-// Partial Cholesky of a J x N column panel F (leading dimension ld): on
-// return F[0:N, 0:N] holds C = chol(F11) (lower) and F[N:J, 0:N] holds
-// F21 C^-T.  Blocked right-looking with NB-column blocks: the diagonal
-// block is factored and inverted in LDS, the rows below are multiplied by
-// that inverse and the remaining panel columns updated, both with wg_gemm.
-// *fail receives the first failing column (or stays -1).
-__device__ __forceinline__ void wg_potrf_panel(double* F, int ld, int J, int N, double* sm,
-                                               int* fail) {
+// Partial Cholesky of a J x N column panel reached through G(i, j)
+// (a reference to entry (i, j), i >= j): on return rows 0..N-1 of the
+// panel hold C = chol(F11) (lower) and rows N..J-1 hold F21 C^-T.  Blocked
+// right-looking with NB-column blocks: the diagonal block is factored and
+// inverted in LDS, the rows below are multiplied by that inverse and the
+// remaining panel columns updated, both with wg_gemm.  With INVDIAG the
+// diagonal blocks are left holding their inverses (for multiplications by
+// the triangular inverse later).  *fail receives the first failing column
+// (or stays -1).
+template <bool INVDIAG = false, class GA>
+__device__ __forceinline__ void wg_potrf_acc(const GA& G, int J, int N, double* sm, int* fail) {
   double* Ld = sm + SMEM_GEMM;
   for (int kb = 0; kb < N; kb += NB) {
     const int nb = min(NB, N - kb);
     for (int e = threadIdx.x; e < nb * nb; e += NT) {
       const int i = e % nb, j = e / nb;
-      if (i >= j) Ld[i + j * LDD] = F[(kb + i) + (int64_t)(kb + j) * ld];
+      if (i >= j) Ld[i + j * LDD] = G(kb + i, kb + j);
     }
     __shared__ int lfail;
     if (threadIdx.x == 0) lfail = -1;
     __syncthreads();
     diag_chol(Ld, nb, &lfail);
     if (threadIdx.x == 0 && lfail >= 0 && *fail < 0) *fail = kb + lfail;
+    double* Li = Ld + NB * LDD;
+    if (kb + nb < J || INVDIAG) diag_trtri(Ld, Li, nb);
+    const double* Lw = INVDIAG ? Li : Ld;
     for (int e = threadIdx.x; e < nb * nb; e += NT) {
       const int i = e % nb, j = e / nb;
-      if (i >= j) F[(kb + i) + (int64_t)(kb + j) * ld] = Ld[i + j * LDD];
+      if (i >= j) G(kb + i, kb + j) = Lw[i + j * LDD];
     }
     // rows below the diagonal block: X <- X C_kk^-T, applied as a product
     // with the explicit inverse of the diagonal block.  In place is safe:
     // nb <= TM gives one column tile, and each row tile reads only its own
     // rows before its epilogue writes them.
     if (kb + nb < J) {
-      double* Li = Ld + NB * LDD;
-      diag_trtri(Ld, Li, nb);
       wg_gemm(
-          J - kb - nb, nb, nb, [&](int i, int k) { return F[(kb + nb + i) + (int64_t)(kb + k) * ld]; },
+          J - kb - nb, nb, nb, [&](int i, int k) { return G(kb + nb + i, kb + k); },
           [&](int k, int j) { return Li[j + k * LDD]; },
-          [&](int i, int j, double acc) { F[(kb + nb + i) + (int64_t)(kb + j) * ld] = acc; }, false,
-          sm);
+          [&](int i, int j, double acc) { G(kb + nb + i, kb + j) = acc; }, false, sm);
     }
     __syncthreads();
     const int r0 = kb + nb;
     if (r0 < N) {
       wg_gemm(
-          J - r0, N - r0, nb, [&](int i, int k) { return F[(r0 + i) + (int64_t)(kb + k) * ld]; },
-          [&](int k, int j) { return F[(r0 + j) + (int64_t)(kb + k) * ld]; },
-          [&](int i, int j, double acc) { F[(r0 + i) + (int64_t)(r0 + j) * ld] -= acc; }, true,
-          sm);
+          J - r0, N - r0, nb, [&](int i, int k) { return G(r0 + i, kb + k); },
+          [&](int k, int j) { return G(r0 + j, kb + k); },
+          [&](int i, int j, double acc) { G(r0 + i, r0 + j) -= acc; }, true, sm);
+      __syncthreads();
+    }
+  }
+}
+
+// wg_potrf_acc on a column-major panel F with leading dimension ld.
+__device__ __forceinline__ void wg_potrf_panel(double* F, int ld, int J, int N, double* sm, int* fail) {
+  wg_potrf_acc([&](int i, int j) -> double& { return F[i + (int64_t)j * ld]; }, J, N, sm, fail);
+}
+
+// In place, on an n x n lower triangle reached through G(i, j) (i >= j):
+// G <- G^-1.  Diagonal blocks from the last to the first: with
+// G = [G11 0; G21 G22] and G22 already inverted in place,
+// inv(G)21 = -inv(G22) G21 inv(G11); the product inv(G22) G21 overwrites
+// G21 row tile by row tile from the bottom (a tile reads only rows at or
+// above its own).  INVDIAG: the diagonal blocks already hold their
+// inverses (wg_potrf_acc<true>).
+template <bool INVDIAG = false, class GA>
+__device__ __forceinline__ void wg_trtri_inplace(const GA& G, int n, double* sm) {
+  double* Ld = sm + SMEM_GEMM;
+  double* Li = Ld + NB * LDD;
+  const int nblk = (n + NB - 1) / NB;
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int jb = bk * NB, nb = min(NB, n - jb);
+    if (INVDIAG) {
+      for (int e = threadIdx.x; e < NB * LDD; e += NT) Li[e] = 0.0;
+      __syncthreads();
+      for (int e = threadIdx.x; e < nb * nb; e += NT) {
+        const int i = e % nb, j = e / nb;
+        if (i >= j) Li[i + j * LDD] = G(jb + i, jb + j);
+      }
+      __syncthreads();
+    } else {
+      for (int e = threadIdx.x; e < nb * nb; e += NT) {
+        const int i = e % nb, j = e / nb;
+        if (i >= j) Ld[i + j * LDD] = G(jb + i, jb + j);
+      }
+      __syncthreads();
+      diag_trtri(Ld, Li, nb);
+    }
+    const int r0 = jb + nb, m = n - r0;
+    if (m > 0) {
+      for (int i0 = ((m - 1) / TM) * TM; i0 >= 0; i0 -= TM) {
+        MfmaTile T(threadIdx.x);
+        tile_mma<false, true>(
+            T, i0, 0, m, nb, 0, min(m, i0 + TM),
+            [&](int i, int k) { return k <= i ? G(r0 + i, r0 + k) : 0.0; },
+            [&](int k, int j) { return G(r0 + k, jb + j); }, sm);
+        tile_store(T, i0, 0, m, nb, [&](int i, int j, double acc) { G(r0 + i, jb + j) = acc; }, false);
+        __syncthreads();
+      }
+      wg_gemm(
+          m, nb, nb, [&](int i, int k) { return G(r0 + i, jb + k); },
+          [&](int k, int j) { return Li[k + j * LDD]; },
+          [&](int i, int j, double acc) { G(r0 + i, jb + j) = -acc; }, false, sm);
+      __syncthreads();
+    }
+    if (!INVDIAG)
+      for (int e = threadIdx.x; e < nb * nb; e += NT) {
+        const int i = e % nb, j = e / nb;
+        if (i >= j) G(jb + i, jb + j) = Li[i + j * LDD];
+      }
+    __syncthreads();
+  }
+}
+
+// In place, on an n x n lower triangle reached through G(i, j) (i >= j):
+// G <- the lower triangle of G^T G, i.e. W(i, j) = sum_{k >= i} G(k, i)
+// G(k, j) for i >= j.  Row tiles from the top; within a row tile the
+// diagonal tile last: a tile reads only rows at or below its own, and the
+// diagonal column block that the other tiles of its row still read is
+// overwritten last.
+template <class GA>
+__device__ __forceinline__ void wg_lauum_inplace(const GA& G, int n, double* sm) {
+  for (int i0 = 0; i0 < n; i0 += TM) {
+    for (int j0 = 0; j0 <= i0; j0 += TM) {
+      // off-diagonal tiles first, in order; the diagonal tile (j0 == i0) last
+      MfmaTile T(threadIdx.x);
+      tile_mma<true, true>(
+          T, 0, 0, TM, TM, i0, n,
+          [&](int i, int k) { return (i0 + i < n && k >= i0 + i) ? G(k, i0 + i) : 0.0; },
+          [&](int k, int j) { return (j0 + j < n && k >= j0 + j) ? G(k, j0 + j) : 0.0; }, sm);
+      tile_store(
+          T, 0, 0, min(TM, n - i0), min(TM, n - j0),
+          [&](int i, int j, double acc) {
+            if (i0 + i >= j0 + j) G(i0 + i, j0 + j) = acc;
+          },
+          false);
       __syncthreads();
     }
   }

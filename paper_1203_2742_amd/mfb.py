@@ -33,6 +33,7 @@ NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTCHORDAL", 3: "ENOTPD", 4: "ENOCOMPLETION"
          5: "ENOMEM", 6: "EHIP", 7: "ESTATE"}
 PLAN_TIE_LAST = 1
 PLAN_NO_GATHER_MAP = 2
+PLAN_WIDE_LOW = 4
 
 
 class MfbError(RuntimeError):

@@ -85,6 +85,7 @@ def test_malformed_ccs_rejected(mutate):
     ("band200", 195, 195, 6),
     ("grid2d_128", 10334, 26, 191),
     ("arrow64", 64, 2, 384),
+    ("grid3d_40", 42165, 298, 2360),
 ])
 def test_workload_plans(name, nsuper, levels, maxfront):
     plan = mfb.plan_symbolic(*get_config(name))
@@ -93,6 +94,22 @@ def test_workload_plans(name, nsuper, levels, maxfront):
     assert info["nlevels_up"] == levels
     assert info["max_front"] == maxfront
     assert info["factor_workspace_bytes"] > 0 and info["rhs_arena_bytes"] > 0
+
+
+def test_large_grid_plan_statistics():
+    """The 3D 7-point grid 40^3 under nested dissection: order, entries, the
+    root front (1601 columns, no ancestors) and the largest front."""
+    n, cp, ri = get_config("grid3d_40")
+    plan = mfb.plan_symbolic(n, cp, ri)
+    info = plan.info
+    assert (info["n"], info["nnz"]) == (64000, 21288984)
+    assert info["max_ncols"] == 1601 and info["max_nanc"] == 2320
+    snode_of, sparent, srep = mfb.plan_supernodes(plan)
+    roots = np.flatnonzero(sparent < 0)
+    assert len(roots) == 1
+    root = int(roots[0])
+    assert int((snode_of == root).sum()) == 1601
+    assert int(cp[srep[root] + 1] - cp[srep[root]]) == 1601
 
 
 def test_forest_and_diagonal_plans():

@@ -9,6 +9,13 @@ Recipe (fixed so that every consumer sees identical inputs):
   positive diagonal, hence positive definite.
 * ``make_y(r)``: every entry of V, diagonal included, is drawn
   uniform(-1, 1) from ``default_rng([seed, r + 1])``.
+* ``make_x_laplacian(delta)``: an ill-conditioned X.  The strict-lower
+  entries are minus the absolute values of uniform(-1, 1) draws from
+  ``default_rng(seed)`` (CCS order); each diagonal entry is the absolute
+  row sum of its full symmetric row plus ``delta``.  X is then a weighted
+  graph Laplacian plus delta I: positive definite, with its smallest
+  eigenvalue delta on a connected pattern and condition number about
+  (largest eigenvalue) / delta.
 
 Values are returned in the CCS order of the pattern (lower triangle,
 diagonal first in each column) as float64 arrays.
@@ -39,6 +46,20 @@ def make_x(n, colptr, rowind, seed: int = 0) -> np.ndarray:
     np.add.at(rowsum, row[strict], a[strict])
     np.add.at(rowsum, col[strict], a[strict])
     x[diag_positions(colptr)] = rowsum + 1.0
+    return x
+
+
+def make_x_laplacian(n, colptr, rowind, delta: float, seed: int = 0) -> np.ndarray:
+    nnz = int(colptr[-1])
+    col = column_index(n, colptr)
+    row = np.asarray(rowind, dtype=np.int64)
+    strict = row != col
+    x = np.zeros(nnz, dtype=np.float64)
+    x[strict] = -np.abs(np.random.default_rng(seed).uniform(-1.0, 1.0, int(strict.sum())))
+    rowsum = np.zeros(n, dtype=np.float64)
+    np.add.at(rowsum, row[strict], -x[strict])
+    np.add.at(rowsum, col[strict], -x[strict])
+    x[diag_positions(colptr)] = rowsum + float(delta)
     return x
 
 
