@@ -65,6 +65,8 @@ typedef int32_t mfb_status_t;
 #define MFB_ENOMEM 5          /* host or device allocation failed */
 #define MFB_EHIP 6            /* a HIP runtime call failed */
 #define MFB_ESTATE 7          /* call order violated (e.g. hessian before factor) */
+#define MFB_ESCRATCH 8        /* mfb_hessian_static: k right-hand sides need more than
+                                 MFB_STATIC_SCRATCH_BYTES of scratch */
 
 typedef struct mfb_plan_s* mfb_plan_t;
 typedef struct mfb_factor_s* mfb_factor_t;
@@ -176,6 +178,22 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y_dev, double*
  * caches (S_AA)^-1 per supernode for the current X. */
 mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t_dev, double* y_dev,
                              void* arena_dev, size_t arena_bytes, void* stream);
+
+/* mfb_hessian without a caller-provided arena, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same inputs, outputs and
+ * kernels as mfb_hessian; the per-RHS arena is carved from a fixed device
+ * array of MFB_STATIC_SCRATCH_BYTES owned by the library, one per GPU it
+ * runs on, held until the process ends.  The call allocates nothing and
+ * records no launch profile.  Returns MFB_ESCRATCH (enqueueing nothing)
+ * when k * plan_info.rhs_arena_bytes exceeds MFB_STATIC_SCRATCH_BYTES.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * GPU (other streams, other threads, other factor handles) race and must
+ * be serialized by the caller.  The array keeps the last call's contents;
+ * every entry a call reads it has written first. */
+#define MFB_STATIC_SCRATCH_BYTES (256u << 20)
+mfb_status_t mfb_hessian_static(mfb_factor_t f, int32_t k, const double* y_dev, double* t_dev,
+                                void* stream);
 
 /* Algorithm 7.3: matrix completion.  Given S in S^n_V with a positive definite
  * completion (s_dev, nnz doubles), replaces the handle's factor by the factor

@@ -176,6 +176,7 @@ const char* mfb_strerror(mfb_status_t s) {
     case MFB_ENOMEM: return "out of memory";
     case MFB_EHIP: return "HIP runtime error";
     case MFB_ESTATE: return "call order violated";
+    case MFB_ESCRATCH: return "the call needs more than the library's static scratch";
   }
   return "unknown status";
 }
@@ -495,16 +496,10 @@ static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, Rhs
   return MFB_OK;
 }
 
-mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, void* arena,
-                         size_t bytes, void* stream) {
-  if (!f || k < 0) return MFB_EINVAL;
-  if (k == 0) return MFB_OK;
-  if (!y || !t) return MFB_EINVAL;
-  if (!f->has_factor) return MFB_ESTATE;
-  RhsArena a;
-  mfb_status_t st = carve(f, k, arena, bytes, &a);
-  if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
+// Hessian steps on k right-hand sides with the per-RHS arena `a`.
+static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, double* t, const RhsArena& a,
+                                hipStream_t s) {
+  mfb_status_t st;
   f->last = s;
   if ((st = ensure_projinv(f, s))) return st;
   struct Ctx { const double* y; double* t; RhsArena a; } ctx{y, t, a};
@@ -571,6 +566,60 @@ mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, 
       &ctx);
   if (st) return st;
   return launched();
+}
+
+mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, void* arena,
+                         size_t bytes, void* stream) {
+  if (!f || k < 0) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!y || !t) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  RhsArena a;
+  mfb_status_t st = carve(f, k, arena, bytes, &a);
+  if (st) return st;
+  return hessian_run(f, k, y, t, a, (hipStream_t)stream);
+}
+
+// ---- the Hessian without a caller arena (callers that cannot allocate) ----
+// The per-RHS arena comes from `scratch`, a fixed device array of this
+// file.  In host code the array's name is not a device address: its
+// address on the current device is looked up once per device with
+// hipGetSymbolAddress and kept in static_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[MFB_STATIC_SCRATCH_BYTES];
+static std::mutex static_scratch_mu;
+constexpr int kMaxDevices = 64;
+static void* static_scratch_ptr[kMaxDevices];
+
+static mfb_status_t static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MFB_EHIP;
+  std::lock_guard<std::mutex> g(static_scratch_mu);
+  if (!static_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MFB_EHIP;
+    static_scratch_ptr[dev] = ptr;
+  }
+  *out = static_scratch_ptr[dev];
+  return MFB_OK;
+}
+
+mfb_status_t mfb_hessian_static(mfb_factor_t f, int32_t k, const double* y, double* t, void* stream) {
+  if (!f || k < 0) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!y || !t) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  if (size_t(k) * rhs_bytes(f->plan) > size_t(MFB_STATIC_SCRATCH_BYTES)) return MFB_ESCRATCH;
+  void* arena = nullptr;
+  mfb_status_t st = static_scratch(&arena);
+  if (st) return st;
+  RhsArena a;
+  if ((st = carve(f, k, arena, size_t(MFB_STATIC_SCRATCH_BYTES), &a))) return st;
+  // no launch records: they would create HIP events
+  const bool prof = f->prof;
+  f->prof = false;
+  st = hessian_run(f, k, y, t, a, (hipStream_t)stream);
+  f->prof = prof;
+  return st;
 }
 
 static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {

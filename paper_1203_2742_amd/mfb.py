@@ -28,9 +28,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfb.so")
 HEADER_PATH = os.path.join(_HERE, "..", "include", "mfb.h")
 
-OK, EINVAL, ENOTCHORDAL, ENOTPD, ENOCOMPLETION, ENOMEM, EHIP, ESTATE = range(8)
+OK, EINVAL, ENOTCHORDAL, ENOTPD, ENOCOMPLETION, ENOMEM, EHIP, ESTATE, ESCRATCH = range(9)
 NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTCHORDAL", 3: "ENOTPD", 4: "ENOCOMPLETION",
-         5: "ENOMEM", 6: "EHIP", 7: "ESTATE"}
+         5: "ENOMEM", 6: "EHIP", 7: "ESTATE", 8: "ESCRATCH"}
+STATIC_SCRATCH_BYTES = 256 << 20
 PLAN_TIE_LAST = 1
 PLAN_NO_GATHER_MAP = 2
 PLAN_WIDE_LOW = 4
@@ -83,6 +84,7 @@ def _load():
         "mfb_projected_inverse": (I32, [P, P, P]),
         "mfb_hessian": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_inv_hessian": (I32, [P, I32, P, P, P, SZ, P]),
+        "mfb_hessian_static": (I32, [P, I32, P, P, P]),
         "mfb_completion": (I32, [P, P, P]),
         "mfb_cholesky_product": (I32, [P, P, P]),
         "mfb_factor_export_ldl": (I32, [P, P, P]),
@@ -225,6 +227,15 @@ def hessian(f: Factor, y, t, arena, k=None, stream=None):
     _dev_f64(t, k * nnz, "t")
     _chk(_lib.mfb_hessian(f.handle, k, _ptr(y), _ptr(t), _ptr(arena),
                           arena.numel() * arena.element_size(), _stream(stream)), "hessian")
+
+
+def hessian_static(f: Factor, y, t, k=None, stream=None):
+    """mfb_hessian_static: the Hessian with the library's static scratch."""
+    nnz = f.plan.nnz
+    k = _k_of(y, nnz) if k is None else int(k)
+    _dev_f64(y, k * nnz, "y")
+    _dev_f64(t, k * nnz, "t")
+    _chk(_lib.mfb_hessian_static(f.handle, k, _ptr(y), _ptr(t), _stream(stream)), "hessian_static")
 
 
 def inv_hessian(f: Factor, t, y, arena, k=None, stream=None):
