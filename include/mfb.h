@@ -234,9 +234,10 @@ const char* mfb_strerror(mfb_status_t s);
 #define MFB_K_VINV 7         /* (S_AA)^-1 per supernode */
 #define MFB_K_PRODUCT 8      /* Algorithm 3.2 in block form */
 #define MFB_K_GATHER_V 9     /* gather of the input blocks S_AA (completion) or T_AA
-                                (inverse Hessian): kernel k_gather_map, one launch
-                                with the plan's source map, else k_gather_v per
-                                root-to-leaf level */
+                                (inverse Hessian): one launch of k_gather_map with
+                                the plan's source map, else one k_wide_extract
+                                launch per root-to-leaf level (profile name
+                                "k_gather") */
 #define MFB_K_COUNT 10
 
 typedef struct {

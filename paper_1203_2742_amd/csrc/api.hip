@@ -92,7 +92,8 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iCf = v32(p->cs_factor.list), iCv = v32(p->cs_vinv.list),
          iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list),
          iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
-         iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre);
+         iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre), iGl = v32(p->cs_gather.list),
+         iGp = v32(p->cs_gather.pre);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -132,6 +133,8 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_factor.d_pre = (const int32_t*)at(iPf);
   p->cs_down.d_pre = (const int32_t*)at(iPd);
   p->cs_hdown.d_pre = (const int32_t*)at(iPh);
+  p->cs_gather.d_list = (const int32_t*)at(iGl);
+  p->cs_gather.d_pre = (const int32_t*)at(iGp);
   return MFB_OK;
 }
 
@@ -378,9 +381,10 @@ static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, 
 // inverse Hessian, k right-hand sides) into `arena`: one elementwise launch
 // with the plan's source map, else level by level from the parents.
 static mfb_status_t gather_blocks(mfb_factor_s* f, hipStream_t s, int k, const double* src, double* arena,
-                                  int64_t src_stride, int64_t arena_stride) {
+                                  int64_t src_stride, int64_t arena_stride, int tag) {
   const mfb_plan_s* p = f->plan;
-  struct Ctx { const double* src; double* arena; int64_t ss, as; } ctx{src, arena, src_stride, arena_stride};
+  struct Ctx { const double* src; double* arena; int64_t ss, as; int tag; } ctx{src, arena, src_stride,
+                                                                              arena_stride, tag};
   if (p->d_gmap) {
     return run_levels(
         f, MFB_K_GATHER_V, p->all_levels, p->d_all_list, s, k, OP_COMPLETION,
@@ -389,15 +393,19 @@ static mfb_status_t gather_blocks(mfb_factor_s* f, hipStream_t s, int k, const d
           const int64_t n = f->plan->update_doubles;
           const unsigned blocks = unsigned(std::min<int64_t>(2048, std::max<int64_t>(1, (n + NT_LAUNCH - 1) / NT_LAUNCH)));
           const dim3 grid(blocks, g.y);
-          k_gather_map<<<grid, NT_LAUNCH, 0, s>>>(f->plan->d_gmap, n, x->src, x->arena, x->ss, x->as);
+          if (x->tag == 1)
+            k_gather_map<1><<<grid, NT_LAUNCH, 0, s>>>(f->plan->d_gmap, n, x->src, x->arena, x->ss, x->as);
+          else
+            k_gather_map<2><<<grid, NT_LAUNCH, 0, s>>>(f->plan->d_gmap, n, x->src, x->arena, x->ss, x->as);
         },
         &ctx);
   }
-  return run_levels(
-      f, MFB_K_GATHER_V, p->down_levels, p->d_down_list, s, k, OP_COMPLETION,
-      [](mfb_factor_s* f, const int32_t* list, dim3 g, hipStream_t s, int64_t, void* c) {
+  return run_classes(
+      f, MFB_K_GATHER_V, p->cs_gather, s, k, OP_COMPLETION,
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t, void* c) {
         Ctx* x = (Ctx*)c;
-        k_gather_v<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, x->src, x->arena, x->ss, x->as);
+        launch_wide_extract(x->tag, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, cs.d_list + sg.lv.begin,
+                            cs.d_pre + sg.aa_off, sg.lv.count, x->src, x->arena, x->ss, x->as);
       },
       &ctx);
 }
@@ -656,7 +664,7 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
   // V'_s = T_{A_s A_s} for every supernode and right-hand side (root-to-leaf
   // gathers), then steps 1+2 of all fronts, which are independent
-  st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd);
+  st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd, 1);
   if (st) return st;
   if (f->plan->ihd_root >= 0) {
     // the root front: three tile-parallel products (steps 1+2 with A = 0)
@@ -730,7 +738,7 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   struct Ctx { const double* s; } ctx{sin};
   // V_s = S_{A_s A_s} for every supernode (root-to-leaf gathers), then the
   // fronts' sweeps, which need nothing but their own S and V_s
-  mfb_status_t st = gather_blocks(f, s, 1, sin, f->Vs, 0, 0);
+  mfb_status_t st = gather_blocks(f, s, 1, sin, f->Vs, 0, 0, 2);
   if (st) return st;
   st = run_classes(
       f, MFB_K_COMPLETION, f->plan->cs_compl_flat, s, 1, OP_COMPLETION,
@@ -768,7 +776,7 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
         } else if (cls == kWide) {
           k_product<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
                                                   f->scratch, slot);
-          launch_wide_update(0, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+          launch_wide_update(3, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
         } else {
           k_product<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
@@ -833,7 +841,7 @@ mfb_status_t mfb_profile_read(mfb_factor_t f, mfb_profile_entry_t* out, int64_t 
 const char* mfb_kernel_name(int32_t kernel) {
   static const char* names[MFB_K_COUNT] = {"k_factor", "k_projinv", "k_hess_up", "k_hess_down",
                                            "k_ihess_down", "k_ihess_up", "k_completion", "k_vinv",
-                                           "k_product", "k_gather_v"};
+                                           "k_product", "k_gather"};
   return (kernel >= 0 && kernel < MFB_K_COUNT) ? names[kernel] : "unknown";
 }
 

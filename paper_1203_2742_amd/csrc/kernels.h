@@ -34,13 +34,13 @@ __global__ void k_completion(DevPlan, const int32_t*, const double*, double*, do
                              double*, double*, double*, DevStatus*, double*, int64_t);
 __global__ void k_vinv(DevPlan, const int32_t*, const double*, double*, DevStatus*, double*,
                        int64_t);
-__global__ void k_gather_v(DevPlan, const int32_t*, const double*, double*, int64_t, int64_t);
 template <int STAGE>
 __global__ void k_hess_down_root(DevPlan, const int32_t*, const double*, const double*, double*, double*,
                                  int64_t);
 template <int STAGE>
 __global__ void k_ihess_down_root(DevPlan, const int32_t*, const double*, const double*, double*, double*,
                                   int64_t);
+template <int TAG>
 __global__ void k_gather_map(const int64_t*, int64_t, const double*, double*, int64_t, int64_t);
 template <bool PANEL>
 __global__ void k_product(DevPlan, const int32_t*, const double*, double*, double*, double*,
@@ -77,12 +77,13 @@ void launch_ihess_down_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, 
 // and root-to-leaf products over the wide fronts of one level.  `pre_aa`
 // numbers the 64 x 64 lower tiles of the A x A blocks, `pre_rt` the 64-row
 // tiles of the A x N blocks, front by front (count + 1 entries each).
-// op: 0 factor / product, 1 Hessian step 1, 2 inverse Hessian step 3.
+// op: 0 factor, 1 Hessian step 1, 2 inverse Hessian step 3, 3 product.
 void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const int32_t* pre, int count, const double* R, const double* LB, const double* Kt,
                         double* Ua, int64_t upd, const double* wsb, int64_t slot);
-void launch_wide_extract(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre,
-                         int count, const double* src, double* arena, int64_t src_stride,
+// tag (profile attribution): 1 inverse Hessian gather, 2 completion gather
+void launch_wide_extract(int tag, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                         const int32_t* pre, int count, const double* src, double* arena, int64_t src_stride,
                          int64_t arena_stride);
 void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre_aa,
                          const int32_t* pre_rt, int count, int n_aa, int n_rt, const double* LB, double* S,

@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(NT_DOWN) k_ihess_down(DevPlan P, const int32_t
     double* MN = Z + (int64_t)A * N;
     double* Dm = MN + (int64_t)N * N;
     double* W = Dm + (int64_t)N * N;
-    // (V'_s = T_{A_s A_s} is in the arena: k_gather_v)
+    // (V'_s = T_{A_s A_s} is in the arena, gathered beforehand)
     // D = C C^T (full)
     wg_gemm_split<NT_DOWN>(
         N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
@@ -457,7 +457,7 @@ template __global__ void k_ihess_up<true>(DevPlan, const int32_t*, const double*
 
 // ---------------------------------------------------------------------------
 // Algorithm 7.3: matrix completion of one front, with V_s = S_{A_s A_s}
-// already gathered (k_gather_v): L_AN = -V_s^-1 S_AN; D^-1 = S_NN +
+// already gathered: L_AN = -V_s^-1 S_AN; D^-1 = S_NN +
 // S_AN^T L_AN; then C = chol(D), B = L_AN C so that the handle holds the
 // factor of X-hat.  Also caches S and the inverse of V_s in its packed
 // block (see kVExplicitMax).  Scratch: 3N^2 + AN.
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
       const int rr = int(e % v.J), c = int(e / v.J);
       if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
     }
-    __syncthreads();  // (V_s was gathered by k_gather_v)
+    __syncthreads();  // (V_s was gathered beforehand)
     const double* V = Vs + P.arena[v.s];
     double* VI = Vi + P.arena[v.s];
     const PackedLower Cvi{VI, A};  // C_V^-1 once formed
@@ -569,22 +569,13 @@ __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, con
   });
 }
 
-// Gather pass (root-to-leaf level) of the steps that read a block of their
-// input: V_s = S_{A_s A_s} for the completion, V'_s = T_{A_s A_s} for the
-// inverse Hessian (right-hand side blockIdx.y), into the packed arena, from
-// the parent's CCS columns and the parent's packed block (the extraction of
-// eq. e-sn-gradient-2 applied to the input itself).  With every block in
-// place those steps depend on nothing but their own front.
-__global__ void __launch_bounds__(NT) k_gather_v(DevPlan P, const int32_t* list, const double* Sin,
-                                                 double* Vs, int64_t src_stride, int64_t arena_stride) {
-  __shared__ double sm[SMEM_DOUBLES];
-  const int64_t r = blockIdx.y;  // right-hand side
-  extract_from_parent(P, SnView(P, list[blockIdx.x]), Sin + r * src_stride, Vs + r * arena_stride, sm);
-}
-
-// The same gather with the plan's source map: arena[e] = src[map[e]] for
+// Gather pass of the steps that read a block of their input (V_s =
+// S_{A_s A_s} for the completion, V'_s = T_{A_s A_s} for the inverse
+// Hessian) with the plan's source map: arena[e] = src[map[e]] for
 // every packed update-block entry e < n (right-hand side blockIdx.y), one
 // elementwise launch for all supernodes.
+// TAG only names the caller in profiles (1 inverse Hessian, 2 completion).
+template <int TAG>
 __global__ void __launch_bounds__(NT) k_gather_map(const int64_t* map, int64_t n, const double* src,
                                                    double* arena, int64_t src_stride, int64_t arena_stride) {
   const int64_t r = blockIdx.y;
@@ -593,6 +584,8 @@ __global__ void __launch_bounds__(NT) k_gather_map(const int64_t* map, int64_t n
   for (int64_t e = int64_t(blockIdx.x) * NT + threadIdx.x; e < n; e += int64_t(gridDim.x) * NT)
     ar[e] = sr[map[e]];
 }
+template __global__ void k_gather_map<1>(const int64_t*, int64_t, const double*, double*, int64_t, int64_t);
+template __global__ void k_gather_map<2>(const int64_t*, int64_t, const double*, double*, int64_t, int64_t);
 
 // ---------------------------------------------------------------------------
 // Algorithm 3.2 in block form (leaf-to-root): with G = sum E U_c E^T,
@@ -995,7 +988,7 @@ __global__ void __launch_bounds__(C::NTH) k_completion_reg(DevPlan P, const int3
   stage_col<C>(v, colc);
   RegFront<C> M;
   load_panel(M, v, Sin);
-  load_packed_block(M, v, VS);  // V_s, gathered by k_gather_v
+  load_packed_block(M, v, VS);  // V_s, gathered beforehand
   // cache S (own columns)
   store_front(M, v, [&](int64_t o, double y) { S[o] = y; }, [](int64_t, double) {});
   const bool badV = M.sweeps(N, J, buf) >= 0;
@@ -1313,7 +1306,7 @@ __global__ void __launch_bounds__(C::NTH) k_ihess_down_reg(DevPlan P, const int3
   double* WZ = MA + (int64_t)A * N;     // J x N
   const double* Vp = va + P.arena[v.s];
   const double* VI = Vi + P.arena[v.s];
-  // V'_s = T_{A_s A_s} is in the arena (k_gather_v)
+  // V'_s = T_{A_s A_s} is in the arena (gathered beforehand)
   RegFront<C, false> M;  // general J x N products ([W; Z] is not symmetric)
   // D = C C^T
   M.zero();

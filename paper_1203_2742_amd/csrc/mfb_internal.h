@@ -149,6 +149,10 @@ struct mfb_plan_s {
   // all_levels: every supernode as one level (canonical counts of a gather)
   std::vector<int64_t> gmap;
   std::vector<mfb::Level> all_levels;
+  // the same gather level by level (plans without the map): per
+  // root-to-leaf level one segment of the fronts with A > 0, its tiles
+  // numbered as in a wide segment
+  mfb::ClassSched cs_gather;
   const int64_t* d_gmap = nullptr;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;

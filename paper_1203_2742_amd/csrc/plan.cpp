@@ -504,6 +504,40 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     }
   }
   p->all_levels.assign(1, Level{0, ns, 0, 0, 0, 0, double(p->update_doubles), 0, 0, 0, 0});
+  // The gather without the map: one launch per root-to-leaf level over the
+  // 64 x 64 lower tiles of every A x A block of the level.
+  {
+    ClassSched& cs = p->cs_gather;
+    cs.list.clear();
+    cs.segs.clear();
+    cs.pre.clear();
+    for (int32_t l = 0; l < int32_t(p->down_levels.size()); ++l) {
+      const Level& L = p->down_levels[l];
+      Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      ClassSeg g{S, l, kWide};
+      g.aa_off = int32_t(cs.pre.size());
+      int32_t acc = 0;
+      for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
+        const int32_t k = p->down_list[t];
+        const int32_t A = p->J[k] - p->N[k];
+        if (A == 0) continue;
+        cs.list.push_back(k);
+        cs.pre.push_back(acc);
+        const int32_t nt = (A + kWideTile - 1) / kWideTile;
+        acc += nt * (nt + 1) / 2;
+        g.lv.count++;
+        g.lv.maxA = std::max(g.lv.maxA, A);
+        g.lv.u += double(A) * (A + 1) / 2;
+      }
+      if (!g.lv.count) {
+        cs.pre.resize(size_t(g.aa_off));
+        continue;
+      }
+      cs.pre.push_back(acc);
+      g.n_aa = acc;
+      cs.segs.push_back(g);
+    }
+  }
 
   // Canonical algorithmic flop counts per supernode (LAPACK conventions).
   for (int32_t k = 0; k < ns; ++k) {

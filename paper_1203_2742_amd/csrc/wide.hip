@@ -84,7 +84,9 @@ __device__ __forceinline__ int find_rel(const int32_t* rl, int Ac, int p) {
 // Thread t owns row t mod 64 and columns t / 64 + 4q of the tile, so the
 // gathers from the children's packed columns and the stores are
 // contiguous across a wavefront.
-enum { WU_FACTOR = 0, WU_HUP = 1, WU_IHUP = 2 };
+// (WU_PRODUCT: the product's update, the same arithmetic as WU_FACTOR under
+// a kernel symbol of its own, so that profiles attribute it.)
+enum { WU_FACTOR = 0, WU_HUP = 1, WU_IHUP = 2, WU_PRODUCT = 3 };
 
 template <int OP>
 __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* list, const int32_t* pre,
@@ -107,16 +109,16 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
     const double* ws = wsb + (r * count + f) * slot;
     double* ua = Ua + r * upd;
     auto P1 = [&](int x, int k) -> double {
-      if (OP == WU_FACTOR) return R[v.an(x, k)];
+      if (OP == WU_FACTOR || OP == WU_PRODUCT) return R[v.an(x, k)];
       if (OP == WU_HUP) return k < N ? LB[v.an(x, k)] : K[v.an(x, k - N)];
       return k < N ? ws[(int64_t)J * N + x + (int64_t)k * A] : LB[v.an(x, k - N)];
     };
     auto P2 = [&](int y, int k) -> double {
-      if (OP == WU_FACTOR) return R[v.an(y, k)];
+      if (OP == WU_FACTOR || OP == WU_PRODUCT) return R[v.an(y, k)];
       if (OP == WU_HUP) return k < N ? ws[(N + y) + (int64_t)k * J] : LB[v.an(y, k - N)];
       return k < N ? LB[v.an(y, k)] : K[v.an(y, k - N)];
     };
-    const int KK = OP == WU_FACTOR ? N : 2 * N;
+    const int KK = (OP == WU_FACTOR || OP == WU_PRODUCT) ? N : 2 * N;
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
@@ -215,7 +217,10 @@ __device__ __forceinline__ void wide_extract_tile(const DevPlan& P, int s, int t
 }
 
 // Tiles of the extraction over the segment (blockIdx.y: right-hand side,
-// with its own source array and arena at the given strides).
+// with its own source array and arena at the given strides).  TAG only
+// names the caller in profiles: 0 the projected inverse, 1 the gather of
+// T_AA for the inverse Hessian, 2 the gather of S_AA for the completion.
+template <int TAG>
 __global__ void __launch_bounds__(NT) k_wide_extract(DevPlan P, const int32_t* list, const int32_t* pre,
                                                      int count, const double* src, double* arena,
                                                      int64_t src_stride, int64_t arena_stride) {
@@ -389,22 +394,28 @@ void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, cons
     case WU_HUP:
       k_wide_update<WU_HUP><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot);
       break;
+    case WU_PRODUCT:
+      k_wide_update<WU_PRODUCT><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot);
+      break;
     default:
       k_wide_update<WU_IHUP><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot);
       break;
   }
 }
 
-void launch_wide_extract(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre,
-                         int count, const double* src, double* arena, int64_t src_stride,
+void launch_wide_extract(int tag, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
+                         const int32_t* pre, int count, const double* src, double* arena, int64_t src_stride,
                          int64_t arena_stride) {
-  k_wide_extract<<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride);
+  if (tag == 1)
+    k_wide_extract<1><<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride);
+  else
+    k_wide_extract<2><<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride);
 }
 
 void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre_aa,
                          const int32_t* pre_rt, int count, int n_aa, int n_rt, const double* LB, double* S,
                          double* Vs) {
-  k_wide_extract<<<dim3(unsigned(n_aa)), NT, 0, s>>>(P, list, pre_aa, count, S, Vs, 0, 0);
+  k_wide_extract<0><<<dim3(unsigned(n_aa)), NT, 0, s>>>(P, list, pre_aa, count, S, Vs, 0, 0);
   k_wide_projinv_an<<<dim3(unsigned(n_rt)), NT, 0, s>>>(P, list, pre_rt, count, LB, S, Vs);
   k_wide_projinv_nn<<<dim3(unsigned(count)), NT, 0, s>>>(P, list, LB, S);
 }

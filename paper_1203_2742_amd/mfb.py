@@ -45,7 +45,7 @@ class MfbError(RuntimeError):
 
 
 KERNELS = ("k_factor", "k_projinv", "k_hess_up", "k_hess_down", "k_ihess_down", "k_ihess_up",
-           "k_completion", "k_vinv", "k_product", "k_gather_v")
+           "k_completion", "k_vinv", "k_product", "k_gather")
 
 
 class ProfileEntry(ctypes.Structure):
