@@ -93,7 +93,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list),
          iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
          iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre), iGl = v32(p->cs_gather.list),
-         iGp = v32(p->cs_gather.pre);
+         iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -135,6 +135,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_hdown.d_pre = (const int32_t*)at(iPh);
   p->cs_gather.d_list = (const int32_t*)at(iGl);
   p->cs_gather.d_pre = (const int32_t*)at(iGp);
+  p->cs_ihd_flat.d_pre = (const int32_t*)at(iPi);
   return MFB_OK;
 }
 
@@ -377,6 +378,13 @@ static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, 
   return MFB_OK;
 }
 
+static WideTiles wide_tiles(const ClassSched& cs, const ClassSeg& g) {
+  return WideTiles{cs.d_pre + g.aa_off, cs.d_pre + g.an_off, cs.d_pre + g.nn_off, g.n_aa, g.n_an, g.n_nn};
+}
+static FatGrid fat_grid(const ClassSeg& g) {
+  return FatGrid{g.lv.maxN, g.lv.maxA, g.lv.maxJ, g.fat_panel, g.fat_fin};
+}
+
 // Packed A_s x A_s blocks of an input (S for the completion, T for the
 // inverse Hessian, k right-hand sides) into `arena`: one elementwise launch
 // with the plan's source map, else level by level from the parents.
@@ -431,6 +439,13 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
                                                  f->part, f->st, f->scratch, slot);
           launch_wide_update(0, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+        } else if (cls == kFat) {
+          const FatGrid fg = fat_grid(sg);
+          launch_fat_panel(0, fg, 1, s, f->plan->dev, list, sg.lv.count, ((Ctx*)c)->x, f->U, 0, f->scratch, slot);
+          launch_fat_factor(fg, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, f->part, f->st, f->scratch, slot);
+          if (sg.n_aa)
+            launch_wide_update(0, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                               sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
         } else {
           k_factor<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
                                                   f->part, f->st, f->scratch, slot);
@@ -461,8 +476,7 @@ static mfb_status_t ensure_projinv(mfb_factor_s* f, hipStream_t s) {
         if (cls < kRegClasses)
           launch_projinv_reg(cls, g, s, f->plan->dev, list, f->LB, f->S, f->Vs);
         else if (cls == kWide)
-          launch_wide_projinv(s, f->plan->dev, list, cs.d_pre + sg.aa_off, cs.d_pre + sg.rt_off, sg.lv.count,
-                              sg.n_aa, sg.n_rt, f->LB, f->S, f->Vs);
+          launch_wide_projinv(s, f->plan->dev, list, wide_tiles(cs, sg), sg.lv.count, f->LB, f->S, f->Vs);
         else
           k_projinv<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->S, f->Vs);
       },
@@ -524,6 +538,15 @@ static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, dou
                                                   x->a.upd, x->a.scr, slot);
           launch_wide_update(1, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+        } else if (cls == kFat) {
+          const FatGrid fg = fat_grid(sg);
+          const int k = int(g.y);
+          launch_fat_panel(1, fg, k, s, f->plan->dev, list, sg.lv.count, x->y, x->a.Ua, x->a.upd, x->a.scr, slot);
+          launch_fat_up_fin(1, fg, k, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, nullptr, x->a.Kt, x->a.scr,
+                            slot);
+          if (sg.n_aa)
+            launch_wide_update(1, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                               sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
         } else {
           k_hess_up<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua,
                                                    x->a.upd, x->a.scr, slot);
@@ -564,9 +587,8 @@ static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, dou
           launch_hess_down_reg(cls, g, s, f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                x->a.upd, x->a.scr, slot);
         else if (cls == kWide)
-          launch_wide_hess_down(int(g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off, cs.d_pre + sg.rt_off,
-                                sg.lv.count, sg.n_aa, sg.n_rt, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua, x->a.upd,
-                                x->a.scr, slot);
+          launch_wide_hess_down(int(g.y), s, f->plan->dev, list, wide_tiles(cs, sg), sg.lv.count, f->LB, f->Vs,
+                                x->a.Kt, x->t, x->a.Ua, x->a.upd, x->a.scr, slot);
         else
           k_hess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                               x->a.upd, x->a.scr, slot);
@@ -700,6 +722,9 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
         if (cls < kRegClasses)
           launch_ihess_down_reg(cls, g, s, f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
                                 x->a.Ua, x->a.upd, x->a.scr, slot);
+        else if (cls == kFat)
+          launch_fat_ihess(fat_grid(sg), int(g.y), s, f->plan->dev, list, sg.lv.count, f->R, f->LB, f->Vi, x->t,
+                           x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
         else
           k_ihess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
                                                x->a.Ua, x->a.upd, x->a.scr, slot);
@@ -719,6 +744,16 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
                                                    x->a.upd, x->a.scr, slot);
           launch_wide_update(2, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+        } else if (cls == kFat) {
+          const FatGrid fg = fat_grid(sg);
+          const int k = int(g.y);
+          launch_fat_panel(2, fg, k, s, f->plan->dev, list, sg.lv.count, nullptr, x->a.Ua, x->a.upd, x->a.scr,
+                           slot);
+          launch_fat_up_fin(2, fg, k, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, x->y, x->a.Kt, x->a.scr,
+                            slot);
+          if (sg.n_aa)
+            launch_wide_update(2, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                               sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
         } else {
           k_ihess_up<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
                                                     x->a.upd, x->a.scr, slot);
@@ -778,6 +813,14 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
                                                   f->scratch, slot);
           launch_wide_update(3, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+        } else if (cls == kFat) {
+          const FatGrid fg = fat_grid(sg);
+          launch_fat_panel(3, fg, 1, s, f->plan->dev, list, sg.lv.count, nullptr, f->U, 0, f->scratch, slot);
+          launch_fat_up_fin(0, fg, 1, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, ((Ctx*)c)->x, nullptr,
+                            f->scratch, slot);
+          if (sg.n_aa)
+            launch_wide_update(3, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
+                               sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
         } else {
           k_product<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
                                                    f->scratch, slot);

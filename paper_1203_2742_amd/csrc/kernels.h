@@ -74,9 +74,14 @@ void launch_ihess_down_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, 
                            double* Kt, double* Va, int64_t upd, double* wsb, int64_t slot);
 
 // Wide fronts (wide.hip): tile-parallel update blocks, parent extraction
-// and root-to-leaf products over the wide fronts of one level.  `pre_aa`
-// numbers the 64 x 64 lower tiles of the A x A blocks, `pre_rt` the 64-row
-// tiles of the A x N blocks, front by front (count + 1 entries each).
+// and root-to-leaf products over the wide fronts of one level.  The tiles
+// of a segment are numbered front by front through prefix arrays (count +
+// 1 entries each): `aa` the 64 x 64 lower tiles of the A x A blocks, `an`
+// the 64 x 64 tiles of the A x N blocks, `nn` those of the N x N blocks.
+struct WideTiles {
+  const int32_t *aa, *an, *nn;
+  int n_aa, n_an, n_nn;
+};
 // op: 0 factor, 1 Hessian step 1, 2 inverse Hessian step 3, 3 product.
 void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const int32_t* pre, int count, const double* R, const double* LB, const double* Kt,
@@ -85,12 +90,28 @@ void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, cons
 void launch_wide_extract(int tag, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                          const int32_t* pre, int count, const double* src, double* arena, int64_t src_stride,
                          int64_t arena_stride);
-void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre_aa,
-                         const int32_t* pre_rt, int count, int n_aa, int n_rt, const double* LB, double* S,
-                         double* Vs);
-void launch_wide_hess_down(int k, hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre_aa,
-                           const int32_t* pre_rt, int count, int n_aa, int n_rt, const double* LB,
-                           const double* Vs, const double* Kt, double* T, double* Va, int64_t upd, double* wsb,
-                           int64_t slot);
+void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w, int count,
+                         const double* LB, double* S, double* Vs);
+void launch_wide_hess_down(int k, hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w,
+                           int count, const double* LB, const double* Vs, const double* Kt, double* T, double* Va,
+                           int64_t upd, double* wsb, int64_t slot);
+// Fat fronts (more than kWideMaxN columns): grids sized by the segment's
+// largest front; `panel` = tiles of the J x N panel, `fin` = NN plus AN
+// tiles.  Panel op: 0 factor (source X), 1 Hessian step 1 (source Y),
+// 2 inverse Hessian step 3, 3 product (children only).
+struct FatGrid {
+  int maxN, maxA, maxJ, panel, fin;
+};
+void launch_fat_panel(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                      int count, const double* src, const double* Ua, int64_t upd, double* wsb, int64_t slot);
+void launch_fat_factor(const FatGrid& g, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
+                       double* R, double* LB, double* part, DevStatus* st, double* wsb, int64_t slot);
+// op: 0 product (Out = X), 1 Hessian step 1 (K), 2 inverse Hessian step 3 (Out = Y)
+void launch_fat_up_fin(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                       int count, const double* R, const double* LB, double* Out, double* Kt, double* wsb,
+                       int64_t slot);
+void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
+                      const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
+                      const double* Va, int64_t upd, double* wsb, int64_t slot);
 
 }  // namespace mfb

@@ -48,7 +48,7 @@ enum Op { OP_FACTOR, OP_PRODUCT, OP_COMPLETION, OP_VINV, OP_HUP, OP_HDOWN, OP_IH
 inline int64_t slot_doubles(Op op, const Level& L) {
   const int64_t N = L.maxN, A = L.maxA, J = L.maxJ;
   switch (op) {
-    case OP_FACTOR: return J * N + N * N;
+    case OP_FACTOR: return J * N + N * N + 64 * N + 4096;  // fat fronts: + inverse diagonal blocks
     case OP_PRODUCT: return J * N;
     case OP_COMPLETION: return 3 * N * N + A * N;
     case OP_VINV: return 1;
@@ -90,6 +90,7 @@ constexpr int kWideMaxN = 64;
 constexpr int kWideJ = 512;     // default threshold on J
 constexpr int kWideJLow = 64;   // with MFB_PLAN_WIDE_LOW
 constexpr int kWide = kRegClasses + 1;  // class value of a wide segment
+constexpr int kFat = kRegClasses + 2;   // class value of a segment of fat fronts
 constexpr int kWideTile = 64;
 
 // A level of a schedule split by class: at most three launches (groups of
@@ -103,7 +104,13 @@ constexpr int kWideTile = 64;
 struct ClassSeg {
   Level lv;  // begin/count index the schedule's own list
   int32_t level, cls;
-  int32_t aa_off = 0, rt_off = 0, n_aa = 0, n_rt = 0;
+  // tile numbering of a wide or fat segment: prefix arrays in the
+  // schedule's `pre` (count + 1 entries each) of the 64 x 64 lower tiles of
+  // the A x A blocks (aa), of the tiles of the A x N blocks (an) and of the
+  // N x N blocks (nn), with their totals; for fat segments also the grid
+  // sizes of the per-front tile sets (largest front)
+  int32_t aa_off = 0, an_off = 0, nn_off = 0, n_aa = 0, n_an = 0, n_nn = 0;
+  int32_t fat_panel = 0, fat_fin = 0;
 };
 struct ClassSched {
   std::vector<int32_t> list;

@@ -260,8 +260,48 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   // launched first on their level, with their tiles numbered: 64 x 64 lower
   // tiles of the A x A block and 64-row tiles of the A rows.
   p->wide_thr = (flags & MFB_PLAN_WIDE_LOW) ? kWideJLow : kWideJ;
-  auto is_wide = [&](int32_t k) {
-    return p->J[k] > p->wide_thr && p->N[k] <= kWideMaxN && p->J[k] > p->N[k];
+  // every front above the threshold is wide in the root-to-leaf sweeps; in
+  // the leaf-to-root ones those with at most kWideMaxN columns (and an
+  // update block) are wide and the others fat
+  auto is_wide = [&](int32_t k) { return p->J[k] > p->wide_thr; };
+  auto up_class = [&](int32_t k) {
+    if (!is_wide(k)) return -1;
+    return p->N[k] > kWideMaxN ? kFat : (p->J[k] > p->N[k] ? kWide : -1);
+  };
+  auto number_tiles = [&](ClassSched& cs, ClassSeg& g) {
+    auto tl = [](int32_t m) { return (m + kWideTile - 1) / kWideTile; };
+    const Level& S = g.lv;
+    int32_t acc = 0;
+    g.aa_off = int32_t(cs.pre.size());
+    for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
+      cs.pre.push_back(acc);
+      const int32_t na = tl(p->J[cs.list[t]] - p->N[cs.list[t]]);
+      acc += na * (na + 1) / 2;
+    }
+    cs.pre.push_back(acc);
+    g.n_aa = acc;
+    g.an_off = int32_t(cs.pre.size());
+    acc = 0;
+    for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
+      cs.pre.push_back(acc);
+      acc += tl(p->J[cs.list[t]] - p->N[cs.list[t]]) * tl(p->N[cs.list[t]]);
+    }
+    cs.pre.push_back(acc);
+    g.n_an = acc;
+    g.nn_off = int32_t(cs.pre.size());
+    acc = 0;
+    for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
+      cs.pre.push_back(acc);
+      acc += tl(p->N[cs.list[t]]) * tl(p->N[cs.list[t]]);
+    }
+    cs.pre.push_back(acc);
+    g.n_nn = acc;
+    g.fat_panel = g.fat_fin = 0;
+    for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
+      const int32_t k = cs.list[t], tn = tl(p->N[k]), ta = tl(p->J[k] - p->N[k]);
+      g.fat_panel = std::max(g.fat_panel, tl(p->J[k]) * tn);
+      g.fat_fin = std::max(g.fat_fin, tn * tn + ta * tn);
+    }
   };
   auto down_reg_level = [&](const std::vector<int32_t>& list, const Level& L, bool wide_ok) {
     bool small = true, roots = true;
@@ -292,10 +332,11 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
         if (!(wide_ok && is_wide(list[t])) && fit_class(list[t]) < kRegClasses)
           lvcls = std::max(lvcls, fit_class(list[t]));
       auto class_of = [&](int32_t k) {
-        if (wide_ok && is_wide(k)) return kWide;
+        if (wide_ok && !down && up_class(k) >= 0) return up_class(k);
+        if (wide_ok && down && is_wide(k)) return kWide;
         return reg_ok && fit_class(k) < kRegClasses ? lvcls : kRegClasses;
       };
-      for (int c : {kWide, kRegClasses, lvcls}) {
+      for (int c : {kFat, kWide, kRegClasses, lvcls}) {
         Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
           const int32_t k = list[t];
@@ -315,26 +356,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
         }
         if (!S.count) continue;
         ClassSeg g{S, l, c};
-        if (c == kWide) {
-          auto tiles = [](int32_t A) { return (A + kWideTile - 1) / kWideTile; };
-          g.aa_off = int32_t(cs.pre.size());
-          int32_t acc = 0;
-          for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
-            cs.pre.push_back(acc);
-            const int32_t nt = tiles(p->J[cs.list[t]] - p->N[cs.list[t]]);
-            acc += nt * (nt + 1) / 2;
-          }
-          cs.pre.push_back(acc);
-          g.n_aa = acc;
-          g.rt_off = int32_t(cs.pre.size());
-          acc = 0;
-          for (int32_t t = S.begin; t < S.begin + S.count; ++t) {
-            cs.pre.push_back(acc);
-            acc += tiles(p->J[cs.list[t]] - p->N[cs.list[t]]);
-          }
-          cs.pre.push_back(acc);
-          g.n_rt = acc;
-        }
+        if (c == kWide || c == kFat) number_tiles(cs, g);
         cs.segs.push_back(g);
       }
     }
@@ -415,14 +437,16 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     ClassSched& cs = p->cs_ihd_flat;
     cs.list.clear();
     cs.segs.clear();
+    cs.pre.clear();
     cs.list.reserve(ns);
     auto kind = [&](int32_t k) {
+      if (is_wide(k) && p->N[k] > kWideMaxN) return kFat;
       const bool reg = p->J[k] <= kDownRegMaxJ || p->J[k] == p->N[k];
       int c = 0;
       while (c < kRegClasses && p->J[k] > kRegMax[c]) ++c;
       return reg ? c : kRegClasses;
     };
-    for (int c = kRegClasses; c >= 0; --c) {
+    for (int c : {kFat, 5, 4, 3, 2, 1, 0}) {
       std::vector<int32_t> fr;
       for (int32_t k = 0; k < ns; ++k)
         if (kind(k) == c) fr.push_back(k);
@@ -435,7 +459,9 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
         T.maxA = std::max(T.maxA, p->J[k] - p->N[k]);
         T.maxJ = std::max(T.maxJ, p->J[k]);
         if (S.count && int64_t(T.count) * slot_doubles(OP_IHDOWN, T) > kFlatScratch) {
-          cs.segs.push_back(ClassSeg{S, -1, c});
+          ClassSeg g{S, -1, c};
+          if (c == kFat) number_tiles(cs, g);
+          cs.segs.push_back(g);
           S = Level{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
           T = S;
           T.count = 1;
@@ -453,7 +479,11 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
         cs.list.push_back(k);
         S = T;
       }
-      if (S.count) cs.segs.push_back(ClassSeg{S, -1, c});
+      if (S.count) {
+        ClassSeg g{S, -1, c};
+        if (c == kFat) number_tiles(cs, g);
+        cs.segs.push_back(g);
+      }
     }
   }
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down, true);
@@ -462,7 +492,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   p->ihd_root = -1;
   if (!p->down_levels.empty() && p->down_levels[0].count == 1) {
     const int32_t s = p->down_list[p->down_levels[0].begin];
-    if (p->J[s] == p->N[s] && p->N[s] > kDownRegMaxJ) {
+    if (p->J[s] == p->N[s] && p->N[s] > kDownRegMaxJ && !is_wide(s)) {
       p->hd_root = s;
       auto& sg = p->cs_hdown.segs;
       sg.erase(std::remove_if(sg.begin(), sg.end(), [](const ClassSeg& g) { return g.level == 0; }), sg.end());

@@ -233,50 +233,69 @@ __global__ void __launch_bounds__(NT) k_wide_extract(DevPlan P, const int32_t* l
   wide_extract_tile(P, list[f], ti, tj, src + r * src_stride, arena + r * arena_stride, rr, rc, cpc);
 }
 
-// Rows [i0, i0 + 64) of V (A x A symmetric, packed) times an A x N operand b:
-// accumulated into T, the k range split so that each part is fetched along
-// its contiguous index (below the tile: packed columns k read down the rows;
-// above it: the transposed entries V(k, i), read along k).
+// Tile (ti, tj) of the ceil(A/64) x ceil(N/64) grid of an A x N block (an
+// "AN tile") or of the ceil(N/64) x ceil(N/64) grid of an N x N block (an
+// "NN tile"), numbered row by row within the front.
+__device__ __forceinline__ void grid_tile(int l, int N, int& ti, int& tj) {
+  const int tn = (N + WT - 1) / WT;
+  ti = l / tn;
+  tj = l - ti * tn;
+}
+
+// Rows [i0, i0 + 64) and columns [j0, j0 + 64) of V b, with V an A x A
+// symmetric packed block and b(k, j) an A x N operand: accumulated into T,
+// the k range split so that each part is fetched along its contiguous
+// index (below the tile: packed columns k read down the rows; above it:
+// the transposed entries V(k, i), read along k).
 template <bool BK, class FB>
-__device__ __forceinline__ void wide_sym_rows(MfmaTile& T, int i0, int A, int N, const double* V, const FB& fb,
-                                              double* sm) {
+__device__ __forceinline__ void wide_sym_rows(MfmaTile& T, int i0, int j0, int A, int N, const double* V,
+                                              const FB& fb, double* sm) {
   auto lo = [&](int i, int k) { return V[pk(i, k, A)]; };  // k <= i
   auto hi = [&](int i, int k) { return V[pk(k, i, A)]; };  // k >= i
   auto mid = [&](int i, int k) { return sym_packed(V, i, k, A); };
   const int d0 = min(i0, A), d1 = min(i0 + WT, A);
-  tile_mma<false, BK>(T, i0, 0, A, N, 0, d0, lo, fb, sm);
-  tile_mma<false, BK>(T, i0, 0, A, N, d0, d1, mid, fb, sm);
-  tile_mma<true, BK>(T, i0, 0, A, N, d1, A, hi, fb, sm);
+  tile_mma<false, BK>(T, i0, j0, A, N, 0, d0, lo, fb, sm);
+  tile_mma<false, BK>(T, i0, j0, A, N, d0, d1, mid, fb, sm);
+  tile_mma<true, BK>(T, i0, j0, A, N, d1, A, hi, fb, sm);
 }
 
 // ---------------------------------------------------------------------------
 // Algorithm 7.2 on wide fronts (after k_wide_extract has put V_s in place):
-// S_AN = -V_s L_AN over 64-row tiles (tiles numbered through `pre`), then
-// S_NN = D^-1 - S_AN^T L_AN per front (k_wide_projinv_nn).
+// S_AN = -V_s L_AN over the AN tiles, then S_NN = D^-1 - S_AN^T L_AN over
+// the lower NN tiles.
 __global__ void __launch_bounds__(NT) k_wide_projinv_an(DevPlan P, const int32_t* list, const int32_t* pre,
                                                         int count, const double* LB, double* S,
                                                         const double* Vs) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   const int f = seg_front(pre, count, blockIdx.x);
-  const int i0 = (blockIdx.x - pre[f]) * WT;
   with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    int ti, tj;
+    grid_tile(blockIdx.x - pre[f], v.N, ti, tj);
+    const int i0 = ti * WT, j0 = tj * WT;
     const double* V = Vs + P.arena[v.s];
     MfmaTile T(threadIdx.x);
-    wide_sym_rows<true>(T, i0, v.A, v.N, V, [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
-    tile_store(T, i0, 0, v.A, v.N, [&](int i, int j, double acc) { S[v.an(i, j)] = -acc; }, false);
+    wide_sym_rows<true>(T, i0, j0, v.A, v.N, V, [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
+    tile_store(T, i0, j0, v.A, v.N, [&](int i, int j, double acc) { S[v.an(i, j)] = -acc; }, false);
   });
 }
 
-__global__ void __launch_bounds__(NT) k_wide_projinv_nn(DevPlan P, const int32_t* list, const double* LB,
-                                                        double* S) {
+__global__ void __launch_bounds__(NT) k_wide_projinv_nn(DevPlan P, const int32_t* list, const int32_t* pre,
+                                                        int count, const double* LB, double* S) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
-  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
-    wg_gemm<true, true>(
-        v.N, v.N, v.A, [&](int i, int k) { return S[v.an(k, i)]; },
-        [&](int k, int j) { return LB[v.an(k, j)]; },
-        [&](int i, int j, double acc) { S[v.at(i, j)] = LB[v.at(i, j)] - acc; }, true, sm);
+  const int f = seg_front(pre, count, blockIdx.x);
+  const int N = P.ncol[list[f]];
+  int ti, tj;
+  grid_tile(blockIdx.x - pre[f], N, ti, tj);
+  if (tj > ti) return;  // a tile wholly above the diagonal (the whole workgroup)
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int i0 = ti * WT, j0 = tj * WT;
+    MfmaTile T(threadIdx.x);
+    tile_mma<true, true>(T, i0, j0, v.N, v.N, 0, v.A, [&](int i, int k) { return S[v.an(k, i)]; },
+                         [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
+    tile_store(T, i0, j0, v.N, v.N, [&](int i, int j, double acc) { S[v.at(i, j)] = LB[v.at(i, j)] - acc; },
+               true);
   });
 }
 
@@ -284,12 +303,19 @@ __global__ void __launch_bounds__(NT) k_wide_projinv_nn(DevPlan P, const int32_t
 // Hessian steps 2+3 on wide fronts, three launches per segment.  Scratch
 // slot per (front, right-hand side): MN (N x N), MA (A x N), Z (A x N),
 // W (N x N), all column-major.
-//  a: the extraction tiles of V'_s (grid part 1), per front W = K_NN D^-1
-//     and MN = D^-1 W (part 2), Z = K_AN D^-1 over 64-row tiles (part 3);
-//  b: per 64-row tile MA = V_s Z and T_AN = MA - V'_s L;
-//  c: per front T_NN = MN - L^T T_AN - MA^T L.
-__global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* list, const int32_t* pre_aa,
-                                                     const int32_t* pre_rt, int count, int n_aa,
+//  a: the extraction tiles of V'_s, W = K_NN D^-1 over the NN tiles and
+//     Z = K_AN D^-1 over the AN tiles;
+//  b: MN = D^-1 W over the lower NN tiles; MA = V_s Z and T_AN = MA - V'_s L
+//     over the AN tiles;
+//  c: T_NN = MN - L^T T_AN - MA^T L over the lower NN tiles.
+struct SegTiles {
+  const int32_t* aa;  // prefix arrays (count + 1 entries each)
+  const int32_t* an;
+  const int32_t* nn;
+  int n_aa, n_an, n_nn;
+};
+
+__global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* list, SegTiles tl, int count,
                                                      const double* LB, const double* Kt, const double* T,
                                                      double* Va, int64_t upd, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
@@ -297,63 +323,79 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* l
   __shared__ int rr[WT], rc[WT];
   __shared__ int64_t cpc[WT];
   const int64_t r = blockIdx.y;
-  const int b = blockIdx.x;
-  if (b < n_aa) {
-    const int f = seg_front(pre_aa, count, b);
+  int b = blockIdx.x;
+  if (b < tl.n_aa) {
+    const int f = seg_front(tl.aa, count, b);
     int ti, tj;
-    tri_tile(b - pre_aa[f], ti, tj);
+    tri_tile(b - tl.aa[f], ti, tj);
     wide_extract_tile(P, list[f], ti, tj, T + r * P.nnz, Va + r * upd, rr, rc, cpc);
     return;
   }
-  const bool nn = b < n_aa + count;
-  const int f = nn ? b - n_aa : seg_front(pre_rt, count, b - n_aa - count);
+  b -= tl.n_aa;
+  const bool nn = b < tl.n_nn;
+  if (!nn) b -= tl.n_nn;
+  const int32_t* pre = nn ? tl.nn : tl.an;
+  const int f = seg_front(pre, count, b);
   with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
     const int N = v.N, A = v.A;
+    int ti, tj;
+    grid_tile(b - pre[f], N, ti, tj);
+    const int i0 = ti * WT, j0 = tj * WT;
     const double* K = Kt + r * P.nnz;
     double* MN = wsb + (r * count + f) * slot;
     double* Z = MN + (int64_t)N * N + (int64_t)A * N;
     double* W = Z + (int64_t)A * N;
     auto Dinv = [&](int i, int j) { return LB[v.nn(i, j)]; };
+    MfmaTile Tt(threadIdx.x);
     if (nn) {
-      wg_gemm<false, true>(
-          N, N, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv,
-          [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
-      __syncthreads();
-      wg_gemm<false, true>(
-          N, N, N, Dinv, [&](int k, int j) { return W[k + (int64_t)j * N]; },
-          [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true, sm);
+      tile_mma<false, true>(Tt, i0, j0, N, N, 0, N, [&](int i, int k) { return K[v.nn(i, k)]; }, Dinv, sm);
+      tile_store(Tt, i0, j0, N, N, [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false);
     } else {
-      const int i0 = (b - n_aa - count - pre_rt[f]) * WT;
-      MfmaTile Tz(threadIdx.x);
-      tile_mma<false, true>(Tz, i0, 0, A, N, 0, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv, sm);
-      tile_store(Tz, i0, 0, A, N, [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false);
+      tile_mma<false, true>(Tt, i0, j0, A, N, 0, N, [&](int i, int k) { return K[v.an(i, k)]; }, Dinv, sm);
+      tile_store(Tt, i0, j0, A, N, [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false);
     }
   });
 }
 
-__global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* list, const int32_t* pre_rt,
-                                                     int count, const double* LB, const double* Vs, double* T,
+__global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* list, SegTiles tl, int count,
+                                                     const double* LB, const double* Vs, double* T,
                                                      const double* Va, int64_t upd, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   const int64_t r = blockIdx.y;
-  const int f = seg_front(pre_rt, count, blockIdx.x);
-  const int i0 = (blockIdx.x - pre_rt[f]) * WT;
+  int b = blockIdx.x;
+  const bool nn = b < tl.n_nn;
+  if (!nn) b -= tl.n_nn;
+  const int32_t* pre = nn ? tl.nn : tl.an;
+  const int f = seg_front(pre, count, b);
+  const int N = P.ncol[list[f]];
+  int ti, tj;
+  grid_tile(b - pre[f], N, ti, tj);
+  if (nn && tj > ti) return;  // MN is read on and below the diagonal only
   with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
-    const int N = v.N, A = v.A;
+    const int A = v.A;
+    const int i0 = ti * WT, j0 = tj * WT;
     double* t = T + r * P.nnz;
     double* MN = wsb + (r * count + f) * slot;
     double* MA = MN + (int64_t)N * N;
     const double* Z = MA + (int64_t)A * N;
+    const double* W = Z + (int64_t)A * N;
+    if (nn) {
+      MfmaTile Tt(threadIdx.x);
+      tile_mma<false, true>(Tt, i0, j0, N, N, 0, N, [&](int i, int k) { return LB[v.nn(i, k)]; },
+                            [&](int k, int j) { return W[k + (int64_t)j * N]; }, sm);
+      tile_store(Tt, i0, j0, N, N, [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true);
+      return;
+    }
     MfmaTile Tm(threadIdx.x);
-    wide_sym_rows<true>(Tm, i0, A, N, Vs + P.arena[v.s], [&](int k, int j) { return Z[k + (int64_t)j * A]; },
+    wide_sym_rows<true>(Tm, i0, j0, A, N, Vs + P.arena[v.s], [&](int k, int j) { return Z[k + (int64_t)j * A]; },
                         sm);
     MfmaTile Tv(threadIdx.x);
-    wide_sym_rows<true>(Tv, i0, A, N, Va + r * upd + P.arena[v.s], [&](int k, int j) { return LB[v.an(k, j)]; },
-                        sm);
+    wide_sym_rows<true>(Tv, i0, j0, A, N, Va + r * upd + P.arena[v.s],
+                        [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int gi = i0 + Tm.row_of(e), gj = Tm.col_of(e);
+      const int gi = i0 + Tm.row_of(e), gj = j0 + Tm.col_of(e);
       if (gi < A && gj < N) {
         const double ma = Tm.get(e);
         MA[gi + (int64_t)gj * A] = ma;
@@ -363,21 +405,448 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* l
   });
 }
 
-__global__ void __launch_bounds__(NT) k_wide_hdown_c(DevPlan P, const int32_t* list, int count,
+__global__ void __launch_bounds__(NT) k_wide_hdown_c(DevPlan P, const int32_t* list, SegTiles tl, int count,
                                                      const double* LB, double* T, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   const int64_t r = blockIdx.y;
-  const int f = blockIdx.x;
+  const int f = seg_front(tl.nn, count, blockIdx.x);
+  const int N = P.ncol[list[f]];
+  int ti, tj;
+  grid_tile(blockIdx.x - tl.nn[f], N, ti, tj);
+  if (tj > ti) return;
   with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
-    const int N = v.N, A = v.A;
+    const int A = v.A;
+    const int i0 = ti * WT, j0 = tj * WT;
     double* t = T + r * P.nnz;
     const double* MN = wsb + (r * count + f) * slot;
     const double* MA = MN + (int64_t)N * N;
-    wg_gemm<true, true>(
-        N, N, 2 * A, [&](int i, int k) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
-        [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
-        [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; }, true, sm);
+    MfmaTile Tt(threadIdx.x);
+    tile_mma<true, true>(
+        Tt, i0, j0, N, N, 0, 2 * A,
+        [&](int i, int k) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
+        [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; }, sm);
+    tile_store(Tt, i0, j0, N, N, [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; },
+               true);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Fat fronts: more than kWideMaxN columns (the large separators and the
+// root).  The leaf-to-root sweeps' panel work (the J x N columns of the
+// front) runs tile-parallel too.  Grids are two-dimensional: blockIdx.x is
+// a tile of the front, blockIdx.y = f + count * r picks the front f of the
+// segment and the right-hand side r; tiles beyond a front's own count exit
+// at once.  Scratch slot per (front, RHS) starts with the panel F (J x N,
+// column-major, leading dimension J).
+
+// Tile counts of a front, in 64-wide tiles.
+struct FatDims {
+  int N, A, J, tn, ta, tj;
+  __device__ __forceinline__ explicit FatDims(const SnView& v)
+      : N(v.N), A(v.A), J(v.J), tn((v.N + WT - 1) / WT), ta((v.A + WT - 1) / WT), tj((v.J + WT - 1) / WT) {}
+};
+
+// The front's panel F (rows 0..J-1, columns 0..N-1; zero above the
+// diagonal) = the input's CCS panel (X for the factor, Y for Hessian step
+// 1; none for the product and inverse Hessian step 3) plus the children's
+// update blocks at their relative positions, children in a fixed order.
+// Tiles: ceil(J/64) x ceil(N/64), those wholly above the diagonal skipped.
+template <int TAG>
+__global__ void __launch_bounds__(NT) k_fat_panel(DevPlan P, const int32_t* list, int count, const double* src,
+                                                  const double* Ua, int64_t upd, double* wsb, int64_t slot) {
+  __shared__ int64_t colc[kColCache];
+  __shared__ int invr[WT], invc[WT];
+  const int f = blockIdx.y % count;
+  const int64_t r = blockIdx.y / count;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const FatDims d(v);
+    const int l = blockIdx.x;
+    if (l >= d.tj * d.tn) return;
+    const int ti = l / d.tn, tj = l - (l / d.tn) * d.tn;
+    const int i0 = ti * WT, j0 = tj * WT;
+    if (i0 + WT - 1 < j0) return;
+    const double* y = src ? src + r * P.nnz : nullptr;
+    const double* ua = Ua + r * upd;
+    double* F = wsb + (r * count + f) * slot;
+    const int row = threadIdx.x & (WT - 1), cq = threadIdx.x >> 6;
+    const int gi = i0 + row;
+    double g[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int gj = j0 + cq + 4 * q;
+      const bool ok = y && gi < d.J && gj < d.N && gi >= gj;
+      const double val = y ? y[ok ? v.at(gi, gj) : v.at(0, 0)] : 0.0;
+      g[q] = ok ? val : 0.0;
+    }
+    for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
+      const int c = P.cidx[t];
+      const int Ac = P.nrow[c] - P.ncol[c];
+      const int32_t* rl = P.rel + P.relbase[c];
+      const double* Uc = ua + P.arena[c];
+      const int tid = threadIdx.x;
+      if (tid < WT)
+        invr[tid] = i0 + tid < d.J ? find_rel(rl, Ac, i0 + tid) : -1;
+      else if (tid < 2 * WT)
+        invc[tid - WT] = j0 + tid - WT < d.N ? find_rel(rl, Ac, j0 + tid - WT) : -1;
+      __syncthreads();
+      const int cx = invr[row];
+      double u[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int cy = invc[cq + 4 * q];
+        const bool ok = cx >= 0 && cy >= 0 && cx >= cy;
+        const double val = Uc[ok ? pk(cx, cy, Ac) : 0];
+        u[q] = ok ? val : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) g[q] += u[q];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int gj = j0 + cq + 4 * q;
+      if (gi < d.J && gj < d.N) F[gi + (int64_t)gj * d.J] = gi >= gj ? g[q] : 0.0;
+    }
+  });
+}
+
+// Dense column-major accessor (reference to entry (i, j)).
+struct DenseAt {
+  double* a;
+  int64_t ld;
+  __device__ __forceinline__ double& operator()(int i, int j) const { return a[i + (int64_t)j * ld]; }
+};
+
+// Blocked Cholesky of the panel F, block column kb (64 columns): the
+// diagonal block by one workgroup per front (Cholesky factor C_kk in F and
+// in R, its inverse in the scratch block list after F, the log det part),
+// then (k_fat_potrf_panel) the rows below times C_kk^-T, then
+// (k_fat_potrf_trail) the remaining panel columns updated.  The inverse
+// blocks are stored 64 x 64 (zero above the diagonal) at F + J N + 4096 b
+// for block column b.
+__global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t* list, int count, int kb,
+                                                       double* R, double* part, DevStatus* st, double* wsb,
+                                                       int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  __shared__ int fail;
+  const int f = blockIdx.y;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    if (kb >= v.N) return;
+    const int nb = min(WT, v.N - kb), J = v.J;
+    double* F = wsb + (int64_t)f * slot;
+    double* Ci = F + (int64_t)J * v.N + (int64_t)(kb / WT) * WT * WT;
+    if (threadIdx.x == 0) fail = -1;
+    __syncthreads();
+    const DenseAt G{F + kb + (int64_t)kb * J, J};
+    wg_potrf_acc(G, nb, nb, sm, &fail);
+    for (int e = threadIdx.x; e < WT * WT; e += NT) {
+      const int i = e & (WT - 1), j = e >> 6;
+      Ci[e] = (i < nb && j < nb && i >= j) ? G(i, j) : 0.0;
+      if (i < nb && j < nb && i >= j) R[v.at(kb + i, kb + j)] = G(i, j);
+    }
+    __syncthreads();
+    wg_trtri_inplace(DenseAt{Ci, WT}, nb, sm);
+    double lg = 0.0;
+    for (int c = threadIdx.x; c < nb; c += NT) lg += 2.0 * log(G(c, c));
+    lg = wg_sum(lg, sm);
+    if (threadIdx.x == 0) {
+      part[v.s] = kb == 0 ? lg : part[v.s] + lg;
+      if (fail >= 0) report(st, MFB_ENOTPD, v.vl[kb + fail]);
+    }
+  });
+}
+
+__global__ void __launch_bounds__(NT) k_fat_potrf_panel(DevPlan P, const int32_t* list, int count, int kb,
+                                                        double* R, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int f = blockIdx.y;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    if (kb >= v.N) return;
+    const int nb = min(WT, v.N - kb), J = v.J;
+    const int i0 = kb + nb + int(blockIdx.x) * WT;
+    if (i0 >= J) return;
+    double* F = wsb + (int64_t)f * slot;
+    const double* Ci = F + (int64_t)J * v.N + (int64_t)(kb / WT) * WT * WT;
+    MfmaTile T(threadIdx.x);
+    tile_mma(T, i0, 0, J, nb, 0, nb, [&](int i, int k) { return F[i + (int64_t)(kb + k) * J]; },
+             [&](int k, int j) { return Ci[j + k * WT]; }, sm);
+    tile_store(
+        T, i0, 0, J, nb,
+        [&](int i, int j, double acc) {
+          F[i + (int64_t)(kb + j) * J] = acc;
+          R[v.at(i, kb + j)] = acc;
+        },
+        false);
+  });
+}
+
+__global__ void __launch_bounds__(NT) k_fat_potrf_trail(DevPlan P, const int32_t* list, int count, int kb,
+                                                        double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const int f = blockIdx.y;
+  const int s = list[f];
+  const int N = P.ncol[s], J = P.nrow[s];
+  if (kb >= N) return;
+  const int nb = min(WT, N - kb), r0 = kb + nb;
+  if (r0 >= N) return;
+  const int tc = (N - r0 + WT - 1) / WT, tr = (J - r0 + WT - 1) / WT;
+  const int l = blockIdx.x;
+  if (l >= tr * tc) return;
+  const int ti = l / tc, tj = l - (l / tc) * tc;
+  if (ti < tj) return;
+  const int i0 = r0 + ti * WT, j0 = r0 + tj * WT;
+  double* F = wsb + (int64_t)f * slot;
+  MfmaTile T(threadIdx.x);
+  tile_mma(T, i0, j0, J, N, 0, nb, [&](int i, int k) { return F[i + (int64_t)(kb + k) * J]; },
+           [&](int k, int c) { return F[c + (int64_t)(kb + k) * J]; }, sm);
+  tile_store(T, i0, j0, J, N, [&](int i, int c, double acc) { F[i + (int64_t)c * J] -= acc; }, true);
+}
+
+// Row block ib of X = C^-1 (C the N x N Cholesky factor in the panel F, X
+// in scratch after the inverse blocks, N x N column-major), one 64 x 64
+// tile (ib, jb), jb <= ib, per workgroup:
+//   X(ib, jb) = C_ib,ib^-1 (delta I - sum_{jb <= m < ib} C(ib, m) X(m, jb)),
+// so a launch per ib completes row block ib from the ones above it.
+__global__ void __launch_bounds__(NT) k_fat_trtri_row(DevPlan P, const int32_t* list, int count, int ib,
+                                                      double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double rb[WT * WLD];
+  const int f = blockIdx.y;
+  const int s = list[f];
+  const int N = P.ncol[s], J = P.nrow[s];
+  const int i0 = ib * WT, jb = blockIdx.x, j0 = jb * WT;
+  if (i0 >= N || jb > ib) return;
+  const int nbi = min(WT, N - i0);
+  double* F = wsb + (int64_t)f * slot;
+  const double* Cinv = F + (int64_t)J * N + (int64_t)ib * WT * WT;
+  double* X = F + (int64_t)J * N + (int64_t)((N + WT - 1) / WT) * WT * WT;
+  MfmaTile T(threadIdx.x);
+  tile_mma<false, true>(T, i0, j0, N, N, j0, i0, [&](int i, int k) { return F[i + (int64_t)k * J]; },
+                        [&](int k, int j) { return X[k + (int64_t)j * N]; }, sm);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int li = T.row_of(e), lj = T.col_of(e);
+    rb[li + lj * WLD] = (jb == ib && li == lj ? 1.0 : 0.0) - T.get(e);
+  }
+  __syncthreads();
+  MfmaTile T2(threadIdx.x);
+  tile_mma(T2, 0, 0, nbi, WT, 0, nbi, [&](int i, int k) { return Cinv[i + k * WT]; },
+           [&](int k, int j) { return rb[k + j * WLD]; }, sm);
+  tile_store(T2, 0, 0, nbi, min(WT, N - j0),
+             [&](int i, int j, double acc) { X[(i0 + i) + (int64_t)(j0 + j) * N] = acc; }, false);
+}
+
+// The factor's closing products on a fat front, X = C^-1 from
+// k_fat_trtri_row: D^-1 = X^T X over the lower NN tiles and
+// L_AN = B X over the AN tiles (B = the panel rows below N).
+__global__ void __launch_bounds__(NT) k_fat_factor_fin(DevPlan P, const int32_t* list, int count, double* LB,
+                                                       double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int f = blockIdx.y;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const FatDims d(v);
+    int b = blockIdx.x;
+    if (b >= d.tn * d.tn + d.ta * d.tn) return;
+    const double* F = wsb + (int64_t)f * slot;
+    const double* X = F + (int64_t)d.J * d.N + (int64_t)d.tn * WT * WT;
+    MfmaTile T(threadIdx.x);
+    if (b < d.tn * d.tn) {
+      const int ti = b / d.tn, tj = b - (b / d.tn) * d.tn;
+      if (tj > ti) return;
+      const int i0 = ti * WT, j0 = tj * WT;
+      tile_mma<true, true>(T, i0, j0, d.N, d.N, i0, d.N, [&](int i, int k) { return X[k + (int64_t)i * d.N]; },
+                           [&](int k, int j) { return X[k + (int64_t)j * d.N]; }, sm);
+      tile_store(T, i0, j0, d.N, d.N, [&](int i, int j, double acc) { LB[v.at(i, j)] = acc; }, true);
+    } else {
+      b -= d.tn * d.tn;
+      const int ti = b / d.tn, tj = b - (b / d.tn) * d.tn;
+      const int i0 = ti * WT, j0 = tj * WT;
+      tile_mma<false, true>(T, i0, j0, d.A, d.N, j0, d.N,
+                            [&](int x, int k) { return F[(d.N + x) + (int64_t)k * d.J]; },
+                            [&](int k, int j) { return X[k + (int64_t)j * d.N]; }, sm);
+      tile_store(T, i0, j0, d.A, d.N, [&](int x, int j, double acc) { LB[v.an(x, j)] = acc; }, false);
+    }
+  });
+}
+
+// The closing products of the other leaf-to-root sweeps on a fat front,
+// over the lower NN tiles and the AN tiles (G = the panel F of children's
+// contributions):
+//  FAT_PRODUCT: X_NN = C C^T - G11, X_AN = B C^T - G21 (Algorithm 3.2);
+//  FAT_HUP:     K_NN = F'11, K_AN = F'21 - L F'11 (Hessian step 1);
+//  FAT_IHUP:    Y_NN = K_NN - G'11, Q = L K_NN + K_AN (kept in the slot
+//               after the panel), Y_AN = Q - G'21 (inverse Hessian step 3).
+enum { FAT_PRODUCT = 0, FAT_HUP = 1, FAT_IHUP = 2 };
+template <int OP>
+__global__ void __launch_bounds__(NT) k_fat_up_fin(DevPlan P, const int32_t* list, int count, const double* R,
+                                                   const double* LB, double* Out, double* Kt, double* wsb,
+                                                   int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int f = blockIdx.y % count;
+  const int64_t r = blockIdx.y / count;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const FatDims d(v);
+    int b = blockIdx.x;
+    if (b >= d.tn * d.tn + d.ta * d.tn) return;
+    double* F = wsb + (r * count + f) * slot;
+    double* out = Out + r * P.nnz;
+    double* K = Kt ? Kt + r * P.nnz : nullptr;
+    const int N = d.N, J = d.J, A = d.A;
+    MfmaTile T(threadIdx.x);
+    if (b < d.tn * d.tn) {
+      const int ti = b / d.tn, tj = b - (b / d.tn) * d.tn;
+      if (tj > ti) return;
+      const int i0 = ti * WT, j0 = tj * WT;
+      if (OP == FAT_PRODUCT) {
+        auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
+        tile_mma(T, i0, j0, N, N, 0, min(N, j0 + WT), C, [&](int k, int j) { return C(j, k); }, sm);
+        tile_store(T, i0, j0, N, N,
+                   [&](int i, int j, double acc) { out[v.at(i, j)] = acc - F[i + (int64_t)j * J]; }, true);
+      } else {
+        // a copy: K_NN = F'11 (Hessian), Y_NN = K_NN - G'11 (inverse Hessian)
+        const int row = threadIdx.x & (WT - 1), cq = threadIdx.x >> 6;
+        const int gi = i0 + row;
+        for (int q = 0; q < 16; ++q) {
+          const int gj = j0 + cq + 4 * q;
+          if (gi < N && gj < N && gi >= gj) {
+            const double fv = F[gi + (int64_t)gj * J];
+            if (OP == FAT_HUP)
+              K[v.at(gi, gj)] = fv;
+            else
+              out[v.at(gi, gj)] = K[v.at(gi, gj)] - fv;
+          }
+        }
+      }
+      return;
+    }
+    b -= d.tn * d.tn;
+    const int ti = b / d.tn, tj = b - (b / d.tn) * d.tn;
+    const int i0 = ti * WT, j0 = tj * WT;
+    if (OP == FAT_PRODUCT) {
+      tile_mma(T, i0, j0, A, N, 0, min(N, j0 + WT), [&](int x, int k) { return R[v.an(x, k)]; },
+               [&](int k, int j) { return k <= j ? R[v.at(j, k)] : 0.0; }, sm);
+      tile_store(T, i0, j0, A, N,
+                 [&](int x, int j, double acc) { out[v.an(x, j)] = acc - F[(N + x) + (int64_t)j * J]; }, false);
+    } else if (OP == FAT_HUP) {
+      auto F11 = [&](int k, int j) { return k >= j ? F[k + (int64_t)j * J] : F[j + (int64_t)k * J]; };
+      tile_mma<false, true>(T, i0, j0, A, N, 0, N, [&](int x, int k) { return LB[v.an(x, k)]; }, F11, sm);
+      tile_store(T, i0, j0, A, N,
+                 [&](int x, int j, double acc) { K[v.an(x, j)] = F[(N + x) + (int64_t)j * J] - acc; }, false);
+    } else {
+      double* Q = F + (int64_t)J * N;
+      tile_mma<false, true>(T, i0, j0, A, N, 0, N, [&](int x, int k) { return LB[v.an(x, k)]; },
+                            [&](int k, int j) { return K[v.nn(k, j)]; }, sm);
+      tile_store(
+          T, i0, j0, A, N,
+          [&](int x, int j, double acc) {
+            const double q = acc + K[v.an(x, j)];
+            Q[x + (int64_t)j * A] = q;
+            out[v.an(x, j)] = q - F[(N + x) + (int64_t)j * J];
+          },
+          false);
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Inverse Hessian steps 1+2 on fat fronts (independent fronts, after the
+// gather of V'_s = T_AA), five launches over [NN tiles | AN tiles] of every
+// (front, RHS).  Scratch slot as for k_ihess_down: MA (A x N), Z (A x N),
+// MN, Dm, W (N x N each).
+//  1: Dm = C C^T (NN), MA = T_AN + V' L (AN);
+//  2: MN = T_NN + L^T MA + T_AN^T L (lower NN tiles, stored symmetric);
+//  3: W = MN Dm (NN), Z = MA Dm (AN);
+//  4: K_NN = Dm W (lower NN); K_AN = V^-1 Z (AN) with the explicit inverse,
+//     else MA <- C_V^-1 Z;
+//  5: K_AN = C_V^-T MA (AN; only when V_s is held as C_V^-1).
+template <int STAGE>
+__global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list, int count, const double* R,
+                                                  const double* LB, const double* Vi, const double* Tin,
+                                                  double* Kt, const double* Va, int64_t upd, double* wsb,
+                                                  int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int f = blockIdx.y % count;
+  const int64_t r = blockIdx.y / count;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const FatDims d(v);
+    const int N = d.N, A = d.A;
+    int b = blockIdx.x;
+    if (b >= d.tn * d.tn + d.ta * d.tn) return;
+    const bool nn = b < d.tn * d.tn;
+    if (!nn) b -= d.tn * d.tn;
+    const int ti = b / d.tn, tj = b - (b / d.tn) * d.tn;
+    const int i0 = ti * WT, j0 = tj * WT;
+    const bool explicit_v = A <= kVExplicitMax;
+    if (nn && tj > ti && (STAGE == 2 || STAGE == 4)) return;
+    if (!nn && STAGE == 2) return;
+    if (nn && STAGE == 5) return;
+    if (STAGE == 5 && explicit_v) return;
+    const double* t = Tin + r * P.nnz;
+    double* K = Kt + r * P.nnz;
+    double* MA = wsb + (r * count + f) * slot;
+    double* Z = MA + (int64_t)A * N;
+    double* MN = Z + (int64_t)A * N;
+    double* Dm = MN + (int64_t)N * N;
+    double* W = Dm + (int64_t)N * N;
+    const double* VI = Vi + P.arena[v.s];
+    MfmaTile T(threadIdx.x);
+    if (STAGE == 1) {
+      if (nn) {
+        auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
+        tile_mma(T, i0, j0, N, N, 0, min(N, min(i0, j0) + WT), C, [&](int k, int j) { return C(j, k); }, sm);
+        tile_store(T, i0, j0, N, N, [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false);
+      } else {
+        wide_sym_rows<true>(T, i0, j0, A, N, Va + r * upd + P.arena[v.s],
+                            [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
+        tile_store(T, i0, j0, A, N,
+                   [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false);
+      }
+    } else if (STAGE == 2) {
+      tile_mma<true, true>(
+          T, i0, j0, N, N, 0, 2 * A, [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
+          [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; }, sm);
+      tile_store(
+          T, i0, j0, N, N,
+          [&](int i, int j, double acc) {
+            const double m = t[v.at(i, j)] + acc;
+            MN[i + (int64_t)j * N] = m;
+            MN[j + (int64_t)i * N] = m;
+          },
+          true);
+    } else if (STAGE == 3) {
+      if (nn) {
+        tile_mma<false, true>(T, i0, j0, N, N, 0, N, [&](int i, int k) { return MN[i + (int64_t)k * N]; },
+                              [&](int k, int j) { return Dm[k + (int64_t)j * N]; }, sm);
+        tile_store(T, i0, j0, N, N, [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false);
+      } else {
+        tile_mma<false, true>(T, i0, j0, A, N, 0, N, [&](int i, int k) { return MA[i + (int64_t)k * A]; },
+                              [&](int k, int j) { return Dm[k + (int64_t)j * N]; }, sm);
+        tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false);
+      }
+    } else if (STAGE == 4) {
+      if (nn) {
+        tile_mma<false, true>(T, i0, j0, N, N, 0, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
+                              [&](int k, int j) { return W[k + (int64_t)j * N]; }, sm);
+        tile_store(T, i0, j0, N, N, [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true);
+      } else if (explicit_v) {
+        wide_sym_rows<true>(T, i0, j0, A, N, VI, [&](int k, int j) { return Z[k + (int64_t)j * A]; }, sm);
+        tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false);
+      } else {
+        tile_mma<false, true>(T, i0, j0, A, N, 0, min(A, i0 + WT), [&](int i, int k) {
+          return k <= i ? VI[pk(i, k, A)] : 0.0; }, [&](int k, int j) { return Z[k + (int64_t)j * A]; }, sm);
+        tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false);
+      }
+    } else {
+      tile_mma<true, true>(T, i0, j0, A, N, i0, A, [&](int i, int k) { return k >= i ? VI[pk(k, i, A)] : 0.0; },
+                           [&](int k, int j) { return MA[k + (int64_t)j * A]; }, sm);
+      tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false);
+    }
   });
 }
 
@@ -412,23 +881,73 @@ void launch_wide_extract(int tag, dim3 grid, hipStream_t s, const DevPlan& P, co
     k_wide_extract<2><<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride);
 }
 
-void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre_aa,
-                         const int32_t* pre_rt, int count, int n_aa, int n_rt, const double* LB, double* S,
-                         double* Vs) {
-  k_wide_extract<0><<<dim3(unsigned(n_aa)), NT, 0, s>>>(P, list, pre_aa, count, S, Vs, 0, 0);
-  k_wide_projinv_an<<<dim3(unsigned(n_rt)), NT, 0, s>>>(P, list, pre_rt, count, LB, S, Vs);
-  k_wide_projinv_nn<<<dim3(unsigned(count)), NT, 0, s>>>(P, list, LB, S);
+void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w, int count,
+                         const double* LB, double* S, double* Vs) {
+  if (w.n_aa) k_wide_extract<0><<<dim3(unsigned(w.n_aa)), NT, 0, s>>>(P, list, w.aa, count, S, Vs, 0, 0);
+  if (w.n_an) k_wide_projinv_an<<<dim3(unsigned(w.n_an)), NT, 0, s>>>(P, list, w.an, count, LB, S, Vs);
+  k_wide_projinv_nn<<<dim3(unsigned(w.n_nn)), NT, 0, s>>>(P, list, w.nn, count, LB, S);
 }
 
-void launch_wide_hess_down(int k, hipStream_t s, const DevPlan& P, const int32_t* list, const int32_t* pre_aa,
-                           const int32_t* pre_rt, int count, int n_aa, int n_rt, const double* LB,
-                           const double* Vs, const double* Kt, double* T, double* Va, int64_t upd, double* wsb,
-                           int64_t slot) {
-  k_wide_hdown_a<<<dim3(unsigned(n_aa + count + n_rt), unsigned(k)), NT, 0, s>>>(
-      P, list, pre_aa, pre_rt, count, n_aa, LB, Kt, T, Va, upd, wsb, slot);
-  k_wide_hdown_b<<<dim3(unsigned(n_rt), unsigned(k)), NT, 0, s>>>(P, list, pre_rt, count, LB, Vs, T, Va, upd,
-                                                                   wsb, slot);
-  k_wide_hdown_c<<<dim3(unsigned(count), unsigned(k)), NT, 0, s>>>(P, list, count, LB, T, wsb, slot);
+void launch_wide_hess_down(int k, hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w,
+                           int count, const double* LB, const double* Vs, const double* Kt, double* T, double* Va,
+                           int64_t upd, double* wsb, int64_t slot) {
+  const SegTiles tl{w.aa, w.an, w.nn, w.n_aa, w.n_an, w.n_nn};
+  k_wide_hdown_a<<<dim3(unsigned(w.n_aa + w.n_nn + w.n_an), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, Kt,
+                                                                                       T, Va, upd, wsb, slot);
+  k_wide_hdown_b<<<dim3(unsigned(w.n_nn + w.n_an), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, Vs, T, Va,
+                                                                              upd, wsb, slot);
+  k_wide_hdown_c<<<dim3(unsigned(w.n_nn), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, T, wsb, slot);
+}
+
+void launch_fat_panel(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                      int count, const double* src, const double* Ua, int64_t upd, double* wsb, int64_t slot) {
+  const dim3 grid(unsigned(g.panel), unsigned(count * k));
+  switch (op) {
+    case 0: k_fat_panel<0><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
+    case 1: k_fat_panel<1><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
+    case 2: k_fat_panel<2><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
+    default: k_fat_panel<3><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
+  }
+}
+
+void launch_fat_factor(const FatGrid& g, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
+                       double* R, double* LB, double* part, DevStatus* st, double* wsb, int64_t slot) {
+  const unsigned c = unsigned(count);
+  for (int kb = 0; kb < g.maxN; kb += WT) {
+    k_fat_potrf_diag<<<dim3(1, c), NT, 0, s>>>(P, list, count, kb, R, part, st, wsb, slot);
+    // grids cover every front of the segment; tiles beyond a front's own exit
+    const int rows = (g.maxJ - kb + WT - 1) / WT, cols = (g.maxN - kb + WT - 1) / WT;
+    k_fat_potrf_panel<<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, count, kb, R, wsb, slot);
+    if (kb + WT < g.maxN)
+      k_fat_potrf_trail<<<dim3(unsigned(rows * cols), c), NT, 0, s>>>(P, list, count, kb, wsb, slot);
+  }
+  for (int ib = 0; ib * WT < g.maxN; ++ib)
+    k_fat_trtri_row<<<dim3(unsigned(ib + 1), c), NT, 0, s>>>(P, list, count, ib, wsb, slot);
+  k_fat_factor_fin<<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, LB, wsb, slot);
+}
+
+void launch_fat_up_fin(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                       int count, const double* R, const double* LB, double* Out, double* Kt, double* wsb,
+                       int64_t slot) {
+  const dim3 grid(unsigned(g.fin), unsigned(count * k));
+  if (op == FAT_PRODUCT)
+    k_fat_up_fin<FAT_PRODUCT><<<grid, NT, 0, s>>>(P, list, count, R, LB, Out, Kt, wsb, slot);
+  else if (op == FAT_HUP)
+    k_fat_up_fin<FAT_HUP><<<grid, NT, 0, s>>>(P, list, count, R, LB, Out, Kt, wsb, slot);
+  else
+    k_fat_up_fin<FAT_IHUP><<<grid, NT, 0, s>>>(P, list, count, R, LB, Out, Kt, wsb, slot);
+}
+
+void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
+                      const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
+                      const double* Va, int64_t upd, double* wsb, int64_t slot) {
+  const dim3 grid(unsigned(g.fin), unsigned(count * k));
+  k_fat_ihess<1><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
+  k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
+  k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
+  k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
+  if (g.maxA > kVExplicitMax)
+    k_fat_ihess<5><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
 }
 
 }  // namespace mfb

@@ -385,6 +385,12 @@ def test_ill_conditioned(name, delta, mfb):
 WIDE_CASES = [
     # name, plan flags: 0 = default wide threshold (front order above 512)
     ("chordal150", "low"),
+    # fronts of more than 64 columns ("fat": the panel work tile-parallel
+    # too), among them roots and a 528-column dense front
+    ("arrow_small", "low"),
+    ("arrow_mixed", "low"),
+    ("roots_mixed", "low"),
+    ("dense528", "default"),
     ("grid3d_8", "low"),
     ("grid3d_12", "low"),
     ("grid2d_128", "low"),
@@ -397,10 +403,12 @@ WIDE_CASES = [
 
 @pytest.mark.parametrize("name,thr", WIDE_CASES)
 def test_wide_fronts(name, thr, mfb):
-    """The tile-parallel wide-front kernels (fronts with at most 64 columns
-    and a large ancestor set) against the oracle on every operation, with
-    the wide threshold lowered to front order 65 where the pattern has no
-    front above 512."""
+    """The tile-parallel kernels of wide fronts (front order above the
+    threshold: those with at most 64 columns in the leaf-to-root sweeps,
+    all of them in the root-to-leaf sweeps) and of fat fronts (above the
+    threshold with more than 64 columns) against the oracle on every
+    operation, with the threshold lowered to front order 65 where the
+    pattern has no front above 512."""
     pat = CASES[name]() if name in CASES else get_config(name)
     flags = mfb.PLAN_WIDE_LOW if thr == "low" else 0
     x = V.make_x(*pat, seed=0)
