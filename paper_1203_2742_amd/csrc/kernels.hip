@@ -37,12 +37,14 @@ struct PackedLower {
 // VI <- C^-1 (lower, packed) for a packed symmetric positive definite
 // A x A block V = C C^T, in place in VI (no scratch): copy V, then the
 // Cholesky factor and its triangular inverse on the packed triangle.
-__device__ __forceinline__ void packed_tri_inverse(const double* V, double* VI, int A, double* sm, int* fail) {
+// d64: LDS of NB2 * LD2 doubles.
+__device__ __forceinline__ void packed_tri_inverse(const double* V, double* VI, int A, double* sm, double* d64,
+                                                   int* fail) {
   const int64_t m = (int64_t)A * (A + 1) / 2;
   for (int64_t e = threadIdx.x; e < m; e += NT) VI[e] = V[e];
   __syncthreads();
-  wg_potrf_acc<true>(PackedLower{VI, A}, A, A, sm, fail);
-  wg_trtri_inplace<true>(PackedLower{VI, A}, A, sm);
+  wg_potrf64(PackedLower{VI, A}, A, sm, d64, fail);
+  wg_trtri64_invdiag(PackedLower{VI, A}, A, sm, d64);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,6 +468,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
                                                    double* Vi, double* part, DevStatus* st,
                                                    double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double d64[NB2 * LD2];
   __shared__ int64_t colc[kColCache];
   __shared__ int fail;
   with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
@@ -481,7 +484,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
     const double* V = Vs + P.arena[v.s];
     double* VI = Vi + P.arena[v.s];
     const PackedLower Cvi{VI, A};  // C_V^-1 once formed
-    if (A > 0) packed_tri_inverse(V, VI, A, sm, &fail);  // VI <- C_V^-1, V = C_V C_V^T
+    if (A > 0) packed_tri_inverse(V, VI, A, sm, d64, &fail);  // VI <- C_V^-1, V = C_V C_V^T
     __syncthreads();
     if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
     double* Dd = ws;
@@ -553,6 +556,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
 __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, const double* Vs,
                                              double* Vi, DevStatus* st, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double d64[NB2 * LD2];
   __shared__ int64_t colc[kColCache];
   __shared__ int fail;
   with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
@@ -560,7 +564,7 @@ __global__ void __launch_bounds__(NT) k_vinv(DevPlan P, const int32_t* list, con
     if (threadIdx.x == 0) fail = -1;
     __syncthreads();
     double* VI = Vi + P.arena[v.s];
-    packed_tri_inverse(Vs + P.arena[v.s], VI, v.A, sm, &fail);
+    packed_tri_inverse(Vs + P.arena[v.s], VI, v.A, sm, d64, &fail);
     if (v.A <= kVExplicitMax) {
       __syncthreads();
       wg_lauum_inplace(PackedLower{VI, v.A}, v.A, sm);

@@ -541,6 +541,101 @@ __device__ __forceinline__ void wg_lauum_inplace(const GA& G, int n, double* sm)
   }
 }
 
+// Dense column-major accessor (reference to entry (i, j)).
+struct DenseAt {
+  double* a;
+  int64_t ld;
+  __device__ __forceinline__ double& operator()(int i, int j) const { return a[i + (int64_t)j * ld]; }
+};
+
+// Block of the left-looking factorizations below, and the leading
+// dimension of their 64 x 64 diagonal block in LDS (d64: NB2 * LD2
+// doubles, passed by the caller).
+constexpr int NB2 = 64;
+constexpr int LD2 = NB2 + 1;
+
+// In place on an n x n lower triangle reached through G(i, j) (i >= j):
+// left-looking blocked Cholesky with 64-column blocks.  Every 64 x 64 tile
+// of the factor is formed once, T = G(I, J) - sum_{k < j0} G(I, k) G(J, k),
+// as one pipelined matrix-core k-loop; the diagonal tile is then factored
+// and inverted in LDS and the tiles below it are multiplied by the
+// transposed inverse.  On return each 64 x 64 diagonal block holds the
+// INVERSE of its Cholesky block (as wg_trtri64_invdiag expects).  *fail
+// receives the first failing column (or stays -1).
+template <class GA>
+__device__ __forceinline__ void wg_potrf64(const GA& G, int n, double* sm, double* d64, int* fail) {
+  const DenseAt D{d64, LD2};
+  for (int j0 = 0; j0 < n; j0 += NB2) {
+    const int nb = min(NB2, n - j0);
+    {
+      MfmaTile T(threadIdx.x);
+      tile_mma(T, 0, 0, nb, nb, 0, j0, [&](int i, int k) { return G(j0 + i, k); },
+               [&](int k, int j) { return G(j0 + j, k); }, sm);
+      for (int e = threadIdx.x; e < NB2 * LD2; e += NT) d64[e] = 0.0;
+      __syncthreads();
+      tile_store(T, 0, 0, nb, nb, [&](int i, int j, double acc) { d64[i + j * LD2] = G(j0 + i, j0 + j) - acc; },
+                 true);
+    }
+    __syncthreads();
+    __shared__ int lf;
+    if (threadIdx.x == 0) lf = -1;
+    __syncthreads();
+    wg_potrf_acc(D, nb, nb, sm, &lf);
+    if (threadIdx.x == 0 && lf >= 0 && *fail < 0) *fail = j0 + lf;
+    wg_trtri_inplace(D, nb, sm);
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (i >= j) G(j0 + i, j0 + j) = d64[i + j * LD2];
+    }
+    __syncthreads();
+    for (int i0 = j0 + nb; i0 < n; i0 += TM) {
+      MfmaTile T(threadIdx.x);
+      tile_mma(T, i0, 0, n, nb, 0, j0, [&](int i, int k) { return G(i, k); },
+               [&](int k, int j) { return G(j0 + j, k); }, sm);
+      tile_store(T, i0, 0, n, nb, [&](int i, int j, double acc) { G(i, j0 + j) = G(i, j0 + j) - acc; }, false);
+      __syncthreads();
+      MfmaTile T2(threadIdx.x);
+      tile_mma(T2, i0, 0, n, nb, 0, nb, [&](int i, int k) { return G(i, j0 + k); },
+               [&](int k, int j) { return d64[j + k * LD2]; }, sm);
+      tile_store(T2, i0, 0, n, nb, [&](int i, int j, double acc) { G(i, j0 + j) = acc; }, false);
+      __syncthreads();
+    }
+  }
+}
+
+// In place on an n x n lower triangle G whose 64 x 64 diagonal blocks
+// already hold their inverses (wg_potrf64): G <- G^-1, diagonal blocks from
+// the last to the first (as wg_trtri_inplace, with 64-column blocks).
+template <class GA>
+__device__ __forceinline__ void wg_trtri64_invdiag(const GA& G, int n, double* sm, double* d64) {
+  const int nblk = (n + NB2 - 1) / NB2;
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int jb = bk * NB2, nb = min(NB2, n - jb);
+    const int r0 = jb + nb, m = n - r0;
+    if (m == 0) continue;
+    for (int e = threadIdx.x; e < NB2 * LD2; e += NT) d64[e] = 0.0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (i >= j) d64[i + j * LD2] = G(jb + i, jb + j);
+    }
+    __syncthreads();
+    for (int i0 = ((m - 1) / TM) * TM; i0 >= 0; i0 -= TM) {
+      MfmaTile T(threadIdx.x);
+      tile_mma<false, true>(
+          T, i0, 0, m, nb, 0, min(m, i0 + TM), [&](int i, int k) { return k <= i ? G(r0 + i, r0 + k) : 0.0; },
+          [&](int k, int j) { return G(r0 + k, jb + j); }, sm);
+      tile_store(T, i0, 0, m, nb, [&](int i, int j, double acc) { G(r0 + i, jb + j) = acc; }, false);
+      __syncthreads();
+    }
+    wg_gemm(
+        m, nb, nb, [&](int i, int k) { return G(r0 + i, jb + k); },
+        [&](int k, int j) { return d64[k + j * LD2]; },
+        [&](int i, int j, double acc) { G(r0 + i, jb + j) = -acc; }, false, sm);
+    __syncthreads();
+  }
+}
+
 // Ci = C^-1 for an N x N lower-triangular C (leading dimensions ldc, ldi),
 // blocked, last diagonal block first: with C = [C11 0; C21 C22],
 // inv(C)21 = -inv(C22) C21 inv(C11).

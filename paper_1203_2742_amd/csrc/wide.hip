@@ -511,13 +511,6 @@ __global__ void __launch_bounds__(NT) k_fat_panel(DevPlan P, const int32_t* list
   });
 }
 
-// Dense column-major accessor (reference to entry (i, j)).
-struct DenseAt {
-  double* a;
-  int64_t ld;
-  __device__ __forceinline__ double& operator()(int i, int j) const { return a[i + (int64_t)j * ld]; }
-};
-
 // Blocked Cholesky of the panel F, block column kb (64 columns): the
 // diagonal block by one workgroup per front (Cholesky factor C_kk in F and
 // in R, its inverse in the scratch block list after F, the log det part),
