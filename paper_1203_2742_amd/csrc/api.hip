@@ -32,7 +32,8 @@ static int64_t plan_scratch(const mfb_plan_s* p, Op op) {
 static int64_t flat_scratch(const ClassSched& cs, Op op) {
   int64_t m = 0;
   for (const ClassSeg& g : cs.segs)
-    if (g.cls == kRegClasses) m = std::max(m, int64_t(g.lv.count) * std::max<int64_t>(1, slot_doubles(op, g.lv)));
+    if (g.cls == kRegClasses || g.cls == kFat)
+      m = std::max(m, int64_t(g.lv.count) * std::max<int64_t>(1, slot_doubles(op, g.lv)));
   return m;
 }
 static int64_t factor_scratch(const mfb_plan_s* p) {
@@ -93,7 +94,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list),
          iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
          iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre), iGl = v32(p->cs_gather.list),
-         iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre);
+         iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre), iPx = v32(p->cs_compl_flat.pre);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -136,6 +137,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_gather.d_list = (const int32_t*)at(iGl);
   p->cs_gather.d_pre = (const int32_t*)at(iGp);
   p->cs_ihd_flat.d_pre = (const int32_t*)at(iPi);
+  p->cs_compl_flat.d_pre = (const int32_t*)at(iPx);
   return MFB_OK;
 }
 
@@ -783,6 +785,9 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
         if (cls < kRegClasses)
           launch_completion_reg(cls, g, s, f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S, f->Vs,
                                 f->Vi, f->part, f->st);
+        else if (cls == kFat)
+          launch_fat_completion(fat_grid(sg), s, f->plan->dev, list, sg.lv.count, ((Ctx*)c)->s, f->R, f->LB, f->S,
+                                f->Vs, f->Vi, f->part, f->st, f->scratch, slot);
         else
           k_completion<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->s, f->R, f->LB, f->S,
                                                f->Vs, f->Vi, f->part, f->st, f->scratch, slot);

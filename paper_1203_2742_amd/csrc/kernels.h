@@ -110,6 +110,9 @@ void launch_fat_factor(const FatGrid& g, hipStream_t s, const DevPlan& P, const 
 void launch_fat_up_fin(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
                        int count, const double* R, const double* LB, double* Out, double* Kt, double* wsb,
                        int64_t slot);
+void launch_fat_completion(const FatGrid& g, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
+                           const double* Sin, double* R, double* LB, double* S, const double* Vs, double* Vi,
+                           double* part, DevStatus* st, double* wsb, int64_t slot);
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                       const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
                       const double* Va, int64_t upd, double* wsb, int64_t slot);

@@ -50,7 +50,7 @@ inline int64_t slot_doubles(Op op, const Level& L) {
   switch (op) {
     case OP_FACTOR: return J * N + N * N + 64 * N + 4096;  // fat fronts: + inverse diagonal blocks
     case OP_PRODUCT: return J * N;
-    case OP_COMPLETION: return 3 * N * N + A * N;
+    case OP_COMPLETION: return 3 * N * N + A * N + 64 * N + 4096;
     case OP_VINV: return 1;
     case OP_HUP: return J * N;
     case OP_HDOWN: return 2 * A * N + 2 * N * N;

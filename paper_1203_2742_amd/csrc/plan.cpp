@@ -371,14 +371,19 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   auto make_flat = [&](bool by_a, Op op, ClassSched& cs) {
     cs.list.clear();
     cs.segs.clear();
+    cs.pre.clear();
     cs.list.reserve(ns);
+    // the completion's fat fronts (above the wide threshold, more than
+    // kWideMaxN columns) run tile-parallel, in one segment of their own
+    const bool fat_ok = op == OP_COMPLETION;
+    auto fat = [&](int32_t k) { return fat_ok && is_wide(k) && p->N[k] > kWideMaxN; };
     auto order = [&](int32_t k) { return by_a ? p->J[k] - p->N[k] : p->J[k]; };
     auto fit = [&](int32_t k) {
       int c = 0;
       while (c < kRegClasses && order(k) > kRegMax[c]) ++c;
       return c;
     };
-    auto wanted = [&](int32_t k) { return !by_a || p->J[k] > p->N[k]; };
+    auto wanted = [&](int32_t k) { return (!by_a || p->J[k] > p->N[k]) && !fat(k); };
     auto add_front = [&](Level& S, int32_t k) {
       cs.list.push_back(k);
       S.count++;
@@ -421,6 +426,16 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
         add_front(S, k);
       }
       if (S.count) cs.segs.push_back(ClassSeg{S, -1, kRegClasses});
+    }
+    {
+      Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int32_t k = 0; k < ns; ++k)
+        if (fat(k)) add_front(S, k);
+      if (S.count) {
+        ClassSeg g{S, -1, kFat};
+        number_tiles(cs, g);
+        cs.segs.push_back(g);
+      }
     }
   };
   // V_s^-1 needs only V_s; the completion's sweeps need only S and V_s,

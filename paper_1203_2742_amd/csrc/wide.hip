@@ -440,6 +440,13 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_c(DevPlan P, const int32_t* l
 // at once.  Scratch slot per (front, RHS) starts with the panel F (J x N,
 // column-major, leading dimension J).
 
+// Lower-triangle accessor of a packed symmetric A x A block.
+struct PackedLowerW {
+  double* u;
+  int A;
+  __device__ __forceinline__ double& operator()(int i, int j) const { return u[pk(i, j, A)]; }
+};
+
 // Tile counts of a front, in 64-wide tiles.
 struct FatDims {
   int N, A, J, tn, ta, tj;
@@ -512,23 +519,41 @@ __global__ void __launch_bounds__(NT) k_fat_panel(DevPlan P, const int32_t* list
 }
 
 // Blocked Cholesky of the panel F, block column kb (64 columns): the
-// diagonal block by one workgroup per front (Cholesky factor C_kk in F and
-// in R, its inverse in the scratch block list after F, the log det part),
-// then (k_fat_potrf_panel) the rows below times C_kk^-T, then
+// diagonal block by one workgroup per front (Cholesky factor C_kk in F,
+// its inverse in the scratch block list after F, the log det part), then
+// (k_fat_potrf_panel) the rows below times C_kk^-T, then
 // (k_fat_potrf_trail) the remaining panel columns updated.  The inverse
-// blocks are stored 64 x 64 (zero above the diagonal) at F + J N + 4096 b
-// for block column b.
+// blocks are stored 64 x 64 (zero above the diagonal) at F + rows N + 4096 b
+// for block column b, and X = C^-1 (k_fat_trtri_row) after them.
+// Two layouts (`sq`):
+//  sq = 0, the factor: F is the J x N panel at the start of the slot
+//          (rows J, leading dimension J); C and B are also written to R,
+//          and part[s] receives log det D = 2 sum log C_kk;
+//  sq = 1, the completion: F is an N x N matrix at slot offset `off`
+//          (rows N, leading dimension N) holding the reversed Schur
+//          complement; nothing goes to R, part[s] receives
+//          -2 sum log C_kk, and a failure is reported as no completion at
+//          the column of the original order.
+struct FatSquare {
+  int sq;
+};
+__device__ __forceinline__ int fat_rows(const FatSquare& q, int N, int J) { return q.sq ? N : J; }
+// F of front f: the slot's start (factor) or after the completion's W (A x N)
+__device__ __forceinline__ double* fat_F(double* wsb, int f, int64_t slot, const FatSquare& q, int N, int A) {
+  return wsb + (int64_t)f * slot + (q.sq ? (int64_t)A * N : 0);
+}
+
 __global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t* list, int count, int kb,
                                                        double* R, double* part, DevStatus* st, double* wsb,
-                                                       int64_t slot) {
+                                                       int64_t slot, FatSquare q) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   __shared__ int fail;
   const int f = blockIdx.y;
   with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
     if (kb >= v.N) return;
-    const int nb = min(WT, v.N - kb), J = v.J;
-    double* F = wsb + (int64_t)f * slot;
+    const int nb = min(WT, v.N - kb), J = fat_rows(q, v.N, v.J);
+    double* F = fat_F(wsb, f, slot, q, v.N, v.A);
     double* Ci = F + (int64_t)J * v.N + (int64_t)(kb / WT) * WT * WT;
     if (threadIdx.x == 0) fail = -1;
     __syncthreads();
@@ -537,7 +562,7 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t*
     for (int e = threadIdx.x; e < WT * WT; e += NT) {
       const int i = e & (WT - 1), j = e >> 6;
       Ci[e] = (i < nb && j < nb && i >= j) ? G(i, j) : 0.0;
-      if (i < nb && j < nb && i >= j) R[v.at(kb + i, kb + j)] = G(i, j);
+      if (!q.sq && i < nb && j < nb && i >= j) R[v.at(kb + i, kb + j)] = G(i, j);
     }
     __syncthreads();
     wg_trtri_inplace(DenseAt{Ci, WT}, nb, sm);
@@ -545,23 +570,29 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t*
     for (int c = threadIdx.x; c < nb; c += NT) lg += 2.0 * log(G(c, c));
     lg = wg_sum(lg, sm);
     if (threadIdx.x == 0) {
-      part[v.s] = kb == 0 ? lg : part[v.s] + lg;
-      if (fail >= 0) report(st, MFB_ENOTPD, v.vl[kb + fail]);
+      const double part_ = q.sq ? -lg : lg;
+      part[v.s] = kb == 0 ? part_ : part[v.s] + part_;
+      if (fail >= 0) {
+        if (q.sq)
+          report(st, MFB_ENOCOMPLETION, v.vl[v.N - 1 - (kb + fail)]);
+        else
+          report(st, MFB_ENOTPD, v.vl[kb + fail]);
+      }
     }
   });
 }
 
 __global__ void __launch_bounds__(NT) k_fat_potrf_panel(DevPlan P, const int32_t* list, int count, int kb,
-                                                        double* R, double* wsb, int64_t slot) {
+                                                        double* R, double* wsb, int64_t slot, FatSquare q) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   const int f = blockIdx.y;
   with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
     if (kb >= v.N) return;
-    const int nb = min(WT, v.N - kb), J = v.J;
+    const int nb = min(WT, v.N - kb), J = fat_rows(q, v.N, v.J);
     const int i0 = kb + nb + int(blockIdx.x) * WT;
     if (i0 >= J) return;
-    double* F = wsb + (int64_t)f * slot;
+    double* F = fat_F(wsb, f, slot, q, v.N, v.A);
     const double* Ci = F + (int64_t)J * v.N + (int64_t)(kb / WT) * WT * WT;
     MfmaTile T(threadIdx.x);
     tile_mma(T, i0, 0, J, nb, 0, nb, [&](int i, int k) { return F[i + (int64_t)(kb + k) * J]; },
@@ -570,18 +601,18 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_panel(DevPlan P, const int32_t
         T, i0, 0, J, nb,
         [&](int i, int j, double acc) {
           F[i + (int64_t)(kb + j) * J] = acc;
-          R[v.at(i, kb + j)] = acc;
+          if (!q.sq) R[v.at(i, kb + j)] = acc;
         },
         false);
   });
 }
 
 __global__ void __launch_bounds__(NT) k_fat_potrf_trail(DevPlan P, const int32_t* list, int count, int kb,
-                                                        double* wsb, int64_t slot) {
+                                                        double* wsb, int64_t slot, FatSquare q) {
   __shared__ double sm[SMEM_DOUBLES];
   const int f = blockIdx.y;
   const int s = list[f];
-  const int N = P.ncol[s], J = P.nrow[s];
+  const int N = P.ncol[s], J = fat_rows(q, N, P.nrow[s]);
   if (kb >= N) return;
   const int nb = min(WT, N - kb), r0 = kb + nb;
   if (r0 >= N) return;
@@ -591,29 +622,29 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_trail(DevPlan P, const int32_t
   const int ti = l / tc, tj = l - (l / tc) * tc;
   if (ti < tj) return;
   const int i0 = r0 + ti * WT, j0 = r0 + tj * WT;
-  double* F = wsb + (int64_t)f * slot;
+  double* F = fat_F(wsb, f, slot, q, N, P.nrow[s] - N);
   MfmaTile T(threadIdx.x);
   tile_mma(T, i0, j0, J, N, 0, nb, [&](int i, int k) { return F[i + (int64_t)(kb + k) * J]; },
            [&](int k, int c) { return F[c + (int64_t)(kb + k) * J]; }, sm);
   tile_store(T, i0, j0, J, N, [&](int i, int c, double acc) { F[i + (int64_t)c * J] -= acc; }, true);
 }
 
-// Row block ib of X = C^-1 (C the N x N Cholesky factor in the panel F, X
-// in scratch after the inverse blocks, N x N column-major), one 64 x 64
-// tile (ib, jb), jb <= ib, per workgroup:
+// Row block ib of X = C^-1 (C the N x N Cholesky factor in F, X in the
+// slot after the inverse blocks, N x N column-major), one 64 x 64 tile
+// (ib, jb), jb <= ib, per workgroup:
 //   X(ib, jb) = C_ib,ib^-1 (delta I - sum_{jb <= m < ib} C(ib, m) X(m, jb)),
 // so a launch per ib completes row block ib from the ones above it.
 __global__ void __launch_bounds__(NT) k_fat_trtri_row(DevPlan P, const int32_t* list, int count, int ib,
-                                                      double* wsb, int64_t slot) {
+                                                      double* wsb, int64_t slot, FatSquare q) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ double rb[WT * WLD];
   const int f = blockIdx.y;
   const int s = list[f];
-  const int N = P.ncol[s], J = P.nrow[s];
+  const int N = P.ncol[s], J = fat_rows(q, N, P.nrow[s]);
   const int i0 = ib * WT, jb = blockIdx.x, j0 = jb * WT;
   if (i0 >= N || jb > ib) return;
   const int nbi = min(WT, N - i0);
-  double* F = wsb + (int64_t)f * slot;
+  double* F = fat_F(wsb, f, slot, q, N, P.nrow[s] - N);
   const double* Cinv = F + (int64_t)J * N + (int64_t)ib * WT * WT;
   double* X = F + (int64_t)J * N + (int64_t)((N + WT - 1) / WT) * WT * WT;
   MfmaTile T(threadIdx.x);
@@ -744,6 +775,118 @@ __global__ void __launch_bounds__(NT) k_fat_up_fin(DevPlan P, const int32_t* lis
           false);
     }
   });
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 7.3 on fat fronts (independent fronts, after the gather of
+// V_s = S_AA).  Scratch slot per front: W (A x N), then the reversed Schur
+// complement Mr (N x N) with the inverse blocks and X = Mr-factor^-1 of the
+// blocked Cholesky after it.
+//  prep (one workgroup per front): S's own columns into the cached S, and
+//       C_V^-1 in place in the packed Vi block;
+//  a:   W = C_V^-1 S_AN (AN tiles);
+//  b:   L_AN = -C_V^-T W (AN tiles) and D^-1 = M = S_NN - W^T W (lower NN
+//       tiles), M also stored reversed, Mr(N-1-j, N-1-i) = M(i, j);
+//  then the blocked Cholesky of Mr = Lr Lr^T (k_fat_potrf_*, sq = 1) and
+//       X = Lr^-1 (k_fat_trtri_row): with the reversal P, M = P Lr Lr^T P,
+//       so D = M^-1 = (P X^T P)(P X^T P)^T and C = chol(D) = P X^T P,
+//       C(i, j) = X(N-1-j, N-1-i), without inverting M explicitly;
+//  c:   R_NN = C and R_AN = L_AN C (NN and AN tiles);
+//  lauum: the explicit V_s^-1 for A <= kVExplicitMax, in place.
+__global__ void __launch_bounds__(NT) k_fat_compl_prep(DevPlan P, const int32_t* list, const double* Sin,
+                                                       double* S, const double* Vs, double* Vi, DevStatus* st) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double d64[NB2 * LD2];
+  __shared__ int64_t colc[kColCache];
+  __shared__ int fail;
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    if (threadIdx.x == 0) fail = -1;
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+      const int rr = int(e % v.J), c = int(e / v.J);
+      if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
+    }
+    __syncthreads();
+    if (v.A == 0) return;
+    const int A = v.A;
+    double* VI = Vi + P.arena[v.s];
+    const double* V = Vs + P.arena[v.s];
+    const int64_t m = (int64_t)A * (A + 1) / 2;
+    for (int64_t e = threadIdx.x; e < m; e += NT) VI[e] = V[e];
+    __syncthreads();
+    wg_potrf64(PackedLowerW{VI, A}, A, sm, d64, &fail);
+    wg_trtri64_invdiag(PackedLowerW{VI, A}, A, sm, d64);
+    if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
+  });
+}
+
+template <int STAGE>
+__global__ void __launch_bounds__(NT) k_fat_compl(DevPlan P, const int32_t* list, int count, const double* Sin,
+                                                  double* R, double* LB, const double* Vi, double* wsb,
+                                                  int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int f = blockIdx.y;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const FatDims d(v);
+    const int N = d.N, A = d.A;
+    int b = blockIdx.x;
+    if (b >= d.tn * d.tn + d.ta * d.tn) return;
+    const bool nn = b < d.tn * d.tn;
+    if (!nn) b -= d.tn * d.tn;
+    const int ti = b / d.tn, tj = b - (b / d.tn) * d.tn;
+    if (nn && (tj > ti || STAGE == 0)) return;
+    const int i0 = ti * WT, j0 = tj * WT;
+    double* W = wsb + (int64_t)f * slot;
+    double* Mr = W + (int64_t)A * N;
+    const double* X = Mr + (int64_t)N * N + (int64_t)d.tn * WT * WT;
+    const double* VI = Vi + P.arena[v.s];
+    MfmaTile T(threadIdx.x);
+    if (STAGE == 0) {
+      tile_mma<false, true>(T, i0, j0, A, N, 0, min(A, i0 + WT),
+                            [&](int i, int k) { return k <= i ? VI[pk(i, k, A)] : 0.0; },
+                            [&](int k, int j) { return Sin[v.an(k, j)]; }, sm);
+      tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { W[i + (int64_t)j * A] = acc; }, false);
+    } else if (STAGE == 1) {
+      if (nn) {
+        tile_mma<true, true>(T, i0, j0, N, N, 0, A, [&](int i, int k) { return W[k + (int64_t)i * A]; },
+                             [&](int k, int j) { return W[k + (int64_t)j * A]; }, sm);
+        tile_store(
+            T, i0, j0, N, N,
+            [&](int i, int j, double acc) {
+              const double m = Sin[v.at(i, j)] - acc;
+              LB[v.at(i, j)] = m;
+              Mr[(N - 1 - j) + (int64_t)(N - 1 - i) * N] = m;
+            },
+            true);
+      } else {
+        tile_mma<true, true>(T, i0, j0, A, N, i0, A, [&](int i, int k) { return k >= i ? VI[pk(k, i, A)] : 0.0; },
+                             [&](int k, int j) { return W[k + (int64_t)j * A]; }, sm);
+        tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false);
+      }
+    } else {
+      // C(k, j) = X(N-1-j, N-1-k), zero for k < j
+      auto C = [&](int k, int j) { return k >= j ? X[(N - 1 - j) + (int64_t)(N - 1 - k) * N] : 0.0; };
+      if (nn) {
+        const int row = threadIdx.x & (WT - 1), cq = threadIdx.x >> 6;
+        const int gi = i0 + row;
+        for (int q = 0; q < 16; ++q) {
+          const int gj = j0 + cq + 4 * q;
+          if (gi < N && gj < N && gi >= gj) R[v.at(gi, gj)] = C(gi, gj);
+        }
+      } else {
+        tile_mma(T, i0, j0, A, N, j0, N, [&](int x, int k) { return LB[v.an(x, k)]; }, C, sm);
+        tile_store(T, i0, j0, A, N, [&](int x, int j, double acc) { R[v.an(x, j)] = acc; }, false);
+      }
+    }
+  });
+}
+
+__global__ void __launch_bounds__(NT) k_fat_compl_lauum(DevPlan P, const int32_t* list, double* Vi) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const int s = list[blockIdx.x];
+  const int A = P.nrow[s] - P.ncol[s];
+  if (A == 0 || A > kVExplicitMax) return;
+  wg_lauum_inplace(PackedLowerW{Vi + P.arena[s], A}, A, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -903,20 +1046,41 @@ void launch_fat_panel(int op, const FatGrid& g, int k, hipStream_t s, const DevP
   }
 }
 
+// The blocked Cholesky (k_fat_potrf_*) and the row blocks of its inverse
+// (k_fat_trtri_row) over a segment's fronts, grids sized by its largest
+// front (maxN columns, maxRows rows); tiles beyond a front's own exit.
+static void fat_potrf_trtri(int maxN, int maxRows, hipStream_t s, const DevPlan& P, const int32_t* list,
+                            int count, double* R, double* part, DevStatus* st, double* wsb, int64_t slot,
+                            FatSquare q) {
+  const unsigned c = unsigned(count);
+  for (int kb = 0; kb < maxN; kb += WT) {
+    k_fat_potrf_diag<<<dim3(1, c), NT, 0, s>>>(P, list, count, kb, R, part, st, wsb, slot, q);
+    const int rows = (maxRows - kb + WT - 1) / WT, cols = (maxN - kb + WT - 1) / WT;
+    k_fat_potrf_panel<<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, count, kb, R, wsb, slot, q);
+    if (kb + WT < maxN)
+      k_fat_potrf_trail<<<dim3(unsigned(rows * cols), c), NT, 0, s>>>(P, list, count, kb, wsb, slot, q);
+  }
+  for (int ib = 0; ib * WT < maxN; ++ib)
+    k_fat_trtri_row<<<dim3(unsigned(ib + 1), c), NT, 0, s>>>(P, list, count, ib, wsb, slot, q);
+}
+
 void launch_fat_factor(const FatGrid& g, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                        double* R, double* LB, double* part, DevStatus* st, double* wsb, int64_t slot) {
   const unsigned c = unsigned(count);
-  for (int kb = 0; kb < g.maxN; kb += WT) {
-    k_fat_potrf_diag<<<dim3(1, c), NT, 0, s>>>(P, list, count, kb, R, part, st, wsb, slot);
-    // grids cover every front of the segment; tiles beyond a front's own exit
-    const int rows = (g.maxJ - kb + WT - 1) / WT, cols = (g.maxN - kb + WT - 1) / WT;
-    k_fat_potrf_panel<<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, count, kb, R, wsb, slot);
-    if (kb + WT < g.maxN)
-      k_fat_potrf_trail<<<dim3(unsigned(rows * cols), c), NT, 0, s>>>(P, list, count, kb, wsb, slot);
-  }
-  for (int ib = 0; ib * WT < g.maxN; ++ib)
-    k_fat_trtri_row<<<dim3(unsigned(ib + 1), c), NT, 0, s>>>(P, list, count, ib, wsb, slot);
+  fat_potrf_trtri(g.maxN, g.maxJ, s, P, list, count, R, part, st, wsb, slot, FatSquare{0});
   k_fat_factor_fin<<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, LB, wsb, slot);
+}
+
+void launch_fat_completion(const FatGrid& g, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
+                           const double* Sin, double* R, double* LB, double* S, const double* Vs, double* Vi,
+                           double* part, DevStatus* st, double* wsb, int64_t slot) {
+  const unsigned c = unsigned(count);
+  k_fat_compl_prep<<<dim3(c), NT, 0, s>>>(P, list, Sin, S, Vs, Vi, st);
+  if (g.maxA > 0) k_fat_compl<0><<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, Sin, R, LB, Vi, wsb, slot);
+  k_fat_compl<1><<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, Sin, R, LB, Vi, wsb, slot);
+  fat_potrf_trtri(g.maxN, g.maxN, s, P, list, count, R, part, st, wsb, slot, FatSquare{1});
+  k_fat_compl<2><<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, Sin, R, LB, Vi, wsb, slot);
+  k_fat_compl_lauum<<<dim3(c), NT, 0, s>>>(P, list, Vi);
 }
 
 void launch_fat_up_fin(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
