@@ -100,6 +100,12 @@ typedef struct {
   /* canonical algorithmic flop counts (LAPACK conventions, summed per supernode) */
   double flops_factor, flops_projinv, flops_hessian, flops_inv_hessian, flops_inv_hessian_x,
       flops_completion, flops_product;
+  /* canonical algorithmic bytes of one call (k = 1): every input entry read
+   * once, every output entry written once, each update block written once
+   * and read once, 8 bytes per double; the per-launch figures of the
+   * profiler (mfb_profile_read) sum to these.  The inverse Hessian's figure
+   * leaves out the one-time (S_AA)^-1 cache. */
+  double bytes_factor, bytes_projinv, bytes_hessian, bytes_inv_hessian, bytes_completion, bytes_product;
 } mfb_plan_info_t;
 
 /* Symbolic analysis of a filled pattern (Sections 2 and 6; Algorithm 6.1).
@@ -195,6 +201,42 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t_dev, dou
 mfb_status_t mfb_hessian_static(mfb_factor_t f, int32_t k, const double* y_dev, double* t_dev,
                                 void* stream);
 
+/* Hessian factor (Section 5.4, Algorithm 5.3): w_r = R(y_r), r = 0..k-1,
+ * the linear map with H = R^adj o R, so that y . H(y') = R(y) . R(y')
+ * under the trace inner product of S^n_V.  Per column j of the scalar
+ * factor X = L D L^T, with K the result of step 1 of the Hessian:
+ * W_jj = K_jj / D_jj and W_{I_j j} = R_j^T K_{I_j j} / sqrt(D_jj), where
+ * S_{I_j I_j} = R_j R_j^T with R_j upper triangular.  w_dev receives the
+ * lower-triangle values of W in the pattern's CCS order.  Same buffer
+ * rules as mfb_hessian (y_dev, w_dev: k*nnz doubles, not overlapping).
+ * Computes the projected inverse if it is not cached, and computes and
+ * caches per supernode the lower triangular G with G^T G = S_AA and G^-1
+ * for the current X. */
+mfb_status_t mfb_hessian_factor(mfb_factor_t f, int32_t k, const double* y_dev, double* w_dev,
+                                void* arena_dev, size_t arena_bytes, void* stream);
+
+/* Adjoint Hessian factor (Section 5.4, Algorithm 5.4): t_r = R^adj(w_r),
+ * the adjoint of mfb_hessian_factor under the trace inner product, so that
+ * mfb_hessian_factor_adj(mfb_hessian_factor(y)) = mfb_hessian(y).  Same
+ * buffer rules and caches as mfb_hessian_factor. */
+mfb_status_t mfb_hessian_factor_adj(mfb_factor_t f, int32_t k, const double* w_dev, double* t_dev,
+                                    void* arena_dev, size_t arena_bytes, void* stream);
+
+/* Gram matrix of m vectors of S^n_V under the trace inner product
+ * (diagonal entries once, strict-lower entries twice):
+ * g(i, j) = w_i . w_j, i, j = 0..m-1.  With w_i = R(a_i) from
+ * mfb_hessian_factor this is the interior-point Schur complement matrix
+ * a_i . H(a_j) (Sections 1.3 and 5.4).
+ *   w_dev: m*nnz doubles (vector i at offset i*nnz); g_dev: m*m doubles
+ *   (symmetric, both triangles written).
+ *   arena_dev: at least mfb_gram_arena_bytes(p, m) device bytes, 256-byte
+ *   aligned, caller-owned scratch for partial sums.
+ * The sum runs in a fixed order (results do not depend on timing).
+ * m = 0 is a no-op; a plan with nnz = 0 gives MFB_EINVAL. */
+size_t mfb_gram_arena_bytes(mfb_plan_t p, int32_t m);
+mfb_status_t mfb_gram(mfb_plan_t p, int32_t m, const double* w_dev, double* g_dev, void* arena_dev,
+                      size_t arena_bytes, void* stream);
+
 /* Algorithm 7.3: matrix completion.  Given S in S^n_V with a positive definite
  * completion (s_dev, nnz doubles), replaces the handle's factor by the factor
  * of X-hat, the X in S^n_V with P(X^-1) = S (eq. e-Xhat-eq); S itself becomes
@@ -238,7 +280,11 @@ const char* mfb_strerror(mfb_status_t s);
                                 the plan's source map, else one k_wide_extract
                                 launch per root-to-leaf level (profile name
                                 "k_gather") */
-#define MFB_K_COUNT 10
+#define MFB_K_GAMMA 10       /* G (G^T G = S_AA) and G^-1 per supernode (Hessian factor) */
+#define MFB_K_HFACTOR 11     /* step-1 output to W = R(Y), Algorithm 5.3 */
+#define MFB_K_HFACTOR_ADJ 12 /* W to the step-2 input of the Hessian's root-to-leaf sweep,
+                                Algorithm 5.4 */
+#define MFB_K_COUNT 13
 
 typedef struct {
   int32_t kernel;   /* MFB_K_* */

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmfb.so")
-SOURCES = ["plan.cpp", "kernels.hip", "wide.hip", "api.hip"]
+SOURCES = ["plan.cpp", "kernels.hip", "wide.hip", "hfactor.hip", "api.hip"]
 ARCH = os.environ.get("MFB_OFFLOAD_ARCH", "gfx950")
 
 

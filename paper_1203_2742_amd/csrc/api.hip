@@ -47,11 +47,11 @@ static int64_t rhs_scratch(const mfb_plan_s* p) {
     flat = std::max(flat, int64_t(g.lv.count) * std::max<int64_t>(1, slot_doubles(OP_IHDOWN, g.lv)));
   if (p->ihd_root >= 0) flat = std::max(flat, 2 * int64_t(p->N[p->ihd_root]) * p->N[p->ihd_root]);
   return std::max({plan_scratch(p, OP_HUP), plan_scratch(p, OP_HDOWN), flat, plan_scratch(p, OP_IHUP),
-                   int64_t(1)});
+                   flat_scratch(p->cs_hfac, OP_HFAC), int64_t(1)});
 }
 static size_t factor_bytes(const mfb_plan_s* p) {
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
-  return 3 * up(nnz * 8) + 3 * up(upd * 8) + up(size_t(std::max(1, p->ns)) * 8) + up(8) +
+  return 3 * up(nnz * 8) + 5 * up(upd * 8) + up(size_t(std::max(1, p->ns)) * 8) + up(8) +
          up(sizeof(DevStatus)) + up(size_t(factor_scratch(p)) * 8);
 }
 static size_t rhs_bytes(const mfb_plan_s* p) {
@@ -94,7 +94,8 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iCd = v32(p->cs_down.list), iCx = v32(p->cs_compl_flat.list), iCh = v32(p->cs_ihd_flat.list),
          iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
          iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre), iGl = v32(p->cs_gather.list),
-         iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre), iPx = v32(p->cs_compl_flat.pre);
+         iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre), iPx = v32(p->cs_compl_flat.pre),
+         iHf = v32(p->cs_hfac.list);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -138,6 +139,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_gather.d_pre = (const int32_t*)at(iGp);
   p->cs_ihd_flat.d_pre = (const int32_t*)at(iPi);
   p->cs_compl_flat.d_pre = (const int32_t*)at(iPx);
+  p->cs_hfac.d_list = (const int32_t*)at(iHf);
   return MFB_OK;
 }
 
@@ -157,9 +159,11 @@ struct mfb_factor_s {
   std::vector<hipEvent_t> pool;
   char* ws = nullptr;
   double *R = nullptr, *LB = nullptr, *S = nullptr, *Vs = nullptr, *Vi = nullptr, *U = nullptr;
+  // per supernode: the lower G with G^T G = S_AA and G^-1 (Hessian factor)
+  double *Gam = nullptr, *Gami = nullptr;
   double *part = nullptr, *logdet = nullptr, *scratch = nullptr;
   DevStatus* st = nullptr;
-  bool has_factor = false, s_valid = false, vinv_valid = false;
+  bool has_factor = false, s_valid = false, vinv_valid = false, gam_valid = false;
   hipStream_t last = nullptr;
 };
 
@@ -224,6 +228,12 @@ mfb_status_t mfb_plan_info(mfb_plan_t p, mfb_plan_info_t* o) {
   o->flops_inv_hessian_x = p->fl_invhess_x;
   o->flops_completion = p->fl_completion;
   o->flops_product = p->fl_product;
+  o->bytes_factor = p->by_factor;
+  o->bytes_projinv = p->by_projinv;
+  o->bytes_hessian = p->by_hess;
+  o->bytes_inv_hessian = p->by_invhess;
+  o->bytes_completion = p->by_completion;
+  o->bytes_product = p->by_product;
   return MFB_OK;
 }
 
@@ -263,6 +273,8 @@ mfb_status_t mfb_factor_create(mfb_plan_t p, void* ws, size_t bytes, mfb_factor_
   f->Vs = (double*)take(upd * 8);
   f->Vi = (double*)take(upd * 8);
   f->U = (double*)take(upd * 8);
+  f->Gam = (double*)take(upd * 8);
+  f->Gami = (double*)take(upd * 8);
   f->part = (double*)take(size_t(std::max(1, p->ns)) * 8);
   f->logdet = (double*)take(8);
   f->st = (DevStatus*)take(sizeof(DevStatus));
@@ -301,6 +313,9 @@ static void canonical(int kid, const Level& L, int k, double* bytes, double* flo
     case MFB_K_VINV: b = 2 * u; fl = L.a3 / 3; break;
     case MFB_K_PRODUCT: b = 2 * p + 2 * u; fl = L.n3 / 3 + L.n2a + L.na2; break;
     case MFB_K_GATHER_V: b = K * 2 * u; fl = 0; break;
+    case MFB_K_GAMMA: b = 3 * u; fl = 2 * L.a3 / 3; break;
+    case MFB_K_HFACTOR: b = p + u + K * 2 * p; fl = K * (7 * L.n3 / 3 + 2 * L.n2a + L.na2); break;
+    case MFB_K_HFACTOR_ADJ: b = p + u + K * 2 * p; fl = K * (2 * L.n3 + 2 * L.n2a + L.na2); break;
   }
   *bytes = 8 * b;
   *flops = fl;
@@ -425,7 +440,7 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
   // the cached state describes the previous X until this factor is enqueued
-  f->has_factor = f->s_valid = f->vinv_valid = false;
+  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* x; } ctx{x};
   mfb_status_t st = run_classes(
@@ -520,14 +535,16 @@ static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, Rhs
   return MFB_OK;
 }
 
-// Hessian steps on k right-hand sides with the per-RHS arena `a`.
-static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, double* t, const RhsArena& a,
-                                hipStream_t s) {
-  mfb_status_t st;
-  f->last = s;
-  if ((st = ensure_projinv(f, s))) return st;
-  struct Ctx { const double* y; double* t; RhsArena a; } ctx{y, t, a};
-  st = run_classes(
+// Hessian step 1 (leaf-to-root) on k right-hand sides: K into a.Kt.
+struct HessCtx {
+  const double* y;
+  double* t;
+  RhsArena a;
+};
+static mfb_status_t hess_up_run(mfb_factor_s* f, int32_t k, const double* y, const RhsArena& a, hipStream_t s) {
+  HessCtx ctx{y, nullptr, a};
+  using Ctx = HessCtx;
+  return run_classes(
       f, MFB_K_HESS_UP, f->plan->cs_factor, s, k, OP_HUP,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
         const int cls = sg.cls;
@@ -555,7 +572,13 @@ static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, dou
         }
       },
       &ctx);
-  if (st) return st;
+}
+
+// Hessian steps 2 and 3 (root-to-leaf) from K in a.Kt: T into t.
+static mfb_status_t hess_down_run(mfb_factor_s* f, int32_t k, double* t, const RhsArena& a, hipStream_t s) {
+  HessCtx ctx{nullptr, t, a};
+  using Ctx = HessCtx;
+  mfb_status_t st;
   if (f->plan->hd_root >= 0) {
     // the root front: two tile-parallel products (Hessian steps 2+3 with A = 0)
     const mfb_plan_s* p = f->plan;
@@ -598,6 +621,16 @@ static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, dou
       &ctx);
   if (st) return st;
   return launched();
+}
+
+// Hessian steps on k right-hand sides with the per-RHS arena `a`.
+static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, double* t, const RhsArena& a,
+                                hipStream_t s) {
+  mfb_status_t st;
+  f->last = s;
+  if ((st = ensure_projinv(f, s))) return st;
+  if ((st = hess_up_run(f, k, y, a, s))) return st;
+  return hess_down_run(f, k, t, a, s);
 }
 
 mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, void* arena,
@@ -670,6 +703,91 @@ static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
   if (st) return st;
   f->vinv_valid = true;
   return MFB_OK;
+}
+
+// G (lower, G^T G = S_AA) and G^-1 per supernode for the current X.
+static mfb_status_t ensure_gamma(mfb_factor_s* f, hipStream_t s) {
+  if (f->gam_valid) return MFB_OK;
+  mfb_status_t st = ensure_projinv(f, s);
+  if (st) return st;
+  st = run_classes(
+      f, MFB_K_GAMMA, f->plan->cs_vinv, s, 1, OP_VINV,
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t, void*) {
+        launch_gamma(g, s, f->plan->dev, cs.d_list + sg.lv.begin, f->Vs, f->Gam, f->Gami, f->st);
+      },
+      nullptr);
+  if (st) return st;
+  f->gam_valid = true;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_hessian_factor(mfb_factor_t f, int32_t k, const double* y, double* w, void* arena,
+                                size_t bytes, void* stream) {
+  if (!f || k < 0) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!y || !w) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  RhsArena a;
+  mfb_status_t st = carve(f, k, arena, bytes, &a);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  if ((st = ensure_gamma(f, s))) return st;
+  if ((st = hess_up_run(f, k, y, a, s))) return st;
+  struct Ctx { double* w; RhsArena a; } ctx{w, a};
+  st = run_classes(
+      f, MFB_K_HFACTOR, f->plan->cs_hfac, s, k, OP_HFAC,
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        Ctx* x = (Ctx*)c;
+        launch_hfactor(g, s, f->plan->dev, cs.d_list + sg.lv.begin, f->R, f->Gam, x->a.Kt, x->w, x->a.scr, slot);
+      },
+      &ctx);
+  if (st) return st;
+  return launched();
+}
+
+mfb_status_t mfb_hessian_factor_adj(mfb_factor_t f, int32_t k, const double* w, double* t, void* arena,
+                                    size_t bytes, void* stream) {
+  if (!f || k < 0) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!w || !t) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  RhsArena a;
+  mfb_status_t st = carve(f, k, arena, bytes, &a);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  if ((st = ensure_gamma(f, s))) return st;
+  struct Ctx { const double* w; RhsArena a; } ctx{w, a};
+  st = run_classes(
+      f, MFB_K_HFACTOR_ADJ, f->plan->cs_hfac, s, k, OP_HFAC,
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        Ctx* x = (Ctx*)c;
+        launch_hfactor_adj(g, s, f->plan->dev, cs.d_list + sg.lv.begin, f->R, f->Gami, x->w, x->a.Kt, x->a.scr,
+                           slot);
+      },
+      &ctx);
+  if (st) return st;
+  return hess_down_run(f, k, t, a, s);
+}
+
+size_t mfb_gram_arena_bytes(mfb_plan_t p, int32_t m) {
+  if (!p || m <= 0) return 0;
+  const GramShape g = gram_shape(std::max<int64_t>(1, p->nnz), p->n, m);
+  return size_t(g.part_doubles) * 8;
+}
+
+mfb_status_t mfb_gram(mfb_plan_t p, int32_t m, const double* w, double* gout, void* arena, size_t bytes,
+                      void* stream) {
+  if (!p || m < 0) return MFB_EINVAL;
+  if (m == 0) return MFB_OK;
+  if (!w || !gout || p->nnz == 0) return MFB_EINVAL;
+  if (!arena || (reinterpret_cast<uintptr_t>(arena) % ALIGN) != 0 || bytes < mfb_gram_arena_bytes(p, m))
+    return MFB_EINVAL;
+  if (mfb_status_t st = ensure_device(p)) return st;
+  const GramShape g = gram_shape(p->nnz, p->n, m);
+  launch_gram((hipStream_t)stream, g, w, p->nnz, p->n, m, p->d_colptr, (double*)arena, gout);
+  return launched();
 }
 
 mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double* y, void* arena,
@@ -770,7 +888,7 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   if (!f || (!sin && f->plan->nnz)) return MFB_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
-  f->has_factor = f->s_valid = f->vinv_valid = false;
+  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* s; } ctx{sin};
   // V_s = S_{A_s A_s} for every supernode (root-to-leaf gathers), then the
@@ -889,7 +1007,8 @@ mfb_status_t mfb_profile_read(mfb_factor_t f, mfb_profile_entry_t* out, int64_t 
 const char* mfb_kernel_name(int32_t kernel) {
   static const char* names[MFB_K_COUNT] = {"k_factor", "k_projinv", "k_hess_up", "k_hess_down",
                                            "k_ihess_down", "k_ihess_up", "k_completion", "k_vinv",
-                                           "k_product", "k_gather"};
+                                           "k_product", "k_gather", "k_gamma", "k_hfactor",
+                                           "k_hfactor_adj"};
   return (kernel >= 0 && kernel < MFB_K_COUNT) ? names[kernel] : "unknown";
 }
 

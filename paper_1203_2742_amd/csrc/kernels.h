@@ -117,4 +117,25 @@ void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, 
                       const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
                       const double* Va, int64_t upd, double* wsb, int64_t slot);
 
+// Hessian factor (hfactor.hip): per supernode with A > 0 the lower G with
+// G^T G = S_AA and G^-1, packed like S_AA (one workgroup per supernode);
+// the conversions between the Hessian's step 1 and W = R(Y) (one workgroup
+// per supernode and right-hand side, scratch 2N^2 + AN); the Gram matrix of
+// m vectors of S^n_V (partials per 64 x 64 tile pair and entry chunk, then
+// an ordered sum).
+void launch_gamma(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Vs, double* Gam,
+                  double* Gami, DevStatus* st);
+void launch_hfactor(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
+                    const double* Gam, const double* Kt, double* Wt, double* wsb, int64_t slot);
+void launch_hfactor_adj(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
+                        const double* Gami, const double* Wt, double* Kt, double* wsb, int64_t slot);
+struct GramShape {
+  int pairs = 0;                          // lower 64 x 64 tile pairs of the m x m result
+  int64_t chunk = 0, nfull = 0, nparts = 0;  // entries per chunk, chunks over nnz, all chunks
+  int64_t part_doubles = 0;                  // partial sums: nparts * pairs 64 x 64 tiles
+};
+GramShape gram_shape(int64_t nnz, int64_t n, int m);
+void launch_gram(hipStream_t s, const GramShape& g, const double* Wt, int64_t nnz, int64_t n, int m,
+                 const int64_t* colptr, double* part, double* Gout);
+
 }  // namespace mfb

@@ -44,7 +44,7 @@ struct Level {
 };
 
 // Scratch (doubles per workgroup) of each kernel for a level's largest front.
-enum Op { OP_FACTOR, OP_PRODUCT, OP_COMPLETION, OP_VINV, OP_HUP, OP_HDOWN, OP_IHDOWN, OP_IHUP };
+enum Op { OP_FACTOR, OP_PRODUCT, OP_COMPLETION, OP_VINV, OP_HUP, OP_HDOWN, OP_IHDOWN, OP_IHUP, OP_HFAC };
 inline int64_t slot_doubles(Op op, const Level& L) {
   const int64_t N = L.maxN, A = L.maxA, J = L.maxJ;
   switch (op) {
@@ -56,6 +56,7 @@ inline int64_t slot_doubles(Op op, const Level& L) {
     case OP_HDOWN: return 2 * A * N + 2 * N * N;
     case OP_IHDOWN: return 2 * A * N + 3 * N * N;
     case OP_IHUP: return J * N + A * N;
+    case OP_HFAC: return 2 * N * N + A * N;
   }
   return 0;
 }
@@ -143,6 +144,10 @@ struct mfb_plan_s {
   // the inverse Hessian's steps 1+2 likewise, in launches whose workgroup
   // scratch stays within kFlatScratch doubles per right-hand side
   mfb::ClassSched cs_compl_flat, cs_ihd_flat;
+  // the Hessian factor's per-supernode conversions: every supernode, one
+  // launch per group of fronts whose workgroup scratch stays within
+  // kFlatScratch doubles per right-hand side
+  mfb::ClassSched cs_hfac;
   // the Hessian down-sweep: cs_down without its root level when that is one
   // front with A = 0 and N > kDownRegMaxJ (hd_root, else -1), which runs as
   // tile-parallel products instead
@@ -163,6 +168,7 @@ struct mfb_plan_s {
   const int64_t* d_gmap = nullptr;
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;
+  double by_factor = 0, by_projinv = 0, by_hess = 0, by_invhess = 0, by_completion = 0, by_product = 0;
   std::vector<int64_t> colptr_h;
   // device copies (uploaded on first use)
   std::mutex mu;

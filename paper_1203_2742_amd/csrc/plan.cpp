@@ -501,6 +501,44 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
       }
     }
   }
+  // The Hessian factor's conversions (both directions) touch one front at
+  // a time: every supernode, blocked kernel, longest first.
+  {
+    ClassSched& cs = p->cs_hfac;
+    cs.list.clear();
+    cs.segs.clear();
+    cs.pre.clear();
+    std::vector<int32_t> fr(static_cast<size_t>(ns));
+    for (int32_t k = 0; k < ns; ++k) fr[size_t(k)] = k;
+    std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) { return p->J[x] > p->J[y]; });
+    Level S{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t k : fr) {
+      Level T = S;
+      T.count++;
+      T.maxN = std::max(T.maxN, p->N[k]);
+      T.maxA = std::max(T.maxA, p->J[k] - p->N[k]);
+      T.maxJ = std::max(T.maxJ, p->J[k]);
+      if (S.count && int64_t(T.count) * slot_doubles(OP_HFAC, T) > kFlatScratch) {
+        cs.segs.push_back(ClassSeg{S, -1, kRegClasses});
+        S = Level{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        T = S;
+        T.count = 1;
+        T.maxN = p->N[k];
+        T.maxA = p->J[k] - p->N[k];
+        T.maxJ = p->J[k];
+      }
+      const double Nn = p->N[k], Jn = p->J[k], An = Jn - Nn;
+      T.p += Nn * Jn - Nn * (Nn - 1) / 2;
+      T.u += An * (An + 1) / 2;
+      T.n3 += Nn * Nn * Nn;
+      T.n2a += Nn * Nn * An;
+      T.na2 += Nn * An * An;
+      T.a3 += An * An * An;
+      cs.list.push_back(k);
+      S = T;
+    }
+    if (S.count) cs.segs.push_back(ClassSeg{S, -1, kRegClasses});
+  }
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down, true);
   p->cs_hdown = p->cs_down;
   p->hd_root = -1;
@@ -594,6 +632,14 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     p->fl_invhess_x += An * An * An / 3;
     p->fl_completion += An * An * An / 3 + 2 * An * An * Nn + An * Nn * Nn + Nn * Nn * Nn;
     p->fl_product += Nn * Nn * Nn / 3 + Nn * Nn * An + Nn * An * An;
+    // canonical doubles moved (panel entries pe, packed update entries ue)
+    const double pe = Nn * (Nn + An) - Nn * (Nn - 1) / 2, ue = An * (An + 1) / 2;
+    p->by_factor += 8 * (2 * pe + 2 * ue);
+    p->by_projinv += 8 * (2 * pe + 2 * ue);
+    p->by_hess += 8 * (6 * pe + 5 * ue);
+    p->by_invhess += 8 * (7 * pe + 7 * ue);
+    p->by_completion += 8 * (4 * pe + 5 * ue);
+    p->by_product += 8 * (2 * pe + 2 * ue);
   }
   return MFB_OK;
 }

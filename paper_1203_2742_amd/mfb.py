@@ -45,7 +45,7 @@ class MfbError(RuntimeError):
 
 
 KERNELS = ("k_factor", "k_projinv", "k_hess_up", "k_hess_down", "k_ihess_down", "k_ihess_up",
-           "k_completion", "k_vinv", "k_product", "k_gather")
+           "k_completion", "k_vinv", "k_product", "k_gather", "k_gamma", "k_hfactor", "k_hfactor_adj")
 
 
 class ProfileEntry(ctypes.Structure):
@@ -61,7 +61,9 @@ class PlanInfo(ctypes.Structure):
                [("factor_workspace_bytes", ctypes.c_size_t), ("rhs_arena_bytes", ctypes.c_size_t)] + \
                [(n, ctypes.c_double) for n in
                 ("flops_factor", "flops_projinv", "flops_hessian", "flops_inv_hessian",
-                 "flops_inv_hessian_x", "flops_completion", "flops_product")]
+                 "flops_inv_hessian_x", "flops_completion", "flops_product",
+                 "bytes_factor", "bytes_projinv", "bytes_hessian", "bytes_inv_hessian",
+                 "bytes_completion", "bytes_product")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +87,10 @@ def _load():
         "mfb_hessian": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_inv_hessian": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_hessian_static": (I32, [P, I32, P, P, P]),
+        "mfb_hessian_factor": (I32, [P, I32, P, P, P, SZ, P]),
+        "mfb_hessian_factor_adj": (I32, [P, I32, P, P, P, SZ, P]),
+        "mfb_gram_arena_bytes": (SZ, [P, I32]),
+        "mfb_gram": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_completion": (I32, [P, P, P]),
         "mfb_cholesky_product": (I32, [P, P, P]),
         "mfb_factor_export_ldl": (I32, [P, P, P]),
@@ -247,6 +253,40 @@ def inv_hessian(f: Factor, t, y, arena, k=None, stream=None):
                               arena.numel() * arena.element_size(), _stream(stream)), "inv_hessian")
 
 
+def hessian_factor(f: Factor, y, w, arena, k=None, stream=None):
+    """mfb_hessian_factor: w_r = R(y_r) (Algorithm 5.3)."""
+    nnz = f.plan.nnz
+    k = _k_of(y, nnz) if k is None else int(k)
+    _dev_f64(y, k * nnz, "y")
+    _dev_f64(w, k * nnz, "w")
+    _chk(_lib.mfb_hessian_factor(f.handle, k, _ptr(y), _ptr(w), _ptr(arena),
+                                 arena.numel() * arena.element_size(), _stream(stream)), "hessian_factor")
+
+
+def hessian_factor_adj(f: Factor, w, t, arena, k=None, stream=None):
+    """mfb_hessian_factor_adj: t_r = R^adj(w_r) (Algorithm 5.4)."""
+    nnz = f.plan.nnz
+    k = _k_of(w, nnz) if k is None else int(k)
+    _dev_f64(w, k * nnz, "w")
+    _dev_f64(t, k * nnz, "t")
+    _chk(_lib.mfb_hessian_factor_adj(f.handle, k, _ptr(w), _ptr(t), _ptr(arena),
+                                     arena.numel() * arena.element_size(), _stream(stream)),
+         "hessian_factor_adj")
+
+
+def gram_arena_bytes(plan: Plan, m):
+    return int(_lib.mfb_gram_arena_bytes(plan.handle, int(m)))
+
+
+def gram(plan: Plan, w, g, arena, m=None, stream=None):
+    """mfb_gram: g(i, j) = w_i . w_j (trace inner product on S^n_V)."""
+    m = _k_of(w, plan.nnz) if m is None else int(m)
+    _dev_f64(w, m * plan.nnz, "w")
+    _dev_f64(g, m * m, "g")
+    _chk(_lib.mfb_gram(plan.handle, m, _ptr(w), _ptr(g), _ptr(arena),
+                       arena.numel() * arena.element_size(), _stream(stream)), "gram")
+
+
 def completion(f: Factor, s, stream=None):
     _chk(_lib.mfb_completion(f.handle, _ptr(_dev_f64(s, f.plan.nnz, "s")), _stream(stream)),
          "completion")
@@ -354,6 +394,26 @@ class SparseBarrier:
         y = torch_empty_like(t)
         inv_hessian(self.f, t, y, self.arena(k), k=k)
         return y
+
+    def hessian_factor(self, y):
+        k = 1 if y.dim() == 1 else y.shape[0]
+        w = torch_empty_like(y)
+        hessian_factor(self.f, y, w, self.arena(k), k=k)
+        return w
+
+    def hessian_factor_adj(self, w):
+        k = 1 if w.dim() == 1 else w.shape[0]
+        t = torch_empty_like(w)
+        hessian_factor_adj(self.f, w, t, self.arena(k), k=k)
+        return t
+
+    def gram(self, w):
+        import torch
+        m = 1 if w.dim() == 1 else w.shape[0]
+        g = torch.empty((m, m), dtype=torch.float64, device=self.device)
+        arena = torch.empty(max(1, gram_arena_bytes(self.f.plan, m)), dtype=torch.uint8, device=self.device)
+        gram(self.f.plan, w, g, arena, m=m)
+        return g
 
     def completion(self, s):
         completion(self.f, s)

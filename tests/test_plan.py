@@ -125,7 +125,7 @@ def test_forest_and_diagonal_plans():
 
 def test_library_exports_every_header_symbol():
     names = mfb.header_symbols()
-    assert len(names) == 20
+    assert len(names) == 24
     lib = ctypes.CDLL(mfb.LIB_PATH)
     for name in names:
         assert hasattr(lib, name), name
@@ -144,3 +144,26 @@ def test_strerror_and_numeric_entry_points_reject_null():
     plan = mfb.plan_symbolic(*P.band(5, 1))
     h = ctypes.c_void_p()
     assert lib.mfb_factor_create(plan.handle, None, 0, ctypes.byref(h)) == mfb.EINVAL
+
+
+def test_plan_info_canonical_bytes():
+    """The plan's canonical byte counts are the per-supernode sums of panel
+    entries p = N J - N(N-1)/2 and packed update entries u = A(A+1)/2."""
+    pat = P.random_chordal(120, 0.04, 3)
+    n, cp, ri = pat
+    plan = mfb.plan_symbolic(*pat)
+    snode_of, _, srep = mfb.plan_supernodes(plan)
+    ns = plan.info["nsuper"]
+    Ns = np.bincount(snode_of, minlength=ns).astype(float)
+    Js = np.array([cp[r + 1] - cp[r] for r in srep], dtype=float)
+    As = Js - Ns
+    pe = (Ns * Js - Ns * (Ns - 1) / 2).sum()
+    ue = (As * (As + 1) / 2).sum()
+    info = plan.info
+    assert pe == cp[-1]  # the panels tile the pattern
+    assert info["bytes_factor"] == 8 * (2 * pe + 2 * ue)
+    assert info["bytes_projinv"] == 8 * (2 * pe + 2 * ue)
+    assert info["bytes_hessian"] == 8 * (6 * pe + 5 * ue)
+    assert info["bytes_inv_hessian"] == 8 * (7 * pe + 7 * ue)
+    assert info["bytes_completion"] == 8 * (4 * pe + 5 * ue)
+    assert info["bytes_product"] == 8 * (2 * pe + 2 * ue)
