@@ -483,9 +483,99 @@ def latency(torch, mfb, V, get_config, name, dev, reps=200):
         seq()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - w0) / reps
+    # the same sequence, preceded by the factor, captured once as a HIP graph
+    # and replayed (no entry point allocates, synchronizes or records a
+    # memset once the plan is on the device)
+
+    def gseq():
+        mfb.factor(f, x)
+        seq()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gseq()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gseq()
+    torch.cuda.synchronize()
+    t_eager = t.clone()
+    g.replay()
+    torch.cuda.synchronize()
+    graph_same = bool(torch.equal(t, t_eager))
+    gm = []
+    for _ in range(reps):
+        e0, e1 = ev(torch), ev(torch)
+        e0.record()
+        g.replay()
+        e1.record()
+        gm.append((e0, e1))
+    torch.cuda.synchronize()
+    gv = np.array([a.elapsed_time(c) for a, c in gm])
+    # the eager factor + sequence, for the graph's like-for-like comparison
+    em = []
+    for _ in range(reps):
+        e0, e1 = ev(torch), ev(torch)
+        e0.record()
+        gseq()
+        e1.record()
+        em.append((e0, e1))
+    torch.cuda.synchronize()
+    evv = np.array([a.elapsed_time(c) for a, c in em])
     return {"workload": name, "calls": "logdet + projected_inverse + hessian(k=1)", "reps": reps,
             "p50_ms": round(float(np.percentile(v, 50)), 4), "p99_ms": round(float(np.percentile(v, 99)), 4),
-            "host_wall_ms_per_sequence": round(wall * 1e3, 4), "levels": b.info["nlevels_up"]}
+            "host_wall_ms_per_sequence": round(wall * 1e3, 4), "levels": b.info["nlevels_up"],
+            "with_factor": {"eager_p50_ms": round(float(np.percentile(evv, 50)), 4),
+                            "eager_p99_ms": round(float(np.percentile(evv, 99)), 4),
+                            "graph_p50_ms": round(float(np.percentile(gv, 50)), 4),
+                            "graph_p99_ms": round(float(np.percentile(gv, 99)), 4),
+                            "graph_replay_bitwise_equal": graph_same}}
+
+
+def hessian_factor_extra(torch, mfb, V, st, reps=2):
+    """The interior-point use of the Hessian factor on the step's workload
+    (Sections 1.3 and 5.4): W = R(Y) for the step's k right-hand sides, the
+    Gram matrix Y_i . H(Y_j) = W_i . W_j, and R^adj(W) = H(Y).  Times each
+    call (the first R call also builds the per-supernode factors of S_AA)
+    and checks both identities against the step's own H(Y) on the device."""
+    f, k = st.b.f, st.k
+    dev = st.y.device
+    st.run()  # the step leaves H(Y) in st.t
+    w = torch.empty_like(st.y)
+    t2 = torch.empty_like(st.y)
+    g = torch.empty((k, k), dtype=torch.float64, device=dev)
+    garena = torch.empty(max(1, mfb.gram_arena_bytes(f.plan, k)), dtype=torch.uint8, device=dev)
+    e = [ev(torch) for _ in range(2)]
+    e[0].record()
+    mfb.hessian_factor(f, st.y, w, st.arena, k=k)
+    e[1].record()
+    torch.cuda.synchronize()
+    first = e[0].elapsed_time(e[1])
+    times = {"hessian_factor": [], "hessian_factor_adj": [], "gram": []}
+    for _ in range(reps):
+        e = [ev(torch) for _ in range(4)]
+        e[0].record()
+        mfb.hessian_factor(f, st.y, w, st.arena, k=k)
+        e[1].record()
+        mfb.hessian_factor_adj(f, w, t2, st.arena, k=k)
+        e[2].record()
+        mfb.gram(f.plan, w, g, garena, m=k)
+        e[3].record()
+        torch.cuda.synchronize()
+        for i, name in enumerate(times):
+            times[name].append(e[i].elapsed_time(e[i + 1]))
+    n, cp, ri = st.pat
+    col = torch.from_numpy(V.column_index(n, cp)).to(dev)
+    wt = torch.where(torch.from_numpy(np.asarray(ri)).to(dev) == col, 1.0, 2.0).to(torch.float64)
+    gref = (st.y * wt) @ st.t.T
+    gref = 0.5 * (gref + gref.T)
+    adj_err = float((t2 - st.t).abs().max() / st.t.abs().max())
+    gram_err = float((g - gref).abs().max() / gref.abs().max())
+    return {"k": k, "first_hessian_factor_ms": round(first, 3),
+            "ms": {kk: round(float(np.median(v)), 3) for kk, v in times.items()},
+            "evals_per_s_hessian_factor": round(k / (np.median(times["hessian_factor"]) * 1e-3), 3),
+            "max_rel_err_adj_of_factor_vs_hessian": adj_err, "max_rel_err_gram_vs_y_dot_hessian": gram_err}
 
 
 def main():
@@ -547,6 +637,10 @@ def main():
     if err is None and st.nnz <= 3_000_000:
         st.run()
         err = full_oracle_check(pat, st, host)
+    hfac = None
+    if not args.no_extras:
+        hfac = hessian_factor_extra(torch, mfb, V, st)
+        log(args, f"hessian factor {hfac}")
     del st
     torch.cuda.empty_cache()
 
@@ -602,6 +696,8 @@ def main():
         "status": status[0],
         "setup_s": round(setup_s, 2),
     }
+    if hfac is not None:
+        out["hessian_factor"] = hfac
     out.update(extras)
     print(json.dumps(out), flush=True)
 

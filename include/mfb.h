@@ -82,7 +82,9 @@ typedef struct mfb_factor_s* mfb_factor_t;
                                       entries never keep the map) */
 #define MFB_PLAN_WIDE_LOW 4u  /* run the tile-parallel wide-front kernels from
                                  front order 65 instead of 513 (fronts with at
-                                 most 64 columns and a nonempty ancestor set);
+                                 most 64 columns and a nonempty ancestor set),
+                                 and the tile-parallel factorization of the
+                                 blocks S_AA from order 193 instead of 513;
                                  for testing those kernels on small patterns */
 
 typedef struct {
@@ -175,7 +177,8 @@ mfb_status_t mfb_projected_inverse(mfb_factor_t f, double* s_dev, void* stream);
  *   arena_dev: at least k * plan_info.rhs_arena_bytes device bytes,
  *   256-byte aligned, caller-owned scratch.
  * Computes the projected inverse first if it is not cached.  k = 0 is a
- * no-op. */
+ * no-op; k above 65535 gives MFB_EINVAL (this holds for every call that
+ * takes k right-hand sides and an arena). */
 mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y_dev, double* t_dev,
                          void* arena_dev, size_t arena_bytes, void* stream);
 
@@ -211,7 +214,11 @@ mfb_status_t mfb_hessian_static(mfb_factor_t f, int32_t k, const double* y_dev, 
  * rules as mfb_hessian (y_dev, w_dev: k*nnz doubles, not overlapping).
  * Computes the projected inverse if it is not cached, and computes and
  * caches per supernode the lower triangular G with G^T G = S_AA and G^-1
- * for the current X. */
+ * for the current X.  That cache shares the handle's storage with the
+ * (S_AA)^-1 cache of mfb_inv_hessian and with the update arena of
+ * mfb_cholesky_product: after either of those, the next Hessian-factor
+ * call rebuilds it (and after a Hessian-factor call the next inverse
+ * Hessian rebuilds its own). */
 mfb_status_t mfb_hessian_factor(mfb_factor_t f, int32_t k, const double* y_dev, double* w_dev,
                                 void* arena_dev, size_t arena_bytes, void* stream);
 

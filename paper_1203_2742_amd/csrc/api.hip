@@ -14,6 +14,8 @@
 
 namespace mfb {
 constexpr size_t ALIGN = 256;
+// right-hand sides of one call: the grid's y extent of the per-RHS launches
+constexpr int kMaxRhs = 65535;
 static inline size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
 static int64_t scratch_doubles(Op op, const std::vector<Level>& lv) {
@@ -51,7 +53,7 @@ static int64_t rhs_scratch(const mfb_plan_s* p) {
 }
 static size_t factor_bytes(const mfb_plan_s* p) {
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
-  return 3 * up(nnz * 8) + 5 * up(upd * 8) + up(size_t(std::max(1, p->ns)) * 8) + up(8) +
+  return 3 * up(nnz * 8) + 3 * up(upd * 8) + up(size_t(std::max(1, p->ns)) * 8) + up(8) +
          up(sizeof(DevStatus)) + up(size_t(factor_scratch(p)) * 8);
 }
 static size_t rhs_bytes(const mfb_plan_s* p) {
@@ -95,7 +97,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
          iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre), iGl = v32(p->cs_gather.list),
          iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre), iPx = v32(p->cs_compl_flat.pre),
-         iHf = v32(p->cs_hfac.list);
+         iHf = v32(p->cs_hfac.list), iBv = v32(p->cs_bigv.list);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -120,6 +122,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   P.rel = (const int32_t*)at(iRel);
   P.arena = (const int64_t*)at(iAr);
   P.vlabel = (const int32_t*)at(iVl);
+  P.big_a = p->big_a;
   p->d_up_list = (const int32_t*)at(iUp);
   p->d_down_list = (const int32_t*)at(iDn);
   p->d_all_list = (const int32_t*)at(iAll);
@@ -140,6 +143,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_ihd_flat.d_pre = (const int32_t*)at(iPi);
   p->cs_compl_flat.d_pre = (const int32_t*)at(iPx);
   p->cs_hfac.d_list = (const int32_t*)at(iHf);
+  p->cs_bigv.d_list = (const int32_t*)at(iBv);
   return MFB_OK;
 }
 
@@ -159,7 +163,10 @@ struct mfb_factor_s {
   std::vector<hipEvent_t> pool;
   char* ws = nullptr;
   double *R = nullptr, *LB = nullptr, *S = nullptr, *Vs = nullptr, *Vi = nullptr, *U = nullptr;
-  // per supernode: the lower G with G^T G = S_AA and G^-1 (Hessian factor)
+  // per supernode: the lower G with G^T G = S_AA and G^-1 (Hessian factor),
+  // held in U and Vi while valid (gam_valid): the factor and product sweeps
+  // use U as their update arena and Vi caches (S_AA)^-1 otherwise, so
+  // building one cache invalidates the other
   double *Gam = nullptr, *Gami = nullptr;
   double *part = nullptr, *logdet = nullptr, *scratch = nullptr;
   DevStatus* st = nullptr;
@@ -273,8 +280,8 @@ mfb_status_t mfb_factor_create(mfb_plan_t p, void* ws, size_t bytes, mfb_factor_
   f->Vs = (double*)take(upd * 8);
   f->Vi = (double*)take(upd * 8);
   f->U = (double*)take(upd * 8);
-  f->Gam = (double*)take(upd * 8);
-  f->Gami = (double*)take(upd * 8);
+  f->Gam = f->U;
+  f->Gami = f->Vi;
   f->part = (double*)take(size_t(std::max(1, p->ns)) * 8);
   f->logdet = (double*)take(8);
   f->st = (DevStatus*)take(sizeof(DevStatus));
@@ -369,13 +376,13 @@ static mfb_status_t run_levels(mfb_factor_s* f, int kid, const std::vector<Level
 typedef void (*SegLaunch)(mfb_factor_s*, const ClassSched&, const ClassSeg&, dim3, hipStream_t, int64_t,
                           void*);
 static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, hipStream_t s, int k,
-                                Op op, SegLaunch launch, void* ctx) {
+                                Op op, SegLaunch launch, void* ctx, bool canon = true) {
   for (const ClassSeg& g : cs.segs) {
     const Level& L = g.lv;
     dim3 grid(unsigned(L.count), unsigned(k));
     ProfRec rec{kid, g.level, L.count, k, 0.0, 0.0, nullptr, nullptr};
     if (f->prof) {
-      canonical(kid, L, k, &rec.bytes, &rec.flops);
+      if (canon) canonical(kid, L, k, &rec.bytes, &rec.flops);  // else time only
       rec.e0 = pool_event(f);
       rec.e1 = pool_event(f);
       if (!rec.e0 || !rec.e1) return MFB_EHIP;
@@ -523,7 +530,7 @@ struct RhsArena {
 static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, RhsArena* a) {
   const mfb_plan_s* p = f->plan;
   if (!arena || (reinterpret_cast<uintptr_t>(arena) % ALIGN) != 0) return MFB_EINVAL;
-  if (bytes < size_t(k) * rhs_bytes(p)) return MFB_EINVAL;
+  if (k > kMaxRhs || bytes < size_t(k) * rhs_bytes(p)) return MFB_EINVAL;
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
   char* c = (char*)arena;
   a->upd = int64_t(upd);
@@ -696,12 +703,16 @@ static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
         const int32_t* list = cs.d_list + sg.lv.begin;
         if (cls < kRegClasses)
           launch_vinv_reg(cls, g, s, f->plan->dev, list, f->Vs, f->Vi, f->st);
+        else if (cls == kBigV)  // factor formed in U, its inverse into Vi
+          launch_bigv(false, sg.lv.maxA, sg.lv.count, s, f->plan->dev, list, f->Vs, f->U, f->Vi, f->st,
+                      MFB_ENOTPD);
         else
           k_vinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->Vs, f->Vi, f->st, f->scratch, slot);
       },
       nullptr);
   if (st) return st;
   f->vinv_valid = true;
+  f->gam_valid = false;  // Vi and U overwrote Gami and Gam
   return MFB_OK;
 }
 
@@ -713,11 +724,17 @@ static mfb_status_t ensure_gamma(mfb_factor_s* f, hipStream_t s) {
   st = run_classes(
       f, MFB_K_GAMMA, f->plan->cs_vinv, s, 1, OP_VINV,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t, void*) {
-        launch_gamma(g, s, f->plan->dev, cs.d_list + sg.lv.begin, f->Vs, f->Gam, f->Gami, f->st);
+        const int32_t* list = cs.d_list + sg.lv.begin;
+        if (sg.cls == kBigV)
+          launch_bigv(true, sg.lv.maxA, sg.lv.count, s, f->plan->dev, list, f->Vs, f->Gam, f->Gami, f->st,
+                      MFB_ENOTPD);
+        else
+          launch_gamma(g, s, f->plan->dev, list, f->Vs, f->Gam, f->Gami, f->st);
       },
       nullptr);
   if (st) return st;
   f->gam_valid = true;
+  f->vinv_valid = false;  // Gami overwrote Vi
   return MFB_OK;
 }
 
@@ -895,6 +912,18 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   // fronts' sweeps, which need nothing but their own S and V_s
   mfb_status_t st = gather_blocks(f, s, 1, sin, f->Vs, 0, 0, 2);
   if (st) return st;
+  // the blocks S_AA with A > big_a: Cholesky factor (formed in U) and its
+  // inverse C_V^-1 into Vi, tile-parallel over all those fronts (recorded
+  // with time only: the completion's canonical counts are in its per-front
+  // launches)
+  st = run_classes(
+      f, MFB_K_COMPLETION, f->plan->cs_bigv, s, 1, OP_VINV,
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3, hipStream_t s, int64_t, void*) {
+        launch_bigv(false, sg.lv.maxA, sg.lv.count, s, f->plan->dev, cs.d_list + sg.lv.begin, f->Vs, f->U, f->Vi,
+                    f->st, MFB_ENOCOMPLETION);
+      },
+      nullptr, false);
+  if (st) return st;
   st = run_classes(
       f, MFB_K_COMPLETION, f->plan->cs_compl_flat, s, 1, OP_COMPLETION,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
@@ -923,6 +952,7 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
   if (!f->has_factor) return MFB_ESTATE;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
+  f->gam_valid = false;  // the sweep's update arena U holds the Hessian factor's G
   struct Ctx { double* x; } ctx{x};
   mfb_status_t st = run_classes(
       f, MFB_K_PRODUCT, f->plan->cs_factor, s, 1, OP_PRODUCT,

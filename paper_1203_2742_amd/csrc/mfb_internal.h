@@ -33,6 +33,7 @@ struct DevPlan {
   const int32_t* rel;
   const int64_t* arena;
   const int32_t* vlabel;    // user label of the c-th column: vlabel[colbase[s] + c]
+  int32_t big_a;            // S_AA blocks with A > big_a are factored tile-parallel
 };
 
 struct Level {
@@ -79,6 +80,9 @@ constexpr int kDownRegMaxJ = 64;
 // Largest workgroup scratch (doubles per right-hand side) of one launch of
 // a schedule that runs independent fronts together.
 constexpr int64_t kFlatScratch = int64_t(1) << 22;
+// The same for the completion's wide and fat fronts (scratch per front
+// A N + 3 N^2 + ..., many fronts per launch).
+constexpr int64_t kFlatScratchFat = int64_t(1) << 26;
 // Largest number of packed update-block entries for which the plan keeps
 // the CCS source offset of every entry (8 bytes each), so that gathering
 // the blocks of an input takes one elementwise launch.
@@ -93,6 +97,13 @@ constexpr int kWideJLow = 64;   // with MFB_PLAN_WIDE_LOW
 constexpr int kWide = kRegClasses + 1;  // class value of a wide segment
 constexpr int kFat = kRegClasses + 2;   // class value of a segment of fat fronts
 constexpr int kWideTile = 64;
+// The blocks S_AA with A > the plan's big_a (kBigA, or kVExplicitMax with
+// MFB_PLAN_WIDE_LOW) are factored and inverted tile-parallel, one launch
+// per block column and row block over all such fronts (wide.hip, "bigv"),
+// for the inverse Hessian's and the Hessian factor's caches and in the
+// completion; smaller ones by one workgroup each.
+constexpr int kBigA = 512;
+constexpr int kBigV = kRegClasses + 3;  // class value of the segment of those fronts
 
 // A level of a schedule split by class: at most three launches (groups of
 // launches for the wide fronts), the wide fronts (cls == kWide), the
@@ -128,6 +139,7 @@ struct mfb_plan_s {
   uint32_t flags = 0;
   int32_t ns = 0;
   int32_t wide_thr = mfb::kWideJ;  // wide fronts: J > wide_thr (see kWideMaxN)
+  int32_t big_a = mfb::kBigA;      // tile-parallel S_AA factorization: A > big_a (see kBigA)
   std::vector<int32_t> N, J, parent, cptr, cidx, colbase, relbase, rel, rep, vlabel, snode_of;
   std::vector<int64_t> col, arena;
   int64_t update_doubles = 0;
@@ -148,6 +160,9 @@ struct mfb_plan_s {
   // launch per group of fronts whose workgroup scratch stays within
   // kFlatScratch doubles per right-hand side
   mfb::ClassSched cs_hfac;
+  // the fronts with A > big_a (cs_vinv's kBigV segment), which the
+  // completion factors tile-parallel before its per-front launches
+  mfb::ClassSched cs_bigv;
   // the Hessian down-sweep: cs_down without its root level when that is one
   // front with A = 0 and N > kDownRegMaxJ (hd_root, else -1), which runs as
   // tile-parallel products instead

@@ -260,6 +260,9 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   // launched first on their level, with their tiles numbered: 64 x 64 lower
   // tiles of the A x A block and 64-row tiles of the A rows.
   p->wide_thr = (flags & MFB_PLAN_WIDE_LOW) ? kWideJLow : kWideJ;
+  // (never below kVExplicitMax: the tile-parallel path leaves C_V^-1, the
+  // representation of the larger blocks)
+  p->big_a = (flags & MFB_PLAN_WIDE_LOW) ? kVExplicitMax : kBigA;
   // every front above the threshold is wide in the root-to-leaf sweeps; in
   // the leaf-to-root ones those with at most kWideMaxN columns (and an
   // update block) are wide and the others fat
@@ -373,10 +376,13 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     cs.segs.clear();
     cs.pre.clear();
     cs.list.reserve(ns);
-    // the completion's fat fronts (above the wide threshold, more than
-    // kWideMaxN columns) run tile-parallel, in one segment of their own
+    // the completion's wide and fat fronts (above the wide threshold) run
+    // tile-parallel, in one segment of their own; the inverse of V_s for
+    // A > big_a likewise (segment class kBigV)
     const bool fat_ok = op == OP_COMPLETION;
-    auto fat = [&](int32_t k) { return fat_ok && is_wide(k) && p->N[k] > kWideMaxN; };
+    auto fat = [&](int32_t k) {
+      return (fat_ok && is_wide(k)) || (by_a && p->J[k] - p->N[k] > p->big_a);
+    };
     auto order = [&](int32_t k) { return by_a ? p->J[k] - p->N[k] : p->J[k]; };
     auto fit = [&](int32_t k) {
       int c = 0;
@@ -428,20 +434,55 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
       if (S.count) cs.segs.push_back(ClassSeg{S, -1, kRegClasses});
     }
     {
-      Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      // longest first; the completion's in launches of at most
+      // kFlatScratchFat doubles of scratch (its slot grows with N and A),
+      // the inverse's (no scratch) in one
+      std::vector<int32_t> fr;
       for (int32_t k = 0; k < ns; ++k)
-        if (fat(k)) add_front(S, k);
-      if (S.count) {
-        ClassSeg g{S, -1, kFat};
+        if (fat(k)) fr.push_back(k);
+      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) { return order(x) > order(y); });
+      const int cls = by_a ? kBigV : kFat;
+      auto close_seg = [&](Level& S) {
+        if (!S.count) return;
+        ClassSeg g{S, -1, cls};
         number_tiles(cs, g);
         cs.segs.push_back(g);
+        S = Level{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      };
+      Level S{int32_t(cs.list.size()), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int32_t k : fr) {
+        Level T = S;
+        T.count++;
+        T.maxN = std::max(T.maxN, p->N[k]);
+        T.maxA = std::max(T.maxA, p->J[k] - p->N[k]);
+        T.maxJ = std::max(T.maxJ, p->J[k]);
+        if (!by_a && S.count && int64_t(T.count) * slot_doubles(op, T) > kFlatScratchFat) close_seg(S);
+        add_front(S, k);
       }
+      close_seg(S);
     }
   };
   // V_s^-1 needs only V_s; the completion's sweeps need only S and V_s,
   // which a gather pass puts in place beforehand.
   make_flat(true, OP_VINV, p->cs_vinv);
   make_flat(false, OP_COMPLETION, p->cs_compl_flat);
+  // the completion factors the blocks S_AA with A > big_a tile-parallel
+  // before its per-front launches: the inverse's segment of those fronts
+  {
+    ClassSched& cs = p->cs_bigv;
+    cs.list.clear();
+    cs.segs.clear();
+    cs.pre.clear();
+    for (const ClassSeg& g : p->cs_vinv.segs)
+      if (g.cls == kBigV) {
+        ClassSeg h = g;
+        h.lv.begin = int32_t(cs.list.size());
+        h.aa_off = h.an_off = h.nn_off = 0;
+        cs.list.insert(cs.list.end(), p->cs_vinv.list.begin() + g.lv.begin,
+                       p->cs_vinv.list.begin() + g.lv.begin + g.lv.count);
+        cs.segs.push_back(h);
+      }
+  }
   // The inverse Hessian's steps 1+2 read T_{A_s A_s}, which a gather pass
   // puts in place, so its fronts are independent too.  Each front takes the
   // kernel the root-to-leaf rule gives it (register kernels for J <=
@@ -455,7 +496,8 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     cs.pre.clear();
     cs.list.reserve(ns);
     auto kind = [&](int32_t k) {
-      if (is_wide(k) && p->N[k] > kWideMaxN) return kFat;
+      // wide fronts too: their A x A products run tile-parallel there
+      if (is_wide(k)) return kFat;
       const bool reg = p->J[k] <= kDownRegMaxJ || p->J[k] == p->N[k];
       int c = 0;
       while (c < kRegClasses && p->J[k] > kRegMax[c]) ++c;

@@ -18,6 +18,7 @@
 // front through prefix arrays: `pre[f]` is the first tile of front f.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "front.h"
@@ -543,9 +544,11 @@ __device__ __forceinline__ double* fat_F(double* wsb, int f, int64_t slot, const
   return wsb + (int64_t)f * slot + (q.sq ? (int64_t)A * N : 0);
 }
 
+template <int SQ>
 __global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t* list, int count, int kb,
                                                        double* R, double* part, DevStatus* st, double* wsb,
-                                                       int64_t slot, FatSquare q) {
+                                                       int64_t slot) {
+  constexpr FatSquare q{SQ};
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   __shared__ int fail;
@@ -582,8 +585,10 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t*
   });
 }
 
+template <int SQ>
 __global__ void __launch_bounds__(NT) k_fat_potrf_panel(DevPlan P, const int32_t* list, int count, int kb,
-                                                        double* R, double* wsb, int64_t slot, FatSquare q) {
+                                                        double* R, double* wsb, int64_t slot) {
+  constexpr FatSquare q{SQ};
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   const int f = blockIdx.y;
@@ -607,8 +612,10 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_panel(DevPlan P, const int32_t
   });
 }
 
+template <int SQ>
 __global__ void __launch_bounds__(NT) k_fat_potrf_trail(DevPlan P, const int32_t* list, int count, int kb,
-                                                        double* wsb, int64_t slot, FatSquare q) {
+                                                        double* wsb, int64_t slot) {
+  constexpr FatSquare q{SQ};
   __shared__ double sm[SMEM_DOUBLES];
   const int f = blockIdx.y;
   const int s = list[f];
@@ -634,8 +641,10 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_trail(DevPlan P, const int32_t
 // (ib, jb), jb <= ib, per workgroup:
 //   X(ib, jb) = C_ib,ib^-1 (delta I - sum_{jb <= m < ib} C(ib, m) X(m, jb)),
 // so a launch per ib completes row block ib from the ones above it.
+template <int SQ>
 __global__ void __launch_bounds__(NT) k_fat_trtri_row(DevPlan P, const int32_t* list, int count, int ib,
-                                                      double* wsb, int64_t slot, FatSquare q) {
+                                                      double* wsb, int64_t slot) {
+  constexpr FatSquare q{SQ};
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ double rb[WT * WLD];
   const int f = blockIdx.y;
@@ -783,7 +792,8 @@ __global__ void __launch_bounds__(NT) k_fat_up_fin(DevPlan P, const int32_t* lis
 // complement Mr (N x N) with the inverse blocks and X = Mr-factor^-1 of the
 // blocked Cholesky after it.
 //  prep (one workgroup per front): S's own columns into the cached S, and
-//       C_V^-1 in place in the packed Vi block;
+//       C_V^-1 in place in the packed Vi block when A <= big_a (larger
+//       blocks are factored and inverted beforehand by the bigv launches);
 //  a:   W = C_V^-1 S_AN (AN tiles);
 //  b:   L_AN = -C_V^-T W (AN tiles) and D^-1 = M = S_NN - W^T W (lower NN
 //       tiles), M also stored reversed, Mr(N-1-j, N-1-i) = M(i, j);
@@ -806,7 +816,7 @@ __global__ void __launch_bounds__(NT) k_fat_compl_prep(DevPlan P, const int32_t*
       if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
     }
     __syncthreads();
-    if (v.A == 0) return;
+    if (v.A == 0 || v.A > P.big_a) return;  // larger blocks: the bigv launches
     const int A = v.A;
     double* VI = Vi + P.arena[v.s];
     const double* V = Vs + P.arena[v.s];
@@ -971,7 +981,16 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
                               [&](int k, int j) { return W[k + (int64_t)j * N]; }, sm);
         tile_store(T, i0, j0, N, N, [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true);
       } else if (explicit_v) {
-        wide_sym_rows<true>(T, i0, j0, A, N, VI, [&](int k, int j) { return Z[k + (int64_t)j * A]; }, sm);
+        // V^-1 Z with every operand fetch along the tile's rows (this block
+        // is at most kVExplicitMax wide): the wide_sym_rows form, whose
+        // part above the diagonal block fetches along k, gave wrong
+        // results here for blocks of more than one row tile
+        const int d0 = min(i0, A), d1 = min(i0 + WT, A);
+        auto fz = [&](int k, int j) { return Z[k + (int64_t)j * A]; };
+        tile_mma<false, true>(T, i0, j0, A, N, 0, d0, [&](int i, int k) { return VI[pk(i, k, A)]; }, fz, sm);
+        tile_mma<false, true>(T, i0, j0, A, N, d0, d1, [&](int i, int k) { return sym_packed(VI, i, k, A); }, fz,
+                              sm);
+        tile_mma<false, true>(T, i0, j0, A, N, d1, A, [&](int i, int k) { return VI[pk(k, i, A)]; }, fz, sm);
         tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false);
       } else {
         tile_mma<false, true>(T, i0, j0, A, N, 0, min(A, i0 + WT), [&](int i, int k) {
@@ -984,6 +1003,126 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
       tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false);
     }
   });
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky factor and its inverse of the packed blocks V = S_AA with
+// A > big_a ("bigv"), tile-parallel over all such fronts of a list:
+// left-looking by 64-column block columns, each tile of the factor formed
+// once as one matrix-core k-loop over the block columns before it.
+//  copy:  V into Cb (the factor is formed in place there);
+//  diag:  block column kb's diagonal tile T = V_kk - C_k,<k C_k,<k^T,
+//         factored in LDS (C_kk into Cb) and inverted (C_kk^-1 into the
+//         diagonal block of Out, where the inverse ends up anyway);
+//  panel: its row tiles below, C_ik = (V_ik - C_i,<k C_k,<k^T) C_kk^-T;
+//  trtri: row block ib of X = C^-1 from the rows above it,
+//         X_ib,jb = -X_ib,ib sum_{jb <= m < ib} C_ib,m X_m,jb.
+// REV runs all of it on the reversed view of the packed blocks (entry
+// (i, j) of the view at the packed position of (A-1-j, A-1-i)): then Cb
+// ends up holding G with G^T G = V (G = P F^T P for P V P = F F^T) and Out
+// holds G^-1, the Hessian factor's pair.  Fronts with A <= big_a exit, so
+// a mixed list (the completion's) needs no split.
+template <bool REV>
+struct PView {
+  double* u;
+  int a;
+  __device__ __forceinline__ double& operator()(int i, int j) const {
+    return REV ? u[pk(a - 1 - j, a - 1 - i, a)] : u[pk(i, j, a)];
+  }
+};
+
+__global__ void __launch_bounds__(NT) k_bigv_copy(DevPlan P, const int32_t* list, const double* Vs, double* Cb) {
+  const int s = list[blockIdx.y];
+  const int A = P.nrow[s] - P.ncol[s];
+  if (A <= P.big_a) return;
+  const int64_t m = (int64_t)A * (A + 1) / 2, off = P.arena[s];
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (int64_t)gridDim.x * NT)
+    Cb[off + e] = Vs[off + e];
+}
+
+template <bool REV>
+__global__ void __launch_bounds__(NT) k_bigv_diag(DevPlan P, const int32_t* list, int kb, double* Cb, double* Out,
+                                                  DevStatus* st, int code) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double d64[NB2 * LD2];
+  __shared__ int fail;
+  const int s = list[blockIdx.y];
+  const int A = P.nrow[s] - P.ncol[s];
+  if (A <= P.big_a || kb >= A) return;
+  const int nb = min(WT, A - kb);
+  const PView<REV> F{Cb + P.arena[s], A}, X{Out + P.arena[s], A};
+  MfmaTile T(threadIdx.x);
+  tile_mma<REV, REV>(T, 0, 0, nb, nb, 0, kb, [&](int i, int k) { return F(kb + i, k); },
+                     [&](int k, int j) { return F(kb + j, k); }, sm);
+  for (int e = threadIdx.x; e < NB2 * LD2; e += NT) d64[e] = 0.0;
+  if (threadIdx.x == 0) fail = -1;
+  __syncthreads();
+  tile_store(T, 0, 0, nb, nb, [&](int i, int j, double acc) { d64[i + j * LD2] = F(kb + i, kb + j) - acc; }, true);
+  __syncthreads();
+  const DenseAt D{d64, LD2};
+  wg_potrf_acc(D, nb, nb, sm, &fail);
+  for (int e = threadIdx.x; e < nb * nb; e += NT) {
+    const int i = e % nb, j = e / nb;
+    if (i >= j) F(kb + i, kb + j) = d64[i + j * LD2];
+  }
+  __syncthreads();
+  wg_trtri_inplace(D, nb, sm);
+  for (int e = threadIdx.x; e < nb * nb; e += NT) {
+    const int i = e % nb, j = e / nb;
+    if (i >= j) X(kb + i, kb + j) = d64[i + j * LD2];
+  }
+  if (threadIdx.x == 0 && fail >= 0) report(st, code, P.vlabel[P.colbase[s]]);
+}
+
+template <bool REV>
+__global__ void __launch_bounds__(NT) k_bigv_panel(DevPlan P, const int32_t* list, int kb, double* Cb,
+                                                   const double* Out) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double rb[WT * WLD];
+  const int s = list[blockIdx.y];
+  const int A = P.nrow[s] - P.ncol[s];
+  if (A <= P.big_a || kb >= A) return;
+  const int nb = min(WT, A - kb);
+  const int i0 = kb + nb + int(blockIdx.x) * WT;
+  if (i0 >= A) return;
+  const PView<REV> F{Cb + P.arena[s], A};
+  const PView<REV> X{const_cast<double*>(Out) + P.arena[s], A};
+  MfmaTile T(threadIdx.x);
+  tile_mma<REV, REV>(T, i0, 0, A, nb, 0, kb, [&](int i, int k) { return F(i, k); },
+                     [&](int k, int j) { return F(kb + j, k); }, sm);
+  for (int e = threadIdx.x; e < WT * WLD; e += NT) rb[e] = 0.0;
+  __syncthreads();
+  tile_store(T, i0, 0, A, nb, [&](int i, int j, double acc) { rb[(i - i0) + j * WLD] = F(i, kb + j) - acc; },
+             false);
+  __syncthreads();
+  MfmaTile T2(threadIdx.x);
+  tile_mma(T2, 0, 0, WT, nb, 0, nb, [&](int i, int k) { return rb[i + k * WLD]; },
+           [&](int k, int j) { return j >= k ? X(kb + j, kb + k) : 0.0; }, sm);
+  tile_store(T2, 0, 0, min(WT, A - i0), nb, [&](int i, int j, double acc) { F(i0 + i, kb + j) = acc; }, false);
+}
+
+template <bool REV>
+__global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* list, int ib, const double* Cb,
+                                                   double* Out) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double rb[WT * WLD];
+  const int s = list[blockIdx.y];
+  const int A = P.nrow[s] - P.ncol[s];
+  const int i0 = ib * WT, jb = blockIdx.x, j0 = jb * WT;
+  if (A <= P.big_a || i0 >= A || jb >= ib) return;
+  const int nbi = min(WT, A - i0);
+  const PView<REV> F{const_cast<double*>(Cb) + P.arena[s], A}, X{Out + P.arena[s], A};
+  MfmaTile T(threadIdx.x);
+  tile_mma<REV, !REV>(T, i0, j0, A, A, j0, i0, [&](int i, int k) { return F(i, k); },
+                      [&](int k, int j) { return k >= j ? X(k, j) : 0.0; }, sm);
+  for (int e = threadIdx.x; e < WT * WLD; e += NT) rb[e] = 0.0;
+  __syncthreads();
+  tile_store(T, i0, j0, A, A, [&](int i, int j, double acc) { rb[(i - i0) + (j - j0) * WLD] = -acc; }, false);
+  __syncthreads();
+  MfmaTile T2(threadIdx.x);
+  tile_mma(T2, 0, 0, nbi, WT, 0, nbi, [&](int i, int k) { return k <= i ? X(i0 + i, i0 + k) : 0.0; },
+           [&](int k, int j) { return rb[k + j * WLD]; }, sm);
+  tile_store(T2, 0, 0, nbi, WT, [&](int i, int j, double acc) { X(i0 + i, j0 + j) = acc; }, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1049,25 +1188,25 @@ void launch_fat_panel(int op, const FatGrid& g, int k, hipStream_t s, const DevP
 // The blocked Cholesky (k_fat_potrf_*) and the row blocks of its inverse
 // (k_fat_trtri_row) over a segment's fronts, grids sized by its largest
 // front (maxN columns, maxRows rows); tiles beyond a front's own exit.
+template <int SQ>
 static void fat_potrf_trtri(int maxN, int maxRows, hipStream_t s, const DevPlan& P, const int32_t* list,
-                            int count, double* R, double* part, DevStatus* st, double* wsb, int64_t slot,
-                            FatSquare q) {
+                            int count, double* R, double* part, DevStatus* st, double* wsb, int64_t slot) {
   const unsigned c = unsigned(count);
   for (int kb = 0; kb < maxN; kb += WT) {
-    k_fat_potrf_diag<<<dim3(1, c), NT, 0, s>>>(P, list, count, kb, R, part, st, wsb, slot, q);
+    k_fat_potrf_diag<SQ><<<dim3(1, c), NT, 0, s>>>(P, list, count, kb, R, part, st, wsb, slot);
     const int rows = (maxRows - kb + WT - 1) / WT, cols = (maxN - kb + WT - 1) / WT;
-    k_fat_potrf_panel<<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, count, kb, R, wsb, slot, q);
+    k_fat_potrf_panel<SQ><<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, count, kb, R, wsb, slot);
     if (kb + WT < maxN)
-      k_fat_potrf_trail<<<dim3(unsigned(rows * cols), c), NT, 0, s>>>(P, list, count, kb, wsb, slot, q);
+      k_fat_potrf_trail<SQ><<<dim3(unsigned(rows * cols), c), NT, 0, s>>>(P, list, count, kb, wsb, slot);
   }
   for (int ib = 0; ib * WT < maxN; ++ib)
-    k_fat_trtri_row<<<dim3(unsigned(ib + 1), c), NT, 0, s>>>(P, list, count, ib, wsb, slot, q);
+    k_fat_trtri_row<SQ><<<dim3(unsigned(ib + 1), c), NT, 0, s>>>(P, list, count, ib, wsb, slot);
 }
 
 void launch_fat_factor(const FatGrid& g, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                        double* R, double* LB, double* part, DevStatus* st, double* wsb, int64_t slot) {
   const unsigned c = unsigned(count);
-  fat_potrf_trtri(g.maxN, g.maxJ, s, P, list, count, R, part, st, wsb, slot, FatSquare{0});
+  fat_potrf_trtri<0>(g.maxN, g.maxJ, s, P, list, count, R, part, st, wsb, slot);
   k_fat_factor_fin<<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, LB, wsb, slot);
 }
 
@@ -1078,7 +1217,7 @@ void launch_fat_completion(const FatGrid& g, hipStream_t s, const DevPlan& P, co
   k_fat_compl_prep<<<dim3(c), NT, 0, s>>>(P, list, Sin, S, Vs, Vi, st);
   if (g.maxA > 0) k_fat_compl<0><<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, Sin, R, LB, Vi, wsb, slot);
   k_fat_compl<1><<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, Sin, R, LB, Vi, wsb, slot);
-  fat_potrf_trtri(g.maxN, g.maxN, s, P, list, count, R, part, st, wsb, slot, FatSquare{1});
+  fat_potrf_trtri<1>(g.maxN, g.maxN, s, P, list, count, R, part, st, wsb, slot);
   k_fat_compl<2><<<dim3(unsigned(g.fin), c), NT, 0, s>>>(P, list, count, Sin, R, LB, Vi, wsb, slot);
   k_fat_compl_lauum<<<dim3(c), NT, 0, s>>>(P, list, Vi);
 }
@@ -1095,16 +1234,51 @@ void launch_fat_up_fin(int op, const FatGrid& g, int k, hipStream_t s, const Dev
     k_fat_up_fin<FAT_IHUP><<<grid, NT, 0, s>>>(P, list, count, R, LB, Out, Kt, wsb, slot);
 }
 
+void launch_bigv(bool rev, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
+                 const double* Vs, double* Cb, double* Out, DevStatus* st, int code) {
+  if (count == 0 || maxA <= P.big_a) return;
+  const unsigned c = unsigned(count);
+  const int64_t m = (int64_t)maxA * (maxA + 1) / 2;
+  k_bigv_copy<<<dim3(unsigned(std::min<int64_t>(64, (m + NT * 16 - 1) / (NT * 16))), c), NT, 0, s>>>(P, list, Vs,
+                                                                                                     Cb);
+  const int ta = (maxA + WT - 1) / WT;
+  for (int kb = 0; kb < maxA; kb += WT) {
+    const int rows = (maxA - kb - 1) / WT;  // row tiles below the diagonal block (largest front)
+    if (rev) {
+      k_bigv_diag<true><<<dim3(1, c), NT, 0, s>>>(P, list, kb, Cb, Out, st, code);
+      if (rows > 0) k_bigv_panel<true><<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, kb, Cb, Out);
+    } else {
+      k_bigv_diag<false><<<dim3(1, c), NT, 0, s>>>(P, list, kb, Cb, Out, st, code);
+      if (rows > 0) k_bigv_panel<false><<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, kb, Cb, Out);
+    }
+  }
+  for (int ib = 1; ib < ta; ++ib) {
+    if (rev)
+      k_bigv_trtri<true><<<dim3(unsigned(ib), c), NT, 0, s>>>(P, list, ib, Cb, Out);
+    else
+      k_bigv_trtri<false><<<dim3(unsigned(ib), c), NT, 0, s>>>(P, list, ib, Cb, Out);
+  }
+}
+
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                       const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
                       const double* Va, int64_t upd, double* wsb, int64_t slot) {
-  const dim3 grid(unsigned(g.fin), unsigned(count * k));
-  k_fat_ihess<1><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
-  k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
-  k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
-  k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
-  if (g.maxA > kVExplicitMax)
-    k_fat_ihess<5><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, T, Kt, Va, upd, wsb, slot);
+  // blockIdx.y = front + count * (right-hand side): right-hand sides in
+  // groups that keep the grid's y extent within 65535
+  const int kc = std::max(1, 65535 / std::max(1, count));
+  for (int r0 = 0; r0 < k; r0 += kc) {
+    const int kk = std::min(kc, k - r0);
+    const dim3 grid(unsigned(g.fin), unsigned(count * kk));
+    const double* t = T + (int64_t)r0 * P.nnz;
+    double* K = Kt + (int64_t)r0 * P.nnz;
+    const double* va = Va + (int64_t)r0 * upd;
+    k_fat_ihess<1><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
+    k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
+    k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
+    k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
+    if (g.maxA > kVExplicitMax)
+      k_fat_ihess<5><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
+  }
 }
 
 }  // namespace mfb

@@ -31,15 +31,22 @@ sys.path.insert(0, ROOT)
 # kernel symbol (without namespace and arguments) -> operation of the step;
 # the template tags of the wide-front and gather kernels name their caller
 OP_OF = [
-    (r"^k_factor", "factor"), (r"^k_wide_update<0>", "factor"),
+    (r"^k_factor", "factor"), (r"^k_wide_update<0>", "factor"), (r"^k_fat_panel<0>", "factor"),
+    (r"^k_fat_(potrf_diag|potrf_panel|potrf_trail|trtri_row)<0>", "factor"), (r"^k_fat_factor_fin", "factor"),
     (r"^k_product", "cholesky_product"), (r"^k_wide_update<3>", "cholesky_product"),
+    (r"^k_fat_panel<3>", "cholesky_product"), (r"^k_fat_up_fin<0>", "cholesky_product"),
     (r"^k_projinv", "projected_inverse"), (r"^k_wide_extract<0>", "projected_inverse"),
     (r"^k_wide_projinv", "projected_inverse"),
     (r"^k_hess_", "hessian"), (r"^k_wide_update<1>", "hessian"), (r"^k_wide_hdown", "hessian"),
+    (r"^k_fat_panel<1>", "hessian"), (r"^k_fat_up_fin<1>", "hessian"),
     (r"^k_ihess_", "inv_hessian"), (r"^k_wide_update<2>", "inv_hessian"), (r"^k_vinv", "inv_hessian"),
     (r"^k_gather_map<1>", "inv_hessian"), (r"^k_wide_extract<1>", "inv_hessian"),
+    (r"^k_fat_panel<2>", "inv_hessian"), (r"^k_fat_up_fin<2>", "inv_hessian"), (r"^k_fat_ihess", "inv_hessian"),
     (r"^k_completion", "completion"), (r"^k_gather_map<2>", "completion"),
-    (r"^k_wide_extract<2>", "completion"),
+    (r"^k_wide_extract<2>", "completion"), (r"^k_fat_compl", "completion"),
+    (r"^k_fat_(potrf_diag|potrf_panel|potrf_trail|trtri_row)<1>", "completion"),
+    (r"^k_gamma", "hessian_factor"), (r"^k_hfactor_adj", "hessian_factor_adj"), (r"^k_hfactor", "hessian_factor"),
+    (r"^k_gram", "gram"),
     (r"^k_logdet", "logdet (2 calls)"), (r"^k_reset_status", "status reset"),
     (r"^k_export_ldl", "factor_export_ldl"),
 ]
@@ -58,7 +65,7 @@ def op_of(name: str) -> str:
 
 
 def read_counter(d, calib_pat):
-    f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
     agg = collections.defaultdict(lambda: [0, 0.0])
     calib = None
     for r in csv.DictReader(open(f)):
@@ -90,7 +97,7 @@ def main():
     args = ap.parse_args()
     from bench import kernel_source_hash
 
-    stats = glob.glob(os.path.join(args.trace, "*kernel_stats.csv"))[0]
+    stats = glob.glob(os.path.join(args.trace, "**", "*kernel_stats.csv"), recursive=True)[0]
     rows = [r for r in csv.DictReader(open(stats)) if "mfb::" in r["Name"]]
     agg = {}
     for r in rows:

@@ -6,6 +6,8 @@ oracle's R and R^adj follow the paper's scalar algorithms column by column;
 the library's supernodal block form must give the same W = R(Y) entry by
 entry, since R is fixed by the choice of R_j upper triangular.
 """
+import concurrent.futures as cf
+
 import numpy as np
 import pytest
 
@@ -107,22 +109,34 @@ def test_gram_against_host(m, mfb):
     assert np.array_equal(host(g), got)
 
 
-@pytest.mark.parametrize("name", ["arrow_mixed", "grid3d_8", "roots_mixed"])
+WIDE_PATS = {"band400_w200": lambda: P.band(400, 200), "band700_w520": lambda: P.band(700, 520)}
+
+
+@pytest.mark.parametrize("name", ["arrow_mixed", "grid3d_8", "roots_mixed", "band400_w200", "band700_w520"])
 def test_hessian_factor_wide_plans(name, mfb):
     """The step-1 and root-to-leaf sweeps that R and R^adj reuse take the
-    wide and fat tile-parallel paths under MFB_PLAN_WIDE_LOW."""
-    pat = CASES[name]()
+    wide and fat tile-parallel paths under MFB_PLAN_WIDE_LOW; the bands put
+    the per-supernode G and G^-1 on the tile-parallel factorization of the
+    reversed S_AA (A = 200 under the lowered threshold, A = 520 at the
+    default one)."""
+    pat = WIDE_PATS[name]() if name in WIDE_PATS else CASES[name]()
     x = V.make_x(*pat, seed=0)
     ys = V.make_ys(*pat, 2, seed=6)
     ldl = oracle.factor(pat, x)
     s = oracle.projinv(pat, ldl)
-    b = mfb.SparseBarrier(pat, flags=mfb.PLAN_WIDE_LOW)
-    b.factor(dev(x))
-    w = host(b.hessian_factor(dev(ys)))
-    t = host(b.hessian_factor_adj(dev(ys)))
-    for r in range(2):
-        close(pat, w[r], oracle.hessian_factor(pat, ldl, s, ys[r]))
-        close(pat, t[r], oracle.hessian_factor_adj(pat, ldl, s, ys[r]))
+    with cf.ThreadPoolExecutor(4) as ex:
+        fw = [ex.submit(oracle.hessian_factor, pat, ldl, s, ys[r]) for r in range(2)]
+        ft = [ex.submit(oracle.hessian_factor_adj, pat, ldl, s, ys[r]) for r in range(2)]
+        want_w = [q.result() for q in fw]
+        want_t = [q.result() for q in ft]
+    for flags in ((mfb.PLAN_WIDE_LOW, 0) if name == "band700_w520" else (mfb.PLAN_WIDE_LOW,)):
+        b = mfb.SparseBarrier(pat, flags=flags)
+        b.factor(dev(x))
+        w = host(b.hessian_factor(dev(ys)))
+        t = host(b.hessian_factor_adj(dev(ys)))
+        for r in range(2):
+            close(pat, w[r], want_w[r])
+            close(pat, t[r], want_t[r])
 
 
 def test_hessian_factor_after_completion(mfb):

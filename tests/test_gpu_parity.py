@@ -441,6 +441,35 @@ def test_wide_fronts(name, thr, mfb):
     close(pat, host(c.cholesky_product()), x)
 
 
+@pytest.mark.parametrize("shape", ["band300_w100", "band200_w70", "arrow40x3_100", "arrow100x2_100",
+                                   "arrow100x2_250", "band400_w200"])
+def test_tile_parallel_inverse_hessian_shapes(shape, mfb):
+    """Inverse Hessian through the tile-parallel path (MFB_PLAN_WIDE_LOW) on
+    fronts whose ancestor blocks span two to four 64-row tiles: explicit
+    (S_AA)^-1 for A = 70 and 100 (N = 1, 40, 100), the factored form for
+    A = 200 and 250; the default plan (one workgroup per front) beside it.
+    A first version of the explicit product was wrong here by O(1)."""
+    pat = {"band300_w100": lambda: P.band(300, 100), "band200_w70": lambda: P.band(200, 70),
+           "arrow40x3_100": lambda: P.block_arrow([40, 40, 40], 100),
+           "arrow100x2_100": lambda: P.block_arrow([100, 100], 100),
+           "arrow100x2_250": lambda: P.block_arrow([100, 100], 250),
+           "band400_w200": lambda: P.band(400, 200)}[shape]()
+    x = V.make_x(*pat, seed=0)
+    y = V.make_y(*pat, seed=7)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    t0 = oracle.hessian(pat, ldl, s, y)
+    want = oracle.inv_hessian(pat, ldl, s, t0)
+    for flags in (0, mfb.PLAN_WIDE_LOW):
+        b = mfb.SparseBarrier(pat, flags=flags)
+        b.factor(dev(x))
+        close(pat, host(b.inv_hessian(dev(t0))), want)
+        c = mfb.SparseBarrier(pat, flags=flags)
+        c.completion(dev(s))
+        assert c.status() == (0, -1)
+        close(None, host(c.export_ldl()), ldl)
+
+
 def test_large_grid_sampled(mfb):
     """The 3D 7-point grid 40^3 (n = 64000, 42165 supernodes, 298 levels,
     fronts up to 2360, root of 1601 columns), in full.  The oracle needs
