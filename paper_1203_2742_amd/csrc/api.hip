@@ -619,7 +619,8 @@ static mfb_status_t hess_down_run(mfb_factor_s* f, int32_t k, double* t, const R
           launch_hess_down_reg(cls, g, s, f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                x->a.upd, x->a.scr, slot);
         else if (cls == kWide)
-          launch_wide_hess_down(int(g.y), s, f->plan->dev, list, wide_tiles(cs, sg), sg.lv.count, f->LB, f->Vs,
+          launch_wide_hess_down(int(g.y), sg.lv.maxN, sg.lv.maxA, s, f->plan->dev, list, wide_tiles(cs, sg),
+                                sg.lv.count, f->LB, f->Vs,
                                 x->a.Kt, x->t, x->a.Ua, x->a.upd, x->a.scr, slot);
         else
           k_hess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,

@@ -92,9 +92,9 @@ void launch_wide_extract(int tag, dim3 grid, hipStream_t s, const DevPlan& P, co
                          int64_t arena_stride);
 void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w, int count,
                          const double* LB, double* S, double* Vs);
-void launch_wide_hess_down(int k, hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w,
-                           int count, const double* LB, const double* Vs, const double* Kt, double* T, double* Va,
-                           int64_t upd, double* wsb, int64_t slot);
+void launch_wide_hess_down(int k, int maxN, int maxA, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const WideTiles& w, int count, const double* LB, const double* Vs, const double* Kt,
+                           double* T, double* Va, int64_t upd, double* wsb, int64_t slot);
 // Fat fronts (more than kWideMaxN columns): grids sized by the segment's
 // largest front; `panel` = tiles of the J x N panel, `fin` = NN plus AN
 // tiles.  Panel op: 0 factor (source X), 1 Hessian step 1 (source Y),

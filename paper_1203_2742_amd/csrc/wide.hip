@@ -260,6 +260,40 @@ __device__ __forceinline__ void wide_sym_rows(MfmaTile& T, int i0, int j0, int A
   tile_mma<true, BK>(T, i0, j0, A, N, d1, A, hi, fb, sm);
 }
 
+// Right-hand sides batched along the columns of a product whose left
+// operand (a packed A x A block shared by all right-hand sides) is the
+// expensive read: column tile c of a front with N columns covers, when
+// N <= 64, the right-hand sides c g .. c g + g - 1 (g = floor(64 / N)), N
+// columns each; when N > 64, 64 columns of one right-hand side.  Tiles
+// per front: ct; the largest ct of a segment is that of its largest N.
+struct RhsCols {
+  int N, k, g, tn, ct;
+  __host__ __device__ RhsCols(int N_, int k_) : N(N_), k(k_) {
+    if (N <= WT) {
+      g = WT / N;
+      tn = 1;
+      ct = (k + g - 1) / g;
+    } else {
+      g = 1;
+      tn = (N + WT - 1) / WT;
+      ct = tn * k;
+    }
+  }
+  // local column lc of tile c -> right-hand side r and column j; false
+  // past the tile's columns
+  __device__ __forceinline__ bool map(int c, int lc, int& r, int& j) const {
+    if (N <= WT) {
+      const int rr = lc / N;
+      r = c * g + rr;
+      j = lc - rr * N;
+      return rr < g && r < k;
+    }
+    r = c / tn;
+    j = (c - r * tn) * WT + lc;
+    return j < N;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Algorithm 7.2 on wide fronts (after k_wide_extract has put V_s in place):
 // S_AN = -V_s L_AN over the AN tiles, then S_NN = D^-1 - S_AN^T L_AN over
@@ -306,8 +340,10 @@ __global__ void __launch_bounds__(NT) k_wide_projinv_nn(DevPlan P, const int32_t
 // W (N x N), all column-major.
 //  a: the extraction tiles of V'_s, W = K_NN D^-1 over the NN tiles and
 //     Z = K_AN D^-1 over the AN tiles;
-//  b: MN = D^-1 W over the lower NN tiles; MA = V_s Z and T_AN = MA - V'_s L
-//     over the AN tiles;
+//  vz: MA = V_s Z over the AN tiles, right-hand sides batched along the
+//     columns (V_s is read once per 64 columns instead of once per RHS);
+//  b: MN = D^-1 W over the lower NN tiles; T_AN = MA - V'_s L over the AN
+//     tiles;
 //  c: T_NN = MN - L^T T_AN - MA^T L over the lower NN tiles.
 struct SegTiles {
   const int32_t* aa;  // prefix arrays (count + 1 entries each)
@@ -378,9 +414,8 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* l
     const int i0 = ti * WT, j0 = tj * WT;
     double* t = T + r * P.nnz;
     double* MN = wsb + (r * count + f) * slot;
-    double* MA = MN + (int64_t)N * N;
-    const double* Z = MA + (int64_t)A * N;
-    const double* W = Z + (int64_t)A * N;
+    const double* MA = MN + (int64_t)N * N;
+    const double* W = MA + 2 * (int64_t)A * N;
     if (nn) {
       MfmaTile Tt(threadIdx.x);
       tile_mma<false, true>(Tt, i0, j0, N, N, 0, N, [&](int i, int k) { return LB[v.nn(i, k)]; },
@@ -388,22 +423,41 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* l
       tile_store(Tt, i0, j0, N, N, [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true);
       return;
     }
-    MfmaTile Tm(threadIdx.x);
-    wide_sym_rows<true>(Tm, i0, j0, A, N, Vs + P.arena[v.s], [&](int k, int j) { return Z[k + (int64_t)j * A]; },
-                        sm);
     MfmaTile Tv(threadIdx.x);
     wide_sym_rows<true>(Tv, i0, j0, A, N, Va + r * upd + P.arena[v.s],
                         [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int gi = i0 + Tm.row_of(e), gj = j0 + Tm.col_of(e);
-      if (gi < A && gj < N) {
-        const double ma = Tm.get(e);
-        MA[gi + (int64_t)gj * A] = ma;
-        t[v.an(gi, gj)] = ma - Tv.get(e);
-      }
-    }
+    tile_store(
+        Tv, i0, j0, A, N, [&](int i, int j, double acc) { t[v.an(i, j)] = MA[i + (int64_t)j * A] - acc; }, false);
   });
+}
+
+// MA_r = V_s Z_r for every right-hand side r of every front of the segment
+// (blockIdx.y), 64-row tile x RhsCols column tile per workgroup.
+__global__ void __launch_bounds__(NT) k_wide_hdown_vz(DevPlan P, const int32_t* list, int count, int k, int ct_max,
+                                                      const double* Vs, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  const int f = blockIdx.y;
+  const int s = list[f];
+  const int N = P.ncol[s], A = P.nrow[s] - N;
+  const int ti = int(blockIdx.x) / ct_max, c = int(blockIdx.x) - ti * ct_max;
+  const RhsCols rc(N, k);
+  if (ti * WT >= A || c >= rc.ct) return;
+  const int i0 = ti * WT;
+  auto base = [&](int r) { return wsb + ((int64_t)r * count + f) * slot + (int64_t)N * N; };  // MA_r, then Z_r
+  MfmaTile T(threadIdx.x);
+  wide_sym_rows<true>(T, i0, 0, A, WT, Vs + P.arena[s],
+                      [&](int kk, int lc) {
+                        int r, j;
+                        return rc.map(c, lc, r, j) ? base(r)[(int64_t)A * N + kk + (int64_t)j * A] : 0.0;
+                      },
+                      sm);
+  tile_store(
+      T, i0, 0, A, WT,
+      [&](int i, int lc, double acc) {
+        int r, j;
+        if (rc.map(c, lc, r, j)) base(r)[i + (int64_t)j * A] = acc;
+      },
+      false);
 }
 
 __global__ void __launch_bounds__(NT) k_wide_hdown_c(DevPlan P, const int32_t* list, SegTiles tl, int count,
@@ -907,9 +961,8 @@ __global__ void __launch_bounds__(NT) k_fat_compl_lauum(DevPlan P, const int32_t
 //  1: Dm = C C^T (NN), MA = T_AN + V' L (AN);
 //  2: MN = T_NN + L^T MA + T_AN^T L (lower NN tiles, stored symmetric);
 //  3: W = MN Dm (NN), Z = MA Dm (AN);
-//  4: K_NN = Dm W (lower NN); K_AN = V^-1 Z (AN) with the explicit inverse,
-//     else MA <- C_V^-1 Z;
-//  5: K_AN = C_V^-T MA (AN; only when V_s is held as C_V^-1).
+//  4: K_NN = Dm W (lower NN tiles); the AN tiles and stage 5 run in
+//     k_fat_ihess_an with the right-hand sides batched.
 template <int STAGE>
 __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list, int count, const double* R,
                                                   const double* LB, const double* Vi, const double* Tin,
@@ -928,11 +981,9 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
     if (!nn) b -= d.tn * d.tn;
     const int ti = b / d.tn, tj = b - (b / d.tn) * d.tn;
     const int i0 = ti * WT, j0 = tj * WT;
-    const bool explicit_v = A <= kVExplicitMax;
     if (nn && tj > ti && (STAGE == 2 || STAGE == 4)) return;
     if (!nn && STAGE == 2) return;
-    if (nn && STAGE == 5) return;
-    if (STAGE == 5 && explicit_v) return;
+    if (!nn && STAGE == 4) return;  // k_fat_ihess_an<4>
     const double* t = Tin + r * P.nnz;
     double* K = Kt + r * P.nnz;
     double* MA = wsb + (r * count + f) * slot;
@@ -940,7 +991,6 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
     double* MN = Z + (int64_t)A * N;
     double* Dm = MN + (int64_t)N * N;
     double* W = Dm + (int64_t)N * N;
-    const double* VI = Vi + P.arena[v.s];
     MfmaTile T(threadIdx.x);
     if (STAGE == 1) {
       if (nn) {
@@ -975,32 +1025,85 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
                               [&](int k, int j) { return Dm[k + (int64_t)j * N]; }, sm);
         tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false);
       }
-    } else if (STAGE == 4) {
-      if (nn) {
-        tile_mma<false, true>(T, i0, j0, N, N, 0, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
-                              [&](int k, int j) { return W[k + (int64_t)j * N]; }, sm);
-        tile_store(T, i0, j0, N, N, [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true);
-      } else if (explicit_v) {
+    } else {
+      tile_mma<false, true>(T, i0, j0, N, N, 0, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
+                            [&](int k, int j) { return W[k + (int64_t)j * N]; }, sm);
+      tile_store(T, i0, j0, N, N, [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true);
+    }
+  });
+}
+
+// Stages 4 (AN tiles) and 5 of the fat inverse Hessian, right-hand sides
+// batched along the columns (RhsCols; the cached V_s^-1 or C_V^-1 is read
+// once per 64 columns): STAGE 4: K_AN = V_s^-1 Z with the explicit inverse,
+// else MA = C_V^-1 Z; STAGE 5: K_AN = C_V^-T MA (factored form only).
+// blockIdx.y: front of the segment; blockIdx.x: 64-row tile x column tile.
+template <int STAGE>
+__global__ void __launch_bounds__(NT) k_fat_ihess_an(DevPlan P, const int32_t* list, int count, int k, int ct_max,
+                                                     const double* Vi, double* Kt, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  const int f = blockIdx.y;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N, A = v.A;
+    const int ti = int(blockIdx.x) / ct_max, c = int(blockIdx.x) - ti * ct_max;
+    const RhsCols rc(N, k);
+    if (ti * WT >= A || c >= rc.ct) return;
+    const bool explicit_v = A <= kVExplicitMax;
+    if (STAGE == 5 && explicit_v) return;
+    const int i0 = ti * WT;
+    const double* VI = Vi + P.arena[v.s];
+    auto MA = [&](int r) { return wsb + ((int64_t)r * count + f) * slot; };  // then Z_r = MA_r + A N
+    MfmaTile T(threadIdx.x);
+    if (STAGE == 4) {
+      auto fz = [&](int kk, int lc) {
+        int r, j;
+        return rc.map(c, lc, r, j) ? MA(r)[(int64_t)A * N + kk + (int64_t)j * A] : 0.0;
+      };
+      if (explicit_v) {
         // V^-1 Z with every operand fetch along the tile's rows (this block
-        // is at most kVExplicitMax wide): the wide_sym_rows form, whose
-        // part above the diagonal block fetches along k, gave wrong
-        // results here for blocks of more than one row tile
+        // is at most kVExplicitMax wide): the wide_sym_rows form, whose part
+        // above the diagonal block fetches along k, gave wrong results here
+        // for blocks of more than one row tile
         const int d0 = min(i0, A), d1 = min(i0 + WT, A);
-        auto fz = [&](int k, int j) { return Z[k + (int64_t)j * A]; };
-        tile_mma<false, true>(T, i0, j0, A, N, 0, d0, [&](int i, int k) { return VI[pk(i, k, A)]; }, fz, sm);
-        tile_mma<false, true>(T, i0, j0, A, N, d0, d1, [&](int i, int k) { return sym_packed(VI, i, k, A); }, fz,
+        tile_mma<false, true>(T, i0, 0, A, WT, 0, d0, [&](int i, int kk) { return VI[pk(i, kk, A)]; }, fz, sm);
+        tile_mma<false, true>(T, i0, 0, A, WT, d0, d1, [&](int i, int kk) { return sym_packed(VI, i, kk, A); }, fz,
                               sm);
-        tile_mma<false, true>(T, i0, j0, A, N, d1, A, [&](int i, int k) { return VI[pk(k, i, A)]; }, fz, sm);
-        tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false);
+        tile_mma<false, true>(T, i0, 0, A, WT, d1, A, [&](int i, int kk) { return VI[pk(kk, i, A)]; }, fz, sm);
+        tile_store(
+            T, i0, 0, A, WT,
+            [&](int i, int lc, double acc) {
+              int r, j;
+              if (rc.map(c, lc, r, j)) Kt[(int64_t)r * P.nnz + v.an(i, j)] = acc;
+            },
+            false);
       } else {
-        tile_mma<false, true>(T, i0, j0, A, N, 0, min(A, i0 + WT), [&](int i, int k) {
-          return k <= i ? VI[pk(i, k, A)] : 0.0; }, [&](int k, int j) { return Z[k + (int64_t)j * A]; }, sm);
-        tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = acc; }, false);
+        tile_mma<false, true>(
+            T, i0, 0, A, WT, 0, min(A, i0 + WT), [&](int i, int kk) { return kk <= i ? VI[pk(i, kk, A)] : 0.0; }, fz,
+            sm);
+        tile_store(
+            T, i0, 0, A, WT,
+            [&](int i, int lc, double acc) {
+              int r, j;
+              if (rc.map(c, lc, r, j)) MA(r)[i + (int64_t)j * A] = acc;
+            },
+            false);
       }
     } else {
-      tile_mma<true, true>(T, i0, j0, A, N, i0, A, [&](int i, int k) { return k >= i ? VI[pk(k, i, A)] : 0.0; },
-                           [&](int k, int j) { return MA[k + (int64_t)j * A]; }, sm);
-      tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { K[v.an(i, j)] = acc; }, false);
+      tile_mma<true, true>(
+          T, i0, 0, A, WT, i0, A, [&](int i, int kk) { return kk >= i ? VI[pk(kk, i, A)] : 0.0; },
+          [&](int kk, int lc) {
+            int r, j;
+            return rc.map(c, lc, r, j) ? MA(r)[kk + (int64_t)j * A] : 0.0;
+          },
+          sm);
+      tile_store(
+          T, i0, 0, A, WT,
+          [&](int i, int lc, double acc) {
+            int r, j;
+            if (rc.map(c, lc, r, j)) Kt[(int64_t)r * P.nnz + v.an(i, j)] = acc;
+          },
+          false);
     }
   });
 }
@@ -1163,12 +1266,16 @@ void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, c
   k_wide_projinv_nn<<<dim3(unsigned(w.n_nn)), NT, 0, s>>>(P, list, w.nn, count, LB, S);
 }
 
-void launch_wide_hess_down(int k, hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w,
-                           int count, const double* LB, const double* Vs, const double* Kt, double* T, double* Va,
-                           int64_t upd, double* wsb, int64_t slot) {
+void launch_wide_hess_down(int k, int maxN, int maxA, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const WideTiles& w, int count, const double* LB, const double* Vs, const double* Kt,
+                           double* T, double* Va, int64_t upd, double* wsb, int64_t slot) {
   const SegTiles tl{w.aa, w.an, w.nn, w.n_aa, w.n_an, w.n_nn};
   k_wide_hdown_a<<<dim3(unsigned(w.n_aa + w.n_nn + w.n_an), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, Kt,
                                                                                        T, Va, upd, wsb, slot);
+  if (maxA > 0) {
+    const int ct = RhsCols(std::max(1, maxN), k).ct, ta = (maxA + WT - 1) / WT;
+    k_wide_hdown_vz<<<dim3(unsigned(ta * ct), unsigned(count)), NT, 0, s>>>(P, list, count, k, ct, Vs, wsb, slot);
+  }
   k_wide_hdown_b<<<dim3(unsigned(w.n_nn + w.n_an), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, Vs, T, Va,
                                                                               upd, wsb, slot);
   k_wide_hdown_c<<<dim3(unsigned(w.n_nn), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, T, wsb, slot);
@@ -1276,8 +1383,12 @@ void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, 
     k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
     k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
     k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
-    if (g.maxA > kVExplicitMax)
-      k_fat_ihess<5><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
+    if (g.maxA > 0) {
+      const int ct = RhsCols(std::max(1, g.maxN), kk).ct, ta = (g.maxA + WT - 1) / WT;
+      const dim3 gan(unsigned(ta * ct), unsigned(count));
+      k_fat_ihess_an<4><<<gan, NT, 0, s>>>(P, list, count, kk, ct, Vi, K, wsb, slot);
+      if (g.maxA > kVExplicitMax) k_fat_ihess_an<5><<<gan, NT, 0, s>>>(P, list, count, kk, ct, Vi, K, wsb, slot);
+    }
   }
 }
 
