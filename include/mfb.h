@@ -81,11 +81,14 @@ typedef struct mfb_factor_s* mfb_factor_t;
                                       launch (plans with more than 2^25 block
                                       entries never keep the map) */
 #define MFB_PLAN_WIDE_LOW 4u  /* run the tile-parallel wide-front kernels from
-                                 front order 65 instead of 513 (fronts with at
+                                 front order 65 instead of 193 (fronts with at
                                  most 64 columns and a nonempty ancestor set),
                                  and the tile-parallel factorization of the
-                                 blocks S_AA from order 193 instead of 513;
-                                 for testing those kernels on small patterns */
+                                 blocks S_AA from order 193 instead of 257;
+                                 for testing those kernels on small patterns.
+                                 Without it, the environment variables
+                                 MFB_WIDE_J and MFB_BIG_A, when set, replace
+                                 those two defaults (192, 256) at plan build */
 
 typedef struct {
   int64_t n;                 /* order of X */

@@ -114,11 +114,12 @@ void launch_fat_completion(const FatGrid& g, hipStream_t s, const DevPlan& P, co
                            const double* Sin, double* R, double* LB, double* S, const double* Vs, double* Vi,
                            double* part, DevStatus* st, double* wsb, int64_t slot);
 // Tile-parallel Cholesky factor (into Cb, packed like S_AA) and its inverse
-// (into Out) of the blocks S_AA with A > big_a of the listed fronts; rev:
-// on the reversed view, giving G (G^T G = S_AA) and G^-1.  Failures are
-// reported with `code`.
-void launch_bigv(bool rev, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
-                 const double* Vs, double* Cb, double* Out, DevStatus* st, int code);
+// (into Out) of the blocks S_AA with A > big_a of the listed fronts.  mode
+// 0: for the inverse Hessian, 1: for the completion (failures reported as
+// no completion), 2: for the Hessian factor, on the reversed view, giving
+// G (G^T G = S_AA) and G^-1.
+void launch_bigv(int mode, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
+                 const double* Vs, double* Cb, double* Out, DevStatus* st);
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                       const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
                       const double* Va, int64_t upd, double* wsb, int64_t slot);

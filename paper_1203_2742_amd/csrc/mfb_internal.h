@@ -92,7 +92,7 @@ constexpr int64_t kGatherMapMax = int64_t(1) << 25;
 // threshold, N <= kWideMaxN, A > 0).  Their A x A and A x N work runs
 // tile-parallel over all wide fronts of a level (wide.hip).
 constexpr int kWideMaxN = 64;
-constexpr int kWideJ = 512;     // default threshold on J
+constexpr int kWideJ = 192;     // default threshold on J (the largest register front)
 constexpr int kWideJLow = 64;   // with MFB_PLAN_WIDE_LOW
 constexpr int kWide = kRegClasses + 1;  // class value of a wide segment
 constexpr int kFat = kRegClasses + 2;   // class value of a segment of fat fronts
@@ -102,7 +102,7 @@ constexpr int kWideTile = 64;
 // per block column and row block over all such fronts (wide.hip, "bigv"),
 // for the inverse Hessian's and the Hessian factor's caches and in the
 // completion; smaller ones by one workgroup each.
-constexpr int kBigA = 512;
+constexpr int kBigA = 256;
 constexpr int kBigV = kRegClasses + 3;  // class value of the segment of those fronts
 
 // A level of a schedule split by class: at most three launches (groups of

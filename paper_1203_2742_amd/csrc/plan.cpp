@@ -6,6 +6,7 @@
 // representative vertices, eq. e-repr-test), 6.2 (supernode partitions,
 // eq. e-new2), 6.3 (clique trees) and Algorithm 6.1 of the paper.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "mfb_internal.h"
@@ -263,6 +264,13 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   // (never below kVExplicitMax: the tile-parallel path leaves C_V^-1, the
   // representation of the larger blocks)
   p->big_a = (flags & MFB_PLAN_WIDE_LOW) ? kVExplicitMax : kBigA;
+  // tuning overrides of the two default thresholds (front order above
+  // which fronts run tile-parallel; ancestor count above which S_AA is
+  // factored tile-parallel), read when the plan is built
+  if (!(flags & MFB_PLAN_WIDE_LOW)) {
+    if (const char* e = std::getenv("MFB_WIDE_J")) p->wide_thr = std::max(kWideJLow, std::atoi(e));
+    if (const char* e = std::getenv("MFB_BIG_A")) p->big_a = std::max(kVExplicitMax, std::atoi(e));
+  }
   // every front above the threshold is wide in the root-to-leaf sweeps; in
   // the leaf-to-root ones those with at most kWideMaxN columns (and an
   // update block) are wide and the others fat

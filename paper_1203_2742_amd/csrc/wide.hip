@@ -1120,10 +1120,13 @@ __global__ void __launch_bounds__(NT) k_fat_ihess_an(DevPlan P, const int32_t* l
 //  panel: its row tiles below, C_ik = (V_ik - C_i,<k C_k,<k^T) C_kk^-T;
 //  trtri: row block ib of X = C^-1 from the rows above it,
 //         X_ib,jb = -X_ib,ib sum_{jb <= m < ib} C_ib,m X_m,jb.
-// REV runs all of it on the reversed view of the packed blocks (entry
-// (i, j) of the view at the packed position of (A-1-j, A-1-i)): then Cb
-// ends up holding G with G^T G = V (G = P F^T P for P V P = F F^T) and Out
-// holds G^-1, the Hessian factor's pair.  Fronts with A <= big_a exit, so
+// MODE names the caller (0: the inverse Hessian's cache, 1: the
+// completion, 2: the Hessian factor); MODE 2 runs all of it on the
+// reversed view of the packed blocks (entry (i, j) of the view at the
+// packed position of (A-1-j, A-1-i)): then Cb ends up holding G with
+// G^T G = V (G = P F^T P for P V P = F F^T) and Out holds G^-1, the
+// Hessian factor's pair.  Failures are reported as MFB_ENOCOMPLETION in
+// the completion, MFB_ENOTPD otherwise.  Fronts with A <= big_a exit, so
 // a mixed list (the completion's) needs no split.
 template <bool REV>
 struct PView {
@@ -1134,6 +1137,7 @@ struct PView {
   }
 };
 
+template <int MODE>
 __global__ void __launch_bounds__(NT) k_bigv_copy(DevPlan P, const int32_t* list, const double* Vs, double* Cb) {
   const int s = list[blockIdx.y];
   const int A = P.nrow[s] - P.ncol[s];
@@ -1143,9 +1147,10 @@ __global__ void __launch_bounds__(NT) k_bigv_copy(DevPlan P, const int32_t* list
     Cb[off + e] = Vs[off + e];
 }
 
-template <bool REV>
+template <int MODE>
 __global__ void __launch_bounds__(NT) k_bigv_diag(DevPlan P, const int32_t* list, int kb, double* Cb, double* Out,
-                                                  DevStatus* st, int code) {
+                                                  DevStatus* st) {
+  constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ double d64[NB2 * LD2];
   __shared__ int fail;
@@ -1174,12 +1179,13 @@ __global__ void __launch_bounds__(NT) k_bigv_diag(DevPlan P, const int32_t* list
     const int i = e % nb, j = e / nb;
     if (i >= j) X(kb + i, kb + j) = d64[i + j * LD2];
   }
-  if (threadIdx.x == 0 && fail >= 0) report(st, code, P.vlabel[P.colbase[s]]);
+  if (threadIdx.x == 0 && fail >= 0) report(st, MODE == 1 ? MFB_ENOCOMPLETION : MFB_ENOTPD, P.vlabel[P.colbase[s]]);
 }
 
-template <bool REV>
+template <int MODE>
 __global__ void __launch_bounds__(NT) k_bigv_panel(DevPlan P, const int32_t* list, int kb, double* Cb,
                                                    const double* Out) {
+  constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ double rb[WT * WLD];
   const int s = list[blockIdx.y];
@@ -1204,9 +1210,10 @@ __global__ void __launch_bounds__(NT) k_bigv_panel(DevPlan P, const int32_t* lis
   tile_store(T2, 0, 0, min(WT, A - i0), nb, [&](int i, int j, double acc) { F(i0 + i, kb + j) = acc; }, false);
 }
 
-template <bool REV>
+template <int MODE>
 __global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* list, int ib, const double* Cb,
                                                    double* Out) {
+  constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ double rb[WT * WLD];
   const int s = list[blockIdx.y];
@@ -1341,30 +1348,31 @@ void launch_fat_up_fin(int op, const FatGrid& g, int k, hipStream_t s, const Dev
     k_fat_up_fin<FAT_IHUP><<<grid, NT, 0, s>>>(P, list, count, R, LB, Out, Kt, wsb, slot);
 }
 
-void launch_bigv(bool rev, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
-                 const double* Vs, double* Cb, double* Out, DevStatus* st, int code) {
-  if (count == 0 || maxA <= P.big_a) return;
+template <int MODE>
+static void bigv_launches(int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Vs,
+                          double* Cb, double* Out, DevStatus* st) {
   const unsigned c = unsigned(count);
   const int64_t m = (int64_t)maxA * (maxA + 1) / 2;
-  k_bigv_copy<<<dim3(unsigned(std::min<int64_t>(64, (m + NT * 16 - 1) / (NT * 16))), c), NT, 0, s>>>(P, list, Vs,
+  k_bigv_copy<MODE><<<dim3(unsigned(std::min<int64_t>(64, (m + NT * 16 - 1) / (NT * 16))), c), NT, 0, s>>>(P, list, Vs,
                                                                                                      Cb);
-  const int ta = (maxA + WT - 1) / WT;
   for (int kb = 0; kb < maxA; kb += WT) {
     const int rows = (maxA - kb - 1) / WT;  // row tiles below the diagonal block (largest front)
-    if (rev) {
-      k_bigv_diag<true><<<dim3(1, c), NT, 0, s>>>(P, list, kb, Cb, Out, st, code);
-      if (rows > 0) k_bigv_panel<true><<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, kb, Cb, Out);
-    } else {
-      k_bigv_diag<false><<<dim3(1, c), NT, 0, s>>>(P, list, kb, Cb, Out, st, code);
-      if (rows > 0) k_bigv_panel<false><<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, kb, Cb, Out);
-    }
+    k_bigv_diag<MODE><<<dim3(1, c), NT, 0, s>>>(P, list, kb, Cb, Out, st);
+    if (rows > 0) k_bigv_panel<MODE><<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, kb, Cb, Out);
   }
-  for (int ib = 1; ib < ta; ++ib) {
-    if (rev)
-      k_bigv_trtri<true><<<dim3(unsigned(ib), c), NT, 0, s>>>(P, list, ib, Cb, Out);
-    else
-      k_bigv_trtri<false><<<dim3(unsigned(ib), c), NT, 0, s>>>(P, list, ib, Cb, Out);
-  }
+  const int ta = (maxA + WT - 1) / WT;
+  for (int ib = 1; ib < ta; ++ib) k_bigv_trtri<MODE><<<dim3(unsigned(ib), c), NT, 0, s>>>(P, list, ib, Cb, Out);
+}
+
+void launch_bigv(int mode, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
+                 const double* Vs, double* Cb, double* Out, DevStatus* st) {
+  if (count == 0 || maxA <= P.big_a) return;
+  if (mode == 0)
+    bigv_launches<0>(maxA, count, s, P, list, Vs, Cb, Out, st);
+  else if (mode == 1)
+    bigv_launches<1>(maxA, count, s, P, list, Vs, Cb, Out, st);
+  else
+    bigv_launches<2>(maxA, count, s, P, list, Vs, Cb, Out, st);
 }
 
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,

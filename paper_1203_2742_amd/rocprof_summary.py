@@ -45,6 +45,7 @@ OP_OF = [
     (r"^k_completion", "completion"), (r"^k_gather_map<2>", "completion"),
     (r"^k_wide_extract<2>", "completion"), (r"^k_fat_compl", "completion"),
     (r"^k_fat_(potrf_diag|potrf_panel|potrf_trail|trtri_row)<1>", "completion"),
+    (r"^k_bigv_\w+<0>", "inv_hessian"), (r"^k_bigv_\w+<1>", "completion"), (r"^k_bigv_\w+<2>", "hessian_factor"),
     (r"^k_gamma", "hessian_factor"), (r"^k_hfactor_adj", "hessian_factor_adj"), (r"^k_hfactor", "hessian_factor"),
     (r"^k_gram", "gram"),
     (r"^k_logdet", "logdet (2 calls)"), (r"^k_reset_status", "status reset"),

@@ -383,7 +383,7 @@ def test_ill_conditioned(name, delta, mfb):
 
 
 WIDE_CASES = [
-    # name, plan flags: 0 = default wide threshold (front order above 512)
+    # name, plan flags: 0 = default wide threshold (front order above 192)
     ("chordal150", "low"),
     # fronts of more than 64 columns ("fat": the panel work tile-parallel
     # too), among them roots and a 528-column dense front
