@@ -49,7 +49,7 @@ OPS = ("factor", "logdet", "projected_inverse", "hessian", "inv_hessian", "compl
 KERNEL_OP = {"k_factor": "factor", "k_projinv": "projected_inverse", "k_hess_up": "hessian",
              "k_hess_down": "hessian", "k_ihess_down": "inv_hessian", "k_ihess_up": "inv_hessian",
              "k_vinv": "inv_hessian", "k_gather": None, "k_completion": "completion",
-             "k_product": "cholesky_product"}
+             "k_product": "cholesky_product", "k_bigv": "completion"}
 
 
 def kernel_source_hash() -> str:

@@ -294,7 +294,9 @@ const char* mfb_strerror(mfb_status_t s);
 #define MFB_K_HFACTOR 11     /* step-1 output to W = R(Y), Algorithm 5.3 */
 #define MFB_K_HFACTOR_ADJ 12 /* W to the step-2 input of the Hessian's root-to-leaf sweep,
                                 Algorithm 5.4 */
-#define MFB_K_COUNT 13
+#define MFB_K_COMPL_SAA 13   /* the completion's tile-parallel factorization of the blocks
+                                S_AA above the plan's size threshold (profile name "k_bigv") */
+#define MFB_K_COUNT 14
 
 typedef struct {
   int32_t kernel;   /* MFB_K_* */

@@ -323,6 +323,7 @@ static void canonical(int kid, const Level& L, int k, double* bytes, double* flo
     case MFB_K_GAMMA: b = 3 * u; fl = 2 * L.a3 / 3; break;
     case MFB_K_HFACTOR: b = p + u + K * 2 * p; fl = K * (7 * L.n3 / 3 + 2 * L.n2a + L.na2); break;
     case MFB_K_HFACTOR_ADJ: b = p + u + K * 2 * p; fl = K * (2 * L.n3 + 2 * L.n2a + L.na2); break;
+    case MFB_K_COMPL_SAA: b = 2 * u; fl = L.a3 / 3; break;
   }
   *bytes = 8 * b;
   *flops = fl;
@@ -376,13 +377,13 @@ static mfb_status_t run_levels(mfb_factor_s* f, int kid, const std::vector<Level
 typedef void (*SegLaunch)(mfb_factor_s*, const ClassSched&, const ClassSeg&, dim3, hipStream_t, int64_t,
                           void*);
 static mfb_status_t run_classes(mfb_factor_s* f, int kid, const ClassSched& cs, hipStream_t s, int k,
-                                Op op, SegLaunch launch, void* ctx, bool canon = true) {
+                                Op op, SegLaunch launch, void* ctx) {
   for (const ClassSeg& g : cs.segs) {
     const Level& L = g.lv;
     dim3 grid(unsigned(L.count), unsigned(k));
     ProfRec rec{kid, g.level, L.count, k, 0.0, 0.0, nullptr, nullptr};
     if (f->prof) {
-      if (canon) canonical(kid, L, k, &rec.bytes, &rec.flops);  // else time only
+      canonical(kid, L, k, &rec.bytes, &rec.flops);
       rec.e0 = pool_event(f);
       rec.e1 = pool_event(f);
       if (!rec.e0 || !rec.e1) return MFB_EHIP;
@@ -912,16 +913,15 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   mfb_status_t st = gather_blocks(f, s, 1, sin, f->Vs, 0, 0, 2);
   if (st) return st;
   // the blocks S_AA with A > big_a: Cholesky factor (formed in U) and its
-  // inverse C_V^-1 into Vi, tile-parallel over all those fronts (recorded
-  // with time only: the completion's canonical counts are in its per-front
-  // launches)
+  // inverse C_V^-1 into Vi, tile-parallel over all those fronts (their
+  // A^3/3 is counted here, not in the per-front launches that follow)
   st = run_classes(
-      f, MFB_K_COMPLETION, f->plan->cs_bigv, s, 1, OP_VINV,
+      f, MFB_K_COMPL_SAA, f->plan->cs_bigv, s, 1, OP_VINV,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3, hipStream_t s, int64_t, void*) {
         launch_bigv(1, sg.lv.maxA, sg.lv.count, s, f->plan->dev, cs.d_list + sg.lv.begin, f->Vs, f->U, f->Vi,
                     f->st);
       },
-      nullptr, false);
+      nullptr);
   if (st) return st;
   st = run_classes(
       f, MFB_K_COMPLETION, f->plan->cs_compl_flat, s, 1, OP_COMPLETION,
@@ -1037,7 +1037,7 @@ const char* mfb_kernel_name(int32_t kernel) {
   static const char* names[MFB_K_COUNT] = {"k_factor", "k_projinv", "k_hess_up", "k_hess_down",
                                            "k_ihess_down", "k_ihess_up", "k_completion", "k_vinv",
                                            "k_product", "k_gather", "k_gamma", "k_hfactor",
-                                           "k_hfactor_adj"};
+                                           "k_hfactor_adj", "k_bigv"};
   return (kernel >= 0 && kernel < MFB_K_COUNT) ? names[kernel] : "unknown";
 }
 

@@ -474,6 +474,14 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
   // which a gather pass puts in place beforehand.
   make_flat(true, OP_VINV, p->cs_vinv);
   make_flat(false, OP_COMPLETION, p->cs_compl_flat);
+  // the A^3 of the completion's fronts with A > big_a belongs to the
+  // tile-parallel factorization that precedes its per-front launches
+  for (ClassSeg& g : p->cs_compl_flat.segs)
+    for (int32_t t = g.lv.begin; t < g.lv.begin + g.lv.count; ++t) {
+      const int32_t k = p->cs_compl_flat.list[t];
+      const double An = p->J[k] - p->N[k];
+      if (An > p->big_a) g.lv.a3 -= An * An * An;
+    }
   // the completion factors the blocks S_AA with A > big_a tile-parallel
   // before its per-front launches: the inverse's segment of those fronts
   {

@@ -260,6 +260,52 @@ __device__ __forceinline__ void wide_sym_rows(MfmaTile& T, int i0, int j0, int A
   tile_mma<true, BK>(T, i0, j0, A, N, d1, A, hi, fb, sm);
 }
 
+// C(i, j) = sum_{k < K} a(k, i) b(k, j) for the lower triangle of a small
+// N x N result (N <= SMALL_N), on the vector units: the workgroup strides
+// over k (consecutive threads, consecutive k), each thread keeps the
+// N(N+1)/2 partial sums, then one fixed-order reduction (a butterfly in
+// each wavefront, then the wavefronts in order through LDS).  For the
+// N x N products with a long k range (2A) of fronts with few columns,
+// where a 64 x 64 matrix-core tile would be mostly empty.  epi(i, j, c)
+// is called once per lower entry, by one thread.
+constexpr int SMALL_N = 8;
+template <class FA, class FB, class EPI>
+__device__ __forceinline__ void small_nn_dot(int N, int K, const FA& fa, const FB& fb, const EPI& epi, double* sm) {
+  constexpr int NP = SMALL_N * (SMALL_N + 1) / 2;
+  double acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
+  for (int k = threadIdx.x; k < K; k += NT) {
+    double a[SMALL_N], b[SMALL_N];
+#pragma unroll
+    for (int i = 0; i < SMALL_N; ++i) {
+      a[i] = i < N ? fa(k, i) : 0.0;
+      b[i] = i < N ? fb(k, i) : 0.0;
+    }
+    int p = 0;
+#pragma unroll
+    for (int i = 0; i < SMALL_N; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) acc[p++] += a[i] * b[j];
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    double v = acc[p];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (l == 0) sm[w * NP + p] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NP) {
+    const int p = threadIdx.x;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= p) ++i;
+    const int j = p - i * (i + 1) / 2;
+    if (i < N) epi(i, j, ((sm[p] + sm[NP + p]) + sm[2 * NP + p]) + sm[3 * NP + p]);
+  }
+  __syncthreads();
+}
+
 // Right-hand sides batched along the columns of a product whose left
 // operand (a packed A x A block shared by all right-hand sides) is the
 // expensive read: column tile c of a front with N columns covers, when
@@ -476,6 +522,13 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_c(DevPlan P, const int32_t* l
     double* t = T + r * P.nnz;
     const double* MN = wsb + (r * count + f) * slot;
     const double* MA = MN + (int64_t)N * N;
+    if (N <= SMALL_N) {
+      small_nn_dot(
+          N, 2 * A, [&](int k, int i) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
+          [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
+          [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; }, sm);
+      return;
+    }
     MfmaTile Tt(threadIdx.x);
     tile_mma<true, true>(
         Tt, i0, j0, N, N, 0, 2 * A,
@@ -1003,6 +1056,16 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
         tile_store(T, i0, j0, A, N,
                    [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false);
       }
+    } else if (STAGE == 2 && N <= SMALL_N) {
+      small_nn_dot(
+          N, 2 * A, [&](int k, int i) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
+          [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
+          [&](int i, int j, double acc) {
+            const double m = t[v.at(i, j)] + acc;
+            MN[i + (int64_t)j * N] = m;
+            MN[j + (int64_t)i * N] = m;
+          },
+          sm);
     } else if (STAGE == 2) {
       tile_mma<true, true>(
           T, i0, j0, N, N, 0, 2 * A, [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },

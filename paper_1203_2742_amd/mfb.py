@@ -45,7 +45,8 @@ class MfbError(RuntimeError):
 
 
 KERNELS = ("k_factor", "k_projinv", "k_hess_up", "k_hess_down", "k_ihess_down", "k_ihess_up",
-           "k_completion", "k_vinv", "k_product", "k_gather", "k_gamma", "k_hfactor", "k_hfactor_adj")
+           "k_completion", "k_vinv", "k_product", "k_gather", "k_gamma", "k_hfactor", "k_hfactor_adj",
+           "k_bigv")
 
 
 class ProfileEntry(ctypes.Structure):
