@@ -58,7 +58,7 @@ static size_t factor_bytes(const mfb_plan_s* p) {
 }
 static size_t rhs_bytes(const mfb_plan_s* p) {
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
-  return (upd + nnz + size_t(rhs_scratch(p))) * 8 + 3 * ALIGN;
+  return (upd + nnz + size_t(rhs_scratch(p)) + size_t(p->part_doubles)) * 8 + 4 * ALIGN;
 }
 }  // namespace mfb
 
@@ -97,7 +97,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
          iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre), iGl = v32(p->cs_gather.list),
          iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre), iPx = v32(p->cs_compl_flat.pre),
-         iHf = v32(p->cs_hfac.list), iBv = v32(p->cs_bigv.list);
+         iHf = v32(p->cs_hfac.list), iBv = v32(p->cs_bigv.list), iPo = v64(p->poff);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -123,6 +123,7 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   P.arena = (const int64_t*)at(iAr);
   P.vlabel = (const int32_t*)at(iVl);
   P.big_a = p->big_a;
+  P.poff = (const int64_t*)at(iPo);
   p->d_up_list = (const int32_t*)at(iUp);
   p->d_down_list = (const int32_t*)at(iDn);
   p->d_all_list = (const int32_t*)at(iAll);
@@ -414,10 +415,11 @@ static FatGrid fat_grid(const ClassSeg& g) {
 // inverse Hessian, k right-hand sides) into `arena`: one elementwise launch
 // with the plan's source map, else level by level from the parents.
 static mfb_status_t gather_blocks(mfb_factor_s* f, hipStream_t s, int k, const double* src, double* arena,
-                                  int64_t src_stride, int64_t arena_stride, int tag) {
+                                  int64_t src_stride, int64_t arena_stride, int tag, double* part = nullptr,
+                                  int64_t pstride = 0) {
   const mfb_plan_s* p = f->plan;
-  struct Ctx { const double* src; double* arena; int64_t ss, as; int tag; } ctx{src, arena, src_stride,
-                                                                              arena_stride, tag};
+  struct Ctx { const double* src; double* arena; int64_t ss, as; int tag; double* part; int64_t ps; } ctx{
+      src, arena, src_stride, arena_stride, tag, part, pstride};
   if (p->d_gmap) {
     return run_levels(
         f, MFB_K_GATHER_V, p->all_levels, p->d_all_list, s, k, OP_COMPLETION,
@@ -438,7 +440,8 @@ static mfb_status_t gather_blocks(mfb_factor_s* f, hipStream_t s, int k, const d
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t, void* c) {
         Ctx* x = (Ctx*)c;
         launch_wide_extract(x->tag, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, cs.d_list + sg.lv.begin,
-                            cs.d_pre + sg.aa_off, sg.lv.count, x->src, x->arena, x->ss, x->as);
+                            cs.d_pre + sg.aa_off, sg.lv.count, x->src, x->arena, x->ss, x->as, f->LB, x->part,
+                            x->ps);
       },
       &ctx);
 }
@@ -525,8 +528,8 @@ mfb_status_t mfb_projected_inverse(mfb_factor_t f, double* s_out, void* stream) 
 }
 
 struct RhsArena {
-  double *Ua, *Kt, *scr;
-  int64_t upd;
+  double *Ua, *Kt, *scr, *part;
+  int64_t upd, pstride;  // pstride: doubles of the partial area per RHS
 };
 static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, RhsArena* a) {
   const mfb_plan_s* p = f->plan;
@@ -539,6 +542,9 @@ static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, Rhs
   c += up(size_t(k) * upd * 8);
   a->Kt = (double*)c;
   c += up(size_t(k) * nnz * 8);
+  a->pstride = p->part_doubles;
+  a->part = (double*)c;
+  c += up(size_t(k) * size_t(std::max<int64_t>(1, p->part_doubles)) * 8);
   a->scr = (double*)c;
   return MFB_OK;
 }
@@ -621,8 +627,8 @@ static mfb_status_t hess_down_run(mfb_factor_s* f, int32_t k, double* t, const R
                                x->a.upd, x->a.scr, slot);
         else if (cls == kWide)
           launch_wide_hess_down(int(g.y), sg.lv.maxN, sg.lv.maxA, s, f->plan->dev, list, wide_tiles(cs, sg),
-                                sg.lv.count, f->LB, f->Vs,
-                                x->a.Kt, x->t, x->a.Ua, x->a.upd, x->a.scr, slot);
+                                sg.lv.count, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua, x->a.upd, x->a.scr, slot,
+                                x->a.part, x->a.pstride);
         else
           k_hess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->LB, f->Vs, x->a.Kt, x->t, x->a.Ua,
                                               x->a.upd, x->a.scr, slot);
@@ -823,7 +829,9 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
   // V'_s = T_{A_s A_s} for every supernode and right-hand side (root-to-leaf
   // gathers), then steps 1+2 of all fronts, which are independent
-  st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd, 1);
+  // (without the source map the level gathers also leave the partial
+  // products T_AA L of the fronts that have a partial area)
+  st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd, 1, a.part, a.pstride);
   if (st) return st;
   if (f->plan->ihd_root >= 0) {
     // the root front: three tile-parallel products (steps 1+2 with A = 0)
@@ -861,7 +869,8 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
                                 x->a.Ua, x->a.upd, x->a.scr, slot);
         else if (cls == kFat)
           launch_fat_ihess(fat_grid(sg), int(g.y), s, f->plan->dev, list, sg.lv.count, f->R, f->LB, f->Vi, x->t,
-                           x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+                           x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, f->plan->d_gmap ? nullptr : x->a.part,
+                           x->a.pstride);
         else
           k_ihess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
                                                x->a.Ua, x->a.upd, x->a.scr, slot);

@@ -87,14 +87,17 @@ void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, cons
                         const int32_t* pre, int count, const double* R, const double* LB, const double* Kt,
                         double* Ua, int64_t upd, const double* wsb, int64_t slot);
 // tag (profile attribution): 1 inverse Hessian gather, 2 completion gather
+// tag 1 (the inverse Hessian's gather) with part: also the partial
+// products of T_AA L_AN of the fronts that have a partial area
 void launch_wide_extract(int tag, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                          const int32_t* pre, int count, const double* src, double* arena, int64_t src_stride,
-                         int64_t arena_stride);
+                         int64_t arena_stride, const double* LB, double* part, int64_t pstride);
 void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w, int count,
                          const double* LB, double* S, double* Vs);
 void launch_wide_hess_down(int k, int maxN, int maxA, hipStream_t s, const DevPlan& P, const int32_t* list,
                            const WideTiles& w, int count, const double* LB, const double* Vs, const double* Kt,
-                           double* T, double* Va, int64_t upd, double* wsb, int64_t slot);
+                           double* T, double* Va, int64_t upd, double* wsb, int64_t slot, double* part,
+                           int64_t pstride);
 // Fat fronts (more than kWideMaxN columns): grids sized by the segment's
 // largest front; `panel` = tiles of the J x N panel, `fin` = NN plus AN
 // tiles.  Panel op: 0 factor (source X), 1 Hessian step 1 (source Y),
@@ -120,9 +123,12 @@ void launch_fat_completion(const FatGrid& g, hipStream_t s, const DevPlan& P, co
 // G (G^T G = S_AA) and G^-1.
 void launch_bigv(int mode, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
                  const double* Vs, double* Cb, double* Out, DevStatus* st);
+// part: the gather's partial products of T_AA L (nullptr when the gather
+// took the source map), per-RHS stride pstride
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                       const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
-                      const double* Va, int64_t upd, double* wsb, int64_t slot);
+                      const double* Va, int64_t upd, double* wsb, int64_t slot, const double* part,
+                      int64_t pstride);
 
 // Hessian factor (hfactor.hip): per supernode with A > 0 the lower G with
 // G^T G = S_AA and G^-1, packed like S_AA (one workgroup per supernode);

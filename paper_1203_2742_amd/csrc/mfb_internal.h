@@ -34,6 +34,7 @@ struct DevPlan {
   const int64_t* arena;
   const int32_t* vlabel;    // user label of the c-th column: vlabel[colbase[s] + c]
   int32_t big_a;            // S_AA blocks with A > big_a are factored tile-parallel
+  const int64_t* poff;      // offset of the front's partial products V' L, or -1 (kPartN)
 };
 
 struct Level {
@@ -104,6 +105,13 @@ constexpr int kWideTile = 64;
 // completion; smaller ones by one workgroup each.
 constexpr int kBigA = 256;
 constexpr int kBigV = kRegClasses + 3;  // class value of the segment of those fronts
+// Wide fronts with at most kPartN columns form the product V' L of the
+// root-to-leaf sweeps (V' = the extracted block: V'_s of the Hessian, T_AA
+// of the inverse Hessian) from partial products taken while each 64 x 64
+// tile of V' is extracted, so V' is not read back: per lower tile (ti, tj)
+// the 64 x N blocks V'_{ti,tj} L_tj and V'_{ti,tj}^T L_ti (strictly lower
+// entries only on the diagonal tile), in a per-RHS area at poff[s].
+constexpr int kPartN = 4;
 
 // A level of a schedule split by class: at most three launches (groups of
 // launches for the wide fronts), the wide fronts (cls == kWide), the
@@ -142,6 +150,11 @@ struct mfb_plan_s {
   int32_t big_a = mfb::kBigA;      // tile-parallel S_AA factorization: A > big_a (see kBigA)
   std::vector<int32_t> N, J, parent, cptr, cidx, colbase, relbase, rel, rep, vlabel, snode_of;
   std::vector<int64_t> col, arena;
+  // per supernode: offset of its partial products in the per-RHS partial
+  // area, or -1 (wide fronts with at most kPartN columns, A > 0), and the
+  // area's size in doubles
+  std::vector<int64_t> poff;
+  int64_t part_doubles = 0;
   int64_t update_doubles = 0;
   int32_t max_front = 0, max_ncols = 0, max_nanc = 0;
   // leaf-to-root schedule: levels by height; root-to-leaf: by depth

@@ -680,6 +680,17 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     }
   }
 
+  // Partial-product offsets of the wide fronts with at most kPartN columns.
+  p->poff.assign(size_t(ns), -1);
+  p->part_doubles = 0;
+  for (int32_t k = 0; k < ns; ++k) {
+    const int32_t A = p->J[k] - p->N[k];
+    if (!is_wide(k) || p->N[k] > kPartN || A == 0) continue;
+    const int64_t ta = (A + kWideTile - 1) / kWideTile;
+    p->poff[size_t(k)] = p->part_doubles;
+    p->part_doubles += ta * (ta + 1) * kWideTile * p->N[k];
+  }
+
   // Canonical algorithmic flop counts per supernode (LAPACK conventions).
   for (int32_t k = 0; k < ns; ++k) {
     const double Nn = p->N[k], An = p->J[k] - p->N[k];

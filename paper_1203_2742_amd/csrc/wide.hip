@@ -179,8 +179,31 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
 // Parent extraction of one lower 64 x 64 tile (ti, tj) of the packed block
 // V_s = E^T [S_NN S_AN^T; S_AN V_p] E (eq. e-sn-gradient-2), from the
 // parent's CCS columns of `src` and its packed block in `arena`.
+// Sum over the partial products of row tile ti (front with ta row tiles,
+// N <= kPartN columns, partial area pb): entry (row, n) of the row block ti
+// of V' L, in a fixed order (tiles (ti, J) for J <= ti, then (J, ti) for
+// J >= ti, J ascending, each tile's two blocks in that order).
+__device__ __forceinline__ double sum_partials(const double* pb, int ta, int ti, int N, int row, int n) {
+  double acc = 0.0;
+  const int64_t blk = (int64_t)WT * N;
+  for (int J = 0; J < ta; ++J) {
+    if (J <= ti) acc += pb[(int64_t)(ti * (ti + 1) / 2 + J) * 2 * blk + row + WT * n];
+    if (J >= ti) acc += pb[(int64_t)(J * (J + 1) / 2 + ti) * 2 * blk + blk + row + WT * n];
+  }
+  return acc;
+}
+
+// Tile (ti, tj) of the extraction V'_s = E^T [.] E (eq. e-sn-gradient-2 and
+// its Hessian counterparts) from the parent's CCS columns of src and its
+// block in arena.  With pbase (a wide front with N <= kPartN columns; ps:
+// 6 * 64 * kPartN doubles of LDS), also the tile's partial products with
+// L = L_AN (taken from LB): P1 = V'_{ti,tj} L_tj and P2 = V'_{ti,tj}^T L_ti
+// (strictly lower entries on a diagonal tile), 64 x N each, at pbase +
+// l * 128 N, l = ti (ti + 1) / 2 + tj.  Ends with a barrier.
 __device__ __forceinline__ void wide_extract_tile(const DevPlan& P, int s, int ti, int tj, const double* src,
-                                                  double* arena, int* rr, int* rc, int64_t* cpc) {
+                                                  double* arena, int* rr, int* rc, int64_t* cpc,
+                                                  const double* LB = nullptr, double* pbase = nullptr,
+                                                  double* ps = nullptr) {
   const int N = P.ncol[s], A = P.nrow[s] - N;
   const int p = P.parent[s];
   const int Np = P.ncol[p], Ap = P.nrow[p] - Np;
@@ -215,23 +238,65 @@ __device__ __forceinline__ void wide_extract_tile(const DevPlan& P, int s, int t
     const int gj = j0 + cq + 4 * q;
     if (gi < A && gj < A && gi >= gj) Vo[pk(gi, gj, A)] = val[q];
   }
+  if (!pbase) return;  // (uniform: a property of the front)
+  const int64_t* cols = P.col + P.colbase[s];
+  double* Lr = ps;                   // L rows i0 .. i0 + 63: Lr[x + 64 n]
+  double* Lc = ps + WT * kPartN;     // L rows j0 .. j0 + 63
+  double* red = ps + 2 * WT * kPartN;  // P1 per wavefront: red[(w kPartN + n) 64 + row]
+  for (int e = tid; e < 2 * WT * N; e += NT) {
+    const int which = e / (WT * N), rem = e - which * WT * N, x = rem % WT, n = rem / WT;
+    const int gx = (which ? j0 : i0) + x;
+    (which ? Lc : Lr)[x + WT * n] = gx < A ? LB[cols[n] + N + gx - n] : 0.0;
+  }
+  __syncthreads();
+  double* out = pbase + (int64_t)(ti * (ti + 1) / 2 + tj) * 2 * WT * N;
+  for (int n = 0; n < N; ++n) {
+    double a1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = cq + 4 * q, gj = j0 + j;
+      if (gi < A && gj < A && gi >= gj) a1 += val[q] * Lc[j + WT * n];
+    }
+    red[(cq * kPartN + n) * WT + row] = a1;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = cq + 4 * q, gj = j0 + j;
+      double a2 = (gi < A && gj < A && (ti != tj ? gi >= gj : gi > gj)) ? val[q] * Lr[row + WT * n] : 0.0;
+      for (int o = 32; o > 0; o >>= 1) a2 += __shfl_xor(a2, o);
+      if (row == 0) out[(int64_t)WT * N + j + WT * n] = a2;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < WT * N; e += NT) {
+    const int x = e % WT, n = e / WT;
+    out[x + WT * n] = ((red[(0 * kPartN + n) * WT + x] + red[(1 * kPartN + n) * WT + x]) +
+                       red[(2 * kPartN + n) * WT + x]) +
+                      red[(3 * kPartN + n) * WT + x];
+  }
+  __syncthreads();
 }
 
 // Tiles of the extraction over the segment (blockIdx.y: right-hand side,
 // with its own source array and arena at the given strides).  TAG only
 // names the caller in profiles: 0 the projected inverse, 1 the gather of
 // T_AA for the inverse Hessian, 2 the gather of S_AA for the completion.
+// TAG 1 also takes the partial products of T_AA L for the fronts with
+// partial areas when part is given (stride pstride per RHS).
 template <int TAG>
 __global__ void __launch_bounds__(NT) k_wide_extract(DevPlan P, const int32_t* list, const int32_t* pre,
                                                      int count, const double* src, double* arena,
-                                                     int64_t src_stride, int64_t arena_stride) {
+                                                     int64_t src_stride, int64_t arena_stride, const double* LB,
+                                                     double* part, int64_t pstride) {
   __shared__ int rr[WT], rc[WT];
   __shared__ int64_t cpc[WT];
+  __shared__ double ps[TAG == 1 ? 6 * WT * kPartN : 1];
   const int f = seg_front(pre, count, blockIdx.x);
   int ti, tj;
   tri_tile(blockIdx.x - pre[f], ti, tj);
   const int64_t r = blockIdx.y;
-  wide_extract_tile(P, list[f], ti, tj, src + r * src_stride, arena + r * arena_stride, rr, rc, cpc);
+  const int s = list[f];
+  double* pbase = (TAG == 1 && part && P.poff[s] >= 0) ? part + r * pstride + P.poff[s] : nullptr;
+  wide_extract_tile(P, s, ti, tj, src + r * src_stride, arena + r * arena_stride, rr, rc, cpc, LB, pbase, ps);
 }
 
 // Tile (ti, tj) of the ceil(A/64) x ceil(N/64) grid of an A x N block (an
@@ -400,7 +465,8 @@ struct SegTiles {
 
 __global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* list, SegTiles tl, int count,
                                                      const double* LB, const double* Kt, const double* T,
-                                                     double* Va, int64_t upd, double* wsb, int64_t slot) {
+                                                     double* Va, int64_t upd, double* wsb, int64_t slot,
+                                                     double* part, int64_t pstride) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   __shared__ int rr[WT], rc[WT];
@@ -411,7 +477,9 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* l
     const int f = seg_front(tl.aa, count, b);
     int ti, tj;
     tri_tile(b - tl.aa[f], ti, tj);
-    wide_extract_tile(P, list[f], ti, tj, T + r * P.nnz, Va + r * upd, rr, rc, cpc);
+    const int s = list[f];
+    double* pbase = P.poff[s] >= 0 ? part + r * pstride + P.poff[s] : nullptr;
+    wide_extract_tile(P, s, ti, tj, T + r * P.nnz, Va + r * upd, rr, rc, cpc, LB, pbase, sm);
     return;
   }
   b -= tl.n_aa;
@@ -442,7 +510,8 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* l
 
 __global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* list, SegTiles tl, int count,
                                                      const double* LB, const double* Vs, double* T,
-                                                     const double* Va, int64_t upd, double* wsb, int64_t slot) {
+                                                     const double* Va, int64_t upd, double* wsb, int64_t slot,
+                                                     const double* part, int64_t pstride) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   const int64_t r = blockIdx.y;
@@ -467,6 +536,15 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* l
       tile_mma<false, true>(Tt, i0, j0, N, N, 0, N, [&](int i, int k) { return LB[v.nn(i, k)]; },
                             [&](int k, int j) { return W[k + (int64_t)j * N]; }, sm);
       tile_store(Tt, i0, j0, N, N, [&](int i, int j, double acc) { MN[i + (int64_t)j * N] = acc; }, true);
+      return;
+    }
+    if (P.poff[v.s] >= 0) {  // V'_s L from the extraction's partial products
+      const double* pb = part + r * pstride + P.poff[v.s];
+      const int ta = (A + WT - 1) / WT;
+      for (int e = threadIdx.x; e < WT * N; e += NT) {
+        const int row = e % WT, n = e / WT, gi = i0 + row;
+        if (gi < A) t[v.an(gi, n)] = MA[gi + (int64_t)n * A] - sum_partials(pb, ta, ti, N, row, n);
+      }
       return;
     }
     MfmaTile Tv(threadIdx.x);
@@ -1020,7 +1098,7 @@ template <int STAGE>
 __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list, int count, const double* R,
                                                   const double* LB, const double* Vi, const double* Tin,
                                                   double* Kt, const double* Va, int64_t upd, double* wsb,
-                                                  int64_t slot) {
+                                                  int64_t slot, const double* part, int64_t pstride, int r0) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   const int f = blockIdx.y % count;
@@ -1050,6 +1128,12 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
         auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
         tile_mma(T, i0, j0, N, N, 0, min(N, min(i0, j0) + WT), C, [&](int k, int j) { return C(j, k); }, sm);
         tile_store(T, i0, j0, N, N, [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false);
+      } else if (part && P.poff[v.s] >= 0) {  // V' L from the gather's partial products
+        const double* pb = part + (r0 + r) * pstride + P.poff[v.s];
+        for (int e = threadIdx.x; e < WT * N; e += NT) {
+          const int row = e % WT, n = e / WT, gi = i0 + row;
+          if (gi < A) MA[gi + (int64_t)n * A] = t[v.an(gi, n)] + sum_partials(pb, d.ta, ti, N, row, n);
+        }
       } else {
         wide_sym_rows<true>(T, i0, j0, A, N, Va + r * upd + P.arena[v.s],
                             [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
@@ -1322,32 +1406,37 @@ void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, cons
 
 void launch_wide_extract(int tag, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                          const int32_t* pre, int count, const double* src, double* arena, int64_t src_stride,
-                         int64_t arena_stride) {
+                         int64_t arena_stride, const double* LB, double* part, int64_t pstride) {
   if (tag == 1)
-    k_wide_extract<1><<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride);
+    k_wide_extract<1><<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride, LB, part,
+                                          pstride);
   else
-    k_wide_extract<2><<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride);
+    k_wide_extract<2><<<grid, NT, 0, s>>>(P, list, pre, count, src, arena, src_stride, arena_stride, nullptr,
+                                          nullptr, 0);
 }
 
 void launch_wide_projinv(hipStream_t s, const DevPlan& P, const int32_t* list, const WideTiles& w, int count,
                          const double* LB, double* S, double* Vs) {
-  if (w.n_aa) k_wide_extract<0><<<dim3(unsigned(w.n_aa)), NT, 0, s>>>(P, list, w.aa, count, S, Vs, 0, 0);
+  if (w.n_aa)
+    k_wide_extract<0><<<dim3(unsigned(w.n_aa)), NT, 0, s>>>(P, list, w.aa, count, S, Vs, 0, 0, nullptr, nullptr, 0);
   if (w.n_an) k_wide_projinv_an<<<dim3(unsigned(w.n_an)), NT, 0, s>>>(P, list, w.an, count, LB, S, Vs);
   k_wide_projinv_nn<<<dim3(unsigned(w.n_nn)), NT, 0, s>>>(P, list, w.nn, count, LB, S);
 }
 
 void launch_wide_hess_down(int k, int maxN, int maxA, hipStream_t s, const DevPlan& P, const int32_t* list,
                            const WideTiles& w, int count, const double* LB, const double* Vs, const double* Kt,
-                           double* T, double* Va, int64_t upd, double* wsb, int64_t slot) {
+                           double* T, double* Va, int64_t upd, double* wsb, int64_t slot, double* part,
+                           int64_t pstride) {
   const SegTiles tl{w.aa, w.an, w.nn, w.n_aa, w.n_an, w.n_nn};
   k_wide_hdown_a<<<dim3(unsigned(w.n_aa + w.n_nn + w.n_an), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, Kt,
-                                                                                       T, Va, upd, wsb, slot);
+                                                                                       T, Va, upd, wsb, slot, part,
+                                                                                       pstride);
   if (maxA > 0) {
     const int ct = RhsCols(std::max(1, maxN), k).ct, ta = (maxA + WT - 1) / WT;
     k_wide_hdown_vz<<<dim3(unsigned(ta * ct), unsigned(count)), NT, 0, s>>>(P, list, count, k, ct, Vs, wsb, slot);
   }
   k_wide_hdown_b<<<dim3(unsigned(w.n_nn + w.n_an), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, Vs, T, Va,
-                                                                              upd, wsb, slot);
+                                                                              upd, wsb, slot, part, pstride);
   k_wide_hdown_c<<<dim3(unsigned(w.n_nn), unsigned(k)), NT, 0, s>>>(P, list, tl, count, LB, T, wsb, slot);
 }
 
@@ -1440,7 +1529,8 @@ void launch_bigv(int mode, int maxA, int count, hipStream_t s, const DevPlan& P,
 
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                       const double* R, const double* LB, const double* Vi, const double* T, double* Kt,
-                      const double* Va, int64_t upd, double* wsb, int64_t slot) {
+                      const double* Va, int64_t upd, double* wsb, int64_t slot, const double* part,
+                      int64_t pstride) {
   // blockIdx.y = front + count * (right-hand side): right-hand sides in
   // groups that keep the grid's y extent within 65535
   const int kc = std::max(1, 65535 / std::max(1, count));
@@ -1450,10 +1540,10 @@ void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, 
     const double* t = T + (int64_t)r0 * P.nnz;
     double* K = Kt + (int64_t)r0 * P.nnz;
     const double* va = Va + (int64_t)r0 * upd;
-    k_fat_ihess<1><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
-    k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
-    k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
-    k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot);
+    k_fat_ihess<1><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
+    k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
+    k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
+    k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
     if (g.maxA > 0) {
       const int ct = RhsCols(std::max(1, g.maxN), kk).ct, ta = (g.maxA + WT - 1) / WT;
       const dim3 gan(unsigned(ta * ct), unsigned(count));

@@ -447,8 +447,10 @@ def test_tile_parallel_inverse_hessian_shapes(shape, mfb):
     """Inverse Hessian through the tile-parallel path (MFB_PLAN_WIDE_LOW) on
     fronts whose ancestor blocks span two to four 64-row tiles: explicit
     (S_AA)^-1 for A = 70 and 100 (N = 1, 40, 100), the factored form for
-    A = 200 and 250; the default plan (one workgroup per front) beside it.
-    A first version of the explicit product was wrong here by O(1)."""
+    A = 200 and 250; the default plan beside it; and the Hessian, whose
+    root-to-leaf sweep forms V' L from partial products on fronts with at
+    most four columns.  A first version of the explicit product was wrong
+    here by O(1)."""
     pat = {"band300_w100": lambda: P.band(300, 100), "band200_w70": lambda: P.band(200, 70),
            "arrow40x3_100": lambda: P.block_arrow([40, 40, 40], 100),
            "arrow100x2_100": lambda: P.block_arrow([100, 100], 100),
@@ -460,10 +462,13 @@ def test_tile_parallel_inverse_hessian_shapes(shape, mfb):
     s = oracle.projinv(pat, ldl)
     t0 = oracle.hessian(pat, ldl, s, y)
     want = oracle.inv_hessian(pat, ldl, s, t0)
-    for flags in (0, mfb.PLAN_WIDE_LOW):
+    # (without the source map the gathers also form the partial products
+    # T_AA L of the fronts with at most four columns)
+    for flags in (0, mfb.PLAN_WIDE_LOW, mfb.PLAN_WIDE_LOW | mfb.PLAN_NO_GATHER_MAP):
         b = mfb.SparseBarrier(pat, flags=flags)
         b.factor(dev(x))
         close(pat, host(b.inv_hessian(dev(t0))), want)
+        close(pat, host(b.hessian(dev(y))), t0)
         c = mfb.SparseBarrier(pat, flags=flags)
         c.completion(dev(s))
         assert c.status() == (0, -1)
