@@ -578,6 +578,43 @@ def hessian_factor_extra(torch, mfb, V, st, reps=2):
             "max_rel_err_adj_of_factor_vs_hessian": adj_err, "max_rel_err_gram_vs_y_dot_hessian": gram_err}
 
 
+def served(torch, dev, nreq=200, npool=12, seed=0):
+    """The served pattern: requests (pattern, X, Y_1..k) with k ~ U{1..8}
+    over a pool of filled Erdos-Renyi patterns (average degree 6) under
+    minimum degree, n log-uniform in [500, 3000], X fresh per request,
+    Poisson arrivals at 0.8 times the sequential plain capacity; 4 streams,
+    half of the free HBM as admission budget."""
+    from paper_1203_2742_amd import serve as sv
+    from workloads import patterns as P
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(np.log(500), np.log(3000), npool)).round().astype(int)
+    pool = [P.er_min_degree(int(n), int(seed * 100 + i + 1)) for i, n in enumerate(ns)]
+    srv = sv.Server(device=dev, streams=4)
+    warm = sv.make_requests(npool, pool, seed=seed + 1)
+    srv.run(warm, realtime=False)  # plans, handles and device index arrays in place
+    reqs = sv.make_requests(nreq, pool, seed=seed + 2)
+    alone, t_seq = srv.run_sequential(reqs[:48])
+    cap = 48 / t_seq
+    arr = np.cumsum(np.random.default_rng(seed + 3).exponential(1.0 / (0.8 * cap), nreq))
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    mix, lat, makespan, peak = srv.run(reqs)
+    same = sv.alone_vs_mix(mix, alone)
+    del mix
+    _, _, makespan_sat, _ = srv.run(reqs, realtime=False)  # every request queued at once
+    v = np.array([lat[r.rid] for r in reqs]) * 1e3
+    evals = sum(r.ys.shape[0] for r in reqs)
+    return {"requests": nreq, "patterns": npool, "n_range": [int(ns.min()), int(ns.max())],
+            "nnz_range": [int(min(p[1][-1] for p in pool)), int(max(p[1][-1] for p in pool))],
+            "streams": 4, "arrival_rate_per_s": round(0.8 * cap, 2),
+            "sequential_requests_per_s": round(cap, 2),
+            "p50_ms": round(float(np.percentile(v, 50)), 3), "p99_ms": round(float(np.percentile(v, 99)), 3),
+            "served_requests_per_s": round(nreq / makespan, 2),
+            "served_hessian_evals_per_s": round(evals / makespan, 2),
+            "saturated_requests_per_s": round(nreq / makespan_sat, 2),
+            "peak_admitted_GB": round(peak / 1e9, 3), "bitwise_equal_alone_vs_mix": bool(same)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -653,6 +690,9 @@ def main():
         torch.cuda.empty_cache()
         extras["latency"] = latency(torch, mfb, V, get_config, "band200", dev)
         log(args, f"latency {extras['latency']}")
+        extras["served"] = served(torch, dev)
+        log(args, f"served {extras['served']}")
+        torch.cuda.empty_cache()
         g2 = Step(torch, mfb, V, get_config("grid2d_128"), 1, dev)
         for _ in range(3):
             g2.run()
