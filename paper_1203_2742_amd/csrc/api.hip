@@ -58,7 +58,8 @@ static size_t factor_bytes(const mfb_plan_s* p) {
 }
 static size_t rhs_bytes(const mfb_plan_s* p) {
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
-  return (upd + nnz + size_t(rhs_scratch(p)) + size_t(p->part_doubles)) * 8 + 4 * ALIGN;
+  return (upd + nnz + size_t(rhs_scratch(p)) + size_t(p->part_doubles)) * 8 + size_t(std::max(1, p->ns)) * 4 +
+         5 * ALIGN;
 }
 }  // namespace mfb
 
@@ -466,14 +467,14 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
           k_factor<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
                                                  f->part, f->st, f->scratch, slot);
           launch_wide_update(0, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                             sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+                             sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot, nullptr);
         } else if (cls == kFat) {
           const FatGrid fg = fat_grid(sg);
-          launch_fat_panel(0, fg, 1, s, f->plan->dev, list, sg.lv.count, ((Ctx*)c)->x, f->U, 0, f->scratch, slot);
+          launch_fat_panel(0, fg, 1, s, f->plan->dev, list, sg.lv.count, ((Ctx*)c)->x, f->U, 0, f->scratch, slot, nullptr);
           launch_fat_factor(fg, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, f->part, f->st, f->scratch, slot);
           if (sg.n_aa)
             launch_wide_update(0, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                               sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+                               sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot, nullptr);
         } else {
           k_factor<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, ((Ctx*)c)->x, f->R, f->LB, f->U,
                                                   f->part, f->st, f->scratch, slot);
@@ -530,6 +531,7 @@ mfb_status_t mfb_projected_inverse(mfb_factor_t f, double* s_out, void* stream) 
 struct RhsArena {
   double *Ua, *Kt, *scr, *part;
   int64_t upd, pstride;  // pstride: doubles of the partial area per RHS
+  int32_t* act;          // Hessian step 1 activity flags, ns per RHS
 };
 static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, RhsArena* a) {
   const mfb_plan_s* p = f->plan;
@@ -545,6 +547,8 @@ static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, Rhs
   a->pstride = p->part_doubles;
   a->part = (double*)c;
   c += up(size_t(k) * size_t(std::max<int64_t>(1, p->part_doubles)) * 8);
+  a->act = (int32_t*)c;
+  c += up(size_t(k) * size_t(std::max(1, p->ns)) * 4);
   a->scr = (double*)c;
   return MFB_OK;
 }
@@ -558,6 +562,9 @@ struct HessCtx {
 static mfb_status_t hess_up_run(mfb_factor_s* f, int32_t k, const double* y, const RhsArena& a, hipStream_t s) {
   HessCtx ctx{y, nullptr, a};
   using Ctx = HessCtx;
+  // every front active until its step-1 kernel finds its subtree's part of
+  // Y zero (pruning; fat fronts keep the flag)
+  launch_fill_i32(s, a.act, int64_t(k) * f->plan->ns, 1);
   return run_classes(
       f, MFB_K_HESS_UP, f->plan->cs_factor, s, k, OP_HUP,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
@@ -565,24 +572,26 @@ static mfb_status_t hess_up_run(mfb_factor_s* f, int32_t k, const double* y, con
         const int32_t* list = cs.d_list + sg.lv.begin;
         Ctx* x = (Ctx*)c;
         if (cls < kRegClasses) {
-          launch_hess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua, x->a.upd);
+          launch_hess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua, x->a.upd, x->a.act);
         } else if (cls == kWide) {
           k_hess_up<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua,
-                                                  x->a.upd, x->a.scr, slot);
+                                                  x->a.upd, x->a.scr, slot, x->a.act);
           launch_wide_update(1, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                             sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+                             sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, x->a.act);
         } else if (cls == kFat) {
           const FatGrid fg = fat_grid(sg);
           const int k = int(g.y);
-          launch_fat_panel(1, fg, k, s, f->plan->dev, list, sg.lv.count, x->y, x->a.Ua, x->a.upd, x->a.scr, slot);
+          launch_fat_panel(1, fg, k, s, f->plan->dev, list, sg.lv.count, x->y, x->a.Ua, x->a.upd, x->a.scr, slot,
+                           x->a.act);
           launch_fat_up_fin(1, fg, k, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, nullptr, x->a.Kt, x->a.scr,
                             slot);
           if (sg.n_aa)
             launch_wide_update(1, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                               sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+                               sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot,
+                               x->a.act);
         } else {
           k_hess_up<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->y, x->a.Kt, x->a.Ua,
-                                                   x->a.upd, x->a.scr, slot);
+                                                   x->a.upd, x->a.scr, slot, x->a.act);
         }
       },
       &ctx);
@@ -762,7 +771,8 @@ mfb_status_t mfb_hessian_factor(mfb_factor_t f, int32_t k, const double* y, doub
       f, MFB_K_HFACTOR, f->plan->cs_hfac, s, k, OP_HFAC,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
         Ctx* x = (Ctx*)c;
-        launch_hfactor(g, s, f->plan->dev, cs.d_list + sg.lv.begin, f->R, f->Gam, x->a.Kt, x->w, x->a.scr, slot);
+        launch_hfactor(g, s, f->plan->dev, cs.d_list + sg.lv.begin, f->R, f->Gam, x->a.Kt, x->w, x->a.scr, slot,
+                       x->a.act);
       },
       &ctx);
   if (st) return st;
@@ -889,17 +899,17 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
           k_ihess_up<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
                                                    x->a.upd, x->a.scr, slot);
           launch_wide_update(2, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                             sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+                             sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, nullptr);
         } else if (cls == kFat) {
           const FatGrid fg = fat_grid(sg);
           const int k = int(g.y);
           launch_fat_panel(2, fg, k, s, f->plan->dev, list, sg.lv.count, nullptr, x->a.Ua, x->a.upd, x->a.scr,
-                           slot);
+                           slot, nullptr);
           launch_fat_up_fin(2, fg, k, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, x->y, x->a.Kt, x->a.scr,
                             slot);
           if (sg.n_aa)
             launch_wide_update(2, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                               sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot);
+                               sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, nullptr);
         } else {
           k_ihess_up<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
                                                     x->a.upd, x->a.scr, slot);
@@ -973,15 +983,15 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
           k_product<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
                                                   f->scratch, slot);
           launch_wide_update(3, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                             sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+                             sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot, nullptr);
         } else if (cls == kFat) {
           const FatGrid fg = fat_grid(sg);
-          launch_fat_panel(3, fg, 1, s, f->plan->dev, list, sg.lv.count, nullptr, f->U, 0, f->scratch, slot);
+          launch_fat_panel(3, fg, 1, s, f->plan->dev, list, sg.lv.count, nullptr, f->U, 0, f->scratch, slot, nullptr);
           launch_fat_up_fin(0, fg, 1, s, f->plan->dev, list, sg.lv.count, f->R, f->LB, ((Ctx*)c)->x, nullptr,
                             f->scratch, slot);
           if (sg.n_aa)
             launch_wide_update(3, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
-                               sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot);
+                               sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot, nullptr);
         } else {
           k_product<false><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
                                                    f->scratch, slot);

@@ -45,15 +45,19 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // a child's entries are spread over the whole workgroup (flat index over
 // its A_c x A_c square, lower entries taken), with its relative indices
 // staged in LDS (`sm`: at least 2048 doubles) when they fit.
+// With `act` (Hessian step 1: per supernode, whether its subtree holds a
+// nonzero of the right-hand side), children marked 0 are skipped: their
+// update blocks are zero and were not written.
 template <int NTH = NT>
 __device__ __forceinline__ void assemble_children(const DevPlan& P, const SnView& v, const double* ua,
-                                                  double* F, double* Us, double* sm) {
+                                                  double* F, double* Us, double* sm,
+                                                  const int32_t* act = nullptr) {
   int* srl = reinterpret_cast<int*>(sm);
   constexpr int CAP = 4096;
   for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
     const int c = P.cidx[t];
     const int Ac = P.nrow[c] - P.ncol[c];
-    if (Ac == 0) continue;  // (a child always has ancestors)
+    if (Ac == 0 || (act && !act[c])) continue;  // (a child always has ancestors)
     const int32_t* rl = P.rel + P.relbase[c];
     const double* Uc = ua + P.arena[c];
     const bool st = Ac <= CAP;
@@ -174,9 +178,10 @@ __device__ __forceinline__ void extract_from_parent(const DevPlan& P, const SnVi
 // barrier.
 template <int NTH = NT>
 __device__ __forceinline__ void assemble_children_panel(const DevPlan& P, const SnView& v, const double* ua,
-                                                        double* F) {
+                                                        double* F, const int32_t* act = nullptr) {
   for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
     const int c = P.cidx[t];
+    if (act && !act[c]) continue;
     const int Ac = P.nrow[c] - P.ncol[c];
     const int32_t* rl = P.rel + P.relbase[c];
     const double* Uc = ua + P.arena[c];
@@ -194,6 +199,15 @@ template <int NTH = NT>
 __device__ __forceinline__ void zero_packed(double* U, int A) {
   const int64_t m = (int64_t)A * (A + 1) / 2;
   for (int64_t e = threadIdx.x; e < m; e += NTH) U[e] = 0.0;
+}
+
+// Hessian step 1 with a sparse right-hand side (pruning, Section 5.5):
+// the front is active when its own panel of Y holds a nonzero (own, this
+// thread's view) or a child is active.  Uniform over the workgroup.
+__device__ __forceinline__ bool step1_active(const DevPlan& P, int s, const int32_t* act, bool own) {
+  bool a = __syncthreads_or(own ? 1 : 0) != 0;
+  for (int t = P.cptr[s]; t < P.cptr[s + 1] && !a; ++t) a = act[P.cidx[t]] != 0;
+  return a;
 }
 
 __device__ __forceinline__ double* slot_ptr(double* wsb, int64_t slot) {

@@ -109,10 +109,12 @@ __global__ void __launch_bounds__(NT) k_gamma(DevPlan P, const int32_t* list, co
 
 // W = R(Y) from the block step-1 output K (CCS, right-hand side
 // blockIdx.y), one workgroup per (supernode, right-hand side); supernodes
-// are independent.  Scratch (doubles): 2 N^2 + A N.
+// are independent.  Scratch (doubles): 2 N^2 + A N.  A supernode that
+// step 1 pruned (act 0: no nonzero of Y in its subtree, so K = 0) gets
+// W = 0 directly (Section 5.5).
 __global__ void __launch_bounds__(NT) k_hfactor(DevPlan P, const int32_t* list, const double* R,
                                                 const double* Gam, const double* Kt, double* Wt, double* wsb,
-                                                int64_t slot) {
+                                                int64_t slot, const int32_t* act) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
@@ -120,6 +122,13 @@ __global__ void __launch_bounds__(NT) k_hfactor(DevPlan P, const int32_t* list, 
     const int N = v.N, A = v.A;
     const double* K = Kt + r * P.nnz;
     double* w = Wt + r * P.nnz;
+    if (!act[r * P.ns + v.s]) {
+      for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) {
+        const int i = int(e % v.J), j = int(e / v.J);
+        if (i >= j) w[v.at(i, j)] = 0.0;
+      }
+      return;
+    }
     double* Ci = slot_ptr(wsb, slot);
     double* T1 = Ci + (int64_t)N * N;
     double* E = T1 + (int64_t)N * N;
@@ -242,8 +251,8 @@ void launch_gamma(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* lis
 }
 
 void launch_hfactor(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
-                    const double* Gam, const double* Kt, double* Wt, double* wsb, int64_t slot) {
-  k_hfactor<<<grid, NT, 0, s>>>(P, list, R, Gam, Kt, Wt, wsb, slot);
+                    const double* Gam, const double* Kt, double* Wt, double* wsb, int64_t slot, const int32_t* act) {
+  k_hfactor<<<grid, NT, 0, s>>>(P, list, R, Gam, Kt, Wt, wsb, slot, act);
 }
 
 void launch_hfactor_adj(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,

@@ -22,7 +22,7 @@ __global__ void k_factor(DevPlan, const int32_t*, const double*, double*, double
 __global__ void k_projinv(DevPlan, const int32_t*, const double*, double*, double*);
 template <bool PANEL>
 __global__ void k_hess_up(DevPlan, const int32_t*, const double*, const double*, double*, double*,
-                          int64_t, double*, int64_t);
+                          int64_t, double*, int64_t, int32_t*);
 __global__ void k_hess_down(DevPlan, const int32_t*, const double*, const double*, const double*,
                             double*, double*, int64_t, double*, int64_t);
 __global__ void k_ihess_down(DevPlan, const int32_t*, const double*, const double*, const double*,
@@ -58,8 +58,11 @@ void launch_factor_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, cons
 void launch_completion_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                            const double* Sin, double* R, double* LB, double* S, double* Vs,
                            double* Vi, double* part, DevStatus* st);
+// act: Hessian step 1's per-(RHS, supernode) activity flags (ns per RHS;
+// entries of pruned fronts are set to 0, others left as they are)
 void launch_hess_up_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
-                        const double* LB, const double* Y, double* Kt, double* Ua, int64_t upd);
+                        const double* LB, const double* Y, double* Kt, double* Ua, int64_t upd, int32_t* act);
+void launch_fill_i32(hipStream_t s, int32_t* x, int64_t n, int32_t v);
 void launch_ihess_up_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                          const double* LB, const double* Kt, double* Y, double* Ua, int64_t upd);
 void launch_product_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
@@ -82,10 +85,11 @@ struct WideTiles {
   const int32_t *aa, *an, *nn;
   int n_aa, n_an, n_nn;
 };
-// op: 0 factor, 1 Hessian step 1, 2 inverse Hessian step 3, 3 product.
+// op: 0 factor, 1 Hessian step 1, 2 inverse Hessian step 3, 3 product;
+// act (op 1, may be null): the step's activity flags, pruned fronts skipped
 void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const int32_t* pre, int count, const double* R, const double* LB, const double* Kt,
-                        double* Ua, int64_t upd, const double* wsb, int64_t slot);
+                        double* Ua, int64_t upd, const double* wsb, int64_t slot, const int32_t* act);
 // tag (profile attribution): 1 inverse Hessian gather, 2 completion gather
 // tag 1 (the inverse Hessian's gather) with part: also the partial
 // products of T_AA L_AN of the fronts that have a partial area
@@ -106,7 +110,8 @@ struct FatGrid {
   int maxN, maxA, maxJ, panel, fin;
 };
 void launch_fat_panel(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
-                      int count, const double* src, const double* Ua, int64_t upd, double* wsb, int64_t slot);
+                      int count, const double* src, const double* Ua, int64_t upd, double* wsb, int64_t slot,
+                      const int32_t* act);
 void launch_fat_factor(const FatGrid& g, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
                        double* R, double* LB, double* part, DevStatus* st, double* wsb, int64_t slot);
 // op: 0 product (Out = X), 1 Hessian step 1 (K), 2 inverse Hessian step 3 (Out = Y)
@@ -139,7 +144,7 @@ void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, 
 void launch_gamma(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Vs, double* Gam,
                   double* Gami, DevStatus* st);
 void launch_hfactor(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
-                    const double* Gam, const double* Kt, double* Wt, double* wsb, int64_t slot);
+                    const double* Gam, const double* Kt, double* Wt, double* wsb, int64_t slot, const int32_t* act);
 void launch_hfactor_adj(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
                         const double* Gami, const double* Wt, double* Kt, double* wsb, int64_t slot);
 struct GramShape {

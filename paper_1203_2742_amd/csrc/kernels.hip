@@ -14,6 +14,8 @@
 // an arena; children are assembled in a fixed order without atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdint>
 
 #include "kernels.h"
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(NT_DOWN) k_projinv(DevPlan P, const int32_t* l
 template <bool PANEL>
 __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, const double* LB,
                                                 const double* Y, double* Kt, double* Ua,
-                                                int64_t upd, double* wsb, int64_t slot) {
+                                                int64_t upd, double* wsb, int64_t slot, int32_t* act) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
@@ -157,16 +159,30 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
     double* ua = Ua + r * upd;
     double* Us = ua + P.arena[v.s];
     double* F = slot_ptr(wsb, slot);
+    int32_t* ac = act + r * P.ns;
+    bool own = false;
     for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
       const int rr = int(e % v.J), c = int(e / v.J);
-      F[e] = rr >= c ? y[v.at(rr, c)] : 0.0;
+      const double yv = rr >= c ? y[v.at(rr, c)] : 0.0;
+      own = own || yv != 0.0;
+      F[e] = yv;
+    }
+    if (!step1_active(P, v.s, ac, own)) {
+      // no nonzero of Y below this front: K = 0 here, and the update block
+      // (zero) is neither formed nor read (the parent skips it)
+      for (int64_t e = threadIdx.x; e < (int64_t)v.J * v.N; e += NT) {
+        const int rr = int(e % v.J), c = int(e / v.J);
+        if (rr >= c) K[v.at(rr, c)] = 0.0;
+      }
+      if (threadIdx.x == 0) ac[v.s] = 0;
+      return;
     }
     if (!PANEL) zero_packed(Us, v.A);
     __syncthreads();
     if (PANEL)
-      assemble_children_panel(P, v, ua, F);
+      assemble_children_panel(P, v, ua, F, ac);
     else
-      assemble_children(P, v, ua, F, Us, sm);
+      assemble_children(P, v, ua, F, Us, sm, ac);
     for (int64_t e = threadIdx.x; e < (int64_t)v.N * v.N; e += NT) {
       const int i = int(e % v.N), c = int(e / v.N);
       if (i >= c) K[v.at(i, c)] = F[i + (int64_t)c * v.J];
@@ -187,9 +203,9 @@ __global__ void __launch_bounds__(NT) k_hess_up(DevPlan P, const int32_t* list, 
   });
 }
 template __global__ void k_hess_up<false>(DevPlan, const int32_t*, const double*, const double*, double*,
-                                          double*, int64_t, double*, int64_t);
+                                          double*, int64_t, double*, int64_t, int32_t*);
 template __global__ void k_hess_up<true>(DevPlan, const int32_t*, const double*, const double*, double*,
-                                         double*, int64_t, double*, int64_t);
+                                         double*, int64_t, double*, int64_t, int32_t*);
 
 // Hessian steps 2 and 3 (root-to-leaf), block form of Algorithm 5.1 with
 // the V_j recursion of its modified step 2 (here V_s is cached):
@@ -793,9 +809,11 @@ __device__ __forceinline__ void load_packed_block(RegFront<C, LO>& M, const SnVi
 // through an inverse relative-index map in LDS (`inv`, MMAX ints).
 template <class C, bool LO>
 __device__ __forceinline__ void gather_children(RegFront<C, LO>& M, const DevPlan& P, const SnView& v,
-                                                const double* ua, int* inv, double sg) {
+                                                const double* ua, int* inv, double sg,
+                                                const int32_t* act = nullptr) {
   for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
     const int c = P.cidx[t];
+    if (act && !act[c]) continue;  // (uniform: a child inactive in Hessian step 1)
     const int Ac = P.nrow[c] - P.ncol[c];
     const int32_t* rl = P.rel + P.relbase[c];
     const double* Uc = ua + P.arena[c];
@@ -1028,7 +1046,7 @@ __global__ void __launch_bounds__(C::NTH) k_completion_reg(DevPlan P, const int3
 template <class C>
 __global__ void __launch_bounds__(C::NTH) k_hess_up_reg(DevPlan P, const int32_t* list, const double* LB,
                                                         const double* Y, double* Kt, double* Ua,
-                                                        int64_t upd) {
+                                                        int64_t upd, int32_t* act) {
   __shared__ double lds[kCongLds<C>];
   __shared__ int inv[C::MMAX];
   const SnView v(P, list[blockIdx.x]);
@@ -1037,9 +1055,24 @@ __global__ void __launch_bounds__(C::NTH) k_hess_up_reg(DevPlan P, const int32_t
   double* K = Kt + r * P.nnz;
   double* ua = Ua + r * upd;
   double* Us = ua + P.arena[v.s];
+  int32_t* ac = act + r * P.ns;
   RegFront<C> M;
   load_panel(M, v, y);
-  gather_children(M, P, v, ua, inv, 1.0);
+  bool own = false;
+#pragma unroll
+  for (int a = 0; a < C::RX; ++a)
+#pragma unroll
+    for (int b = 0; b < C::RY; ++b) own = own || M.v[a][b] != 0.0;
+  bool active = __syncthreads_or(own ? 1 : 0) != 0;
+  for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1] && !active; ++t) active = ac[P.cidx[t]] != 0;
+  if (!active) {
+    // no nonzero of Y below this front: K = 0 (the panel loaded as zero)
+    // and no update block (the parent skips it)
+    store_front(M, v, [&](int64_t o, double x) { K[o] = x; }, [&](int64_t, double) {});
+    if (threadIdx.x == 0) ac[v.s] = 0;
+    return;
+  }
+  gather_children(M, P, v, ua, inv, 1.0, ac);
   congruences<C>(M, v, LB, -1.0, lds);
   store_front(M, v, [&](int64_t o, double x) { K[o] = x; }, [&](int64_t e, double x) { Us[e] = x; });
 }
@@ -1404,8 +1437,8 @@ static void go_completion(dim3 g, hipStream_t s, const DevPlan& P, const int32_t
 }
 template <class C>
 static void go_hess_up(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* LB,
-                       const double* Y, double* Kt, double* Ua, int64_t upd) {
-  k_hess_up_reg<C><<<g, C::NTH, 0, s>>>(P, list, LB, Y, Kt, Ua, upd);
+                       const double* Y, double* Kt, double* Ua, int64_t upd, int32_t* act) {
+  k_hess_up_reg<C><<<g, C::NTH, 0, s>>>(P, list, LB, Y, Kt, Ua, upd, act);
 }
 template <class C>
 static void go_ihess_up(dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list, const double* LB,
@@ -1458,9 +1491,19 @@ void launch_completion_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, con
                            double* Vi, double* part, DevStatus* st) {
   MFB_REG_SWITCH(go_completion, g, s, P, list, Sin, R, LB, S, Vs, Vi, part, st)
 }
+// x[0 .. n) = v (kernel launch, not a memset: graph-capture safe)
+__global__ void __launch_bounds__(NT) k_fill_i32(int32_t* x, int64_t n, int32_t v) {
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) x[e] = v;
+}
+void launch_fill_i32(hipStream_t s, int32_t* x, int64_t n, int32_t v) {
+  if (n <= 0) return;
+  const int64_t b = std::min<int64_t>(1024, (n + NT - 1) / NT);
+  k_fill_i32<<<dim3(unsigned(b)), NT, 0, s>>>(x, n, v);
+}
+
 void launch_hess_up_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
-                        const double* LB, const double* Y, double* Kt, double* Ua, int64_t upd) {
-  MFB_REG_SWITCH(go_hess_up, g, s, P, list, LB, Y, Kt, Ua, upd)
+                        const double* LB, const double* Y, double* Kt, double* Ua, int64_t upd, int32_t* act) {
+  MFB_REG_SWITCH(go_hess_up, g, s, P, list, LB, Y, Kt, Ua, upd, act)
 }
 void launch_ihess_up_reg(int cls, dim3 g, hipStream_t s, const DevPlan& P, const int32_t* list,
                          const double* LB, const double* Kt, double* Y, double* Ua, int64_t upd) {

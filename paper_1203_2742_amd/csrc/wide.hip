@@ -93,7 +93,7 @@ template <int OP>
 __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* list, const int32_t* pre,
                                                     int count, const double* R, const double* LB,
                                                     const double* Kt, double* Ua, int64_t upd,
-                                                    const double* wsb, int64_t slot) {
+                                                    const double* wsb, int64_t slot, const int32_t* act) {
   __shared__ double p1[WKC * WLD], p2[WKC * WLD];
   __shared__ int invr[WT], invc[WT];
   __shared__ int64_t colc[kColCache];
@@ -102,6 +102,10 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
   int ti, tj;
   tri_tile(b - pre[f], ti, tj);
   const int64_t r = blockIdx.y;
+  // Hessian step 1: a front whose subtree holds no nonzero of Y (marked by
+  // its panel kernel) has a zero update block, neither formed nor read
+  const int32_t* ac = (OP == WU_HUP && act) ? act + r * P.ns : nullptr;
+  if (ac && !ac[list[f]]) return;  // (the whole workgroup)
   with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
     const int N = v.N, A = v.A, J = v.J;
     const int i0 = ti * WT, j0 = tj * WT;
@@ -144,6 +148,7 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
     for (int q = 0; q < 16; ++q) g[q] = 0.0;
     for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
       const int c = P.cidx[t];
+      if (ac && !ac[c]) continue;  // (uniform)
       const int Ac = P.nrow[c] - P.ncol[c];
       const int32_t* rl = P.rel + P.relbase[c];
       const double* Uc = ua + P.arena[c];
@@ -647,7 +652,8 @@ struct FatDims {
 // Tiles: ceil(J/64) x ceil(N/64), those wholly above the diagonal skipped.
 template <int TAG>
 __global__ void __launch_bounds__(NT) k_fat_panel(DevPlan P, const int32_t* list, int count, const double* src,
-                                                  const double* Ua, int64_t upd, double* wsb, int64_t slot) {
+                                                  const double* Ua, int64_t upd, double* wsb, int64_t slot,
+                                                  const int32_t* act) {
   __shared__ int64_t colc[kColCache];
   __shared__ int invr[WT], invc[WT];
   const int f = blockIdx.y % count;
@@ -674,6 +680,7 @@ __global__ void __launch_bounds__(NT) k_fat_panel(DevPlan P, const int32_t* list
     }
     for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
       const int c = P.cidx[t];
+      if (TAG == 1 && act && !act[r * P.ns + c]) continue;  // (uniform) pruned child, Hessian step 1
       const int Ac = P.nrow[c] - P.ncol[c];
       const int32_t* rl = P.rel + P.relbase[c];
       const double* Uc = ua + P.arena[c];
@@ -1387,19 +1394,19 @@ __global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* lis
 
 void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const int32_t* pre, int count, const double* R, const double* LB, const double* Kt,
-                        double* Ua, int64_t upd, const double* wsb, int64_t slot) {
+                        double* Ua, int64_t upd, const double* wsb, int64_t slot, const int32_t* act) {
   switch (op) {
     case WU_FACTOR:
-      k_wide_update<WU_FACTOR><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot);
+      k_wide_update<WU_FACTOR><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot, act);
       break;
     case WU_HUP:
-      k_wide_update<WU_HUP><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot);
+      k_wide_update<WU_HUP><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot, act);
       break;
     case WU_PRODUCT:
-      k_wide_update<WU_PRODUCT><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot);
+      k_wide_update<WU_PRODUCT><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot, act);
       break;
     default:
-      k_wide_update<WU_IHUP><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot);
+      k_wide_update<WU_IHUP><<<grid, NT, 0, s>>>(P, list, pre, count, R, LB, Kt, Ua, upd, wsb, slot, act);
       break;
   }
 }
@@ -1441,13 +1448,14 @@ void launch_wide_hess_down(int k, int maxN, int maxA, hipStream_t s, const DevPl
 }
 
 void launch_fat_panel(int op, const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
-                      int count, const double* src, const double* Ua, int64_t upd, double* wsb, int64_t slot) {
+                      int count, const double* src, const double* Ua, int64_t upd, double* wsb, int64_t slot,
+                      const int32_t* act) {
   const dim3 grid(unsigned(g.panel), unsigned(count * k));
   switch (op) {
-    case 0: k_fat_panel<0><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
-    case 1: k_fat_panel<1><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
-    case 2: k_fat_panel<2><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
-    default: k_fat_panel<3><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot); break;
+    case 0: k_fat_panel<0><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot, act); break;
+    case 1: k_fat_panel<1><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot, act); break;
+    case 2: k_fat_panel<2><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot, act); break;
+    default: k_fat_panel<3><<<grid, NT, 0, s>>>(P, list, count, src, Ua, upd, wsb, slot, act); break;
   }
 }
 

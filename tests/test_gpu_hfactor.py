@@ -173,3 +173,48 @@ def test_hessian_factor_arguments(mfb):
     with pytest.raises(mfb.MfbError) as e:
         mfb.gram(plan, y, g, small, m=1)
     assert e.value.code == mfb.EINVAL
+
+
+def _sparse_ys(pat, k, nz, seed):
+    """k right-hand sides with nz random nonzero entries each (one of them
+    all zero when k > 2): the sparse arguments of Section 5.5."""
+    rng = np.random.default_rng(seed)
+    nnz = pat[1][-1]
+    ys = np.zeros((k, nnz))
+    for r in range(k):
+        if k > 2 and r == 1:
+            continue
+        pos = rng.choice(nnz, size=min(nz, nnz), replace=False)
+        ys[r, pos] = rng.uniform(-1, 1, pos.size)
+    return ys
+
+
+@pytest.mark.parametrize("name", ["arrow_mixed", "grid3d_8", "chordal150", "grid2d_24", "band400_w200"])
+def test_sparse_arguments_pruned(name, mfb):
+    """Hessian step 1 skips the fronts whose subtree holds no nonzero of
+    the right-hand side (their K and update blocks are zero) and the Hessian
+    factor writes W = 0 there: R(Y) and H(Y) for sparse Y (a few nonzeros,
+    one right-hand side all zero, one dense beside them) against the oracle,
+    on the default plan and with the tile-parallel kernels forced."""
+    pat = WIDE_PATS[name]() if name in WIDE_PATS else CASES[name]()
+    x = V.make_x(*pat, seed=0)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    ys = _sparse_ys(pat, 4, 3, seed=11)
+    ys[3] = V.make_y(*pat, seed=12)
+    with cf.ThreadPoolExecutor(4) as ex:
+        fw = [ex.submit(oracle.hessian_factor, pat, ldl, s, ys[r]) for r in range(4)]
+        ft = [ex.submit(oracle.hessian, pat, ldl, s, ys[r]) for r in range(4)]
+        want_w = [q.result() for q in fw]
+        want_t = [q.result() for q in ft]
+    for flags in (0, mfb.PLAN_WIDE_LOW):
+        b = mfb.SparseBarrier(pat, flags=flags)
+        b.factor(dev(x))
+        w = host(b.hessian_factor(dev(ys)))
+        t = host(b.hessian(dev(ys)))
+        assert not w[1].any() and not t[1].any()
+        for r in (0, 2, 3):
+            close(pat, w[r], want_w[r])
+            close(pat, t[r], want_t[r])
+        # a sparse right-hand side alone gives the bits it has in the batch
+        assert np.array_equal(host(b.hessian_factor(dev(ys[0]))), w[0])
