@@ -273,6 +273,50 @@ mfb_status_t mfb_get_status(mfb_factor_t f, int64_t* bad_index_host);
 /* Static description of a status code. */
 const char* mfb_strerror(mfb_status_t s);
 
+/* ---- captured steps ------------------------------------------------------ */
+
+/* One interior-point step on a factor handle captured once as a HIP graph
+ * and replayed with a single launch: the level-by-level launches of every
+ * operation in `ops` (flags below, run in the order listed) with the
+ * buffers of `args` baked in.  The step starts with the factorization
+ * (MFB_STEP_FACTOR is required), so every cache the later operations use
+ * is rebuilt inside each replay.  Same buffer rules as the individual
+ * entry points; the buffers, the arena and the factor handle must outlive
+ * the graph, and a replay must not overlap another use of the handle.
+ * Capture records no memset and allocates nothing on the device; the plan's
+ * device arrays exist from mfb_factor_create on, so no eager call is needed
+ * first.  Creation runs no kernel but leaves the handle's host-side state as
+ * the captured calls leave it: launch the graph once before using the
+ * handle eagerly.  Errors: MFB_EINVAL (NULL f, args or out, or
+ * MFB_STEP_FACTOR missing), the argument errors of the captured calls,
+ * MFB_EHIP when capture or instantiation fails; *out is NULL on error. */
+#define MFB_STEP_FACTOR 1u       /* mfb_factor(args->x) */
+#define MFB_STEP_LOGDET 2u       /* mfb_logdet -> args->logdet (1 double) */
+#define MFB_STEP_PROJINV 4u      /* mfb_projected_inverse -> args->s */
+#define MFB_STEP_HESSIAN 8u      /* mfb_hessian(args->k, args->y -> args->t) */
+#define MFB_STEP_INV_HESSIAN 16u /* mfb_inv_hessian(args->k, args->t_in -> args->y_out) */
+typedef struct {
+  const double* x;
+  double* logdet;
+  double* s;
+  int32_t k;
+  const double* y;
+  double* t;
+  const double* t_in;
+  double* y_out;
+  void* arena;        /* at least k * rhs_arena_bytes, 256-byte aligned */
+  size_t arena_bytes;
+} mfb_step_args_t;
+typedef struct mfb_graph_s* mfb_graph_t;
+mfb_status_t mfb_step_graph_create(mfb_factor_t f, uint32_t ops, const mfb_step_args_t* args,
+                                   mfb_graph_t* out);
+/* Enqueues one replay of the captured step on `stream` (MFB_EINVAL for a
+ * NULL graph, MFB_EHIP when the launch fails). */
+mfb_status_t mfb_graph_launch(mfb_graph_t g, void* stream);
+/* Frees the graph; the caller makes sure no replay is still running.
+ * NULL is ignored. */
+void mfb_graph_destroy(mfb_graph_t g);
+
 /* ---- launch profiling (tracing aid; off by default) -------------------- */
 
 /* Kernel identifiers reported by the profiler. */

@@ -1025,6 +1025,62 @@ mfb_status_t mfb_get_status(mfb_factor_t f, int64_t* bad) {
   return h.code;
 }
 
+struct mfb_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+mfb_status_t mfb_step_graph_create(mfb_factor_t f, uint32_t ops, const mfb_step_args_t* a, mfb_graph_t* out) {
+  if (!f || !a || !out || !(ops & MFB_STEP_FACTOR)) return MFB_EINVAL;
+  *out = nullptr;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MFB_EHIP;
+  const bool prof = f->prof;
+  f->prof = false;  // no events inside the graph
+  mfb_status_t st = MFB_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    st = MFB_EHIP;
+  } else {
+    st = mfb_factor(f, a->x, cs);
+    if (!st && (ops & MFB_STEP_LOGDET)) st = mfb_logdet(f, a->logdet, cs);
+    if (!st && (ops & MFB_STEP_PROJINV)) st = mfb_projected_inverse(f, a->s, cs);
+    if (!st && (ops & MFB_STEP_HESSIAN)) st = mfb_hessian(f, a->k, a->y, a->t, a->arena, a->arena_bytes, cs);
+    if (!st && (ops & MFB_STEP_INV_HESSIAN))
+      st = mfb_inv_hessian(f, a->k, a->t_in, a->y_out, a->arena, a->arena_bytes, cs);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cs, &g) != hipSuccess && !st) st = MFB_EHIP;
+    if (!st) {
+      mfb_graph_s* h = new (std::nothrow) mfb_graph_s();
+      if (!h) {
+        st = MFB_ENOMEM;
+      } else if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        delete h;
+        st = MFB_EHIP;
+      } else {
+        h->graph = g;
+        g = nullptr;
+        *out = h;
+      }
+    }
+    if (g) (void)hipGraphDestroy(g);
+  }
+  f->prof = prof;
+  (void)hipStreamDestroy(cs);
+  return st;
+}
+
+mfb_status_t mfb_graph_launch(mfb_graph_t g, void* stream) {
+  if (!g) return MFB_EINVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? MFB_OK : MFB_EHIP;
+}
+
+void mfb_graph_destroy(mfb_graph_t g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
 mfb_status_t mfb_profile_enable(mfb_factor_t f, int32_t enable) {
   if (!f) return MFB_EINVAL;
   f->prof = enable != 0;

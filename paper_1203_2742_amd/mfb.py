@@ -70,6 +70,16 @@ class PlanInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StepArgs(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("logdet", ctypes.c_void_p), ("s", ctypes.c_void_p),
+                ("k", ctypes.c_int32), ("y", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("t_in", ctypes.c_void_p), ("y_out", ctypes.c_void_p), ("arena", ctypes.c_void_p),
+                ("arena_bytes", ctypes.c_size_t)]
+
+
+STEP_FACTOR, STEP_LOGDET, STEP_PROJINV, STEP_HESSIAN, STEP_INV_HESSIAN = 1, 2, 4, 8, 16
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1203_2742_amd.build")
@@ -91,6 +101,9 @@ def _load():
         "mfb_hessian_factor": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_hessian_factor_adj": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_gram_arena_bytes": (SZ, [P, I32]),
+        "mfb_step_graph_create": (I32, [P, ctypes.c_uint32, ctypes.POINTER(StepArgs), ctypes.POINTER(P)]),
+        "mfb_graph_launch": (I32, [P, P]),
+        "mfb_graph_destroy": (None, [P]),
         "mfb_gram": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_completion": (I32, [P, P, P]),
         "mfb_cholesky_product": (I32, [P, P, P]),
@@ -286,6 +299,44 @@ def gram(plan: Plan, w, g, arena, m=None, stream=None):
     _dev_f64(g, m * m, "g")
     _chk(_lib.mfb_gram(plan.handle, m, _ptr(w), _ptr(g), _ptr(arena),
                        arena.numel() * arena.element_size(), _stream(stream)), "gram")
+
+
+class Graph:
+    """A captured step (mfb_step_graph_create); keeps its buffers alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self.keep = keep
+
+    def launch(self, stream=None):
+        _chk(_lib.mfb_graph_launch(self.handle, _stream(stream)), "graph_launch")
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.mfb_graph_destroy(h)
+
+
+def step_graph(f: Factor, ops, x, logdet=None, s=None, k=0, y=None, t=None, t_in=None, y_out=None,
+               arena=None):
+    """Capture factor(x) followed by the operations set in `ops` (STEP_*
+    flags; STEP_FACTOR is required) into one replayable graph.  The buffers
+    are bound at capture: a launch reads and writes these same tensors."""
+    nnz = f.plan.nnz
+    need = {"x": (x, nnz, STEP_FACTOR), "logdet": (logdet, 1, STEP_LOGDET), "s": (s, nnz, STEP_PROJINV),
+            "y": (y, k * nnz, STEP_HESSIAN), "t": (t, k * nnz, STEP_HESSIAN),
+            "t_in": (t_in, k * nnz, STEP_INV_HESSIAN), "y_out": (y_out, k * nnz, STEP_INV_HESSIAN)}
+    for name, (v, n, bit) in need.items():
+        if ops & bit:
+            _dev_f64(v, n, name)
+
+    def ad(v):
+        return v.data_ptr() if v is not None else None
+    a = StepArgs(ad(x), ad(logdet), ad(s), int(k), ad(y), ad(t), ad(t_in), ad(y_out), ad(arena),
+                 arena.numel() * arena.element_size() if arena is not None else 0)
+    h = ctypes.c_void_p()
+    _chk(_lib.mfb_step_graph_create(f.handle, int(ops), ctypes.byref(a), ctypes.byref(h)), "step_graph_create")
+    return Graph(h, (f, x, logdet, s, y, t, t_in, y_out, arena))
 
 
 def completion(f: Factor, s, stream=None):

@@ -84,3 +84,44 @@ def test_step_graph_replays_match_eager(name, mfb):
         mfb.hessian(f, other, scratch, arena, k=k)
         torch.cuda.synchronize()
     assert b.status() == (0, -1)
+
+
+@pytest.mark.parametrize("name", ["arrow_small", "grid3d_8"])
+def test_native_step_graph(name, mfb):
+    """mfb_step_graph_create: factor, logdet, gradient, Hessian (k = 2) and
+    inverse Hessian captured by the library itself; three replays with
+    eager work in between, each bitwise equal to the eager step."""
+    pat = CASES[name]()
+    k = 2
+    b = mfb.SparseBarrier(pat, flags=mfb.PLAN_WIDE_LOW)
+    f = b.f
+    nnz = pat[1][-1]
+    x = dev(V.make_x(*pat, seed=0))
+    y = dev(V.make_ys(*pat, k, seed=1))
+    ld = torch.empty(1, dtype=torch.float64, device="cuda")
+    s = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    t = torch.empty_like(y)
+    yi = torch.empty_like(y)
+    arena = b.arena(k)
+    ops = mfb.STEP_FACTOR | mfb.STEP_LOGDET | mfb.STEP_PROJINV | mfb.STEP_HESSIAN | mfb.STEP_INV_HESSIAN
+    mfb.factor(f, x)
+    mfb.logdet(f, ld)
+    mfb.projected_inverse(f, s)
+    mfb.hessian(f, y, t, arena, k=k)
+    mfb.inv_hessian(f, t, yi, arena, k=k)
+    want = [host(v).copy() for v in (ld, s, t, yi)]
+    g = mfb.step_graph(f, ops, x, logdet=ld, s=s, k=k, y=y, t=t, t_in=t, y_out=yi, arena=arena)
+    other = dev(V.make_ys(*pat, k, seed=9))
+    scratch = torch.empty_like(other)
+    for rep in range(3):
+        for v in (ld, s, t, yi):
+            v.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, v in enumerate((ld, s, t, yi)):
+            assert np.array_equal(host(v), want[i]), (rep, i)
+        mfb.hessian(f, other, scratch, arena, k=k)
+        torch.cuda.synchronize()
+    with pytest.raises(mfb.MfbError):
+        mfb.step_graph(f, mfb.STEP_HESSIAN, x, k=k, y=y, t=t, arena=arena)
