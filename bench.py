@@ -2,10 +2,16 @@
 
 One step = one pass over every stage of the path on one input: factor X
 (Algorithm 7.1), log det, projected inverse S = P(X^-1) (Algorithm 7.2),
-Hessian T = P(X^-1 Y X^-1) for k right-hand sides, inverse Hessian of T,
-completion of S (Algorithm 7.3) with log det X-hat, and the values of X-hat
-(Cholesky product).  Inputs are resident in HBM before timing starts; CCS
-ingest and egress are fused into the kernels.
+Hessian T = P(X^-1 Y X^-1) for k right-hand sides, completion of S
+(Algorithm 7.3) with log det X-hat, inverse Hessian of T at X-hat (the
+Hessian of the dual barrier at S), and the values of X-hat (Cholesky
+product).  Factor, log det, gradient and Hessian run on a relaxed plan
+(supernodes merged up to --relax explicit zeros; exact for these
+operations); completion, inverse Hessian and product run on the
+fundamental plan, whose handle the completion fills with the factor of
+X-hat = X.  --relax -1 runs every operation on the fundamental plan, with
+the inverse Hessian at X before the completion.  Inputs are resident in HBM
+before timing starts.
 
 The headline workload is the filled 3D 7-point grid 40^3 under nested
 dissection (n = 64000, fronts up to 2360) with k = 16 right-hand sides.  The
@@ -67,6 +73,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid3d_40")
     ap.add_argument("--k", type=int, default=16, help="Hessian right-hand sides per step")
+    ap.add_argument("--relax", type=float, default=0.05,
+                    help="zero budget of the relaxed plan of the forward operations (-1: none)")
     ap.add_argument("--batch-workload", default="arrow64")
     ap.add_argument("--batch-k", type=int, default=64)
     ap.add_argument("--cpu-columns", type=int, default=5000,
@@ -95,11 +103,15 @@ def ev(torch):
 class Step:
     """Device buffers and the operation list of one step on one workload."""
 
-    def __init__(self, torch, mfb, V, pat, k, dev, seed=0):
+    def __init__(self, torch, mfb, V, pat, k, dev, seed=0, relax=None):
         n, cp, ri = pat
         self.pat, self.k, self.nnz = pat, k, int(cp[-1])
+        self.relax = relax
         self.b = mfb.SparseBarrier(pat, device=dev)
         self.info = self.b.info
+        # the forward operations' handle (the same one without relaxation)
+        self.fw = mfb.SparseBarrier(pat, device=dev, relax=relax) if relax is not None else self.b
+        self.info_fw = self.fw.info
         self.x_h = V.make_x(*pat, seed=seed)
         self.y_h = V.make_ys(*pat, k, seed=seed)
         self.x = torch.from_numpy(self.x_h).to(dev)
@@ -109,18 +121,26 @@ class Step:
         self.y2 = torch.empty_like(self.y)
         self.xhat = torch.empty(self.nnz, dtype=torch.float64, device=dev)
         self.ld = torch.empty(2, dtype=torch.float64, device=dev)
+        # one arena serves both handles (their calls run one after another)
         self.arena = self.b.arena(k)
-        f = self.b.f
-        self.ops = [
-            ("factor", lambda: mfb.factor(f, self.x)),
-            ("logdet", lambda: mfb.logdet(f, self.ld[0:1])),
-            ("projected_inverse", lambda: mfb.projected_inverse(f, self.s)),
-            ("hessian", lambda: mfb.hessian(f, self.y, self.t, self.arena, k=k)),
-            ("inv_hessian", lambda: mfb.inv_hessian(f, self.t, self.y2, self.arena, k=k)),
+        f, g = self.b.f, self.fw.f
+        fwd = [
+            ("factor", lambda: mfb.factor(g, self.x)),
+            ("logdet", lambda: mfb.logdet(g, self.ld[0:1])),
+            ("projected_inverse", lambda: mfb.projected_inverse(g, self.s)),
+            ("hessian", lambda: mfb.hessian(g, self.y, self.t, self.arena, k=k)),
+        ]
+        inv = ("inv_hessian", lambda: mfb.inv_hessian(f, self.t, self.y2, self.arena, k=k))
+        compl = [
             ("completion", lambda: mfb.completion(f, self.s)),
             ("logdet_completion", lambda: mfb.logdet(f, self.ld[1:2])),
-            ("cholesky_product", lambda: mfb.cholesky_product(f, self.xhat)),
         ]
+        prod = ("cholesky_product", lambda: mfb.cholesky_product(f, self.xhat))
+        if relax is None:
+            self.ops = fwd + [inv] + compl + [prod]
+        else:
+            self.ops = fwd + compl + [inv, prod]
+        self.handles = [self.b] if relax is None else [self.fw, self.b]
 
     def run(self):
         for _, op in self.ops:
@@ -157,13 +177,15 @@ def per_op_times(torch, st, reps):
 def profiled_step(torch, mfb, st):
     """One step with the library's launch records (HIP events on the step's
     stream around every level launch)."""
-    f = st.b.f
-    mfb.profile_enable(f, True)
+    for h in st.handles:
+        mfb.profile_enable(h.f, True)
     torch.cuda.synchronize()
     st.run()
     torch.cuda.synchronize()
-    recs = mfb.profile_read(f)
-    mfb.profile_enable(f, False)
+    recs = []
+    for h in st.handles:
+        recs += mfb.profile_read(h.f)
+        mfb.profile_enable(h.f, False)
     return recs
 
 
@@ -249,10 +271,10 @@ def golden_check(pat, st, host):
 
     def rel(a, b):
         return float(np.sqrt(np.sum(w * (a - b) ** 2)) / np.sqrt(np.sum(w * b * b)))
-    st.b.factor(st.x)
-    ldl = host(st.b.export_ldl())
-    s = host(st.b.projected_inverse())
-    ld = float(host(st.b.logdet())[0])
+    st.fw.factor(st.x)
+    ldl = host(st.fw.export_ldl())
+    s = host(st.fw.projected_inverse())
+    ld = float(host(st.fw.logdet())[0])
     t0 = host(st.t[0])  # from the timed step, same X and Y_0
     y0 = host(st.y2[0])
     xhat = host(st.xhat)
@@ -669,9 +691,11 @@ def main():
     n, cp, ri = pat
     k = args.k
     t0 = time.perf_counter()
-    st = Step(torch, mfb, V, pat, k, dev)
+    relax = args.relax if args.relax >= 0 else None
+    st = Step(torch, mfb, V, pat, k, dev, relax=relax)
     setup_s = time.perf_counter() - t0
     info = st.info
+    st_info_fw = st.info_fw
     log(args, f"workload {args.workload}: n={n} nnz={st.nnz} k={k} (setup {setup_s:.1f} s)")
 
     for _ in range(args.warmup):
@@ -680,7 +704,7 @@ def main():
     K = args.steps
     total_ms, step_ms, wall = timed_steps(torch, st, K)
     log(args, f"timed {K} steps: {total_ms:.3f} ms (wall {wall * 1e3:.3f} ms)")
-    status = st.b.status()
+    status = max(h.status() for h in st.handles)
     value = k * K / (total_ms * 1e-3)
     if args.profile_run:
         print(json.dumps({"metric": METRIC, "value": round(value, 4), "unit": "Hessian evals/s",
@@ -715,11 +739,11 @@ def main():
         extras["served"] = served(torch, dev)
         log(args, f"served {extras['served']}")
         torch.cuda.empty_cache()
-        g2 = Step(torch, mfb, V, get_config("grid2d_128"), 1, dev)
+        g2 = Step(torch, mfb, V, get_config("grid2d_128"), 1, dev, relax=relax)
         for _ in range(3):
             g2.run()
         tot, per, _ = timed_steps(torch, g2, 20)
-        extras["grid2d_128"] = {"k": 1, "ms_per_step": round(tot / 20, 4),
+        extras["grid2d_128"] = {"k": 1, "relax": relax, "ms_per_step": round(tot / 20, 4),
                                 "p50_ms": round(float(np.percentile(per, 50)), 4),
                                 "p99_ms": round(float(np.percentile(per, 99)), 4),
                                 "per_op_ms": {kk: round(v, 4) for kk, v in per_op_times(torch, g2, 5).items()}}
@@ -746,7 +770,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": int(n), "nnz": st_nnz(cp), "k": k,
                    "nsuper": info["nsuper"], "levels": info["nlevels_up"], "max_front": info["max_front"],
-                   "step": "factor+logdet+projected_inverse+hessian(k)+inv_hessian(k)+completion+logdet+product"},
+                   "relax": relax,
+                   "relaxed_plan": None if relax is None else {
+                       "nsuper": st_info_fw["nsuper"], "levels": st_info_fw["nlevels_up"],
+                       "nnz": st_info_fw["nnz_relaxed"], "update_GB": round(st_info_fw["update_doubles"] * 8e-9, 3),
+                       "max_front": st_info_fw["max_front"]},
+                   "step": ("factor+logdet+projected_inverse+hessian(k)+inv_hessian(k)+completion+logdet+product"
+                            if relax is None else
+                            "relaxed plan: factor+logdet+projected_inverse+hessian(k); fundamental plan: "
+                            "completion+logdet+inv_hessian(k) at X-hat+product")},
         "p50_ms": round(float(np.percentile(step_ms, 50)), 4),
         "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
         "per_op_ms": {kk: round(v, 4) for kk, v in per_op.items()},

@@ -111,6 +111,10 @@ typedef struct {
    * profiler (mfb_profile_read) sum to these.  The inverse Hessian's figure
    * leaves out the one-time (S_AA)^-1 cache. */
   double bytes_factor, bytes_projinv, bytes_hessian, bytes_inv_hessian, bytes_completion, bytes_product;
+  /* entries of the pattern the sweeps run on: nnz for a plan of
+   * mfb_plan_symbolic, |V'| for one of mfb_plan_symbolic_relaxed (the other
+   * sizes, counts and bytes above then describe V' too, except nnz) */
+  int64_t nnz_relaxed;
 } mfb_plan_info_t;
 
 /* Symbolic analysis of a filled pattern (Sections 2 and 6; Algorithm 6.1).
@@ -131,6 +135,33 @@ typedef struct {
  * filled, MFB_ENOMEM on allocation failure. */
 mfb_status_t mfb_plan_symbolic(int64_t n, const int64_t* colptr_host, const int32_t* rowind_host,
                                uint32_t flags, mfb_plan_t* out);
+
+/* The same analysis on relaxed supernodes (the amalgamation Section 8
+ * names as a refinement).  The fundamental partition of V is formed first;
+ * then, from the leaves up, each supernode absorbs the child whose merge
+ * adds the fewest explicit zeros, provided the merged supernode (columns N,
+ * ancestors A) holds at most max_zero_frac * (N(N+1)/2 + N A) zeros,
+ * counting those it inherited.  The result is a filled pattern V' that
+ * contains V, with fewer, larger supernodes and far smaller update blocks;
+ * the sweeps run on V' and the caller's arrays stay on V (nnz entries of V,
+ * CCS order as above), mapped in and out by the entry points.
+ *   max_zero_frac  in [0, 1); 0 gives the fundamental partition.
+ * Exact on V' for the operations whose inputs vanish on V' \ V and whose
+ * outputs restricted to V are those of V: mfb_factor, mfb_logdet,
+ * mfb_projected_inverse, mfb_hessian (and mfb_hessian_static),
+ * mfb_cholesky_product and mfb_factor_export_ldl.  The inverse Hessian and
+ * the completion take inputs that are unknown on V' \ V, and the Hessian
+ * factor depends on the partition: mfb_inv_hessian, mfb_completion,
+ * mfb_hessian_factor and mfb_hessian_factor_adj return MFB_EINVAL on a
+ * relaxed plan.  Errors as mfb_plan_symbolic, and MFB_EINVAL for a
+ * max_zero_frac outside [0, 1). */
+mfb_status_t mfb_plan_symbolic_relaxed(int64_t n, const int64_t* colptr_host, const int32_t* rowind_host,
+                                       uint32_t flags, double max_zero_frac, mfb_plan_t* out);
+
+/* The pattern the plan's sweeps run on (V, or V' for a relaxed plan), in
+ * the CCS form mfb_plan_symbolic takes.
+ *   colptr_host  int64[n+1] or NULL; rowind_host  int32[nnz_relaxed] or NULL. */
+mfb_status_t mfb_plan_pattern(mfb_plan_t plan, int64_t* colptr_host, int32_t* rowind_host);
 
 /* Sizes, workspace requirements and canonical flop counts of a plan. */
 mfb_status_t mfb_plan_info(mfb_plan_t plan, mfb_plan_info_t* out_host);

@@ -53,13 +53,15 @@ static int64_t rhs_scratch(const mfb_plan_s* p) {
 }
 static size_t factor_bytes(const mfb_plan_s* p) {
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
-  return 3 * up(nnz * 8) + 3 * up(upd * 8) + up(size_t(std::max(1, p->ns)) * 8) + up(8) +
+  // relaxed plans: one more V' array for the caller's values mapped in or out
+  return (p->relaxed ? 4 : 3) * up(nnz * 8) + 3 * up(upd * 8) + up(size_t(std::max(1, p->ns)) * 8) + up(8) +
          up(sizeof(DevStatus)) + up(size_t(factor_scratch(p)) * 8);
 }
 static size_t rhs_bytes(const mfb_plan_s* p) {
   const size_t nnz = size_t(std::max<int64_t>(1, p->nnz)), upd = size_t(std::max<int64_t>(1, p->update_doubles));
-  return (upd + nnz + size_t(rhs_scratch(p)) + size_t(p->part_doubles)) * 8 + size_t(std::max(1, p->ns)) * 4 +
-         5 * ALIGN;
+  // relaxed plans: Y mapped onto V' (then T on V') per right-hand side
+  return (upd + nnz + size_t(rhs_scratch(p)) + size_t(p->part_doubles) + (p->relaxed ? nnz : 0)) * 8 +
+         size_t(std::max(1, p->ns)) * 4 + 6 * ALIGN;
 }
 }  // namespace mfb
 
@@ -98,7 +100,8 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
          iGm = v64(p->gmap), iHd = v32(p->cs_hdown.list), iPf = v32(p->cs_factor.pre),
          iPd = v32(p->cs_down.pre), iPh = v32(p->cs_hdown.pre), iGl = v32(p->cs_gather.list),
          iGp = v32(p->cs_gather.pre), iPi = v32(p->cs_ihd_flat.pre), iPx = v32(p->cs_compl_flat.pre),
-         iHf = v32(p->cs_hfac.list), iBv = v32(p->cs_bigv.list), iPo = v64(p->poff);
+         iHf = v32(p->cs_hfac.list), iBv = v32(p->cs_bigv.list), iPo = v64(p->poff), iVs = v32(p->vshift),
+         iZp = v64(p->zpos), iUc = v64(p->ucolptr_h);
   void* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(total, 256)) != hipSuccess) return MFB_ENOMEM;
   for (const auto& b : blobs)
@@ -146,6 +149,11 @@ static mfb_status_t ensure_device(mfb_plan_s* p) {
   p->cs_compl_flat.d_pre = (const int32_t*)at(iPx);
   p->cs_hfac.d_list = (const int32_t*)at(iHf);
   p->cs_bigv.d_list = (const int32_t*)at(iBv);
+  if (p->relaxed) {
+    p->d_vshift = (const int32_t*)at(iVs);
+    p->d_zpos = (const int64_t*)at(iZp);
+    p->d_ucolptr = (const int64_t*)at(iUc);
+  }
   return MFB_OK;
 }
 
@@ -171,6 +179,9 @@ struct mfb_factor_s {
   // building one cache invalidates the other
   double *Gam = nullptr, *Gami = nullptr;
   double *part = nullptr, *logdet = nullptr, *scratch = nullptr;
+  // relaxed plans: the caller's X mapped onto V', and the V' outputs of the
+  // product and the export before they are mapped back
+  double* Xw = nullptr;
   DevStatus* st = nullptr;
   bool has_factor = false, s_valid = false, vinv_valid = false, gam_valid = false;
   hipStream_t last = nullptr;
@@ -211,8 +222,29 @@ mfb_status_t mfb_plan_symbolic(int64_t n, const int64_t* colptr, const int32_t* 
     delete p;
     return st;
   }
-  p->colptr_h.assign(colptr, colptr + n + 1);
   *out = p;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_plan_symbolic_relaxed(int64_t n, const int64_t* colptr, const int32_t* rowind, uint32_t flags,
+                                       double max_zero_frac, mfb_plan_t* out) {
+  if (!out) return MFB_EINVAL;
+  *out = nullptr;
+  mfb_plan_s* p = new (std::nothrow) mfb_plan_s();
+  if (!p) return MFB_ENOMEM;
+  mfb_status_t st = build_plan_relaxed(n, colptr, rowind, flags, max_zero_frac, p);
+  if (st) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return MFB_OK;
+}
+
+mfb_status_t mfb_plan_pattern(mfb_plan_t p, int64_t* colptr, int32_t* rowind) {
+  if (!p) return MFB_EINVAL;
+  if (colptr) std::copy(p->colptr_h.begin(), p->colptr_h.end(), colptr);
+  if (rowind) std::copy(p->rowind_h.begin(), p->rowind_h.end(), rowind);
   return MFB_OK;
 }
 
@@ -220,7 +252,8 @@ mfb_status_t mfb_plan_info(mfb_plan_t p, mfb_plan_info_t* o) {
   if (!p || !o) return MFB_EINVAL;
   std::memset(o, 0, sizeof(*o));
   o->n = p->n;
-  o->nnz = p->nnz;
+  o->nnz = p->nnz_user;
+  o->nnz_relaxed = p->nnz;
   o->nsuper = p->ns;
   o->nlevels_up = int64_t(p->up_levels.size());
   o->nlevels_down = int64_t(p->down_levels.size());
@@ -288,6 +321,7 @@ mfb_status_t mfb_factor_create(mfb_plan_t p, void* ws, size_t bytes, mfb_factor_
   f->logdet = (double*)take(8);
   f->st = (DevStatus*)take(sizeof(DevStatus));
   f->scratch = (double*)take(size_t(factor_scratch(p)) * 8);
+  if (p->relaxed) f->Xw = (double*)take(nnz * 8);
   *out = f;
   return MFB_OK;
 }
@@ -454,6 +488,11 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
   // the cached state describes the previous X until this factor is enqueued
   f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
+  const mfb_plan_s* p = f->plan;
+  if (p->relaxed) {  // X on V' (zero on V' \ V)
+    launch_relax_in(s, 1, x, p->nnz_user, p->d_vshift, p->d_zpos, int64_t(p->zpos.size()), f->Xw, p->nnz);
+    x = f->Xw;
+  }
   struct Ctx { const double* x; } ctx{x};
   mfb_status_t st = run_classes(
       f, MFB_K_FACTOR, f->plan->cs_factor, s, 1, OP_FACTOR,
@@ -523,13 +562,19 @@ mfb_status_t mfb_projected_inverse(mfb_factor_t f, double* s_out, void* stream) 
   f->s_valid = false;  // recompute on request
   mfb_status_t st = ensure_projinv(f, s);
   if (st) return st;
-  if (s_out && f->plan->nnz)
-    HIPCHK(hipMemcpyAsync(s_out, f->S, size_t(f->plan->nnz) * 8, hipMemcpyDeviceToDevice, s));
+  const mfb_plan_s* p = f->plan;
+  if (s_out && p->nnz) {
+    if (p->relaxed)
+      launch_relax_out(s, 1, f->S, p->nnz, p->d_vshift, s_out, p->nnz_user);
+    else
+      HIPCHK(hipMemcpyAsync(s_out, f->S, size_t(p->nnz) * 8, hipMemcpyDeviceToDevice, s));
+  }
   return launched();
 }
 
 struct RhsArena {
   double *Ua, *Kt, *scr, *part;
+  double* Yw;            // relaxed plans: Y, then T, on V' (k arrays)
   int64_t upd, pstride;  // pstride: doubles of the partial area per RHS
   int32_t* act;          // Hessian step 1 activity flags, ns per RHS
 };
@@ -549,6 +594,11 @@ static mfb_status_t carve(mfb_factor_s* f, int k, void* arena, size_t bytes, Rhs
   c += up(size_t(k) * size_t(std::max<int64_t>(1, p->part_doubles)) * 8);
   a->act = (int32_t*)c;
   c += up(size_t(k) * size_t(std::max(1, p->ns)) * 4);
+  a->Yw = nullptr;
+  if (p->relaxed) {
+    a->Yw = (double*)c;
+    c += up(size_t(k) * nnz * 8);
+  }
   a->scr = (double*)c;
   return MFB_OK;
 }
@@ -653,8 +703,17 @@ static mfb_status_t hessian_run(mfb_factor_s* f, int32_t k, const double* y, dou
   mfb_status_t st;
   f->last = s;
   if ((st = ensure_projinv(f, s))) return st;
-  if ((st = hess_up_run(f, k, y, a, s))) return st;
-  return hess_down_run(f, k, t, a, s);
+  const mfb_plan_s* p = f->plan;
+  if (!p->relaxed) {
+    if ((st = hess_up_run(f, k, y, a, s))) return st;
+    return hess_down_run(f, k, t, a, s);
+  }
+  // Y onto V' in a.Yw; step 1 is its only reader, so steps 2-3 write T there
+  launch_relax_in(s, k, y, p->nnz_user, p->d_vshift, p->d_zpos, int64_t(p->zpos.size()), a.Yw, p->nnz);
+  if ((st = hess_up_run(f, k, a.Yw, a, s))) return st;
+  if ((st = hess_down_run(f, k, a.Yw, a, s))) return st;
+  launch_relax_out(s, k, a.Yw, p->nnz, p->d_vshift, t, p->nnz_user);
+  return launched();
 }
 
 mfb_status_t mfb_hessian(mfb_factor_t f, int32_t k, const double* y, double* t, void* arena,
@@ -755,7 +814,7 @@ static mfb_status_t ensure_gamma(mfb_factor_s* f, hipStream_t s) {
 
 mfb_status_t mfb_hessian_factor(mfb_factor_t f, int32_t k, const double* y, double* w, void* arena,
                                 size_t bytes, void* stream) {
-  if (!f || k < 0) return MFB_EINVAL;
+  if (!f || k < 0 || f->plan->relaxed) return MFB_EINVAL;
   if (k == 0) return MFB_OK;
   if (!y || !w) return MFB_EINVAL;
   if (!f->has_factor) return MFB_ESTATE;
@@ -781,7 +840,7 @@ mfb_status_t mfb_hessian_factor(mfb_factor_t f, int32_t k, const double* y, doub
 
 mfb_status_t mfb_hessian_factor_adj(mfb_factor_t f, int32_t k, const double* w, double* t, void* arena,
                                     size_t bytes, void* stream) {
-  if (!f || k < 0) return MFB_EINVAL;
+  if (!f || k < 0 || f->plan->relaxed) return MFB_EINVAL;
   if (k == 0) return MFB_OK;
   if (!w || !t) return MFB_EINVAL;
   if (!f->has_factor) return MFB_ESTATE;
@@ -806,7 +865,7 @@ mfb_status_t mfb_hessian_factor_adj(mfb_factor_t f, int32_t k, const double* w, 
 
 size_t mfb_gram_arena_bytes(mfb_plan_t p, int32_t m) {
   if (!p || m <= 0) return 0;
-  const GramShape g = gram_shape(std::max<int64_t>(1, p->nnz), p->n, m);
+  const GramShape g = gram_shape(std::max<int64_t>(1, p->nnz_user), p->n, m);
   return size_t(g.part_doubles) * 8;
 }
 
@@ -814,18 +873,20 @@ mfb_status_t mfb_gram(mfb_plan_t p, int32_t m, const double* w, double* gout, vo
                       void* stream) {
   if (!p || m < 0) return MFB_EINVAL;
   if (m == 0) return MFB_OK;
-  if (!w || !gout || p->nnz == 0) return MFB_EINVAL;
+  if (!w || !gout || p->nnz_user == 0) return MFB_EINVAL;
   if (!arena || (reinterpret_cast<uintptr_t>(arena) % ALIGN) != 0 || bytes < mfb_gram_arena_bytes(p, m))
     return MFB_EINVAL;
   if (mfb_status_t st = ensure_device(p)) return st;
-  const GramShape g = gram_shape(p->nnz, p->n, m);
-  launch_gram((hipStream_t)stream, g, w, p->nnz, p->n, m, p->d_colptr, (double*)arena, gout);
+  // the vectors are on the caller's pattern V (also for a relaxed plan)
+  const GramShape g = gram_shape(p->nnz_user, p->n, m);
+  launch_gram((hipStream_t)stream, g, w, p->nnz_user, p->n, m, p->relaxed ? p->d_ucolptr : p->d_colptr,
+              (double*)arena, gout);
   return launched();
 }
 
 mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double* y, void* arena,
                              size_t bytes, void* stream) {
-  if (!f || k < 0) return MFB_EINVAL;
+  if (!f || k < 0 || f->plan->relaxed) return MFB_EINVAL;
   if (k == 0) return MFB_OK;
   if (!y || !t) return MFB_EINVAL;
   if (!f->has_factor) return MFB_ESTATE;
@@ -921,7 +982,7 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
 }
 
 mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
-  if (!f || (!sin && f->plan->nnz)) return MFB_EINVAL;
+  if (!f || (!sin && f->plan->nnz) || f->plan->relaxed) return MFB_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
   f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
@@ -971,6 +1032,9 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
   f->gam_valid = false;  // the sweep's update arena U holds the Hessian factor's G
+  const mfb_plan_s* p = f->plan;
+  double* xo = x;
+  if (p->relaxed) x = f->Xw;  // on V', restricted to V below
   struct Ctx { double* x; } ctx{x};
   mfb_status_t st = run_classes(
       f, MFB_K_PRODUCT, f->plan->cs_factor, s, 1, OP_PRODUCT,
@@ -999,6 +1063,7 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
       },
       &ctx);
   if (st) return st;
+  if (p->relaxed) launch_relax_out(s, 1, f->Xw, p->nnz, p->d_vshift, xo, p->nnz_user);
   return launched();
 }
 
@@ -1007,10 +1072,12 @@ mfb_status_t mfb_factor_export_ldl(mfb_factor_t f, double* out, void* stream) {
   if (!f->has_factor) return MFB_ESTATE;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
-  const int64_t nnz = f->plan->nnz;
+  const mfb_plan_s* p = f->plan;
+  const int64_t nnz = p->nnz;
   if (nnz == 0) return MFB_OK;
   const int blocks = int(std::min<int64_t>((nnz + NT_LAUNCH - 1) / NT_LAUNCH, 4096));
-  k_export_ldl<<<blocks, NT_LAUNCH, 0, s>>>(f->R, f->plan->d_colptr, f->plan->d_colidx, nnz, out);
+  k_export_ldl<<<blocks, NT_LAUNCH, 0, s>>>(f->R, p->d_colptr, p->d_colidx, nnz, p->relaxed ? f->Xw : out);
+  if (p->relaxed) launch_relax_out(s, 1, f->Xw, nnz, p->d_vshift, out, p->nnz_user);
   return launched();
 }
 

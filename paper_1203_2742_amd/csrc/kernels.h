@@ -48,6 +48,11 @@ __global__ void k_product(DevPlan, const int32_t*, const double*, double*, doubl
 __global__ void k_logdet(const double*, int, double*);
 __global__ void k_export_ldl(const double*, const int64_t*, const int32_t*, int64_t, double*);
 __global__ void k_reset_status(DevStatus*);
+// relaxed plans: caller arrays on V in and out of the sweeps' V'
+void launch_relax_in(hipStream_t s, int k, const double* src, int64_t nu, const int32_t* shift, const int64_t* zpos,
+                     int64_t nz, double* dst, int64_t nv);
+void launch_relax_out(hipStream_t s, int k, const double* src, int64_t nv, const int32_t* shift, double* dst,
+                      int64_t nu);
 
 // Register-front kernels for fronts of order <= kRegMax[cls] (host
 // launchers; cls selects the workgroup shape).

@@ -672,6 +672,46 @@ __global__ void __launch_bounds__(NT) k_export_ldl(const double* R, const int64_
   }
 }
 
+// Relaxed plans.  In: k arrays on V (nu entries each) onto V' (nv each),
+// entry e to e + shift[e] and zero on the nz entries of V' \ V.  Out: the
+// reverse restriction.  Right-hand side r = blockIdx.y.
+__global__ void __launch_bounds__(NT) k_relax_in(const double* __restrict__ src, int64_t nu,
+                                                 const int32_t* __restrict__ shift,
+                                                 const int64_t* __restrict__ zpos, int64_t nz,
+                                                 double* __restrict__ dst, int64_t nv) {
+  src += int64_t(blockIdx.y) * nu;
+  dst += int64_t(blockIdx.y) * nv;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nu + nz; e += (int64_t)gridDim.x * NT) {
+    if (e < nu)
+      dst[e + shift[e]] = src[e];
+    else
+      dst[zpos[e - nu]] = 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_relax_out(const double* __restrict__ src, int64_t nv,
+                                                  const int32_t* __restrict__ shift, double* __restrict__ dst,
+                                                  int64_t nu) {
+  src += int64_t(blockIdx.y) * nv;
+  dst += int64_t(blockIdx.y) * nu;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < nu; e += (int64_t)gridDim.x * NT)
+    dst[e] = src[e + shift[e]];
+}
+
+void launch_relax_in(hipStream_t s, int k, const double* src, int64_t nu, const int32_t* shift, const int64_t* zpos,
+                     int64_t nz, double* dst, int64_t nv) {
+  if (k <= 0 || nu + nz == 0) return;
+  const unsigned bx = unsigned(std::min<int64_t>((nu + nz + NT - 1) / NT, 4096));
+  k_relax_in<<<dim3(bx, unsigned(k)), NT, 0, s>>>(src, nu, shift, zpos, nz, dst, nv);
+}
+
+void launch_relax_out(hipStream_t s, int k, const double* src, int64_t nv, const int32_t* shift, double* dst,
+                      int64_t nu) {
+  if (k <= 0 || nu == 0) return;
+  const unsigned bx = unsigned(std::min<int64_t>((nu + NT - 1) / NT, 4096));
+  k_relax_out<<<dim3(bx, unsigned(k)), NT, 0, s>>>(src, nv, shift, dst, nu);
+}
+
 __global__ void k_reset_status(DevStatus* st) {
   if (threadIdx.x == 0) {
     st->code = 0;

@@ -197,7 +197,20 @@ struct mfb_plan_s {
   double fl_factor = 0, fl_projinv = 0, fl_hess = 0, fl_invhess = 0, fl_invhess_x = 0,
          fl_completion = 0, fl_product = 0;
   double by_factor = 0, by_projinv = 0, by_hess = 0, by_invhess = 0, by_completion = 0, by_product = 0;
+  // the pattern the plan factors on (CCS, host)
   std::vector<int64_t> colptr_h;
+  std::vector<int32_t> rowind_h;
+  // relaxed plans: the plan is that of V', a filled superset of the
+  // caller's pattern V; the caller's arrays (nnz_user entries) are on V.
+  // Entry e of V sits at e + vshift[e] in V'; zpos lists V' \ V.
+  bool relaxed = false;
+  double relax_frac = 0;
+  int64_t nnz_user = 0;
+  std::vector<int32_t> vshift;
+  std::vector<int64_t> zpos, ucolptr_h;
+  const int32_t* d_vshift = nullptr;
+  const int64_t* d_zpos = nullptr;
+  const int64_t* d_ucolptr = nullptr;
   // device copies (uploaded on first use)
   std::mutex mu;
   void* dmem = nullptr;  // one allocation holding every index array
@@ -213,4 +226,8 @@ namespace mfb {
 // Host symbolic analysis (plan.cpp).  Fills everything except device copies.
 mfb_status_t build_plan(int64_t n, const int64_t* colptr, const int32_t* rowind, uint32_t flags,
                         mfb_plan_s* p);
+// The same on relaxed supernodes: zeros per merged supernode within `frac`
+// of its entries.
+mfb_status_t build_plan_relaxed(int64_t n, const int64_t* colptr, const int32_t* rowind, uint32_t flags,
+                                double frac, mfb_plan_s* p);
 }  // namespace mfb

@@ -27,13 +27,14 @@ static mfb_status_t validate(int64_t n, const int64_t* cp, const int32_t* ri) {
   return MFB_OK;
 }
 
+static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags,
+                                const std::vector<std::vector<int32_t>>& members,
+                                const std::vector<int32_t>& spar0, mfb_plan_s* p);
+
 mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags,
                         mfb_plan_s* p) {
   mfb_status_t st = validate(n, cp, ri);
   if (st) return st;
-  p->n = n;
-  p->nnz = n ? cp[n] : 0;
-  p->flags = flags;
 
   // Elimination tree: parent(j) = min I_j (the first off-diagonal row).
   std::vector<int32_t> epar(n), deg(n);
@@ -88,6 +89,20 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     int32_t last = members[s].back();
     if (epar[last] >= 0) spar0[s] = sn_of[epar[last]];
   }
+  return finish_plan(n, cp, ri, flags, members, spar0, p);
+}
+
+// The plan of a supernode partition (members ascending, clique-tree parent
+// spar0) of a pattern: clique-tree postorder, the supernode property of
+// every column (column c of a supernode holds rows J_s[c:]), relative
+// indices, schedules and counts.
+static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags,
+                                const std::vector<std::vector<int32_t>>& members,
+                                const std::vector<int32_t>& spar0, mfb_plan_s* p) {
+  p->n = n;
+  p->nnz = n ? cp[n] : 0;
+  p->flags = flags;
+  const int32_t ns = int32_t(members.size());
   // Postorder of the clique tree; children visited in order of their
   // representative vertex, roots likewise.
   std::vector<int32_t> chead(ns, -1), cnext(ns, -1);
@@ -710,6 +725,125 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     p->by_completion += 8 * (4 * pe + 5 * ue);
     p->by_product += 8 * (2 * pe + 2 * ue);
   }
+  p->colptr_h.assign(cp, cp + n + 1);
+  p->rowind_h.assign(ri, ri + p->nnz);
+  p->nnz_user = p->nnz;
+  return MFB_OK;
+}
+
+// Relaxed supernodes (the amalgamation mentioned in Section 8).  Bottom-up
+// over the fundamental clique tree, a parent absorbs the child whose merge
+// adds the fewest explicit zeros, as long as the merged supernode's zeros
+// (its own and those it inherited) stay within `frac` of its entries.  A
+// group of G columns whose top supernode has ancestors A is made a dense
+// trapezoid: each of its columns holds the group's later columns and A, so
+// it has G(G+1)/2 + G A entries whatever the labels, and merging child c
+// (G_c columns, ancestors A_c) into p adds G_c |J_p| - G_c |A_c| zeros.
+// The union V' of the trapezoids and V is filled in the same order (A_c
+// lies inside J_p), and the groups partition it into supernodes: the plan
+// is that of V' on this partition; the caller's arrays stay on V and are
+// mapped in and out by the entry points.
+mfb_status_t build_plan_relaxed(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags, double frac,
+                                mfb_plan_s* p) {
+  if (!(frac >= 0.0 && frac < 1.0)) return MFB_EINVAL;
+  mfb_plan_s f;
+  mfb_status_t st = build_plan(n, cp, ri, flags, &f);
+  if (st) return st;
+  const int32_t ns = f.ns;
+  std::vector<int32_t> into(ns, -1);
+  std::vector<int64_t> cols(ns), zeros(ns, 0);
+  for (int32_t s = 0; s < ns; ++s) cols[s] = f.N[s];
+  for (int32_t s = 0; s < ns; ++s) {  // postorder: the children's groups are final
+    const int64_t Js = f.J[s], As = f.J[s] - f.N[s];
+    int32_t best = -1;
+    int64_t bz = 0;
+    for (int32_t q = f.cptr[s]; q < f.cptr[s + 1]; ++q) {
+      const int32_t c = f.cidx[q];
+      const int64_t Ac = f.J[c] - f.N[c];
+      const int64_t z = zeros[c] + zeros[s] + cols[c] * (Js - Ac);
+      const double Nm = double(cols[c] + cols[s]);
+      if (double(z) <= frac * (Nm * (Nm + 1) / 2 + Nm * double(As)) && (best < 0 || z < bz)) {
+        best = c;
+        bz = z;
+      }
+    }
+    if (best >= 0) {
+      into[best] = s;
+      cols[s] += cols[best];
+      zeros[s] = bz;
+    }
+  }
+  std::vector<int32_t> top(ns);
+  for (int32_t s = ns - 1; s >= 0; --s) top[s] = into[s] < 0 ? s : top[into[s]];
+  // members of every group in ascending column order
+  std::vector<int64_t> gptr(size_t(ns) + 1, 0);
+  for (int64_t v = 0; v < n; ++v) gptr[size_t(top[f.snode_of[v]]) + 1]++;
+  for (int32_t s = 0; s < ns; ++s) gptr[s + 1] += gptr[s];
+  std::vector<int32_t> mem(static_cast<size_t>(n));
+  {
+    std::vector<int64_t> fill(gptr.begin(), gptr.end() - 1);
+    for (int64_t v = 0; v < n; ++v) mem[size_t(fill[top[f.snode_of[v]]]++)] = int32_t(v);
+  }
+  // V': column mem[g][i] holds rows mem[g][i..] followed by A of the group's top
+  std::vector<int64_t> cp2(static_cast<size_t>(n) + 1, 0);
+  for (int32_t g = 0; g < ns; ++g) {
+    if (top[g] != g) continue;
+    const int64_t G = gptr[g + 1] - gptr[g], a = f.J[g] - f.N[g];
+    for (int64_t i = 0; i < G; ++i) cp2[size_t(mem[size_t(gptr[g] + i)]) + 1] = G - i + a;
+  }
+  for (int64_t v = 0; v < n; ++v) cp2[size_t(v) + 1] += cp2[size_t(v)];
+  const int64_t nnz2 = cp2[size_t(n)];
+  if (nnz2 - cp[n] >= (int64_t(1) << 31)) return MFB_EINVAL;
+  std::vector<int32_t> ri2(static_cast<size_t>(std::max<int64_t>(1, nnz2)));
+  for (int32_t g = 0; g < ns; ++g) {
+    if (top[g] != g) continue;
+    const int64_t G = gptr[g + 1] - gptr[g], a = f.J[g] - f.N[g];
+    const int32_t* Ag = ri + cp[f.rep[g]] + f.N[g];
+    if (a > 0 && mem[size_t(gptr[g + 1] - 1)] >= Ag[0]) return MFB_ENOTCHORDAL;
+    for (int64_t i = 0; i < G; ++i) {
+      int64_t o = cp2[size_t(mem[size_t(gptr[g] + i)])];
+      for (int64_t t = i; t < G; ++t) ri2[size_t(o++)] = mem[size_t(gptr[g] + t)];
+      for (int64_t t = 0; t < a; ++t) ri2[size_t(o++)] = Ag[t];
+    }
+  }
+  // V inside V': shift of every entry, and the entries of V' \ V
+  std::vector<int32_t> shift(static_cast<size_t>(std::max<int64_t>(1, cp[n])));
+  std::vector<int64_t> zpos;
+  zpos.reserve(size_t(nnz2 - cp[n]));
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t e = cp[v];
+    for (int64_t q = cp2[size_t(v)]; q < cp2[size_t(v) + 1]; ++q) {
+      if (e < cp[v + 1] && ri[e] == ri2[size_t(q)]) {
+        shift[size_t(e)] = int32_t(q - e);
+        ++e;
+      } else {
+        zpos.push_back(q);
+      }
+    }
+    if (e != cp[v + 1]) return MFB_ENOTCHORDAL;  // V is not inside V'
+  }
+  // the merged groups are the partition of V' (Algorithm 6.1 on V' could
+  // pair a parent with another child of equal degree: a supernode need not
+  // be a range of labels, and a merged child may sit inside its parent's
+  // label range)
+  if ((st = validate(n, cp2.data(), ri2.data()))) return st;
+  std::vector<int32_t> gid(ns, -1);
+  std::vector<std::vector<int32_t>> groups;
+  for (int32_t g = 0; g < ns; ++g)
+    if (top[g] == g) {
+      gid[g] = int32_t(groups.size());
+      groups.emplace_back(mem.begin() + gptr[g], mem.begin() + gptr[g + 1]);
+    }
+  std::vector<int32_t> gpar(groups.size(), -1);
+  for (int32_t g = 0; g < ns; ++g)
+    if (top[g] == g && f.parent[g] >= 0) gpar[size_t(gid[g])] = gid[top[f.parent[g]]];
+  if ((st = finish_plan(n, cp2.data(), ri2.data(), flags, groups, gpar, p))) return st;
+  p->relaxed = true;
+  p->relax_frac = frac;
+  p->nnz_user = cp[n];
+  p->vshift = std::move(shift);
+  p->zpos = std::move(zpos);
+  p->ucolptr_h.assign(cp, cp + n + 1);
   return MFB_OK;
 }
 

@@ -64,7 +64,8 @@ class PlanInfo(ctypes.Structure):
                 ("flops_factor", "flops_projinv", "flops_hessian", "flops_inv_hessian",
                  "flops_inv_hessian_x", "flops_completion", "flops_product",
                  "bytes_factor", "bytes_projinv", "bytes_hessian", "bytes_inv_hessian",
-                 "bytes_completion", "bytes_product")]
+                 "bytes_completion", "bytes_product")] + \
+               [("nnz_relaxed", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,6 +88,8 @@ def _load():
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
         "mfb_plan_symbolic": (I32, [I64, P, P, ctypes.c_uint32, ctypes.POINTER(P)]),
+        "mfb_plan_symbolic_relaxed": (I32, [I64, P, P, ctypes.c_uint32, ctypes.c_double, ctypes.POINTER(P)]),
+        "mfb_plan_pattern": (I32, [P, P, P]),
         "mfb_plan_info": (I32, [P, ctypes.POINTER(PlanInfo)]),
         "mfb_plan_supernodes": (I32, [P, P, P, P]),
         "mfb_plan_destroy": (None, [P]),
@@ -172,15 +175,29 @@ class Plan:
             _lib.mfb_plan_destroy(h)
 
 
-def plan_symbolic(n, colptr, rowind, flags: int = 0) -> Plan:
+def plan_symbolic(n, colptr, rowind, flags: int = 0, relax=None) -> Plan:
+    """mfb_plan_symbolic, or mfb_plan_symbolic_relaxed with max_zero_frac =
+    relax when relax is not None.  Plan.nnz is the caller's pattern's."""
     cp = np.ascontiguousarray(np.asarray(colptr), dtype=np.int64)
     ri = np.ascontiguousarray(np.asarray(rowind), dtype=np.int32)
     if cp.shape != (int(n) + 1,):
         raise MfbError(EINVAL, "plan_symbolic: colptr length")
     h = ctypes.c_void_p()
-    _chk(_lib.mfb_plan_symbolic(int(n), cp.ctypes.data, ri.ctypes.data, flags, ctypes.byref(h)),
-         "plan_symbolic")
+    if relax is None:
+        _chk(_lib.mfb_plan_symbolic(int(n), cp.ctypes.data, ri.ctypes.data, flags, ctypes.byref(h)),
+             "plan_symbolic")
+    else:
+        _chk(_lib.mfb_plan_symbolic_relaxed(int(n), cp.ctypes.data, ri.ctypes.data, flags, float(relax),
+                                            ctypes.byref(h)), "plan_symbolic_relaxed")
     return Plan(h, int(n), int(cp[-1]) if n else 0)
+
+
+def plan_pattern(plan: Plan):
+    """The pattern the sweeps run on, (colptr int64[n+1], rowind int32[nnz_relaxed])."""
+    cp = np.empty(plan.n + 1, np.int64)
+    ri = np.empty(max(1, plan.info["nnz_relaxed"]), np.int32)
+    _chk(_lib.mfb_plan_pattern(plan.handle, cp.ctypes.data, ri.ctypes.data), "plan_pattern")
+    return cp, ri[:plan.info["nnz_relaxed"]]
 
 
 def plan_info(plan: Plan) -> dict:
@@ -397,10 +414,10 @@ def kernel_name(kernel: int) -> str:
 class SparseBarrier:
     """A plan plus a factor handle with torch-allocated device buffers."""
 
-    def __init__(self, pattern, device="cuda", flags=0):
+    def __init__(self, pattern, device="cuda", flags=0, relax=None):
         import torch
         n, cp, ri = pattern
-        self.plan = plan_symbolic(n, cp, ri, flags)
+        self.plan = plan_symbolic(n, cp, ri, flags, relax)
         self.info = self.plan.info
         self.nnz = self.plan.nnz
         self.device = torch.device(device)
