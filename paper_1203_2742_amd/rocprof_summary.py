@@ -50,6 +50,7 @@ OP_OF = [
     (r"^k_gram", "gram"),
     (r"^k_logdet", "logdet (2 calls)"), (r"^k_reset_status", "status reset"),
     (r"^k_export_ldl", "factor_export_ldl"),
+    (r"^k_relax_(in|out)", "relaxed-plan maps (X, Y in; S, T out)"),
 ]
 
 
