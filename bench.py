@@ -73,8 +73,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid3d_40")
     ap.add_argument("--k", type=int, default=16, help="Hessian right-hand sides per step")
-    ap.add_argument("--relax", type=float, default=0.05,
-                    help="zero budget of the relaxed plan of the forward operations (-1: none)")
+    ap.add_argument("--relax", type=float, default=None,
+                    help="zero budget of the relaxed plan of the forward operations (-1: none; default: the "
+                         "autotuner's cached choice, else 0.05)")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuner cache (default options)")
     ap.add_argument("--batch-workload", default="arrow64")
     ap.add_argument("--batch-k", type=int, default=64)
     ap.add_argument("--cpu-columns", type=int, default=5000,
@@ -103,14 +105,16 @@ def ev(torch):
 class Step:
     """Device buffers and the operation list of one step on one workload."""
 
-    def __init__(self, torch, mfb, V, pat, k, dev, seed=0, relax=None):
+    def __init__(self, torch, mfb, V, pat, k, dev, seed=0, relax=None, fwd_opts=None, fund_opts=None):
         n, cp, ri = pat
         self.pat, self.k, self.nnz = pat, k, int(cp[-1])
         self.relax = relax
-        self.b = mfb.SparseBarrier(pat, device=dev)
+        fo = {kk: int(v) for kk, v in (fund_opts or {}).items() if kk in ("wide_j", "big_a")}
+        wo = {kk: int(v) for kk, v in (fwd_opts or {}).items() if kk == "wide_j"}
+        self.b = mfb.SparseBarrier(pat, device=dev, **fo)
         self.info = self.b.info
         # the forward operations' handle (the same one without relaxation)
-        self.fw = mfb.SparseBarrier(pat, device=dev, relax=relax) if relax is not None else self.b
+        self.fw = mfb.SparseBarrier(pat, device=dev, relax=relax, **wo) if relax is not None else self.b
         self.info_fw = self.fw.info
         self.x_h = V.make_x(*pat, seed=seed)
         self.y_h = V.make_ys(*pat, k, seed=seed)
@@ -691,8 +695,24 @@ def main():
     n, cp, ri = pat
     k = args.k
     t0 = time.perf_counter()
-    relax = args.relax if args.relax >= 0 else None
-    st = Step(torch, mfb, V, pat, k, dev, relax=relax)
+    from paper_1203_2742_amd import autotune
+    devname = torch.cuda.get_device_name(dev)
+
+    def tuning_for(p, kk):
+        ent = None if args.no_tuning else autotune.lookup(p, kk, devname)
+        if ent is None:
+            return {"source": "default", "forward": dict(autotune.DEFAULT_FORWARD),
+                    "fundamental": dict(autotune.DEFAULT_FUNDAMENTAL)}
+        return {"source": f"autotuner cache ({ent['match']})", "forward": ent["forward"],
+                "fundamental": ent["fundamental"]}
+
+    def relax_of(tun):
+        r = args.relax if args.relax is not None else tun["forward"]["relax"]
+        return r if r >= 0 else None
+
+    tuning = tuning_for(pat, k)
+    relax = relax_of(tuning)
+    st = Step(torch, mfb, V, pat, k, dev, relax=relax, fwd_opts=tuning["forward"], fund_opts=tuning["fundamental"])
     setup_s = time.perf_counter() - t0
     info = st.info
     st_info_fw = st.info_fw
@@ -739,11 +759,15 @@ def main():
         extras["served"] = served(torch, dev)
         log(args, f"served {extras['served']}")
         torch.cuda.empty_cache()
-        g2 = Step(torch, mfb, V, get_config("grid2d_128"), 1, dev, relax=relax)
+        p2 = get_config("grid2d_128")
+        tun2 = tuning_for(p2, 1)
+        g2 = Step(torch, mfb, V, p2, 1, dev, relax=relax_of(tun2), fwd_opts=tun2["forward"],
+                  fund_opts=tun2["fundamental"])
         for _ in range(3):
             g2.run()
         tot, per, _ = timed_steps(torch, g2, 20)
-        extras["grid2d_128"] = {"k": 1, "relax": relax, "ms_per_step": round(tot / 20, 4),
+        extras["grid2d_128"] = {"k": 1, "relax": relax_of(tun2), "tuning": tun2["source"],
+                                "ms_per_step": round(tot / 20, 4),
                                 "p50_ms": round(float(np.percentile(per, 50)), 4),
                                 "p99_ms": round(float(np.percentile(per, 99)), 4),
                                 "per_op_ms": {kk: round(v, 4) for kk, v in per_op_times(torch, g2, 5).items()}}
@@ -771,6 +795,7 @@ def main():
         "config": {"workload": args.workload, "n": int(n), "nnz": st_nnz(cp), "k": k,
                    "nsuper": info["nsuper"], "levels": info["nlevels_up"], "max_front": info["max_front"],
                    "relax": relax,
+                   "tuning": tuning,
                    "relaxed_plan": None if relax is None else {
                        "nsuper": st_info_fw["nsuper"], "levels": st_info_fw["nlevels_up"],
                        "nnz": st_info_fw["nnz_relaxed"], "update_GB": round(st_info_fw["update_doubles"] * 8e-9, 3),

@@ -88,7 +88,8 @@ typedef struct mfb_factor_s* mfb_factor_t;
                                  for testing those kernels on small patterns.
                                  Without it, the environment variables
                                  MFB_WIDE_J and MFB_BIG_A, when set, replace
-                                 those two defaults (192, 256) at plan build */
+                                 those two defaults (192, 256) at plan build;
+                                 mfb_plan_symbolic_opts sets them directly */
 
 typedef struct {
   int64_t n;                 /* order of X */
@@ -112,7 +113,7 @@ typedef struct {
    * leaves out the one-time (S_AA)^-1 cache. */
   double bytes_factor, bytes_projinv, bytes_hessian, bytes_inv_hessian, bytes_completion, bytes_product;
   /* entries of the pattern the sweeps run on: nnz for a plan of
-   * mfb_plan_symbolic, |V'| for one of mfb_plan_symbolic_relaxed (the other
+   * mfb_plan_symbolic, |V'| for one of mfb_plan_symbolic_opts with max_zero_frac >= 0 (the other
    * sizes, counts and bytes above then describe V' too, except nnz) */
   int64_t nnz_relaxed;
 } mfb_plan_info_t;
@@ -136,27 +137,45 @@ typedef struct {
 mfb_status_t mfb_plan_symbolic(int64_t n, const int64_t* colptr_host, const int32_t* rowind_host,
                                uint32_t flags, mfb_plan_t* out);
 
-/* The same analysis on relaxed supernodes (the amalgamation Section 8
- * names as a refinement).  The fundamental partition of V is formed first;
- * then, from the leaves up, each supernode absorbs the child whose merge
- * adds the fewest explicit zeros, provided the merged supernode (columns N,
- * ancestors A) holds at most max_zero_frac * (N(N+1)/2 + N A) zeros,
- * counting those it inherited.  The result is a filled pattern V' that
- * contains V, with fewer, larger supernodes and far smaller update blocks;
- * the sweeps run on V' and the caller's arrays stay on V (nnz entries of V,
- * CCS order as above), mapped in and out by the entry points.
- *   max_zero_frac  in [0, 1); 0 gives the fundamental partition.
- * Exact on V' for the operations whose inputs vanish on V' \ V and whose
- * outputs restricted to V are those of V: mfb_factor, mfb_logdet,
- * mfb_projected_inverse, mfb_hessian (and mfb_hessian_static),
+/* The same analysis with options.  Fields:
+ *   flags          MFB_PLAN_* bits.
+ *   max_zero_frac  relaxed supernodes (the amalgamation Section 8 names as a
+ *                  refinement) when >= 0, the fundamental partition when < 0.
+ *                  The fundamental partition of V is formed first; then,
+ *                  from the leaves up, each supernode absorbs the child whose
+ *                  merge adds the fewest explicit zeros, provided the merged
+ *                  supernode (columns N, ancestors A) holds at most
+ *                  max_zero_frac * (N(N+1)/2 + N A) zeros, counting those it
+ *                  inherited.  The result is a filled pattern V' that
+ *                  contains V, with fewer, larger supernodes and far smaller
+ *                  update blocks; the sweeps run on V' and the caller's
+ *                  arrays stay on V (nnz entries of V, CCS order as above),
+ *                  mapped in and out by the entry points.  0 gives the
+ *                  fundamental partition.
+ *   wide_j         fronts of order above this run tile-parallel (>= 64; 0:
+ *                  the default 192, or 64 under MFB_PLAN_WIDE_LOW, or the
+ *                  environment's MFB_WIDE_J).
+ *   big_a          blocks S_AA with more rows than this are factored
+ *                  tile-parallel (>= 192; 0: the default 256, or 192 under
+ *                  MFB_PLAN_WIDE_LOW, or the environment's MFB_BIG_A).
+ * The thresholds change which kernels run, not the results beyond rounding.
+ * A relaxed plan is exact on V' for the operations whose inputs vanish on
+ * V' \ V and whose outputs restricted to V are those of V: mfb_factor,
+ * mfb_logdet, mfb_projected_inverse, mfb_hessian (and mfb_hessian_static),
  * mfb_cholesky_product and mfb_factor_export_ldl.  The inverse Hessian and
  * the completion take inputs that are unknown on V' \ V, and the Hessian
  * factor depends on the partition: mfb_inv_hessian, mfb_completion,
  * mfb_hessian_factor and mfb_hessian_factor_adj return MFB_EINVAL on a
- * relaxed plan.  Errors as mfb_plan_symbolic, and MFB_EINVAL for a
- * max_zero_frac outside [0, 1). */
-mfb_status_t mfb_plan_symbolic_relaxed(int64_t n, const int64_t* colptr_host, const int32_t* rowind_host,
-                                       uint32_t flags, double max_zero_frac, mfb_plan_t* out);
+ * relaxed plan.  Errors as mfb_plan_symbolic, and MFB_EINVAL for a NULL
+ * opts, max_zero_frac >= 1 or NaN, or a threshold below its minimum. */
+typedef struct {
+  uint32_t flags;
+  double max_zero_frac;
+  int32_t wide_j;
+  int32_t big_a;
+} mfb_plan_opts_t;
+mfb_status_t mfb_plan_symbolic_opts(int64_t n, const int64_t* colptr_host, const int32_t* rowind_host,
+                                    const mfb_plan_opts_t* opts, mfb_plan_t* out);
 
 /* The pattern the plan's sweeps run on (V, or V' for a relaxed plan), in
  * the CCS form mfb_plan_symbolic takes.

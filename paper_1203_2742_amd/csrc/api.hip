@@ -226,13 +226,21 @@ mfb_status_t mfb_plan_symbolic(int64_t n, const int64_t* colptr, const int32_t* 
   return MFB_OK;
 }
 
-mfb_status_t mfb_plan_symbolic_relaxed(int64_t n, const int64_t* colptr, const int32_t* rowind, uint32_t flags,
-                                       double max_zero_frac, mfb_plan_t* out) {
-  if (!out) return MFB_EINVAL;
+mfb_status_t mfb_plan_symbolic_opts(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                                    const mfb_plan_opts_t* opts, mfb_plan_t* out) {
+  if (!out || !opts) return MFB_EINVAL;
   *out = nullptr;
+  if ((opts->wide_j != 0 && opts->wide_j < kWideJLow) || (opts->big_a != 0 && opts->big_a < kVExplicitMax))
+    return MFB_EINVAL;
+  if (opts->max_zero_frac >= 1.0 || opts->max_zero_frac != opts->max_zero_frac) return MFB_EINVAL;
   mfb_plan_s* p = new (std::nothrow) mfb_plan_s();
   if (!p) return MFB_ENOMEM;
-  mfb_status_t st = build_plan_relaxed(n, colptr, rowind, flags, max_zero_frac, p);
+  PlanTuning tune;
+  tune.wide_j = opts->wide_j;
+  tune.big_a = opts->big_a;
+  mfb_status_t st = opts->max_zero_frac >= 0.0
+                        ? build_plan_relaxed(n, colptr, rowind, opts->flags, opts->max_zero_frac, p, tune)
+                        : build_plan(n, colptr, rowind, opts->flags, p, tune);
   if (st) {
     delete p;
     return st;

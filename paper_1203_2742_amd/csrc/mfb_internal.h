@@ -223,11 +223,15 @@ struct mfb_plan_s {
 };
 
 namespace mfb {
+// Plan thresholds chosen by the caller (0: the default or the environment's)
+struct PlanTuning {
+  int32_t wide_j = 0, big_a = 0;
+};
 // Host symbolic analysis (plan.cpp).  Fills everything except device copies.
 mfb_status_t build_plan(int64_t n, const int64_t* colptr, const int32_t* rowind, uint32_t flags,
-                        mfb_plan_s* p);
+                        mfb_plan_s* p, const PlanTuning& tune = PlanTuning{});
 // The same on relaxed supernodes: zeros per merged supernode within `frac`
 // of its entries.
 mfb_status_t build_plan_relaxed(int64_t n, const int64_t* colptr, const int32_t* rowind, uint32_t flags,
-                                double frac, mfb_plan_s* p);
+                                double frac, mfb_plan_s* p, const PlanTuning& tune = PlanTuning{});
 }  // namespace mfb

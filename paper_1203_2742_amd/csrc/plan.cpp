@@ -28,11 +28,11 @@ static mfb_status_t validate(int64_t n, const int64_t* cp, const int32_t* ri) {
 }
 
 static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags,
-                                const std::vector<std::vector<int32_t>>& members,
+                                const PlanTuning& tune, const std::vector<std::vector<int32_t>>& members,
                                 const std::vector<int32_t>& spar0, mfb_plan_s* p);
 
-mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags,
-                        mfb_plan_s* p) {
+mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags, mfb_plan_s* p,
+                        const PlanTuning& tune) {
   mfb_status_t st = validate(n, cp, ri);
   if (st) return st;
 
@@ -89,7 +89,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
     int32_t last = members[s].back();
     if (epar[last] >= 0) spar0[s] = sn_of[epar[last]];
   }
-  return finish_plan(n, cp, ri, flags, members, spar0, p);
+  return finish_plan(n, cp, ri, flags, tune, members, spar0, p);
 }
 
 // The plan of a supernode partition (members ascending, clique-tree parent
@@ -97,7 +97,7 @@ mfb_status_t build_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_
 // every column (column c of a supernode holds rows J_s[c:]), relative
 // indices, schedules and counts.
 static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags,
-                                const std::vector<std::vector<int32_t>>& members,
+                                const PlanTuning& tune, const std::vector<std::vector<int32_t>>& members,
                                 const std::vector<int32_t>& spar0, mfb_plan_s* p) {
   p->n = n;
   p->nnz = n ? cp[n] : 0;
@@ -279,13 +279,15 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
   // (never below kVExplicitMax: the tile-parallel path leaves C_V^-1, the
   // representation of the larger blocks)
   p->big_a = (flags & MFB_PLAN_WIDE_LOW) ? kVExplicitMax : kBigA;
-  // tuning overrides of the two default thresholds (front order above
-  // which fronts run tile-parallel; ancestor count above which S_AA is
-  // factored tile-parallel), read when the plan is built
+  // the two thresholds (front order above which fronts run tile-parallel;
+  // ancestor count above which S_AA is factored tile-parallel): the plan
+  // options when given, else the environment overrides, else the defaults
   if (!(flags & MFB_PLAN_WIDE_LOW)) {
     if (const char* e = std::getenv("MFB_WIDE_J")) p->wide_thr = std::max(kWideJLow, std::atoi(e));
     if (const char* e = std::getenv("MFB_BIG_A")) p->big_a = std::max(kVExplicitMax, std::atoi(e));
   }
+  if (tune.wide_j > 0) p->wide_thr = tune.wide_j;
+  if (tune.big_a > 0) p->big_a = tune.big_a;
   // every front above the threshold is wide in the root-to-leaf sweeps; in
   // the leaf-to-root ones those with at most kWideMaxN columns (and an
   // update block) are wide and the others fat
@@ -744,7 +746,7 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
 // is that of V' on this partition; the caller's arrays stay on V and are
 // mapped in and out by the entry points.
 mfb_status_t build_plan_relaxed(int64_t n, const int64_t* cp, const int32_t* ri, uint32_t flags, double frac,
-                                mfb_plan_s* p) {
+                                mfb_plan_s* p, const PlanTuning& tune) {
   if (!(frac >= 0.0 && frac < 1.0)) return MFB_EINVAL;
   mfb_plan_s f;
   mfb_status_t st = build_plan(n, cp, ri, flags, &f);
@@ -837,7 +839,7 @@ mfb_status_t build_plan_relaxed(int64_t n, const int64_t* cp, const int32_t* ri,
   std::vector<int32_t> gpar(groups.size(), -1);
   for (int32_t g = 0; g < ns; ++g)
     if (top[g] == g && f.parent[g] >= 0) gpar[size_t(gid[g])] = gid[top[f.parent[g]]];
-  if ((st = finish_plan(n, cp2.data(), ri2.data(), flags, groups, gpar, p))) return st;
+  if ((st = finish_plan(n, cp2.data(), ri2.data(), flags, tune, groups, gpar, p))) return st;
   p->relaxed = true;
   p->relax_frac = frac;
   p->nnz_user = cp[n];

@@ -71,6 +71,11 @@ class PlanInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("max_zero_frac", ctypes.c_double), ("wide_j", ctypes.c_int32),
+                ("big_a", ctypes.c_int32)]
+
+
 class StepArgs(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("logdet", ctypes.c_void_p), ("s", ctypes.c_void_p),
                 ("k", ctypes.c_int32), ("y", ctypes.c_void_p), ("t", ctypes.c_void_p),
@@ -82,13 +87,21 @@ STEP_FACTOR, STEP_LOGDET, STEP_PROJINV, STEP_HESSIAN, STEP_INV_HESSIAN = 1, 2, 4
 
 
 def _load():
+    # torch ships its own HIP runtime; loading it first makes the library bind
+    # to that runtime instead of bringing a second one (from the system ROCm)
+    # into the process, where device allocations of one runtime are not the
+    # other's
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1203_2742_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
         "mfb_plan_symbolic": (I32, [I64, P, P, ctypes.c_uint32, ctypes.POINTER(P)]),
-        "mfb_plan_symbolic_relaxed": (I32, [I64, P, P, ctypes.c_uint32, ctypes.c_double, ctypes.POINTER(P)]),
+        "mfb_plan_symbolic_opts": (I32, [I64, P, P, ctypes.POINTER(PlanOpts), ctypes.POINTER(P)]),
         "mfb_plan_pattern": (I32, [P, P, P]),
         "mfb_plan_info": (I32, [P, ctypes.POINTER(PlanInfo)]),
         "mfb_plan_supernodes": (I32, [P, P, P, P]),
@@ -175,20 +188,22 @@ class Plan:
             _lib.mfb_plan_destroy(h)
 
 
-def plan_symbolic(n, colptr, rowind, flags: int = 0, relax=None) -> Plan:
-    """mfb_plan_symbolic, or mfb_plan_symbolic_relaxed with max_zero_frac =
-    relax when relax is not None.  Plan.nnz is the caller's pattern's."""
+def plan_symbolic(n, colptr, rowind, flags: int = 0, relax=None, wide_j: int = 0, big_a: int = 0) -> Plan:
+    """mfb_plan_symbolic, or mfb_plan_symbolic_opts when any option is given
+    (relax: max_zero_frac of relaxed supernodes; wide_j, big_a: the two front
+    thresholds, 0 for the default).  Plan.nnz is the caller's pattern's."""
     cp = np.ascontiguousarray(np.asarray(colptr), dtype=np.int64)
     ri = np.ascontiguousarray(np.asarray(rowind), dtype=np.int32)
     if cp.shape != (int(n) + 1,):
         raise MfbError(EINVAL, "plan_symbolic: colptr length")
     h = ctypes.c_void_p()
-    if relax is None:
+    if relax is None and not wide_j and not big_a:
         _chk(_lib.mfb_plan_symbolic(int(n), cp.ctypes.data, ri.ctypes.data, flags, ctypes.byref(h)),
              "plan_symbolic")
     else:
-        _chk(_lib.mfb_plan_symbolic_relaxed(int(n), cp.ctypes.data, ri.ctypes.data, flags, float(relax),
-                                            ctypes.byref(h)), "plan_symbolic_relaxed")
+        o = PlanOpts(int(flags), -1.0 if relax is None else float(relax), int(wide_j), int(big_a))
+        _chk(_lib.mfb_plan_symbolic_opts(int(n), cp.ctypes.data, ri.ctypes.data, ctypes.byref(o), ctypes.byref(h)),
+             "plan_symbolic_opts")
     return Plan(h, int(n), int(cp[-1]) if n else 0)
 
 
@@ -414,10 +429,10 @@ def kernel_name(kernel: int) -> str:
 class SparseBarrier:
     """A plan plus a factor handle with torch-allocated device buffers."""
 
-    def __init__(self, pattern, device="cuda", flags=0, relax=None):
+    def __init__(self, pattern, device="cuda", flags=0, relax=None, wide_j=0, big_a=0):
         import torch
         n, cp, ri = pattern
-        self.plan = plan_symbolic(n, cp, ri, flags, relax)
+        self.plan = plan_symbolic(n, cp, ri, flags, relax, wide_j, big_a)
         self.info = self.plan.info
         self.nnz = self.plan.nnz
         self.device = torch.device(device)

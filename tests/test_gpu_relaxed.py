@@ -1,5 +1,5 @@
-"""GPU parity of relaxed plans (mfb_plan_symbolic_relaxed) against the CPU
-oracle on the caller's pattern V, through the C ABI.
+"""GPU parity of relaxed plans (mfb_plan_symbolic_opts with a zero
+budget) against the CPU oracle on the caller's pattern V, through the C ABI.
 
 A relaxed plan runs the sweeps on a filled superset V' of V with fewer,
 larger supernodes.  The factor of X is the same matrix on V' (its entries

@@ -1,5 +1,5 @@
-"""Host-side tests of relaxed plans (mfb_plan_symbolic_relaxed): the
-pattern V' they run on contains the caller's V, is filled, is cut into
+"""Host-side tests of relaxed plans (mfb_plan_symbolic_opts with a zero
+budget): the pattern V' they run on contains the caller's V, is filled, is cut into
 dense-trapezoid supernodes that each stay within the zero budget, and has
 as many supernodes as a separate bottom-up merge computed here from the
 fundamental partition.  No GPU."""
@@ -122,11 +122,27 @@ def test_large_grid_relaxed_statistics():
     assert info["nlevels_up"] <= base["nlevels_up"]
 
 
-@pytest.mark.parametrize("frac", [-0.1, 1.0, float("nan")])
+@pytest.mark.parametrize("frac", [1.0, 1.5, float("nan")])
 def test_relaxed_rejects_bad_budget(frac):
     with pytest.raises(mfb.MfbError) as e:
         mfb.plan_symbolic(*P.band(10, 2), relax=frac)
     assert e.value.code == mfb.EINVAL
+
+
+def test_plan_options_thresholds():
+    """A negative budget is the fundamental partition; the front thresholds
+    move fronts between kernel classes without changing the plan's
+    structure; thresholds below their minimum are refused."""
+    pat = get_config("grid3d_12")
+    base = mfb.plan_symbolic(*pat).info
+    for kw in ({"relax": -1.0}, {"wide_j": 64}, {"big_a": 192}, {"wide_j": 512, "big_a": 1024}):
+        info = mfb.plan_symbolic(*pat, **kw).info
+        for key in ("nsuper", "nnz", "nnz_relaxed", "update_doubles", "max_front", "flops_hessian"):
+            assert info[key] == base[key], (kw, key)
+    for kw in ({"wide_j": 63}, {"big_a": 191}, {"wide_j": -5}):
+        with pytest.raises(mfb.MfbError) as e:
+            mfb.plan_symbolic(*pat, **kw)
+        assert e.value.code == mfb.EINVAL
 
 
 def test_relaxed_rejects_unfilled_pattern():
