@@ -13,7 +13,9 @@ A step of a barrier method on one pattern uses two plans:
 `tune` times candidate options on the device with the library's own entry
 points (coordinate search: the budget first, then the thresholds; each
 candidate is a fresh plan and handle, timed as the median of a few calls
-after one warm-up) and stores the best in a JSON cache.  Entries are keyed by
+after one warm-up; a candidate replaces the current choice only when it is
+at least MIN_GAIN faster, so timing noise does not move the defaults) and
+stores the choice in a JSON cache.  Entries are keyed by
 a hash of the pattern, k and the device name, and carry the plan statistics
 (n, nnz, supernodes, levels, largest front); `lookup` finds the exact entry,
 or else the entry of the same device and k whose statistics are nearest
@@ -46,6 +48,7 @@ DEFAULT_FUNDAMENTAL = {"wide_j": 0, "big_a": 0}
 RELAX = (0.0, 0.01, 0.02, 0.05, 0.1, 0.2)
 WIDE_J = (96, 128, 192, 256, 384)
 BIG_A = (192, 256, 384, 512)
+MIN_GAIN = 0.02
 
 
 def pattern_hash(pattern) -> str:
@@ -176,7 +179,7 @@ def tune(pattern, k, device="cuda", cache=None, reps=2, log=print):
                 ms = timer(cand)
                 tried.append({"plan": kind, **cand, "ms": round(ms, 3)})
                 log(f"[autotune] {kind} {cand} {ms:.2f} ms")
-                if ms < best_ms:
+                if ms < (1.0 - MIN_GAIN) * best_ms:
                     best, best_ms = cand, ms
         return dict(best, ms=round(best_ms, 3))
 
