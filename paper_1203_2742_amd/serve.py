@@ -5,7 +5,9 @@ S = P(X^-1) and the Hessian products T_r = P(X^-1 Y_r X^-1), the call
 sequence of one interior-point iteration on one cone.  The server keeps
 
 * a plan cache keyed by the pattern's CCS arrays (symbolic analysis and the
-  plan's device index arrays are done once per distinct pattern);
+  plan's device index arrays are done once per distinct pattern); with
+  `relax`, plans on relaxed supernodes (exact for the gradient and the
+  Hessian, the calls a request makes);
 * a pool of factor handles per plan, each with its own workspace, reused
   across requests;
 * HBM admission: a request is started only while the device bytes of the
@@ -53,7 +55,7 @@ def pattern_key(pattern) -> str:
 
 
 class Server:
-    def __init__(self, device="cuda:0", streams: int = 4, hbm_budget: int | None = None):
+    def __init__(self, device="cuda:0", streams: int = 4, hbm_budget: int | None = None, relax=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -62,6 +64,7 @@ class Server:
             free, _ = torch.cuda.mem_get_info(self.device)
             hbm_budget = free // 2
         self.budget = int(hbm_budget)
+        self.relax = relax
         self.plans = {}                            # key -> mfb.Plan
         self.pool = collections.defaultdict(list)  # key -> free factor handles
 
@@ -69,7 +72,7 @@ class Server:
     def plan(self, key, pattern):
         if key not in self.plans:
             n, cp, ri = pattern
-            self.plans[key] = mfb.plan_symbolic(n, cp, ri)
+            self.plans[key] = mfb.plan_symbolic(n, cp, ri, relax=self.relax)
         return self.plans[key]
 
     def need_bytes(self, req: Request) -> int:

@@ -28,14 +28,15 @@ def _pool():
     return [P.er_min_degree(n, seed) for n, seed in ((300, 1), (600, 2), (900, 3), (1200, 4))]
 
 
-def test_mix_matches_alone_and_oracle(serve):
+@pytest.mark.parametrize("relax", [None, 0.05])
+def test_mix_matches_alone_and_oracle(serve, relax):
     pool = _pool()
     reqs = serve.make_requests(24, pool, seed=5, kmax=4, rate=2000.0)
-    print(f"[gpu-serve] {len(reqs)} requests over {len(pool)} patterns", flush=True)
-    srv = serve.Server(streams=4)
+    print(f"[gpu-serve] {len(reqs)} requests over {len(pool)} patterns, relax={relax}", flush=True)
+    srv = serve.Server(streams=4, relax=relax)
     mix, lat, makespan, peak = srv.run(reqs)
     assert len(mix) == len(reqs) and all(v >= 0 for v in lat.values())
-    alone, _ = serve.Server(streams=1).run_sequential(reqs)
+    alone, _ = serve.Server(streams=1, relax=relax).run_sequential(reqs)
     assert serve.alone_vs_mix(mix, alone)
     for r in reqs[:6]:
         ldl = oracle.factor(r.pattern, r.x)
