@@ -1340,7 +1340,7 @@ template <int MODE>
 __global__ void __launch_bounds__(NT) k_bigv_panel(DevPlan P, const int32_t* list, int kb, double* Cb,
                                                    const double* Out) {
   constexpr bool REV = MODE == 2;
-  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
   __shared__ double rb[WT * WLD];
   const int s = list[blockIdx.y];
   const int A = P.nrow[s] - P.ncol[s];
@@ -1368,7 +1368,7 @@ template <int MODE>
 __global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* list, int ib, const double* Cb,
                                                    double* Out) {
   constexpr bool REV = MODE == 2;
-  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
   __shared__ double rb[WT * WLD];
   const int s = list[blockIdx.y];
   const int A = P.nrow[s] - P.ncol[s];
