@@ -965,8 +965,8 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
         if (cls < kRegClasses) {
           launch_ihess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua, x->a.upd);
         } else if (cls == kWide) {
-          k_ihess_up<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua,
-                                                   x->a.upd, x->a.scr, slot);
+          launch_ihess_up_tiles(sg.lv.maxA, sg.lv.count, int(g.y), s, f->plan->dev, list, f->LB, x->a.Kt, x->y,
+                                x->a.Ua, x->a.upd, x->a.scr, slot);
           launch_wide_update(2, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, nullptr);
         } else if (cls == kFat) {

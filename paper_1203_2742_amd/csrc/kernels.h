@@ -95,6 +95,12 @@ struct WideTiles {
 void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const int32_t* pre, int count, const double* R, const double* LB, const double* Kt,
                         double* Ua, int64_t upd, const double* wsb, int64_t slot, const int32_t* act);
+// Inverse Hessian step 3, panel part of the wide fronts of a segment (maxA:
+// its largest ancestor count), tile-parallel over 64-row tiles; k
+// right-hand sides
+void launch_ihess_up_tiles(int maxA, int count, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* LB, const double* Kt, double* Y, const double* Ua, int64_t upd, double* wsb,
+                           int64_t slot);
 // tag (profile attribution): 1 inverse Hessian gather, 2 completion gather
 // tag 1 (the inverse Hessian's gather) with part: also the partial
 // products of T_AA L_AN of the fronts that have a partial area

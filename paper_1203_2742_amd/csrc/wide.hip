@@ -68,6 +68,20 @@ __device__ __forceinline__ int find_rel(const int32_t* rl, int Ac, int p) {
   return (lo < Ac && rl[lo] == p) ? lo : -1;
 }
 
+// First index t of a child's increasing relative-index list rl[0 .. Ac)
+// with rl[t] >= p (Ac when there is none).
+__device__ __forceinline__ int lower_rel(const int32_t* rl, int Ac, int p) {
+  int lo = 0, hi = Ac;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (rl[mid] < p)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Update block of a wide front, one 64 x 64 lower tile per workgroup
 // (blockIdx.x: tile of the segment, blockIdx.y: right-hand side):
@@ -1387,6 +1401,81 @@ __global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* lis
   tile_mma(T2, 0, 0, nbi, WT, 0, nbi, [&](int i, int k) { return k <= i ? X(i0 + i, i0 + k) : 0.0; },
            [&](int k, int j) { return rb[k + j * WLD]; }, sm);
   tile_store(T2, 0, 0, nbi, WT, [&](int i, int j, double acc) { X(i0 + i, j0 + j) = acc; }, false);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse Hessian step 3, panel part, of wide fronts (N <= kWideMaxN), spread
+// over 64-row tiles of the A rows: workgroup blockIdx.x = f * ta + ti (front
+// f of the segment, row tile ti; tiles beyond the front's A exit) and
+// right-hand side blockIdx.y forms rows [64 ti, 64 ti + 64) of
+// Q = L K_NN + K_AN and Y_AN = Q - G'21, where G' = sum of the children's
+// E U'_c E^T assembled child by child in the fixed order (so every entry
+// takes its terms in the order of the one-workgroup panel kernel); tile 0
+// also forms Y_NN = K_NN - G'11.  Q goes to the (front, right-hand side)
+// scratch slot, after the J x N panel area, where k_wide_update reads it.
+__global__ void __launch_bounds__(NT) k_ihess_up_tiles(DevPlan P, const int32_t* list, int count, int ta,
+                                                       const double* LB, const double* Kt, double* Y,
+                                                       const double* Ua, int64_t upd, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_GEMM];
+  __shared__ double G[WT * kWideMaxN];
+  __shared__ int64_t colc[kColCache];
+  const int f = int(blockIdx.x) / ta, ti = int(blockIdx.x) - f * ta;
+  const int s = list[f];
+  if (ti > 0 && ti * WT >= P.nrow[s] - P.ncol[s]) return;  // the whole workgroup
+  const int64_t r = blockIdx.y;
+  with_staged_cols(SnView(P, s), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N, A = v.A, J = v.J;
+    const int i0 = ti * WT, m = min(WT, A - i0);
+    const double* ua = Ua + r * upd;
+    const double* K = Kt + r * P.nnz;
+    double* y = Y + r * P.nnz;
+    auto assemble = [&](int lo, int hi, int ld) {  // rows of the front [lo, hi), into G(row - lo, col)
+      for (int e = threadIdx.x; e < WT * kWideMaxN; e += NT) G[e] = 0.0;
+      __syncthreads();
+      for (int t = P.cptr[v.s]; t < P.cptr[v.s + 1]; ++t) {
+        const int c = P.cidx[t];
+        const int Ac = P.nrow[c] - P.ncol[c];
+        const int32_t* rl = P.rel + P.relbase[c];
+        const double* Uc = ua + P.arena[c];
+        const int xb = lower_rel(rl, Ac, lo), xe = lower_rel(rl, Ac, hi);
+        for (int yy = 0; yy < Ac; ++yy) {
+          const int ry = rl[yy];  // the same for every thread
+          if (ry >= N) break;
+          for (int x = max(xb, yy) + int(threadIdx.x); x < xe; x += NT)
+            G[(rl[x] - lo) + (int64_t)ry * ld] += Uc[pk(x, yy, Ac)];
+        }
+        __syncthreads();
+      }
+    };
+    if (m > 0) {
+      assemble(N + i0, N + i0 + m, WT);
+      double* Q = wsb + (r * count + f) * slot + (int64_t)J * N;
+      wg_gemm<false, true>(
+          m, N, N, [&](int i, int k) { return LB[v.an(i0 + i, k)]; }, [&](int k, int j) { return K[v.nn(k, j)]; },
+          [&](int i, int j, double acc) {
+            const double q = acc + K[v.an(i0 + i, j)];
+            Q[(i0 + i) + (int64_t)j * A] = q;
+            y[v.an(i0 + i, j)] = q - G[i + j * WT];
+          },
+          false, sm);
+    }
+    if (ti == 0) {
+      __syncthreads();  // G is reused
+      assemble(0, N, N);
+      for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+        const int i = int(e % N), c = int(e / N);
+        if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + c * N];
+      }
+    }
+  });
+}
+
+void launch_ihess_up_tiles(int maxA, int count, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* LB, const double* Kt, double* Y, const double* Ua, int64_t upd, double* wsb,
+                           int64_t slot) {
+  const int ta = std::max(1, (maxA + WT - 1) / WT);
+  k_ihess_up_tiles<<<dim3(unsigned(count * ta), unsigned(k)), NT, 0, s>>>(P, list, count, ta, LB, Kt, Y, Ua, upd,
+                                                                          wsb, slot);
 }
 
 // ---------------------------------------------------------------------------
