@@ -965,8 +965,8 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
         if (cls < kRegClasses) {
           launch_ihess_up_reg(cls, g, s, f->plan->dev, list, f->LB, x->a.Kt, x->y, x->a.Ua, x->a.upd);
         } else if (cls == kWide) {
-          launch_ihess_up_tiles(sg.lv.maxA, sg.lv.count, int(g.y), s, f->plan->dev, list, f->LB, x->a.Kt, x->y,
-                                x->a.Ua, x->a.upd, x->a.scr, slot);
+          launch_up_panel_tiles(UP_IHESS, sg.lv.maxA, sg.lv.count, int(g.y), s, f->plan->dev, list, nullptr, f->LB,
+                                x->a.Kt, x->y, x->a.Ua, x->a.upd, x->a.scr, slot);
           launch_wide_update(2, dim3(unsigned(sg.n_aa), g.y), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, nullptr, f->LB, x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, nullptr);
         } else if (cls == kFat) {
@@ -1052,8 +1052,8 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
         if (cls < kRegClasses) {
           launch_product_reg(cls, g, s, f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U);
         } else if (cls == kWide) {
-          k_product<true><<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->R, ((Ctx*)c)->x, f->U,
-                                                  f->scratch, slot);
+          launch_up_panel_tiles(UP_PRODUCT, sg.lv.maxA, sg.lv.count, 1, s, f->plan->dev, list, f->R, nullptr, nullptr,
+                                ((Ctx*)c)->x, f->U, 0, f->scratch, slot);
           launch_wide_update(3, dim3(unsigned(sg.n_aa)), s, f->plan->dev, list, cs.d_pre + sg.aa_off,
                              sg.lv.count, f->R, f->LB, nullptr, f->U, 0, f->scratch, slot, nullptr);
         } else if (cls == kFat) {

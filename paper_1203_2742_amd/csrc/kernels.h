@@ -95,12 +95,13 @@ struct WideTiles {
 void launch_wide_update(int op, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                         const int32_t* pre, int count, const double* R, const double* LB, const double* Kt,
                         double* Ua, int64_t upd, const double* wsb, int64_t slot, const int32_t* act);
-// Inverse Hessian step 3, panel part of the wide fronts of a segment (maxA:
-// its largest ancestor count), tile-parallel over 64-row tiles; k
-// right-hand sides
-void launch_ihess_up_tiles(int maxA, int count, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
-                           const double* LB, const double* Kt, double* Y, const double* Ua, int64_t upd, double* wsb,
-                           int64_t slot);
+// Panel part of the product (UP_PRODUCT, Y = X, k = 1) or of the inverse
+// Hessian's step 3 (UP_IHESS) for the wide fronts of a segment (maxA: its
+// largest ancestor count), tile-parallel over 64-row tiles
+enum { UP_PRODUCT = 0, UP_IHESS = 1 };
+void launch_up_panel_tiles(int up, int maxA, int count, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* R, const double* LB, const double* Kt, double* Y, const double* Ua,
+                           int64_t upd, double* wsb, int64_t slot);
 // tag (profile attribution): 1 inverse Hessian gather, 2 completion gather
 // tag 1 (the inverse Hessian's gather) with part: also the partial
 // products of T_AA L_AN of the fronts that have a partial area

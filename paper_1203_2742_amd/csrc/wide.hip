@@ -1404,18 +1404,25 @@ __global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* lis
 }
 
 // ---------------------------------------------------------------------------
-// Inverse Hessian step 3, panel part, of wide fronts (N <= kWideMaxN), spread
-// over 64-row tiles of the A rows: workgroup blockIdx.x = f * ta + ti (front
-// f of the segment, row tile ti; tiles beyond the front's A exit) and
-// right-hand side blockIdx.y forms rows [64 ti, 64 ti + 64) of
-// Q = L K_NN + K_AN and Y_AN = Q - G'21, where G' = sum of the children's
-// E U'_c E^T assembled child by child in the fixed order (so every entry
-// takes its terms in the order of the one-workgroup panel kernel); tile 0
-// also forms Y_NN = K_NN - G'11.  Q goes to the (front, right-hand side)
-// scratch slot, after the J x N panel area, where k_wide_update reads it.
-__global__ void __launch_bounds__(NT) k_ihess_up_tiles(DevPlan P, const int32_t* list, int count, int ta,
-                                                       const double* LB, const double* Kt, double* Y,
-                                                       const double* Ua, int64_t upd, double* wsb, int64_t slot) {
+// Panel part of the leaf-to-root sweeps of wide fronts (N <= kWideMaxN) that
+// need nothing but the children's update blocks and the front's own columns,
+// spread over 64-row tiles of the A rows: workgroup blockIdx.x = f * ta + ti
+// (front f of the segment, row tile ti; tiles beyond the front's A exit),
+// right-hand side blockIdx.y.  G' = sum of the children's E U_c E^T is
+// assembled child by child in the fixed order, so every entry takes its terms
+// in the order of the one-workgroup panel kernels (k_product<true>,
+// k_ihess_up<true>), and the products use the same 64-row tiles.
+//   UP_PRODUCT (Algorithm 3.2): X_AN = R_AN C^T - G'21 on tile ti's rows and,
+//     on tile 0, X_NN = C C^T - G'11 (C the lower N x N block of R);
+//   UP_IHESS (inverse Hessian step 3): Q = L K_NN + K_AN and
+//     Y_AN = Q - G'21 on tile ti's rows, Y_NN = K_NN - G'11 on tile 0; Q
+//     goes to the (front, right-hand side) scratch slot, after the J x N
+//     panel area, where k_wide_update reads it.
+template <int UP>
+__global__ void __launch_bounds__(NT) k_up_panel_tiles(DevPlan P, const int32_t* list, int count, int ta,
+                                                       const double* R, const double* LB, const double* Kt,
+                                                       double* Y, const double* Ua, int64_t upd, double* wsb,
+                                                       int64_t slot) {
   __shared__ double sm[SMEM_GEMM];
   __shared__ double G[WT * kWideMaxN];
   __shared__ int64_t colc[kColCache];
@@ -1427,8 +1434,9 @@ __global__ void __launch_bounds__(NT) k_ihess_up_tiles(DevPlan P, const int32_t*
     const int N = v.N, A = v.A, J = v.J;
     const int i0 = ti * WT, m = min(WT, A - i0);
     const double* ua = Ua + r * upd;
-    const double* K = Kt + r * P.nnz;
+    const double* K = UP == UP_IHESS ? Kt + r * P.nnz : nullptr;
     double* y = Y + r * P.nnz;
+    auto C = [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; };
     auto assemble = [&](int lo, int hi, int ld) {  // rows of the front [lo, hi), into G(row - lo, col)
       for (int e = threadIdx.x; e < WT * kWideMaxN; e += NT) G[e] = 0.0;
       __syncthreads();
@@ -1449,33 +1457,48 @@ __global__ void __launch_bounds__(NT) k_ihess_up_tiles(DevPlan P, const int32_t*
     };
     if (m > 0) {
       assemble(N + i0, N + i0 + m, WT);
-      double* Q = wsb + (r * count + f) * slot + (int64_t)J * N;
-      wg_gemm<false, true>(
-          m, N, N, [&](int i, int k) { return LB[v.an(i0 + i, k)]; }, [&](int k, int j) { return K[v.nn(k, j)]; },
-          [&](int i, int j, double acc) {
-            const double q = acc + K[v.an(i0 + i, j)];
-            Q[(i0 + i) + (int64_t)j * A] = q;
-            y[v.an(i0 + i, j)] = q - G[i + j * WT];
-          },
-          false, sm);
+      if (UP == UP_PRODUCT) {
+        wg_gemm(
+            m, N, N, [&](int i, int k) { return R[v.an(i0 + i, k)]; }, [&](int k, int j) { return C(j, k); },
+            [&](int i, int j, double acc) { y[v.an(i0 + i, j)] = acc - G[i + j * WT]; }, false, sm);
+      } else {
+        double* Q = wsb + (r * count + f) * slot + (int64_t)J * N;
+        wg_gemm<false, true>(
+            m, N, N, [&](int i, int k) { return LB[v.an(i0 + i, k)]; }, [&](int k, int j) { return K[v.nn(k, j)]; },
+            [&](int i, int j, double acc) {
+              const double q = acc + K[v.an(i0 + i, j)];
+              Q[(i0 + i) + (int64_t)j * A] = q;
+              y[v.an(i0 + i, j)] = q - G[i + j * WT];
+            },
+            false, sm);
+      }
     }
     if (ti == 0) {
       __syncthreads();  // G is reused
       assemble(0, N, N);
-      for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
-        const int i = int(e % N), c = int(e / N);
-        if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + c * N];
+      if (UP == UP_PRODUCT) {
+        wg_gemm(
+            N, N, N, C, [&](int k, int j) { return C(j, k); },
+            [&](int i, int j, double acc) { y[v.at(i, j)] = acc - G[i + j * N]; }, true, sm);
+      } else {
+        for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+          const int i = int(e % N), c = int(e / N);
+          if (i >= c) y[v.at(i, c)] = K[v.at(i, c)] - G[i + c * N];
+        }
       }
     }
   });
 }
 
-void launch_ihess_up_tiles(int maxA, int count, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
-                           const double* LB, const double* Kt, double* Y, const double* Ua, int64_t upd, double* wsb,
-                           int64_t slot) {
+void launch_up_panel_tiles(int up, int maxA, int count, int k, hipStream_t s, const DevPlan& P, const int32_t* list,
+                           const double* R, const double* LB, const double* Kt, double* Y, const double* Ua,
+                           int64_t upd, double* wsb, int64_t slot) {
   const int ta = std::max(1, (maxA + WT - 1) / WT);
-  k_ihess_up_tiles<<<dim3(unsigned(count * ta), unsigned(k)), NT, 0, s>>>(P, list, count, ta, LB, Kt, Y, Ua, upd,
-                                                                          wsb, slot);
+  const dim3 grid(unsigned(count * ta), unsigned(k));
+  if (up == UP_PRODUCT)
+    k_up_panel_tiles<UP_PRODUCT><<<grid, NT, 0, s>>>(P, list, count, ta, R, LB, Kt, Y, Ua, upd, wsb, slot);
+  else
+    k_up_panel_tiles<UP_IHESS><<<grid, NT, 0, s>>>(P, list, count, ta, R, LB, Kt, Y, Ua, upd, wsb, slot);
 }
 
 // ---------------------------------------------------------------------------
