@@ -69,17 +69,23 @@ __device__ __forceinline__ int find_rel(const int32_t* rl, int Ac, int p) {
 }
 
 // First index t of a child's increasing relative-index list rl[0 .. Ac)
-// with rl[t] >= p (Ac when there is none).
+// with rl[t] >= p (Ac when there is none), by a 64-way search of each
+// wavefront: every round probes 64 increasing positions at once and keeps
+// the gap the answer lies in, so a list of up to 64 * 65 entries takes two
+// dependent loads.  Called by whole wavefronts (the result is uniform).
 __device__ __forceinline__ int lower_rel(const int32_t* rl, int Ac, int p) {
-  int lo = 0, hi = Ac;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (rl[mid] < p)
-      lo = mid + 1;
-    else
-      hi = mid;
+  const int lane = int(threadIdx.x) & 63;
+  int lo = 0, hi = Ac;  // the answer lies in [lo, hi]
+  while (hi - lo > 64) {
+    const int n = hi - lo;
+    const bool lt = rl[lo + int((int64_t)(lane + 1) * n / 65)] < p;
+    const int c = __popcll(__ballot(lt));  // probes below p: a prefix of the lanes
+    const int nlo = c > 0 ? lo + int((int64_t)c * n / 65) + 1 : lo;
+    hi = c < 64 ? lo + int((int64_t)(c + 1) * n / 65) : hi;
+    lo = nlo;
   }
-  return lo;
+  const bool lt = lane < hi - lo && rl[lo + lane] < p;
+  return lo + __popcll(__ballot(lt));
 }
 
 // ---------------------------------------------------------------------------

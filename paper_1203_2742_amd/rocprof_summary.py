@@ -51,6 +51,7 @@ OP_OF = [
     (r"^k_logdet", "logdet (2 calls)"), (r"^k_reset_status", "status reset"),
     (r"^k_export_ldl", "factor_export_ldl"),
     (r"^k_relax_(in|out)", "relaxed-plan maps (X, Y in; S, T out)"),
+    (r"^k_up_panel_tiles<0>", "cholesky_product"), (r"^k_up_panel_tiles<1>", "inv_hessian"),
 ]
 
 
