@@ -520,3 +520,28 @@ def test_large_grid_sampled(mfb):
     close(pat, host(c.cholesky_product()), x)
     fstar = float(host(c.logdet())[0]) - n
     assert abs(fstar - (ld - n)) / abs(ld - n) <= TOL
+
+
+@pytest.mark.parametrize("shape", ["band300_w100", "arrow100x2_250", "grid3d_8"])
+def test_wide_inverse_hessian_batched(shape, mfb):
+    """The tile-parallel panel part of the inverse Hessian's step 3 (fronts
+    x 64-row tiles x right-hand sides in one grid) with k = 3 under
+    MFB_PLAN_WIDE_LOW: every right-hand side against the oracle, and each
+    one alone bitwise equal to its column of the batch."""
+    pat = {"band300_w100": lambda: P.band(300, 100),
+           "arrow100x2_250": lambda: P.block_arrow([100, 100], 250),
+           "grid3d_8": lambda: get_config("grid3d_8")}[shape]()
+    x = V.make_x(*pat, seed=0)
+    ys = V.make_ys(*pat, 3, seed=9)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    with cf.ThreadPoolExecutor(3) as ex:
+        ts = [q.result() for q in [ex.submit(oracle.hessian, pat, ldl, s, y) for y in ys]]
+    print(f"[gpu-parity] batched wide inverse Hessian {shape}", flush=True)
+    b = mfb.SparseBarrier(pat, flags=mfb.PLAN_WIDE_LOW)
+    b.factor(dev(x))
+    yk = host(b.inv_hessian(dev(np.stack(ts))))
+    for r in range(3):
+        close(pat, yk[r], ys[r], 1e-9)
+        assert np.array_equal(host(b.inv_hessian(dev(ts[r]))), yk[r])
+    close(pat, host(b.cholesky_product()), x)
