@@ -788,7 +788,8 @@ static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
         if (cls < kRegClasses)
           launch_vinv_reg(cls, g, s, f->plan->dev, list, f->Vs, f->Vi, f->st);
         else if (cls == kBigV)  // factor formed in U, its inverse into Vi
-          launch_bigv(0, sg.lv.maxA, sg.lv.count, s, f->plan->dev, list, f->Vs, f->U, f->Vi, f->st);
+          launch_bigv(0, sg.lv.maxA, sg.lv.count, sg.acnt.empty() ? nullptr : sg.acnt.data(), s, f->plan->dev,
+                      list, f->Vs, f->U, f->Vi, f->st);
         else
           k_vinv<<<g, NT_LAUNCH, 0, s>>>(f->plan->dev, list, f->Vs, f->Vi, f->st, f->scratch, slot);
       },
@@ -809,7 +810,8 @@ static mfb_status_t ensure_gamma(mfb_factor_s* f, hipStream_t s) {
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t, void*) {
         const int32_t* list = cs.d_list + sg.lv.begin;
         if (sg.cls == kBigV)
-          launch_bigv(2, sg.lv.maxA, sg.lv.count, s, f->plan->dev, list, f->Vs, f->Gam, f->Gami, f->st);
+          launch_bigv(2, sg.lv.maxA, sg.lv.count, sg.acnt.empty() ? nullptr : sg.acnt.data(), s, f->plan->dev,
+                      list, f->Vs, f->Gam, f->Gami, f->st);
         else
           launch_gamma(g, s, f->plan->dev, list, f->Vs, f->Gam, f->Gami, f->st);
       },
@@ -1006,8 +1008,8 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   st = run_classes(
       f, MFB_K_COMPL_SAA, f->plan->cs_bigv, s, 1, OP_VINV,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3, hipStream_t s, int64_t, void*) {
-        launch_bigv(1, sg.lv.maxA, sg.lv.count, s, f->plan->dev, cs.d_list + sg.lv.begin, f->Vs, f->U, f->Vi,
-                    f->st);
+        launch_bigv(1, sg.lv.maxA, sg.lv.count, sg.acnt.empty() ? nullptr : sg.acnt.data(), s, f->plan->dev,
+                    cs.d_list + sg.lv.begin, f->Vs, f->U, f->Vi, f->st);
       },
       nullptr);
   if (st) return st;

@@ -138,8 +138,10 @@ void launch_fat_completion(const FatGrid& g, hipStream_t s, const DevPlan& P, co
 // 0: for the inverse Hessian, 1: for the completion (failures reported as
 // no completion), 2: for the Hessian factor, on the reversed view, giving
 // G (G^T G = S_AA) and G^-1.
-void launch_bigv(int mode, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
-                 const double* Vs, double* Cb, double* Out, DevStatus* st);
+// acnt (host, may be null): the segment's prefix counts (ClassSeg::acnt),
+// so that each step launches only the fronts it has work for.
+void launch_bigv(int mode, int maxA, int count, const int32_t* acnt, hipStream_t s, const DevPlan& P,
+                 const int32_t* list, const double* Vs, double* Cb, double* Out, DevStatus* st);
 // part: the gather's partial products of T_AA L (nullptr when the gather
 // took the source map), per-RHS stride pstride
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,

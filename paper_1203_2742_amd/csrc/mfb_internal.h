@@ -131,6 +131,9 @@ struct ClassSeg {
   // sizes of the per-front tile sets (largest front)
   int32_t aa_off = 0, an_off = 0, nn_off = 0, n_aa = 0, n_an = 0, n_nn = 0;
   int32_t fat_panel = 0, fat_fin = 0;
+  // kBigV segments (fronts in decreasing order of A): acnt[t] = number of
+  // fronts with A > 64 t, the prefix of the list a step at row 64 t needs
+  std::vector<int32_t> acnt;
 };
 struct ClassSched {
   std::vector<int32_t> list;

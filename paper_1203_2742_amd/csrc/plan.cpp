@@ -490,6 +490,22 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
   // V_s^-1 needs only V_s; the completion's sweeps need only S and V_s,
   // which a gather pass puts in place beforehand.
   make_flat(true, OP_VINV, p->cs_vinv);
+  for (ClassSeg& g : p->cs_vinv.segs)
+    if (g.cls == kBigV) {
+      const int steps = (g.lv.maxA + 63) / 64 + 2;
+      auto a_of = [&](int32_t t) { return p->J[p->cs_vinv.list[t]] - p->N[p->cs_vinv.list[t]]; };
+      bool sorted = true;
+      for (int32_t t = g.lv.begin + 1; t < g.lv.begin + g.lv.count; ++t) sorted = sorted && a_of(t) <= a_of(t - 1);
+      // the length of the prefix with A > 64 q (every front when the list
+      // were not in decreasing order of A)
+      g.acnt.assign(size_t(steps), g.lv.count);
+      if (sorted)
+        for (int q = 0; q < steps; ++q) {
+          int32_t c = 0;
+          while (c < g.lv.count && a_of(g.lv.begin + c) > 64 * q) ++c;
+          g.acnt[size_t(q)] = c;
+        }
+    }
   make_flat(false, OP_COMPLETION, p->cs_compl_flat);
   // the A^3 of the completion's fronts with A > big_a belongs to the
   // tile-parallel factorization that precedes its per-front launches

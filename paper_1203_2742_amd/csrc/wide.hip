@@ -1627,30 +1627,38 @@ void launch_fat_up_fin(int op, const FatGrid& g, int k, hipStream_t s, const Dev
 }
 
 template <int MODE>
-static void bigv_launches(int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Vs,
-                          double* Cb, double* Out, DevStatus* st) {
-  const unsigned c = unsigned(count);
+static void bigv_launches(int maxA, int count, const int32_t* acnt, hipStream_t s, const DevPlan& P,
+                          const int32_t* list, const double* Vs, double* Cb, double* Out, DevStatus* st) {
+  // the fronts a step at row kb needs are those with A > kb (A > kb + 64
+  // for the row tiles below the diagonal block): acnt[kb / 64] of them, a
+  // prefix of the list (decreasing A); without acnt every front is launched
+  // and the others exit
+  auto fronts = [&](int kb) { return acnt ? std::min(count, acnt[kb / WT]) : count; };
   const int64_t m = (int64_t)maxA * (maxA + 1) / 2;
-  k_bigv_copy<MODE><<<dim3(unsigned(std::min<int64_t>(64, (m + NT * 16 - 1) / (NT * 16))), c), NT, 0, s>>>(P, list, Vs,
-                                                                                                     Cb);
+  k_bigv_copy<MODE><<<dim3(unsigned(std::min<int64_t>(64, (m + NT * 16 - 1) / (NT * 16))), unsigned(count)), NT, 0,
+                      s>>>(P, list, Vs, Cb);
   for (int kb = 0; kb < maxA; kb += WT) {
     const int rows = (maxA - kb - 1) / WT;  // row tiles below the diagonal block (largest front)
-    k_bigv_diag<MODE><<<dim3(1, c), NT, 0, s>>>(P, list, kb, Cb, Out, st);
-    if (rows > 0) k_bigv_panel<MODE><<<dim3(unsigned(rows), c), NT, 0, s>>>(P, list, kb, Cb, Out);
+    if (const int c = fronts(kb)) k_bigv_diag<MODE><<<dim3(1, unsigned(c)), NT, 0, s>>>(P, list, kb, Cb, Out, st);
+    if (rows > 0)
+      if (const int c = fronts(kb + WT))
+        k_bigv_panel<MODE><<<dim3(unsigned(rows), unsigned(c)), NT, 0, s>>>(P, list, kb, Cb, Out);
   }
   const int ta = (maxA + WT - 1) / WT;
-  for (int ib = 1; ib < ta; ++ib) k_bigv_trtri<MODE><<<dim3(unsigned(ib), c), NT, 0, s>>>(P, list, ib, Cb, Out);
+  for (int ib = 1; ib < ta; ++ib)
+    if (const int c = fronts(ib * WT))
+      k_bigv_trtri<MODE><<<dim3(unsigned(ib), unsigned(c)), NT, 0, s>>>(P, list, ib, Cb, Out);
 }
 
-void launch_bigv(int mode, int maxA, int count, hipStream_t s, const DevPlan& P, const int32_t* list,
-                 const double* Vs, double* Cb, double* Out, DevStatus* st) {
+void launch_bigv(int mode, int maxA, int count, const int32_t* acnt, hipStream_t s, const DevPlan& P,
+                 const int32_t* list, const double* Vs, double* Cb, double* Out, DevStatus* st) {
   if (count == 0 || maxA <= P.big_a) return;
   if (mode == 0)
-    bigv_launches<0>(maxA, count, s, P, list, Vs, Cb, Out, st);
+    bigv_launches<0>(maxA, count, acnt, s, P, list, Vs, Cb, Out, st);
   else if (mode == 1)
-    bigv_launches<1>(maxA, count, s, P, list, Vs, Cb, Out, st);
+    bigv_launches<1>(maxA, count, acnt, s, P, list, Vs, Cb, Out, st);
   else
-    bigv_launches<2>(maxA, count, s, P, list, Vs, Cb, Out, st);
+    bigv_launches<2>(maxA, count, acnt, s, P, list, Vs, Cb, Out, st);
 }
 
 void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, const int32_t* list, int count,
