@@ -201,6 +201,106 @@ __device__ __forceinline__ void tile_mma(MfmaTile& T, int i0, int j0, int M, int
   }
 }
 
+// A 64 x NC output tile (NC = 16 or 32) for products with few columns:
+// wavefront w owns rows 16 w .. 16 w + 15 as NC / 16 blocks of 16 x 16
+// (lane layout as MfmaTile).  Each entry takes the same 4-wide k-steps in
+// the same order as in a 64 x 64 tile, so it gets the same value, with a
+// quarter (NC = 16) or half (NC = 32) of the matrix-core work when the
+// other columns would be empty.
+template <int NC>
+struct NarrowTile {
+  static_assert(NC == 16 || NC == 32, "16 or 32 columns");
+  v4d acc[NC / 16];
+  int wr, lr, lk;
+  __device__ __forceinline__ explicit NarrowTile(int tid) {
+    wr = (tid >> 6) * 16;
+    lr = tid & 15;
+    lk = (tid & 63) >> 4;
+#pragma unroll
+    for (int b = 0; b < NC / 16; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  // the KC k-steps of one staged chunk (As: [k][LDS_TM], Bs: [k][NC + 1])
+  __device__ __forceinline__ void chunk(const double* As, const double* Bs) {
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = 4 * s + lk;
+      const double a = As[k * LDS_TM + wr + lr];
+#pragma unroll
+      for (int b = 0; b < NC / 16; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[k * (NC + 1) + 16 * b + lr], acc[b], 0, 0, 0);
+    }
+  }
+  static constexpr int kEntries = 4 * (NC / 16);
+  __device__ __forceinline__ double get(int e) const { return acc[e >> 2][e & 3]; }
+  __device__ __forceinline__ int row_of(int e) const { return wr + lk + 4 * (e & 3); }
+  __device__ __forceinline__ int col_of(int e) const { return 16 * (e >> 2) + lr; }
+};
+
+// tile_mma for a NarrowTile at (i0, j0): accumulates
+// sum_{kb <= k < ke} a(i, k) b(k, j) over rows i < M, columns j < N.
+template <bool AK = false, bool BK = false, int NC, class FA, class FB>
+__device__ __forceinline__ void tile_mma_narrow(NarrowTile<NC>& T, int i0, int j0, int M, int N, int kb, int ke,
+                                                const FA& fa, const FB& fb, double* sm) {
+  double* As = sm;
+  double* Bs = sm + KC * LDS_TM;
+  const int tid = threadIdx.x;
+  constexpr int PA = KC * TM / NT, PB = (KC * NC + NT - 1) / NT;
+  auto slot_a = [&](int q, int& i, int& k) {
+    const int e = tid + q * NT;
+    i = AK ? e / KC : e & (TM - 1);
+    k = AK ? e & (KC - 1) : e / TM;
+  };
+  auto slot_b = [&](int q, int& j, int& k) {  // valid when e < KC * NC
+    const int e = tid + q * NT;
+    j = BK ? e / KC : e % NC;
+    k = BK ? e % KC : e / NC;
+  };
+  double ra[PA], rb[PB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      int i, ka;
+      slot_a(q, i, ka);
+      ra[q] = (i0 + i < M && k0 + ka < ke) ? fa(i0 + i, k0 + ka) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      int j, kb2;
+      slot_b(q, j, kb2);
+      rb[q] = (tid + q * NT < KC * NC && j0 + j < N && k0 + kb2 < ke) ? fb(k0 + kb2, j0 + j) : 0.0;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      int i, ka;
+      slot_a(q, i, ka);
+      As[ka * LDS_TM + i] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      int j, kb2;
+      slot_b(q, j, kb2);
+      if (tid + q * NT < KC * NC) Bs[kb2 * (NC + 1) + j] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + KC < ke) fetch(k0 + KC);
+    T.chunk(As, Bs);
+    __syncthreads();
+  }
+}
+
+template <int NC, class EPI>
+__device__ __forceinline__ void tile_store_narrow(const NarrowTile<NC>& T, int i0, int j0, int M, int N,
+                                                  const EPI& epi) {
+#pragma unroll
+  for (int e = 0; e < NarrowTile<NC>::kEntries; ++e) {
+    const int gi = i0 + T.row_of(e), gj = j0 + T.col_of(e);
+    if (gi < M && gj < N) epi(gi, gj, T.get(e));
+  }
+}
+
 // Passes the entries (i, j) of tile T at (i0, j0) with i < M, j < N (and
 // i >= j when `lower`) to epi(i, j, value).
 template <class EPI>

@@ -350,6 +350,19 @@ __device__ __forceinline__ void wide_sym_rows(MfmaTile& T, int i0, int j0, int A
   tile_mma<true, BK>(T, i0, j0, A, N, d1, A, hi, fb, sm);
 }
 
+// wide_sym_rows on a NarrowTile (fronts with at most NC columns).
+template <bool BK, int NC, class FB>
+__device__ __forceinline__ void wide_sym_rows_narrow(NarrowTile<NC>& T, int i0, int j0, int A, int N, const double* V,
+                                                     const FB& fb, double* sm) {
+  auto lo = [&](int i, int k) { return V[pk(i, k, A)]; };  // k <= i
+  auto hi = [&](int i, int k) { return V[pk(k, i, A)]; };  // k >= i
+  auto mid = [&](int i, int k) { return sym_packed(V, i, k, A); };
+  const int d0 = min(i0, A), d1 = min(i0 + WT, A);
+  tile_mma_narrow<false, BK>(T, i0, j0, A, N, 0, d0, lo, fb, sm);
+  tile_mma_narrow<false, BK>(T, i0, j0, A, N, d0, d1, mid, fb, sm);
+  tile_mma_narrow<true, BK>(T, i0, j0, A, N, d1, A, hi, fb, sm);
+}
+
 // C(i, j) = sum_{k < K} a(k, i) b(k, j) for the lower triangle of a small
 // N x N result (N <= SMALL_N), on the vector units: the workgroup strides
 // over k (consecutive threads, consecutive k), each thread keeps the
@@ -1162,10 +1175,23 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
           if (gi < A) MA[gi + (int64_t)n * A] = t[v.an(gi, n)] + sum_partials(pb, d.ta, ti, N, row, n);
         }
       } else {
-        wide_sym_rows<true>(T, i0, j0, A, N, Va + r * upd + P.arena[v.s],
-                            [&](int k, int j) { return LB[v.an(k, j)]; }, sm);
-        tile_store(T, i0, j0, A, N,
-                   [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false);
+        // fronts with few columns on a narrow tile (the same sums, less
+        // matrix-core work on empty columns)
+        const double* Vp = Va + r * upd + P.arena[v.s];
+        auto lb = [&](int k, int j) { return LB[v.an(k, j)]; };
+        auto out = [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; };
+        if (N <= 16) {
+          NarrowTile<16> Tn(threadIdx.x);
+          wide_sym_rows_narrow<true>(Tn, i0, j0, A, N, Vp, lb, sm);
+          tile_store_narrow(Tn, i0, j0, A, N, out);
+        } else if (N <= 32) {
+          NarrowTile<32> Tn(threadIdx.x);
+          wide_sym_rows_narrow<true>(Tn, i0, j0, A, N, Vp, lb, sm);
+          tile_store_narrow(Tn, i0, j0, A, N, out);
+        } else {
+          wide_sym_rows<true>(T, i0, j0, A, N, Vp, lb, sm);
+          tile_store(T, i0, j0, A, N, out, false);
+        }
       }
     } else if (STAGE == 2 && N <= SMALL_N) {
       small_nn_dot(
