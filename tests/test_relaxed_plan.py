@@ -152,3 +152,17 @@ def test_relaxed_rejects_unfilled_pattern():
     with pytest.raises(mfb.MfbError) as e:
         mfb.plan_symbolic(3, cp, ri, relax=0.1)
     assert e.value.code == mfb.ENOTCHORDAL
+
+
+@pytest.mark.parametrize("pat", [(0, np.zeros(1, np.int64), np.zeros(0, np.int32)), P.band(12, 11), P.band(9, 0)],
+                         ids=["empty", "dense", "diagonal"])
+def test_relaxed_degenerate_patterns(pat):
+    """No supernode, one dense supernode (nothing to merge) and a diagonal
+    (roots only, nothing to merge) give the fundamental plan."""
+    n = pat[0]
+    base = mfb.plan_symbolic(*pat).info
+    info = mfb.plan_symbolic(*pat, relax=0.5).info
+    assert info["nsuper"] == base["nsuper"] and info["nnz_relaxed"] == info["nnz"] == int(pat[1][-1])
+    cp2, ri2 = mfb.plan_pattern(mfb.plan_symbolic(*pat, relax=0.5))
+    assert np.array_equal(cp2, np.asarray(pat[1])) and np.array_equal(ri2, np.asarray(pat[2]))
+    assert n >= 0
