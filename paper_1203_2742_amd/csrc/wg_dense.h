@@ -313,6 +313,27 @@ __device__ __forceinline__ void tile_store(const MfmaTile& T, int i0, int j0, in
   }
 }
 
+// epi(i, j, sum_{kb <= k < ke} a(i, k) b(k, j)) for the rows [i0, i0 + 64)
+// and the columns [j0, N) of an output with at most 64 columns from j0:
+// on a narrow tile when they are at most 32 (uniform over the workgroup).
+template <bool AK, bool BK, class FA, class FB, class EPI>
+__device__ __forceinline__ void mma_cols(int i0, int j0, int M, int N, int kb, int ke, const FA& fa, const FB& fb,
+                                         const EPI& epi, double* sm) {
+  if (N - j0 <= 16) {
+    NarrowTile<16> T(threadIdx.x);
+    tile_mma_narrow<AK, BK>(T, i0, j0, M, N, kb, ke, fa, fb, sm);
+    tile_store_narrow(T, i0, j0, M, N, epi);
+  } else if (N - j0 <= 32) {
+    NarrowTile<32> T(threadIdx.x);
+    tile_mma_narrow<AK, BK>(T, i0, j0, M, N, kb, ke, fa, fb, sm);
+    tile_store_narrow(T, i0, j0, M, N, epi);
+  } else {
+    MfmaTile T(threadIdx.x);
+    tile_mma<AK, BK>(T, i0, j0, M, N, kb, ke, fa, fb, sm);
+    tile_store(T, i0, j0, M, N, epi, false);
+  }
+}
+
 // One 64 x 64 output tile (i0, j0) of wg_gemm's product by one 256-thread
 // workgroup, for products spread over many workgroups (one tile each).
 template <bool AK = false, bool BK = false, class FA, class FB, class EPI>

@@ -409,6 +409,75 @@ __device__ __forceinline__ void small_nn_dot(int N, int K, const FA& fa, const F
   __syncthreads();
 }
 
+// The same product for SMALL_N < N <= 32 on the matrix cores: a 32 x 32
+// tile whose k range the four wavefronts split (wavefront w takes k-steps
+// 8w .. 8w + 7 of every staged chunk of 32), the four partial tiles then
+// summed in wavefront order, so the result does not depend on timing.  The
+// operands are read along k (consecutive lanes, consecutive k).  sm holds
+// at least 4 * 32 * 32 doubles.
+template <class FA, class FB, class EPI>
+__device__ __forceinline__ void small_nn_mfma(int N, int K, const FA& fa, const FB& fb, const EPI& epi,
+                                              double* sm) {
+  constexpr int T32 = 32, LD = T32 + 1, KS = 32, PER = KS * T32 / NT;
+  double* As = sm;  // [k][LD]
+  double* Bs = sm + KS * LD;
+  const int tid = threadIdx.x, w = tid >> 6, lr = tid & 15, lk = (tid & 63) >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  double ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NT, k = e & (KS - 1), i = e / KS;
+      const bool ok = i < N && k0 + k < K;
+      ra[q] = ok ? fa(k0 + k, i) : 0.0;
+      rb[q] = ok ? fb(k0 + k, i) : 0.0;
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NT, k = e & (KS - 1), i = e / KS;
+      As[k * LD + i] = ra[q];
+      Bs[k * LD + i] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + KS < K) fetch(k0 + KS);
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int k = 8 * w + 4 * st + lk;
+      const double a0 = As[k * LD + lr], a1 = As[k * LD + 16 + lr];
+      const double b0 = Bs[k * LD + lr], b1 = Bs[k * LD + 16 + lr];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* red = sm;  // [wavefront][32 x 32]
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = 16 * (e >> 3) + lk + 4 * (e & 3), col = 16 * ((e >> 2) & 1) + lr;
+    red[w * T32 * T32 + row * T32 + col] = acc[e >> 3][(e >> 2) & 1][e & 3];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < T32 * T32; idx += NT) {
+    const int row = idx / T32, col = idx % T32;
+    if (row < N && col <= row) {
+      double c = red[idx];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) c += red[q * T32 * T32 + idx];
+      epi(row, col, c);
+    }
+  }
+  __syncthreads();
+}
+
 // Right-hand sides batched along the columns of a product whose left
 // operand (a packed A x A block shared by all right-hand sides) is the
 // expensive read: column tile c of a front with N columns covers, when
@@ -638,11 +707,15 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_c(DevPlan P, const int32_t* l
     double* t = T + r * P.nnz;
     const double* MN = wsb + (r * count + f) * slot;
     const double* MA = MN + (int64_t)N * N;
+    auto fa = [&](int k, int i) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; };
+    auto fb = [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; };
+    auto out = [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; };
     if (N <= SMALL_N) {
-      small_nn_dot(
-          N, 2 * A, [&](int k, int i) { return k < A ? LB[v.an(k, i)] : MA[(k - A) + (int64_t)i * A]; },
-          [&](int k, int j) { return k < A ? t[v.an(k, j)] : LB[v.an(k - A, j)]; },
-          [&](int i, int j, double acc) { t[v.at(i, j)] = MN[i + (int64_t)j * N] - acc; }, sm);
+      small_nn_dot(N, 2 * A, fa, fb, out, sm);
+      return;
+    }
+    if (N <= 32) {
+      small_nn_mfma(N, 2 * A, fa, fb, out, sm);
       return;
     }
     MfmaTile Tt(threadIdx.x);
@@ -1077,26 +1150,31 @@ __global__ void __launch_bounds__(NT) k_fat_compl(DevPlan P, const int32_t* list
     const double* VI = Vi + P.arena[v.s];
     MfmaTile T(threadIdx.x);
     if (STAGE == 0) {
-      tile_mma<false, true>(T, i0, j0, A, N, 0, min(A, i0 + WT),
-                            [&](int i, int k) { return k <= i ? VI[pk(i, k, A)] : 0.0; },
-                            [&](int k, int j) { return Sin[v.an(k, j)]; }, sm);
-      tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { W[i + (int64_t)j * A] = acc; }, false);
+      mma_cols<false, true>(
+          i0, j0, A, N, 0, min(A, i0 + WT), [&](int i, int k) { return k <= i ? VI[pk(i, k, A)] : 0.0; },
+          [&](int k, int j) { return Sin[v.an(k, j)]; },
+          [&](int i, int j, double acc) { W[i + (int64_t)j * A] = acc; }, sm);
     } else if (STAGE == 1) {
       if (nn) {
-        tile_mma<true, true>(T, i0, j0, N, N, 0, A, [&](int i, int k) { return W[k + (int64_t)i * A]; },
-                             [&](int k, int j) { return W[k + (int64_t)j * A]; }, sm);
-        tile_store(
-            T, i0, j0, N, N,
-            [&](int i, int j, double acc) {
-              const double m = Sin[v.at(i, j)] - acc;
-              LB[v.at(i, j)] = m;
-              Mr[(N - 1 - j) + (int64_t)(N - 1 - i) * N] = m;
-            },
-            true);
+        auto out = [&](int i, int j, double acc) {
+          const double m = Sin[v.at(i, j)] - acc;
+          LB[v.at(i, j)] = m;
+          Mr[(N - 1 - j) + (int64_t)(N - 1 - i) * N] = m;
+        };
+        if (N <= 32) {
+          small_nn_mfma(
+              N, A, [&](int k, int i) { return W[k + (int64_t)i * A]; },
+              [&](int k, int j) { return W[k + (int64_t)j * A]; }, out, sm);
+        } else {
+          tile_mma<true, true>(T, i0, j0, N, N, 0, A, [&](int i, int k) { return W[k + (int64_t)i * A]; },
+                               [&](int k, int j) { return W[k + (int64_t)j * A]; }, sm);
+          tile_store(T, i0, j0, N, N, out, true);
+        }
       } else {
-        tile_mma<true, true>(T, i0, j0, A, N, i0, A, [&](int i, int k) { return k >= i ? VI[pk(k, i, A)] : 0.0; },
-                             [&](int k, int j) { return W[k + (int64_t)j * A]; }, sm);
-        tile_store(T, i0, j0, A, N, [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false);
+        mma_cols<true, true>(
+            i0, j0, A, N, i0, A, [&](int i, int k) { return k >= i ? VI[pk(k, i, A)] : 0.0; },
+            [&](int k, int j) { return W[k + (int64_t)j * A]; },
+            [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, sm);
       }
     } else {
       // C(k, j) = X(N-1-j, N-1-k), zero for k < j
@@ -1193,16 +1271,18 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
           tile_store(T, i0, j0, A, N, out, false);
         }
       }
-    } else if (STAGE == 2 && N <= SMALL_N) {
-      small_nn_dot(
-          N, 2 * A, [&](int k, int i) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
-          [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
-          [&](int i, int j, double acc) {
-            const double m = t[v.at(i, j)] + acc;
-            MN[i + (int64_t)j * N] = m;
-            MN[j + (int64_t)i * N] = m;
-          },
-          sm);
+    } else if (STAGE == 2 && N <= 32) {
+      auto fa = [&](int k, int i) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; };
+      auto fb = [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; };
+      auto out = [&](int i, int j, double acc) {
+        const double m = t[v.at(i, j)] + acc;
+        MN[i + (int64_t)j * N] = m;
+        MN[j + (int64_t)i * N] = m;
+      };
+      if (N <= SMALL_N)
+        small_nn_dot(N, 2 * A, fa, fb, out, sm);
+      else
+        small_nn_mfma(N, 2 * A, fa, fb, out, sm);
     } else if (STAGE == 2) {
       tile_mma<true, true>(
           T, i0, j0, N, N, 0, 2 * A, [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
