@@ -113,7 +113,11 @@ def main():
              "", "## rocprofv3 --kernel-trace --stats, per operation of the step", "",
              f"Every kernel is attributed to the operation whose call launches it; the time per step is "
              f"the total over the run divided by its {steps} steps.  bench.py's roofline names one "
-             f"operation and its time per call (all its launches), which this column reproduces.", "",
+             f"operation and its time per call (all its launches), which this column reproduces.  "
+             f"Operations that the step runs concurrently on two streams (the completion and the "
+             f"product beside the Hessian) show their kernels' durations under that contention, longer "
+             f"than alone (bench.py's per_op_ms times every operation alone); the operation named by "
+             f"the roofline runs alone.", "",
              "| operation | kernel launches | total ms | ms per step | % of kernel time |",
              "|---|---|---|---|---|"]
     for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["total"]):
