@@ -533,11 +533,11 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
       }
   }
   // The inverse Hessian's steps 1+2 read T_{A_s A_s}, which a gather pass
-  // puts in place, so its fronts are independent too.  Each front takes the
-  // kernel the root-to-leaf rule gives it (register kernels for J <=
-  // kDownRegMaxJ and for roots, blocked otherwise); fronts of one kind run
-  // together, longest first, in launches of at most kFlatScratch doubles
-  // of workgroup scratch.
+  // puts in place, so its fronts are independent too.  Wide fronts and the
+  // other fronts above kDownRegMaxJ that are not roots take the
+  // tile-parallel kernels, the others the register kernels of their order
+  // (blocked above order 192); fronts of one kind run together, longest
+  // first, in launches of at most kFlatScratch doubles of workgroup scratch.
   {
     ClassSched& cs = p->cs_ihd_flat;
     cs.list.clear();
@@ -545,12 +545,15 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
     cs.pre.clear();
     cs.list.reserve(ns);
     auto kind = [&](int32_t k) {
-      // wide fronts too: their A x A products run tile-parallel there
-      if (is_wide(k)) return kFat;
-      const bool reg = p->J[k] <= kDownRegMaxJ || p->J[k] == p->N[k];
+      // wide fronts, and every front above the register kernels' order of
+      // the root-to-leaf sweeps that is not a root, on the tile-parallel
+      // kernels: all fronts run at once here, and one workgroup per front
+      // and right-hand side left the chip mostly idle on the 40^3 grid
+      // (9,300 fronts of order 65-192, 38 ms for 16 right-hand sides)
+      if (is_wide(k) || (p->J[k] > kDownRegMaxJ && p->J[k] != p->N[k])) return kFat;
       int c = 0;
       while (c < kRegClasses && p->J[k] > kRegMax[c]) ++c;
-      return reg ? c : kRegClasses;
+      return c;
     };
     for (int c : {kFat, 5, 4, 3, 2, 1, 0}) {
       std::vector<int32_t> fr;
