@@ -465,7 +465,13 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
       std::vector<int32_t> fr;
       for (int32_t k = 0; k < ns; ++k)
         if (fat(k)) fr.push_back(k);
-      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) { return order(x) > order(y); });
+      // the completion's fronts by decreasing N first: its per-front
+      // Cholesky of the N x N block steps through the segment's largest N,
+      // so the few fronts with many columns share segments of their own
+      std::stable_sort(fr.begin(), fr.end(), [&](int32_t x, int32_t y) {
+        if (!by_a && p->N[x] != p->N[y]) return p->N[x] > p->N[y];
+        return order(x) > order(y);
+      });
       const int cls = by_a ? kBigV : kFat;
       auto close_seg = [&](Level& S) {
         if (!S.count) return;
