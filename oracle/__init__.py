@@ -14,6 +14,10 @@ Functions (all values float64 in the CCS order of the pattern):
 * ``product(pat, ldl) -> x``            Algorithm 3.2
 * ``projinv(pat, ldl) -> s``            Algorithm 4.1, S = P(X^-1)
 * ``completion(pat, s) -> ldl``         Algorithm 4.2 (factor of X-hat)
+* ``completion_factored(pat, s, with_r=False)``  Algorithm 4.3: the same
+                                       factor, computed with the update
+                                       matrices held as V_j = R_j R_j^T;
+                                       with_r also returns every R_j
 * ``hessian(pat, ldl, s, y) -> t``      Algorithm 5.1
 * ``inv_hessian(pat, ldl, s, t) -> y``  Algorithm 5.2
 * ``hessian_factor(pat, ldl, s, y)``    Algorithm 5.3 (W = R(Y))
@@ -71,6 +75,7 @@ def _lib():
                 "orc_product": [I64, P, P, P, P],
                 "orc_projinv": [I64, P, P, P, P],
                 "orc_completion": [I64, P, P, P, P, P],
+                "orc_completion_factored": [I64, P, P, P, P, P, P],
                 "orc_hessian": [I64, P, P, P, P, P, P],
                 "orc_inv_hessian": [I64, P, P, P, P, P, P],
                 "orc_hessian_factor": [I64, P, P, P, P, P, P],
@@ -145,6 +150,29 @@ def completion(pat, s):
     _check(_lib().orc_completion(n, cp.ctypes.data, ri.ctypes.data, s.ctypes.data, out.ctypes.data,
                                  ctypes.addressof(bad)), bad)
     return out
+
+
+def completion_factored(pat, s, with_r=False):
+    """Algorithm 4.3.  Returns ldl, or (ldl, r) with r[j] the upper
+    triangular R_j (|I_j| x |I_j|, positive diagonal), V_j = R_j R_j^T."""
+    n, cp, ri = _pat(pat)
+    s = _vec(s, cp[-1])
+    out = np.empty_like(s)
+    mi = np.diff(cp) - 1
+    roff = np.concatenate([[0], np.cumsum(mi * (mi + 1) // 2)])
+    rbuf = np.zeros(max(1, int(roff[-1])), dtype=np.float64) if with_r else None
+    bad = ctypes.c_int64(-1)
+    _check(_lib().orc_completion_factored(n, cp.ctypes.data, ri.ctypes.data, s.ctypes.data, out.ctypes.data,
+                                          rbuf.ctypes.data if with_r else None, ctypes.addressof(bad)), bad)
+    if not with_r:
+        return out
+    rs = []
+    for j in range(n):
+        m = int(mi[j])
+        r = np.zeros((m, m))
+        r[np.triu_indices(m)] = rbuf[roff[j]:roff[j + 1]]
+        rs.append(r)
+    return out, rs
 
 
 def _three(fn, pat, ldl, s, v):

@@ -16,6 +16,8 @@
  *   orc_product      Algorithm 3.2 (Cholesky product, eq. e-mf-prod)
  *   orc_projinv      Algorithm 4.1 (projected inverse, eqs. e-mf-gradient-1/2)
  *   orc_completion   Algorithm 4.2 (matrix completion, eqs. e-mf-compl-1/2)
+ *   orc_completion_factored  Algorithm 4.3 (the same with factored update
+ *                    matrices V_j = R_j R_j^T, Householder row deletion)
  *   orc_hessian      Algorithm 5.1 (Hessian evaluation, Section 5.2)
  *   orc_inv_hessian  Algorithm 5.2 (inverse Hessian evaluation, Section 5.3)
  *   orc_hessian_factor      Algorithm 5.3 (W = R(Y), Section 5.4)
@@ -401,6 +403,126 @@ int orc_completion(int64_t n, const int64_t* cp, const int32_t* ri, const double
   }
   for (int64_t j = 0; j < n; ++j) free(V[j]);
   free(V); free(pos); tree_free(&t);
+  return rc;
+}
+
+/* --- Algorithm 4.3: matrix completion with factored update matrices -----
+ * The update matrix V_j = S_{I_j I_j} is carried as V_j = R_j R_j^T with
+ * R_j upper triangular of order |I_j| (dense, row-major).  In reverse
+ * topological order:
+ *   eq. e-mf-compl-1-factored: L_Ij = -R_j^-T R_j^-1 S_Ij (back, then forward
+ *     substitution), D_jj = (S_jj + S_Ij^T L_Ij)^-1;
+ *   for every child i, eq. e-mfp-compl-3-factored: C = E^T R_j, the rows of
+ *     R_j at the positions of I_i \ {j} in I_j, reduced to C = R Q^T by
+ *     Householder reflections applied from the right (last row first, each
+ *     moving the row's weight into its diagonal column; none where the
+ *     row has no weight left of that column);
+ *   eq. e-mf-compl-2-factored: R_i = [(S_jj - |w|^2)^1/2, w^T; 0, R] with
+ *     w = R^-1 b, b = E^T S_Ij.
+ * Every diagonal is made positive (by the sign of R's columns, which leaves
+ * R R^T unchanged), so R_i is the unique upper triangular factor of V_i
+ * with a positive diagonal.  rout (optional) receives R_j for every j, its
+ * upper triangle by rows, |I_j|(|I_j|+1)/2 values per column j, j ascending.
+ * Errors as orc_completion (ORC_ENOCOMPL at the column whose pivot or
+ * update factor is not positive).                                          */
+int orc_completion_factored(int64_t n, const int64_t* cp, const int32_t* ri, const double* s, double* ldl,
+                            double* rout, int64_t* bad) {
+  tree_t t;
+  int rc = tree_init(&t, n, cp, ri);
+  if (rc) return rc;
+  double** R = (double**)calloc((size_t)n + 1, sizeof(double*));
+  int64_t* pos = NEW(int64_t, n);
+  int64_t* roff = NEW(int64_t, n + 1);
+  roff[0] = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t mi = cp[j + 1] - cp[j] - 1;
+    roff[j + 1] = roff[j] + mi * (mi + 1) / 2;
+  }
+  if (bad) *bad = -1;
+  for (int64_t j = n - 1; j >= 0 && rc == ORC_OK; --j) {
+    int64_t mi = cp[j + 1] - cp[j] - 1;
+    const double* r = R[j];                                /* R_j, mi x mi */
+    const double* sij = s + cp[j] + 1;
+    if (rout)
+      for (int64_t a = 0, q = roff[j]; a < mi; ++a)
+        for (int64_t b = a; b < mi; ++b) rout[q++] = r[a * mi + b];
+    /* z = R_j^-1 S_Ij, then L_Ij = -R_j^-T z */
+    double* z = NEW(double, mi);
+    for (int64_t a = mi - 1; a >= 0; --a) {
+      double acc = sij[a];
+      for (int64_t b = a + 1; b < mi; ++b) acc -= r[a * mi + b] * z[b];
+      z[a] = acc / r[a * mi + a];
+    }
+    double* l = ldl + cp[j] + 1;
+    for (int64_t a = 0; a < mi; ++a) {
+      double acc = z[a];
+      for (int64_t b = 0; b < a; ++b) acc -= r[b * mi + a] * l[b];
+      l[a] = acc / r[a * mi + a];
+    }
+    for (int64_t a = 0; a < mi; ++a) l[a] = -l[a];
+    free(z);
+    double den = s[cp[j]];
+    for (int64_t a = 0; a < mi; ++a) den += sij[a] * l[a];
+    if (!(den > 0.0)) { rc = ORC_ENOCOMPL; if (bad) *bad = j; break; }
+    ldl[cp[j]] = 1.0 / den;
+    for (int64_t c = t.chead[j]; c != -1 && rc == ORC_OK; c = t.cnext[c]) {
+      int64_t mc = cp[c + 1] - cp[c] - 1, m = mc - 1;      /* |I_c \ {j}| = m */
+      /* positions of I_c \ {j} among the rows of column j (J_j = {j} U I_j) */
+      rc = relpos(&t, c, j, pos);
+      if (rc) break;
+      double* cm = NEW(double, m * mi);                    /* C = E^T R_j */
+      for (int64_t k = 0; k < m; ++k)
+        for (int64_t b = 0; b < mi; ++b) cm[k * mi + b] = r[(pos[k + 1] - 1) * mi + b];
+      double* v = NEW(double, mi);
+      for (int64_t k = m - 1; k >= 0; --k) {
+        int64_t q = mi - m + k;                            /* the row's diagonal column */
+        double rest = 0.0;
+        for (int64_t b = 0; b < q; ++b) rest += cm[k * mi + b] * cm[k * mi + b];
+        if (rest == 0.0) continue;                         /* already e_q times a scalar: H = I */
+        double nrm = sqrt(rest + cm[k * mi + q] * cm[k * mi + q]);
+        double alpha = cm[k * mi + q] >= 0.0 ? -nrm : nrm;
+        double vtv = 0.0;
+        for (int64_t b = 0; b <= q; ++b) {
+          v[b] = cm[k * mi + b] - (b == q ? alpha : 0.0);
+          vtv += v[b] * v[b];
+        }
+        if (vtv > 0.0)
+          for (int64_t x = 0; x < k; ++x) {
+            double d = 0.0;
+            for (int64_t b = 0; b <= q; ++b) d += cm[x * mi + b] * v[b];
+            d *= 2.0 / vtv;
+            for (int64_t b = 0; b <= q; ++b) cm[x * mi + b] -= d * v[b];
+          }
+        for (int64_t b = 0; b < q; ++b) cm[k * mi + b] = 0.0;
+        cm[k * mi + q] = alpha;
+      }
+      free(v);
+      /* R = the last m columns of C Q; positive diagonal */
+      double* rc_ = (double*)calloc((size_t)(mc * mc) + 1, sizeof(double));
+      for (int64_t k = 0; k < m; ++k)
+        for (int64_t b = k; b < m; ++b) rc_[(k + 1) * mc + (b + 1)] = cm[k * mi + (mi - m + b)];
+      for (int64_t b = 0; b < m; ++b)
+        if (rc_[(b + 1) * mc + (b + 1)] < 0.0)
+          for (int64_t k = 0; k <= b; ++k) rc_[(k + 1) * mc + (b + 1)] = -rc_[(k + 1) * mc + (b + 1)];
+      free(cm);
+      /* w = R^-1 b, b = E^T S_Ij; first row of R_c */
+      double ww = 0.0;
+      for (int64_t k = m - 1; k >= 0; --k) {
+        double acc = sij[pos[k + 1] - 1];
+        for (int64_t b = k + 1; b < m; ++b) acc -= rc_[(k + 1) * mc + (b + 1)] * rc_[b + 1];
+        double wk = acc / rc_[(k + 1) * mc + (k + 1)];
+        rc_[k + 1] = wk;                                   /* row 0, column k + 1 */
+        ww += wk * wk;
+      }
+      double rho = s[cp[j]] - ww;
+      if (!(rho > 0.0) || !(mc > 0)) { rc = ORC_ENOCOMPL; if (bad) *bad = c; free(rc_); break; }
+      rc_[0] = sqrt(rho);
+      R[c] = rc_;
+    }
+    free(R[j]); R[j] = NULL;
+  }
+  for (int64_t j = 0; j < n; ++j) free(R[j]);
+  free(R); free(pos); free(roff); tree_free(&t);
   return rc;
 }
 
