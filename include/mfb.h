@@ -304,6 +304,22 @@ mfb_status_t mfb_gram(mfb_plan_t p, int32_t m, const double* w_dev, double* g_de
  * positive definite) sets MFB_ENOCOMPLETION. */
 mfb_status_t mfb_completion(mfb_factor_t f, const double* s_dev, void* stream);
 
+/* Matrix completion with factored update matrices (Algorithm 4.3, in the
+ * supernodal form of the paper's appendix on supernodal algorithms): the
+ * same result and handle state as mfb_completion, computed root to leaf
+ * with each V_s = S_{A_s A_s} carried as V_s = R_s R_s^T (R_s upper
+ * triangular) and R_s obtained from the parent's factor by deleting rows
+ * and retriangularizing with Householder reflections (eqs.
+ * e-mfp-compl-3-factored and e-mf-compl-2-factored), so that no S_AA is
+ * factored from scratch.  Then L_AN = -R_s^-T R_s^-1 S_AN (eq.
+ * e-mf-compl-1-factored).  One launch per level of the clique tree, one
+ * workgroup per front.  Arguments, buffers and errors as mfb_completion
+ * (MFB_ENOCOMPLETION when a retriangularized block or a Schur complement
+ * is not positive definite; MFB_EINVAL on a relaxed plan).  The R_s blocks
+ * are left in the handle's update arena; the cached inverse blocks of
+ * S_AA are not formed (the inverse Hessian forms them on its first call). */
+mfb_status_t mfb_completion_factored(mfb_factor_t f, const double* s_dev, void* stream);
+
 /* Algorithm 3.2 (block form): values of L D L^T on V, written to x_dev
  * (nnz doubles).  For a completion this gives X-hat = -grad f_*(S). */
 mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x_dev, void* stream);

@@ -38,10 +38,19 @@ static int64_t flat_scratch(const ClassSched& cs, Op op) {
       m = std::max(m, int64_t(g.lv.count) * std::max<int64_t>(1, slot_doubles(op, g.lv)));
   return m;
 }
+// Workgroup scratch (doubles) of the factored completion on front s (the
+// layout of k_completion_factored; Ap is the parent's ancestor count).
+static int64_t complf_slot(const mfb_plan_s* p, int32_t s) {
+  const int64_t N = p->N[s], A = p->J[s] - N;
+  const int32_t q = p->parent[s];
+  const int64_t Ap = q >= 0 ? p->J[q] - p->N[q] : 0;
+  return 3 * N * N + 2 * A * N + A * Ap + A * A + Ap + 64;
+}
 static int64_t factor_scratch(const mfb_plan_s* p) {
+  int64_t complf = 1;
+  for (int32_t s = 0; s < p->ns; ++s) complf = std::max(complf, complf_slot(p, s));
   return std::max({plan_scratch(p, OP_FACTOR), plan_scratch(p, OP_PRODUCT),
-                   flat_scratch(p->cs_compl_flat, OP_COMPLETION), flat_scratch(p->cs_vinv, OP_VINV),
-                   int64_t(1)});
+                   flat_scratch(p->cs_compl_flat, OP_COMPLETION), flat_scratch(p->cs_vinv, OP_VINV), complf});
 }
 static int64_t rhs_scratch(const mfb_plan_s* p) {
   int64_t flat = 0;
@@ -1033,6 +1042,36 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   f->has_factor = true;
   f->s_valid = true;
   f->vinv_valid = true;
+  return launched();
+}
+
+mfb_status_t mfb_completion_factored(mfb_factor_t f, const double* sin, void* stream) {
+  if (!f || (!sin && f->plan->nnz) || f->plan->relaxed) return MFB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
+  k_reset_status<<<1, 64, 0, s>>>(f->st);
+  const mfb_plan_s* p = f->plan;
+  // V_s = S_{A_s A_s} for the Hessian sweeps that may follow (the
+  // completion itself reads S and the parents' R_p)
+  mfb_status_t st = gather_blocks(f, s, 1, sin, f->Vs, 0, 0, 2);
+  if (st) return st;
+  // level by level from the roots; a level's fronts in launches whose
+  // scratch stays within the factor's scratch area
+  const int64_t budget = factor_scratch(p);
+  for (const Level& L : p->down_levels) {
+    int64_t sl = 1;
+    for (int32_t t = L.begin; t < L.begin + L.count; ++t) sl = std::max(sl, complf_slot(p, p->down_list[t]));
+    const int32_t chunk = int32_t(std::max<int64_t>(1, std::min<int64_t>(L.count, budget / sl)));
+    for (int32_t b = 0; b < L.count; b += chunk) {
+      const int32_t c = std::min(chunk, L.count - b);
+      launch_completion_factored(dim3(unsigned(c)), s, p->dev, p->d_down_list + L.begin + b, sin, f->R, f->LB,
+                                 f->S, f->U, f->part, f->st, f->scratch, sl);
+      if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+    }
+  }
+  f->has_factor = true;
+  f->s_valid = true;
   return launched();
 }
 

@@ -63,6 +63,12 @@ void launch_factor_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, cons
 void launch_completion_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,
                            const double* Sin, double* R, double* LB, double* S, double* Vs,
                            double* Vi, double* part, DevStatus* st);
+// Algorithm 7.3 with factored update matrices V_s = R_s R_s^T, one
+// root-to-leaf level (grid.x fronts of list); Ru: the packed R_s^T blocks
+// at the plan's arena offsets (parents' in place, the level's written).
+void launch_completion_factored(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Sin,
+                                double* R, double* LB, double* S, double* Ru, double* part, DevStatus* st,
+                                double* wsb, int64_t slot);
 // act: Hessian step 1's per-(RHS, supernode) activity flags (ns per RHS;
 // entries of pruned fronts are set to 0, others left as they are)
 void launch_hess_up_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,

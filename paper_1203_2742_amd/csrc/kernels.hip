@@ -473,6 +473,59 @@ template __global__ void k_ihess_up<false>(DevPlan, const int32_t*, const double
 template __global__ void k_ihess_up<true>(DevPlan, const int32_t*, const double*, const double*, double*,
                                           double*, int64_t, double*, int64_t);
 
+// The end of Algorithm 7.3 on one front once W (A x N, leading dimension A,
+// with W^T W = S_AN^T V_s^-1 S_AN) and L_AN (in LB) are in place:
+// D^-1 = S_NN - W^T W into LB, then C = chol(D) and B = L_AN C into R, and
+// the front's part of log det.  ws: 3 N^2 doubles.  No barrier at the end:
+// callers synchronize before they reuse LB or R.
+__device__ __forceinline__ void completion_finish(const SnView& v, const double* Sin, double* R, double* LB,
+                                                  double* part, DevStatus* st, double* ws, const double* W,
+                                                  double* sm, int* fail) {
+  const int N = v.N, A = v.A;
+  double* Dd = ws;
+  double* Gi = ws + (int64_t)N * N;
+  double* Dm = Gi + (int64_t)N * N;
+  wg_gemm<true, true>(
+      N, N, A, [&](int i, int k) { return W[k + (int64_t)i * A]; },
+      [&](int k, int j) { return W[k + (int64_t)j * A]; },
+      [&](int i, int j, double acc) {
+        const double d = Sin[v.at(i, j)] - acc;
+        LB[v.at(i, j)] = d;
+        Dd[i + (int64_t)j * N] = d;
+      },
+      true, sm);
+  __syncthreads();
+  if (threadIdx.x == 0) *fail = -1;
+  __syncthreads();
+  // D = (D^-1)^-1 via its Cholesky factor, then C = chol(D)
+  wg_potrf_panel(Dd, N, N, N, sm, fail);
+  if (threadIdx.x == 0 && *fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[*fail]);
+  wg_trtri([&](int i, int j) { return Dd[i + (int64_t)j * N]; }, N, Gi, N, sm);
+  wg_gemm<true, true>(
+      N, N, N, [&](int i, int k) { return Gi[k + (int64_t)i * N]; },
+      [&](int k, int j) { return Gi[k + (int64_t)j * N]; },
+      [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, true, sm);
+  __syncthreads();
+  if (threadIdx.x == 0) *fail = -1;
+  __syncthreads();
+  wg_potrf_panel(Dm, N, N, N, sm, fail);
+  double lg = 0.0;
+  for (int c = threadIdx.x; c < N; c += NT) lg += 2.0 * log(Dm[c + (int64_t)c * N]);
+  lg = wg_sum(lg, sm);
+  if (threadIdx.x == 0) {
+    part[v.s] = lg;
+    if (*fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[*fail]);
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
+    const int i = int(e % N), c = int(e / N);
+    if (i >= c) R[v.at(i, c)] = Dm[e];
+  }
+  wg_gemm<false, true>(
+      A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
+      [&](int k, int j) { return k >= j ? Dm[k + (int64_t)j * N] : 0.0; },
+      [&](int i, int j, double acc) { R[v.an(i, j)] = acc; }, false, sm);
+}
+
 // ---------------------------------------------------------------------------
 // Algorithm 7.3: matrix completion of one front, with V_s = S_{A_s A_s}
 // already gathered: L_AN = -V_s^-1 S_AN; D^-1 = S_NN +
@@ -503,10 +556,7 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
     if (A > 0) packed_tri_inverse(V, VI, A, sm, d64, &fail);  // VI <- C_V^-1, V = C_V C_V^T
     __syncthreads();
     if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
-    double* Dd = ws;
-    double* Gi = ws + (int64_t)N * N;
-    double* Dm = Gi + (int64_t)N * N;
-    double* W = Dm + (int64_t)N * N;
+    double* W = ws + 3 * (int64_t)N * N;  // after completion_finish's 3 N^2
     // W = C_V^-1 S_AN, L_AN = -C_V^-T W, D^-1 = S_NN - W^T W: the Schur
     // complement as a difference of Gram products (no explicit V^-1, whose
     // product with S_AN would cancel against S_NN)
@@ -519,51 +569,217 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
         A, N, A, [&](int i, int k) { return k >= i ? Cvi(k, i) : 0.0; },
         [&](int k, int j) { return W[k + (int64_t)j * A]; },
         [&](int i, int j, double acc) { LB[v.an(i, j)] = -acc; }, false, sm);
-    wg_gemm<true, true>(
-        N, N, A, [&](int i, int k) { return W[k + (int64_t)i * A]; },
-        [&](int k, int j) { return W[k + (int64_t)j * A]; },
-        [&](int i, int j, double acc) {
-          const double d = Sin[v.at(i, j)] - acc;
-          LB[v.at(i, j)] = d;
-          Dd[i + (int64_t)j * N] = d;
-        },
-        true, sm);
-    __syncthreads();
-    if (threadIdx.x == 0) fail = -1;
-    __syncthreads();
-    // D = (D^-1)^-1 via its Cholesky factor, then C = chol(D)
-    wg_potrf_panel(Dd, N, N, N, sm, &fail);
-    if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
-    wg_trtri([&](int i, int j) { return Dd[i + (int64_t)j * N]; }, N, Gi, N, sm);
-    wg_gemm<true, true>(
-        N, N, N, [&](int i, int k) { return Gi[k + (int64_t)i * N]; },
-        [&](int k, int j) { return Gi[k + (int64_t)j * N]; },
-        [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, true, sm);
-    __syncthreads();
-    if (threadIdx.x == 0) fail = -1;
-    __syncthreads();
-    wg_potrf_panel(Dm, N, N, N, sm, &fail);
-    double lg = 0.0;
-    for (int c = threadIdx.x; c < N; c += NT) lg += 2.0 * log(Dm[c + (int64_t)c * N]);
-    lg = wg_sum(lg, sm);
-    if (threadIdx.x == 0) {
-      part[v.s] = lg;
-      if (fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[fail]);
-    }
-    for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += NT) {
-      const int i = int(e % N), c = int(e / N);
-      if (i >= c) R[v.at(i, c)] = Dm[e];
-    }
-    wg_gemm<false, true>(
-        A, N, N, [&](int i, int k) { return LB[v.an(i, k)]; },
-        [&](int k, int j) { return k >= j ? Dm[k + (int64_t)j * N] : 0.0; },
-        [&](int i, int j, double acc) { R[v.an(i, j)] = acc; }, false, sm);
+    completion_finish(v, Sin, R, LB, part, st, ws, W, sm, &fail);
     // the cached block: V^-1 itself up to kVExplicitMax, C_V^-1 beyond
     if (A > 0 && A <= kVExplicitMax) {
       __syncthreads();
       wg_lauum_inplace(Cvi, A, sm);
     }
   });
+}
+
+// Triangular solves with an upper triangular U (n x n; U(i, j), i <= j,
+// read through a functor) in one workgroup, in place on a column-major B
+// (leading dimension ldb, nc columns), blocked by NB: each diagonal block
+// is inverted in LDS (diag_trtri of its transpose), the rest are wg_gemm
+// updates.  TRANS = false: B <- U^-1 B (last block row first); TRANS =
+// true: B <- U^-T B (first block row first).  Ends with a barrier.
+template <bool TRANS, class UF>
+__device__ __forceinline__ void wg_upper_solve(const UF& U, int n, double* B, int64_t ldb, int nc, double* sm) {
+  double* Ld = sm + SMEM_GEMM;
+  double* Li = Ld + NB * LDD;
+  const int nblk = (n + NB - 1) / NB;
+  for (int t = 0; t < nblk; ++t) {
+    const int bk = TRANS ? t : nblk - 1 - t;
+    const int jb = bk * NB, nb = min(NB, n - jb), r1 = jb + nb;
+    if (!TRANS && r1 < n) {
+      wg_gemm(
+          nb, nc, n - r1, [&](int i, int k) { return U(jb + i, r1 + k); },
+          [&](int k, int j) { return B[(r1 + k) + j * ldb]; },
+          [&](int i, int j, double acc) { B[(jb + i) + j * ldb] -= acc; }, false, sm);
+      __syncthreads();
+    }
+    if (TRANS && jb > 0) {
+      wg_gemm(
+          nb, nc, jb, [&](int i, int k) { return U(k, jb + i); }, [&](int k, int j) { return B[k + j * ldb]; },
+          [&](int i, int j, double acc) { B[(jb + i) + j * ldb] -= acc; }, false, sm);
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (i >= j) Ld[i + j * LDD] = U(jb + j, jb + i);  // the block's transpose (lower)
+    }
+    __syncthreads();
+    diag_trtri(Ld, Li, nb);  // Li = U_bb^-T
+    wg_gemm(
+        nb, nc, nb,
+        [&](int i, int k) {
+          return TRANS ? (k <= i ? Li[i + k * LDD] : 0.0) : (k >= i ? Li[k + i * LDD] : 0.0);
+        },
+        [&](int k, int j) { return B[(jb + k) + j * ldb]; },
+        [&](int i, int j, double acc) { B[(jb + i) + j * ldb] = acc; }, false, sm);
+    __syncthreads();
+  }
+}
+
+// Algorithm 7.3 with factored update matrices (the supernodal form of
+// Algorithm 4.3): V_s = S_{A_s A_s} is carried as V_s = R_s R_s^T, R_s
+// upper triangular with a positive diagonal, obtained from the parent's
+// R_p instead of being factored from scratch.  A_s splits into A_s ∩ N_p
+// (its first p1 indices) and A_s \ N_p (m indices, all in A_p), so that
+// V_s = [A B^T; B C C^T] with A and B from the parent's panel of S and C
+// the rows of R_p at A_s \ N_p.  C = R Q^T by Householder reflections
+// applied from the right (last row first; a row with no weight left of its
+// diagonal column is left alone), R's diagonal made positive by column
+// signs; W = R^-1 B; A - W^T W = T T^T with T upper triangular (Cholesky
+// of the index-reversed matrix); R_s = [T W^T; 0 R], kept as R_s^T packed
+// lower in the front's block of Ru.  Then Z = R_s^-1 S_AN, L_AN =
+// -R_s^-T Z, and the front is finished as in k_completion with W = Z.
+// One root-to-leaf level per launch (the parents' R_p are in place).
+// Scratch: 3N^2 + 2AN + A Ap + A^2 + Ap + 64 doubles (Ap: the parent's A).
+__global__ void __launch_bounds__(NT) k_completion_factored(DevPlan P, const int32_t* list, const double* Sin,
+                                                            double* R, double* LB, double* S, double* Ru,
+                                                            double* part, DevStatus* st, double* wsb,
+                                                            int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  __shared__ int fail, sh_p1;
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N, A = v.A;
+    double* ws = slot_ptr(wsb, slot);
+    double* Z = ws + 3 * (int64_t)N * N;
+    double* X = Z + (int64_t)A * N;
+    double* Cm = X + (int64_t)A * N;
+    if (threadIdx.x == 0) fail = -1;
+    for (int64_t e = threadIdx.x; e < (int64_t)v.J * N; e += NT) {
+      const int rr = int(e % v.J), c = int(e / v.J);
+      if (rr >= c) S[v.at(rr, c)] = Sin[v.at(rr, c)];
+    }
+    double* Rs = Ru + P.arena[v.s];
+    if (A > 0) {
+      const int p = P.parent[v.s];
+      const SnView vp(P, p);
+      const int Np = vp.N, Ap = vp.A;
+      const int32_t* rl = P.rel + P.relbase[v.s];  // positions of A_s in J_p, ascending
+      const double* Rp = Ru + P.arena[p];
+      if (threadIdx.x == 0) {
+        int lo = 0, hi = A;  // first position at or beyond N_p
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (rl[mid] < Np) lo = mid + 1;
+          else hi = mid;
+        }
+        sh_p1 = lo;
+      }
+      __syncthreads();
+      const int p1 = sh_p1, m = A - p1;
+      const int c0 = m > 0 ? rl[p1] - Np : 0, wC = Ap - c0;  // C holds columns c0 .. Ap-1 of R_p
+      const int qc = wC - m;                                 // R: the last m of them
+      double* Wb = Cm + (int64_t)m * wC;
+      double* Fl = Wb + (int64_t)m * p1;
+      double* vh = Fl + (int64_t)p1 * p1;
+      auto Rm = [&](int i, int j) { return Cm[i + (int64_t)(qc + j) * m]; };
+      if (m > 0) {
+        for (int64_t e = threadIdx.x; e < (int64_t)m * wC; e += NT) {
+          const int cc = int(e % wC), k = int(e / wC);
+          const int r = rl[p1 + k] - Np, c = c0 + cc;
+          Cm[k + (int64_t)cc * m] = c >= r ? Rp[pk(c, r, Ap)] : 0.0;  // R_p(r, c) = R_p^T(c, r)
+        }
+        __syncthreads();
+        for (int k = m - 1; k >= 0; --k) {
+          const int lo = rl[p1 + k] - Np - c0, q = qc + k;  // the row's first and diagonal columns
+          double acc = 0.0;
+          for (int b = lo + threadIdx.x; b < q; b += NT) acc += Cm[k + (int64_t)b * m] * Cm[k + (int64_t)b * m];
+          const double rest = wg_sum(acc, sm);
+          if (rest == 0.0) continue;  // (uniform)
+          const double xq = Cm[k + (int64_t)q * m];
+          const double nrm = sqrt(rest + xq * xq);
+          const double alpha = xq >= 0.0 ? -nrm : nrm;
+          const double tau = 2.0 / (rest + (xq - alpha) * (xq - alpha));
+          for (int b = lo + threadIdx.x; b <= q; b += NT) vh[b] = b == q ? xq - alpha : Cm[k + (int64_t)b * m];
+          __syncthreads();
+          for (int x = threadIdx.x; x < k; x += NT) {
+            double d = 0.0;
+            for (int b = lo; b <= q; ++b) d += Cm[x + (int64_t)b * m] * vh[b];
+            d *= tau;
+            for (int b = lo; b <= q; ++b) Cm[x + (int64_t)b * m] -= d * vh[b];
+          }
+          for (int b = lo + threadIdx.x; b < q; b += NT) Cm[k + (int64_t)b * m] = 0.0;
+          if (threadIdx.x == 0) Cm[k + (int64_t)q * m] = alpha;
+          __syncthreads();
+        }
+        for (int b = threadIdx.x; b < m; b += NT) vh[b] = Rm(b, b) < 0.0 ? -1.0 : 1.0;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += NT) {
+          const int i = int(e % m), j = int(e / m);
+          if (i <= j && vh[j] < 0.0) Cm[i + (int64_t)(qc + j) * m] = -Cm[i + (int64_t)(qc + j) * m];
+        }
+        __syncthreads();
+        if (p1 > 0) {
+          // W = R^-1 B, B(x, y) = S(A_s[p1 + x], A_s[y]) from the parent's panel
+          for (int64_t e = threadIdx.x; e < (int64_t)m * p1; e += NT) {
+            const int x = int(e % m), y = int(e / m);
+            Wb[e] = Sin[vp.at(rl[p1 + x], rl[y])];
+          }
+          __syncthreads();
+          wg_upper_solve<false>(Rm, m, Wb, m, p1, sm);
+        }
+      }
+      if (p1 > 0) {
+        // A - W^T W, index-reversed (Fl(p1-1-j, p1-1-i) for i >= j), then its Cholesky
+        wg_gemm<true, true>(
+            p1, p1, m, [&](int i, int k) { return Wb[k + (int64_t)i * m]; },
+            [&](int k, int j) { return Wb[k + (int64_t)j * m]; },
+            [&](int i, int j, double acc) {
+              Fl[(p1 - 1 - j) + (int64_t)(p1 - 1 - i) * p1] = Sin[vp.at(rl[i], rl[j])] - acc;
+            },
+            true, sm);
+        __syncthreads();
+        wg_potrf_panel(Fl, p1, p1, p1, sm, &fail);
+        __syncthreads();
+      }
+      if (threadIdx.x == 0 && fail >= 0) report(st, MFB_ENOCOMPLETION, v.vl[0]);
+      // R_s^T packed lower: entry (x, y), x >= y, is R_s(y, x)
+      for (int64_t e = threadIdx.x; e < (int64_t)A * A; e += NT) {
+        const int x = int(e % A), y = int(e / A);
+        if (x < y) continue;
+        double val;
+        if (y >= p1)
+          val = Rm(y - p1, x - p1);
+        else if (x >= p1)
+          val = Wb[(x - p1) + (int64_t)y * m];
+        else
+          val = Fl[(p1 - 1 - y) + (int64_t)(p1 - 1 - x) * p1];
+        Rs[pk(x, y, A)] = val;
+      }
+      __syncthreads();
+    }
+    // Z = R_s^-1 S_AN; L_AN = -R_s^-T Z
+    for (int64_t e = threadIdx.x; e < (int64_t)A * N; e += NT) {
+      const int x = int(e % A), c = int(e / A);
+      Z[e] = Sin[v.an(x, c)];
+    }
+    __syncthreads();
+    if (A > 0) {
+      auto Rsf = [&](int i, int j) { return Rs[pk(j, i, A)]; };  // R_s(i, j), i <= j
+      wg_upper_solve<false>(Rsf, A, Z, A, N, sm);
+      for (int64_t e = threadIdx.x; e < (int64_t)A * N; e += NT) X[e] = Z[e];
+      __syncthreads();
+      wg_upper_solve<true>(Rsf, A, X, A, N, sm);
+      for (int64_t e = threadIdx.x; e < (int64_t)A * N; e += NT) {
+        const int x = int(e % A), c = int(e / A);
+        LB[v.an(x, c)] = -X[e];
+      }
+      __syncthreads();
+    }
+    completion_finish(v, Sin, R, LB, part, st, ws, Z, sm, &fail);
+  });
+}
+
+void launch_completion_factored(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Sin,
+                                double* R, double* LB, double* S, double* Ru, double* part, DevStatus* st,
+                                double* wsb, int64_t slot) {
+  k_completion_factored<<<grid, NT, 0, s>>>(P, list, Sin, R, LB, S, Ru, part, st, wsb, slot);
 }
 
 // The inverse of S_{A_s A_s} for every supernode in the list (needs the

@@ -122,6 +122,7 @@ def _load():
         "mfb_graph_destroy": (None, [P]),
         "mfb_gram": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_completion": (I32, [P, P, P]),
+        "mfb_completion_factored": (I32, [P, P, P]),
         "mfb_cholesky_product": (I32, [P, P, P]),
         "mfb_factor_export_ldl": (I32, [P, P, P]),
         "mfb_get_status": (I32, [P, ctypes.POINTER(I64)]),
@@ -376,6 +377,11 @@ def completion(f: Factor, s, stream=None):
          "completion")
 
 
+def completion_factored(f: Factor, s, stream=None):
+    _chk(_lib.mfb_completion_factored(f.handle, _ptr(_dev_f64(s, f.plan.nnz, "s")), _stream(stream)),
+         "completion_factored")
+
+
 def cholesky_product(f: Factor, x, stream=None):
     _chk(_lib.mfb_cholesky_product(f.handle, _ptr(_dev_f64(x, f.plan.nnz, "x")), _stream(stream)),
          "cholesky_product")
@@ -501,6 +507,9 @@ class SparseBarrier:
 
     def completion(self, s):
         completion(self.f, s)
+
+    def completion_factored(self, s):
+        completion_factored(self.f, s)
 
     def cholesky_product(self):
         x = self._new()

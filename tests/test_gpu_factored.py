@@ -1,0 +1,128 @@
+"""GPU parity of the completion with factored update matrices
+(mfb_completion_factored: Algorithm 4.3 in supernodal form) against the
+oracle's Algorithm 4.3, through the C ABI, element by element.  The
+completion factor is unique, so the result must also agree with
+mfb_completion and with the factor of the X whose projected inverse is S;
+the handle must serve the operations that follow a completion (log det,
+product, Hessian, inverse Hessian)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.test_gpu_parity import CASES, TOL, close, dev, host
+from workloads import get_config, patterns as P, values as V
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mfb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1203_2742_amd import mfb as m
+    return m
+
+
+PATS = dict(CASES)
+PATS["band300_40"] = lambda: P.band(300, 40)
+PATS["grid3d_12"] = lambda: get_config("grid3d_12")
+NAMES = ["fig1", "band200", "diag50", "full70", "forest", "chordal150", "tree300", "arrow_small",
+         "arrow_mixed", "dense528", "roots_mixed", "grid2d_24", "grid3d_8", "band300_40", "grid3d_12"]
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_factored_completion_matches_oracle(name, mfb):
+    pat = PATS[name]()
+    print(f"[gpu-factored] {name}", flush=True)
+    x = V.make_x(*pat, seed=0)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    want = oracle.completion_factored(pat, s)
+    b = mfb.SparseBarrier(pat)
+    b.completion_factored(dev(s))
+    assert b.status() == (0, -1)
+    got = host(b.export_ldl())
+    close(None, got, want)
+    close(None, got, ldl)
+    # the same factor as the completion that factors every S_AA from scratch
+    a = mfb.SparseBarrier(pat)
+    a.completion(dev(s))
+    close(None, got, host(a.export_ldl()))
+    n = pat[0]
+    ld = float(host(b.logdet())[0])
+    want_ld = oracle.logdet(pat, want)
+    assert abs(ld - want_ld) / max(1.0, abs(want_ld)) <= TOL
+    close(pat, host(b.cholesky_product()), x)
+
+
+@pytest.mark.parametrize("name", ["arrow_mixed", "grid2d_24", "grid3d_8"])
+def test_factored_completion_serves_the_hessians(name, mfb):
+    """S cached and V_s gathered: the Hessian and inverse Hessian that
+    follow the completion match the oracle at X."""
+    pat = PATS[name]()
+    x = V.make_x(*pat, seed=0)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    ys = V.make_ys(*pat, 2, seed=3)
+    b = mfb.SparseBarrier(pat)
+    b.completion_factored(dev(s))
+    t = host(b.hessian(dev(ys)))
+    for r in range(2):
+        close(pat, t[r], oracle.hessian(pat, ldl, s, ys[r]))
+    yi = host(b.inv_hessian(dev(ys)))
+    for r in range(2):
+        close(pat, yi[r], oracle.inv_hessian(pat, ldl, s, ys[r]))
+
+
+def test_factored_completion_of_general_s(mfb):
+    pat = P.random_chordal(60, 0.06, 8)
+    s = V.project(*pat, V.make_spd_dense(pat[0], 3))
+    want = oracle.completion_factored(pat, s)
+    b = mfb.SparseBarrier(pat)
+    b.completion_factored(dev(s))
+    assert b.status() == (0, -1)
+    close(None, host(b.export_ldl()), want)
+
+
+def test_factored_completion_repeated_and_after_other_ops(mfb):
+    """Two calls in a row (the second with another S) and a call after a
+    factor and an inverse Hessian (whose cached blocks live where the
+    completion keeps its R_s) give the oracle's results."""
+    pat = PATS["arrow_mixed"]()
+    b = mfb.SparseBarrier(pat)
+    for seed in (0, 4):
+        x = V.make_x(*pat, seed=seed)
+        s = oracle.projinv(pat, oracle.factor(pat, x))
+        b.factor(dev(x))
+        b.inv_hessian(dev(V.make_ys(*pat, 1, seed=1)))
+        b.completion_factored(dev(s))
+        assert b.status() == (0, -1)
+        close(None, host(b.export_ldl()), oracle.completion_factored(pat, s))
+
+
+def test_factored_completion_not_completable(mfb):
+    pat = P.band(6, 2)
+    n, cp, ri = pat
+    s = np.zeros(cp[-1])
+    for j in range(n):
+        s[cp[j]] = 1.0
+        for e in range(cp[j] + 1, cp[j + 1]):
+            s[e] = 0.99
+    s[cp[2] + 1] = -0.99
+    with pytest.raises(oracle.OracleError):
+        oracle.completion_factored(pat, s)
+    b = mfb.SparseBarrier(pat)
+    b.completion_factored(dev(s))
+    code, _ = b.status()
+    assert code == mfb.ENOCOMPLETION
+
+
+def test_factored_completion_refused_on_relaxed_plan(mfb):
+    pat = get_config("grid3d_8")
+    b = mfb.SparseBarrier(pat, relax=0.2)
+    s = dev(np.ones(pat[1][-1]))
+    with pytest.raises(mfb.MfbError) as e:
+        mfb.completion_factored(b.f, s)
+    assert e.value.code == mfb.EINVAL
