@@ -654,6 +654,47 @@ def hessian_factor_extra(torch, mfb, V, st, reps=2):
                                                                  np.median(sp_ms)), 2)}}
 
 
+def factored_completion(torch, mfb, V, dev, reps=3):
+    """The paper's comparison of the primal gradient (projected inverse)
+    with the dual gradient computed by the completion, plain and with
+    factored update matrices, on band and arrow patterns of order 2000
+    (width w): GPU milliseconds per call (median of reps after one warm-up)
+    and the largest difference between the two completion factors."""
+    from workloads import patterns as P
+    out = {}
+    for kind, w in (("band", 10), ("band", 100), ("arrow", 10), ("arrow", 100), ("arrow", 1000)):
+        pat = P.band(2000, w) if kind == "band" else P.block_arrow([1] * (2000 - w), w)
+        b = mfb.SparseBarrier(pat, device=dev)
+        x = torch.from_numpy(V.make_x(*pat, seed=0)).to(dev)
+        b.factor(x)
+        s = b.projected_inverse().clone()
+
+        def ms(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return round(float(np.median(ts)), 4)
+        t_pi = ms(lambda: mfb.projected_inverse(b.f, s))
+        t_c = ms(lambda: b.completion(s))
+        l1 = b.export_ldl().cpu().numpy()
+        t_f = ms(lambda: b.completion_factored(s))
+        l2 = b.export_ldl().cpu().numpy()
+        out[f"{kind}2000_w{w}"] = {"projected_inverse_ms": t_pi, "completion_ms": t_c,
+                                   "completion_factored_ms": t_f, "status": b.status()[0],
+                                   "max_rel_diff": float(np.max(np.abs(l1 - l2)) / np.max(np.abs(l1)))}
+        del b
+        torch.cuda.empty_cache()
+    return out
+
+
 def served(torch, dev, nreq=200, npool=12, seed=0):
     """The served pattern: requests (pattern, X, Y_1..k) with k ~ U{1..8}
     over a pool of filled Erdos-Renyi patterns (average degree 6) under
@@ -796,6 +837,8 @@ def main():
         log(args, f"latency {extras['latency']}")
         extras["served"] = served(torch, dev)
         log(args, f"served {extras['served']}")
+        extras["factored_completion"] = factored_completion(torch, mfb, V, dev)
+        log(args, f"factored completion {extras['factored_completion']}")
         torch.cuda.empty_cache()
         p2 = get_config("grid2d_128")
         tun2 = tuning_for(p2, 1)

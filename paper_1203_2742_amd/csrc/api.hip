@@ -44,7 +44,7 @@ static int64_t complf_slot(const mfb_plan_s* p, int32_t s) {
   const int64_t N = p->N[s], A = p->J[s] - N;
   const int32_t q = p->parent[s];
   const int64_t Ap = q >= 0 ? p->J[q] - p->N[q] : 0;
-  return 3 * N * N + 2 * A * N + A * Ap + A * A + Ap + 64;
+  return 3 * N * N + 2 * A * N + A * Ap + A * A + 2 * Ap + 64;
 }
 static int64_t factor_scratch(const mfb_plan_s* p) {
   int64_t complf = 1;

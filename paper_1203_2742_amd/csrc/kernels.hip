@@ -636,7 +636,7 @@ __device__ __forceinline__ void wg_upper_solve(const UF& U, int n, double* B, in
 // lower in the front's block of Ru.  Then Z = R_s^-1 S_AN, L_AN =
 // -R_s^-T Z, and the front is finished as in k_completion with W = Z.
 // One root-to-leaf level per launch (the parents' R_p are in place).
-// Scratch: 3N^2 + 2AN + A Ap + A^2 + Ap + 64 doubles (Ap: the parent's A).
+// Scratch: 3N^2 + 2AN + A Ap + A^2 + 2 Ap + 64 doubles (Ap: the parent's A).
 __global__ void __launch_bounds__(NT) k_completion_factored(DevPlan P, const int32_t* list, const double* Sin,
                                                             double* R, double* LB, double* S, double* Ru,
                                                             double* part, DevStatus* st, double* wsb,
@@ -644,6 +644,7 @@ __global__ void __launch_bounds__(NT) k_completion_factored(DevPlan P, const int
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
   __shared__ int fail, sh_p1;
+  __shared__ double sh_tau[2];
   with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
     const int N = v.N, A = v.A;
     double* ws = slot_ptr(wsb, slot);
@@ -686,28 +687,47 @@ __global__ void __launch_bounds__(NT) k_completion_factored(DevPlan P, const int
           Cm[k + (int64_t)cc * m] = c >= r ? Rp[pk(c, r, Ap)] : 0.0;  // R_p(r, c) = R_p^T(c, r)
         }
         __syncthreads();
+        // Row x belongs to thread x % NT, which alone reads and writes it, so
+        // a step needs one barrier: the owner of row k forms its reflection
+        // (v, tau) from the row as it left it, publishes v in one of two
+        // buffers (LDS when C is at most kHhLds columns wide), and every
+        // thread applies it to its rows above k.  A buffer is rewritten two
+        // steps later, after every thread has passed the barrier between.
+        constexpr int kHhLds = SMEM_DOUBLES / 2;
+        double* vb = wC <= kHhLds ? sm : vh;
+        const int vstride = wC <= kHhLds ? kHhLds : wC;
         for (int k = m - 1; k >= 0; --k) {
           const int lo = rl[p1 + k] - Np - c0, q = qc + k;  // the row's first and diagonal columns
-          double acc = 0.0;
-          for (int b = lo + threadIdx.x; b < q; b += NT) acc += Cm[k + (int64_t)b * m] * Cm[k + (int64_t)b * m];
-          const double rest = wg_sum(acc, sm);
-          if (rest == 0.0) continue;  // (uniform)
-          const double xq = Cm[k + (int64_t)q * m];
-          const double nrm = sqrt(rest + xq * xq);
-          const double alpha = xq >= 0.0 ? -nrm : nrm;
-          const double tau = 2.0 / (rest + (xq - alpha) * (xq - alpha));
-          for (int b = lo + threadIdx.x; b <= q; b += NT) vh[b] = b == q ? xq - alpha : Cm[k + (int64_t)b * m];
-          __syncthreads();
-          for (int x = threadIdx.x; x < k; x += NT) {
-            double d = 0.0;
-            for (int b = lo; b <= q; ++b) d += Cm[x + (int64_t)b * m] * vh[b];
-            d *= tau;
-            for (int b = lo; b <= q; ++b) Cm[x + (int64_t)b * m] -= d * vh[b];
+          double* v = vb + (k & 1) * vstride;
+          if (threadIdx.x == k % NT) {
+            double rest = 0.0;
+            for (int b = lo; b < q; ++b) rest += Cm[k + (int64_t)b * m] * Cm[k + (int64_t)b * m];
+            double tau = 0.0;  // no weight left of the diagonal column: H = I
+            if (rest != 0.0) {
+              const double xq = Cm[k + (int64_t)q * m];
+              const double nrm = sqrt(rest + xq * xq);
+              const double alpha = xq >= 0.0 ? -nrm : nrm;
+              tau = 2.0 / (rest + (xq - alpha) * (xq - alpha));
+              for (int b = lo; b < q; ++b) {
+                v[b] = Cm[k + (int64_t)b * m];
+                Cm[k + (int64_t)b * m] = 0.0;
+              }
+              v[q] = xq - alpha;
+              Cm[k + (int64_t)q * m] = alpha;
+            }
+            sh_tau[k & 1] = tau;
           }
-          for (int b = lo + threadIdx.x; b < q; b += NT) Cm[k + (int64_t)b * m] = 0.0;
-          if (threadIdx.x == 0) Cm[k + (int64_t)q * m] = alpha;
           __syncthreads();
+          const double tau = sh_tau[k & 1];
+          if (tau != 0.0)
+            for (int x = threadIdx.x; x < k; x += NT) {
+              double d = 0.0;
+              for (int b = lo; b <= q; ++b) d += Cm[x + (int64_t)b * m] * v[b];
+              d *= tau;
+              for (int b = lo; b <= q; ++b) Cm[x + (int64_t)b * m] -= d * v[b];
+            }
         }
+        __syncthreads();
         for (int b = threadIdx.x; b < m; b += NT) vh[b] = Rm(b, b) < 0.0 ? -1.0 : 1.0;
         __syncthreads();
         for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += NT) {
