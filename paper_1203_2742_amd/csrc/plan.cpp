@@ -331,10 +331,16 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
       g.fat_fin = std::max(g.fat_fin, tn * tn + ta * tn);
     }
   };
+  // mid_wide: the Hessian's root-to-leaf sweep also takes the non-root
+  // fronts above kDownRegMaxJ tile-parallel (wide class)
+  bool mid_wide = false;
+  auto down_wide = [&](int32_t k) {
+    return is_wide(k) || (mid_wide && p->J[k] > kDownRegMaxJ && p->J[k] != p->N[k]);
+  };
   auto down_reg_level = [&](const std::vector<int32_t>& list, const Level& L, bool wide_ok) {
     bool small = true, roots = true;
     for (int32_t t = L.begin; t < L.begin + L.count; ++t) {
-      if (wide_ok && is_wide(list[t])) continue;
+      if (wide_ok && down_wide(list[t])) continue;
       small = small && p->J[list[t]] <= kDownRegMaxJ;
       roots = roots && p->J[list[t]] == p->N[list[t]];
     }
@@ -357,11 +363,11 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
       const bool reg_ok = !down || down_reg_level(list, L, wide_ok);
       int lvcls = 0;
       for (int32_t t = L.begin; t < L.begin + L.count; ++t)
-        if (!(wide_ok && is_wide(list[t])) && fit_class(list[t]) < kRegClasses)
+        if (!(wide_ok && (down ? down_wide(list[t]) : is_wide(list[t]))) && fit_class(list[t]) < kRegClasses)
           lvcls = std::max(lvcls, fit_class(list[t]));
       auto class_of = [&](int32_t k) {
         if (wide_ok && !down && up_class(k) >= 0) return up_class(k);
-        if (wide_ok && down && is_wide(k)) return kWide;
+        if (wide_ok && down && down_wide(k)) return kWide;
         return reg_ok && fit_class(k) < kRegClasses ? lvcls : kRegClasses;
       };
       for (int c : {kFat, kWide, kRegClasses, lvcls}) {
@@ -640,7 +646,13 @@ static mfb_status_t finish_plan(int64_t n, const int64_t* cp, const int32_t* ri,
     if (S.count) cs.segs.push_back(ClassSeg{S, -1, kRegClasses});
   }
   make_classes(p->down_list, p->down_levels, false, true, p->cs_down, true);
-  p->cs_hdown = p->cs_down;
+  // the Hessian's steps 2-3: non-root fronts above kDownRegMaxJ on the
+  // tile-parallel kernels too (on the 40^3 grid's relaxed plans, thousands
+  // of fronts of order 65-192 per sweep, one workgroup per front and
+  // right-hand side on the blocked kernel otherwise)
+  mid_wide = true;
+  make_classes(p->down_list, p->down_levels, false, true, p->cs_hdown, true);
+  mid_wide = false;
   p->hd_root = -1;
   p->ihd_root = -1;
   if (!p->down_levels.empty() && p->down_levels[0].count == 1) {
