@@ -126,3 +126,29 @@ def test_factored_completion_refused_on_relaxed_plan(mfb):
     with pytest.raises(mfb.MfbError) as e:
         mfb.completion_factored(b.f, s)
     assert e.value.code == mfb.EINVAL
+
+
+@pytest.mark.parametrize("name,flags", [("empty", 0), ("roots_mixed", 0), ("arrow_mixed", 1), ("grid3d_8", 1)])
+def test_factored_completion_edge_plans(name, flags, mfb):
+    """No supernode at all; a forest of roots beside a band (fronts with
+    A = 0 next to fronts whose parent holds every ancestor); plans with the
+    tile-parallel classes forced low (the factored completion ignores the
+    classes, the plain one does not, and both must agree)."""
+    if name == "empty":
+        pat = (0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+        b = mfb.SparseBarrier(pat)
+        b.completion_factored(torch.zeros(1, dtype=torch.float64, device="cuda")[:0])
+        assert b.status() == (0, -1)
+        return
+    pat = PATS[name]()
+    x = V.make_x(*pat, seed=2)
+    s = oracle.projinv(pat, oracle.factor(pat, x))
+    fl = mfb.PLAN_WIDE_LOW if flags else 0
+    b = mfb.SparseBarrier(pat, flags=fl)
+    b.completion_factored(dev(s))
+    assert b.status() == (0, -1)
+    got = host(b.export_ldl())
+    close(None, got, oracle.completion_factored(pat, s))
+    a = mfb.SparseBarrier(pat, flags=fl)
+    a.completion(dev(s))
+    close(None, got, host(a.export_ldl()))
