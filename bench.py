@@ -659,7 +659,9 @@ def factored_completion(torch, mfb, V, dev, reps=3):
     with the dual gradient computed by the completion, plain and with
     factored update matrices, on band and arrow patterns of order 2000
     (width w): GPU milliseconds per call (median of reps after one warm-up)
-    and the largest difference between the two completion factors."""
+    and the largest difference between the two completion factors; also
+    the inverse Hessian of 4 right-hand sides with S_AA used through those
+    factors and through the cached inverse factors."""
     from workloads import patterns as P
     out = {}
     for kind, w in (("band", 10), ("band", 100), ("arrow", 10), ("arrow", 100), ("arrow", 1000)):
@@ -687,9 +689,22 @@ def factored_completion(torch, mfb, V, dev, reps=3):
         l1 = b.export_ldl().cpu().numpy()
         t_f = ms(lambda: b.completion_factored(s))
         l2 = b.export_ldl().cpu().numpy()
+        # the inverse Hessian of 4 right-hand sides with S_AA through the
+        # R_s of the factored completion, and through the cached inverse
+        # factors after the plain completion
+        tk = torch.from_numpy(V.make_ys(*pat, 4, seed=1)).to(dev)
+        yf = torch.empty_like(tk)
+        yp = torch.empty_like(tk)
+        ar = b.arena(4)
+        t_if = ms(lambda: mfb.inv_hessian_factored(b.f, tk, yf, ar, k=4))
+        b.completion(s)
+        t_ip = ms(lambda: mfb.inv_hessian(b.f, tk, yp, ar, k=4))
+        dy = float((yf - yp).abs().max() / yp.abs().max())
         out[f"{kind}2000_w{w}"] = {"projected_inverse_ms": t_pi, "completion_ms": t_c,
                                    "completion_factored_ms": t_f, "status": b.status()[0],
-                                   "max_rel_diff": float(np.max(np.abs(l1 - l2)) / np.max(np.abs(l1)))}
+                                   "max_rel_diff": float(np.max(np.abs(l1 - l2)) / np.max(np.abs(l1))),
+                                   "inv_hessian_k4_ms": t_ip, "inv_hessian_factored_k4_ms": t_if,
+                                   "inv_hessian_max_rel_diff": dy}
         del b
         torch.cuda.empty_cache()
     return out

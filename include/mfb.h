@@ -320,6 +320,20 @@ mfb_status_t mfb_completion(mfb_factor_t f, const double* s_dev, void* stream);
  * S_AA are not formed (the inverse Hessian forms them on its first call). */
 mfb_status_t mfb_completion_factored(mfb_factor_t f, const double* s_dev, void* stream);
 
+/* Inverse Hessian at the X of the last mfb_completion_factored (Algorithm
+ * 5.2 with the improvement noted after it): steps 1 and 2 use S_{A_s A_s}
+ * through the factors V_s = R_s R_s^T that the factored completion left in
+ * the handle, K_AN = R_s^-T R_s^-1 (M_AN D) by two triangular solves per
+ * front, so no inverse of S_AA is formed; step 3 as in mfb_inv_hessian.
+ * One workgroup per front and right-hand side for steps 1 and 2.  Buffer
+ * rules as mfb_hessian.  MFB_ESTATE unless the handle's last factor came
+ * from mfb_completion_factored and no call that rewrites its update arena
+ * (mfb_factor, mfb_completion, mfb_cholesky_product, mfb_inv_hessian,
+ * mfb_hessian_factor, mfb_hessian_factor_adj) followed it; MFB_EINVAL on a
+ * relaxed plan. */
+mfb_status_t mfb_inv_hessian_factored(mfb_factor_t f, int32_t k, const double* t_dev, double* y_dev,
+                                      void* arena_dev, size_t arena_bytes, void* stream);
+
 /* Algorithm 3.2 (block form): values of L D L^T on V, written to x_dev
  * (nnz doubles).  For a completion this gives X-hat = -grad f_*(S). */
 mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x_dev, void* stream);

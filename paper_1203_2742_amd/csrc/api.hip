@@ -193,6 +193,9 @@ struct mfb_factor_s {
   double* Xw = nullptr;
   DevStatus* st = nullptr;
   bool has_factor = false, s_valid = false, vinv_valid = false, gam_valid = false;
+  // U holds the factored completion's R_s blocks (written by
+  // mfb_completion_factored; every other user of U clears it)
+  bool rfac_valid = false;
   hipStream_t last = nullptr;
 };
 
@@ -503,7 +506,7 @@ mfb_status_t mfb_factor(mfb_factor_t f, const double* x, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
   // the cached state describes the previous X until this factor is enqueued
-  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
+  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = f->rfac_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   const mfb_plan_s* p = f->plan;
   if (p->relaxed) {  // X on V' (zero on V' \ V)
@@ -806,6 +809,7 @@ static mfb_status_t ensure_vinv(mfb_factor_s* f, hipStream_t s) {
   if (st) return st;
   f->vinv_valid = true;
   f->gam_valid = false;  // Vi and U overwrote Gami and Gam
+  f->rfac_valid = false;
   return MFB_OK;
 }
 
@@ -828,6 +832,7 @@ static mfb_status_t ensure_gamma(mfb_factor_s* f, hipStream_t s) {
   if (st) return st;
   f->gam_valid = true;
   f->vinv_valid = false;  // Gami overwrote Vi
+  f->rfac_valid = false;
   return MFB_OK;
 }
 
@@ -903,70 +908,39 @@ mfb_status_t mfb_gram(mfb_plan_t p, int32_t m, const double* w, double* gout, vo
   return launched();
 }
 
-mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double* y, void* arena,
-                             size_t bytes, void* stream) {
-  if (!f || k < 0 || f->plan->relaxed) return MFB_EINVAL;
-  if (k == 0) return MFB_OK;
-  if (!y || !t) return MFB_EINVAL;
-  if (!f->has_factor) return MFB_ESTATE;
-  RhsArena a;
-  mfb_status_t st = carve(f, k, arena, bytes, &a);
-  if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
-  f->last = s;
-  if ((st = ensure_projinv(f, s))) return st;
-  if ((st = ensure_vinv(f, s))) return st;
-  struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
-  // V'_s = T_{A_s A_s} for every supernode and right-hand side (root-to-leaf
-  // gathers), then steps 1+2 of all fronts, which are independent
-  // (without the source map the level gathers also leave the partial
-  // products T_AA L of the fronts that have a partial area)
-  st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd, 1, a.part, a.pstride);
-  if (st) return st;
-  if (f->plan->ihd_root >= 0) {
-    // the root front: three tile-parallel products (steps 1+2 with A = 0)
-    const mfb_plan_s* p = f->plan;
-    const int N = p->N[p->ihd_root];
-    const unsigned tiles = unsigned((N + 63) / 64);
-    const int32_t* root = p->d_all_list + p->ihd_root;
-    ProfRec rec{MFB_K_IHESS_DOWN, 0, 1, k, 0.0, 0.0, nullptr, nullptr};
-    if (f->prof) {
-      canonical(MFB_K_IHESS_DOWN, p->down_levels[0], k, &rec.bytes, &rec.flops);
-      rec.e0 = pool_event(f);
-      rec.e1 = pool_event(f);
-      if (!rec.e0 || !rec.e1) return MFB_EHIP;
-      if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
-    }
-    const dim3 grid(tiles, tiles, unsigned(k));
-    const int64_t ws = 2 * int64_t(N) * N;
-    k_ihess_down_root<0><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
-    k_ihess_down_root<1><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
-    k_ihess_down_root<2><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
-    if (hipGetLastError() != hipSuccess) return MFB_EHIP;
-    if (f->prof) {
-      if (hipEventRecord(rec.e1, s) != hipSuccess) return MFB_EHIP;
-      f->recs.push_back(rec);
-    }
+// Inverse Hessian steps 1+2 on the root front when it runs alone (A = 0):
+// three tile-parallel products.
+static mfb_status_t ihess_root(mfb_factor_s* f, int32_t k, const double* t, const RhsArena& a, hipStream_t s) {
+  if (f->plan->ihd_root < 0) return MFB_OK;
+  const mfb_plan_s* p = f->plan;
+  const int N = p->N[p->ihd_root];
+  const unsigned tiles = unsigned((N + 63) / 64);
+  const int32_t* root = p->d_all_list + p->ihd_root;
+  ProfRec rec{MFB_K_IHESS_DOWN, 0, 1, k, 0.0, 0.0, nullptr, nullptr};
+  if (f->prof) {
+    canonical(MFB_K_IHESS_DOWN, p->down_levels[0], k, &rec.bytes, &rec.flops);
+    rec.e0 = pool_event(f);
+    rec.e1 = pool_event(f);
+    if (!rec.e0 || !rec.e1) return MFB_EHIP;
+    if (hipEventRecord(rec.e0, s) != hipSuccess) return MFB_EHIP;
   }
-  st = run_classes(
-      f, MFB_K_IHESS_DOWN, f->plan->cs_ihd_flat, s, k, OP_IHDOWN,
-      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
-        const int cls = sg.cls;
-        const int32_t* list = cs.d_list + sg.lv.begin;
-        Ctx* x = (Ctx*)c;
-        if (cls < kRegClasses)
-          launch_ihess_down_reg(cls, g, s, f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
-                                x->a.Ua, x->a.upd, x->a.scr, slot);
-        else if (cls == kFat)
-          launch_fat_ihess(fat_grid(sg), int(g.y), s, f->plan->dev, list, sg.lv.count, f->R, f->LB, f->Vi, x->t,
-                           x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, f->plan->d_gmap ? nullptr : x->a.part,
-                           x->a.pstride);
-        else
-          k_ihess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
-                                               x->a.Ua, x->a.upd, x->a.scr, slot);
-      },
-      &ctx);
-  if (st) return st;
+  const dim3 grid(tiles, tiles, unsigned(k));
+  const int64_t ws = 2 * int64_t(N) * N;
+  k_ihess_down_root<0><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
+  k_ihess_down_root<1><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
+  k_ihess_down_root<2><<<grid, NT_LAUNCH, 0, s>>>(p->dev, root, f->R, t, a.Kt, a.scr, ws);
+  if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+  if (f->prof) {
+    if (hipEventRecord(rec.e1, s) != hipSuccess) return MFB_EHIP;
+    f->recs.push_back(rec);
+  }
+  return MFB_OK;
+}
+
+// Inverse Hessian step 3 (leaf-to-root) from K in a.Kt: Y into y.
+static mfb_status_t ihess_up_run(mfb_factor_s* f, int32_t k, double* y, const RhsArena& a, hipStream_t s) {
+  struct Ctx { const double* t; double* y; RhsArena a; } ctx{nullptr, y, a};
+  mfb_status_t st;
   st = run_classes(
       f, MFB_K_IHESS_UP, f->plan->cs_factor, s, k, OP_IHUP,
       [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
@@ -1000,11 +974,81 @@ mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double*
   return launched();
 }
 
+mfb_status_t mfb_inv_hessian(mfb_factor_t f, int32_t k, const double* t, double* y, void* arena,
+                             size_t bytes, void* stream) {
+  if (!f || k < 0 || f->plan->relaxed) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!y || !t) return MFB_EINVAL;
+  if (!f->has_factor) return MFB_ESTATE;
+  RhsArena a;
+  mfb_status_t st = carve(f, k, arena, bytes, &a);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  if ((st = ensure_projinv(f, s))) return st;
+  if ((st = ensure_vinv(f, s))) return st;
+  struct Ctx { const double* t; double* y; RhsArena a; } ctx{t, y, a};
+  // V'_s = T_{A_s A_s} for every supernode and right-hand side (root-to-leaf
+  // gathers), then steps 1+2 of all fronts, which are independent
+  // (without the source map the level gathers also leave the partial
+  // products T_AA L of the fronts that have a partial area)
+  st = gather_blocks(f, s, k, t, a.Ua, f->plan->nnz, a.upd, 1, a.part, a.pstride);
+  if (st) return st;
+  if ((st = ihess_root(f, k, t, a, s))) return st;
+  st = run_classes(
+      f, MFB_K_IHESS_DOWN, f->plan->cs_ihd_flat, s, k, OP_IHDOWN,
+      [](mfb_factor_s* f, const ClassSched& cs, const ClassSeg& sg, dim3 g, hipStream_t s, int64_t slot, void* c) {
+        const int cls = sg.cls;
+        const int32_t* list = cs.d_list + sg.lv.begin;
+        Ctx* x = (Ctx*)c;
+        if (cls < kRegClasses)
+          launch_ihess_down_reg(cls, g, s, f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
+                                x->a.Ua, x->a.upd, x->a.scr, slot);
+        else if (cls == kFat)
+          launch_fat_ihess(fat_grid(sg), int(g.y), s, f->plan->dev, list, sg.lv.count, f->R, f->LB, f->Vi, x->t,
+                           x->a.Kt, x->a.Ua, x->a.upd, x->a.scr, slot, f->plan->d_gmap ? nullptr : x->a.part,
+                           x->a.pstride);
+        else
+          k_ihess_down<<<g, NT_DOWN, 0, s>>>(f->plan->dev, list, f->R, f->LB, f->Vi, x->t, x->a.Kt,
+                                               x->a.Ua, x->a.upd, x->a.scr, slot);
+      },
+      &ctx);
+  if (st) return st;
+  return ihess_up_run(f, k, y, ctx.a, s);
+}
+
+mfb_status_t mfb_inv_hessian_factored(mfb_factor_t f, int32_t k, const double* t, double* y, void* arena,
+                                      size_t bytes, void* stream) {
+  if (!f || k < 0 || f->plan->relaxed) return MFB_EINVAL;
+  if (k == 0) return MFB_OK;
+  if (!y || !t) return MFB_EINVAL;
+  if (!f->has_factor || !f->s_valid || !f->rfac_valid) return MFB_ESTATE;
+  RhsArena a;
+  mfb_status_t st = carve(f, k, arena, bytes, &a);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  f->last = s;
+  const mfb_plan_s* p = f->plan;
+  // T_{A_s A_s} for every supernode (root-to-leaf gathers), then steps 1+2
+  // of all fronts, which are independent, with S_AA through R_s in U
+  st = gather_blocks(f, s, k, t, a.Ua, p->nnz, a.upd, 1, a.part, a.pstride);
+  if (st) return st;
+  if ((st = ihess_root(f, k, t, a, s))) return st;
+  for (const ClassSeg& sg : p->cs_ihd_flat.segs) {
+    const int64_t slot = std::max<int64_t>(1, slot_doubles(OP_IHDOWN, sg.lv));
+    launch_ihess_down_factored(dim3(unsigned(sg.lv.count), unsigned(k)), s, p->dev,
+                               p->cs_ihd_flat.d_list + sg.lv.begin, f->R, f->LB, f->U, t, a.Kt, a.Ua, a.upd,
+                               a.scr, slot);
+    if (hipGetLastError() != hipSuccess) return MFB_EHIP;
+  }
+  return ihess_up_run(f, k, y, a, s);
+}
+
 mfb_status_t mfb_completion(mfb_factor_t f, const double* sin, void* stream) {
   if (!f || (!sin && f->plan->nnz) || f->plan->relaxed) return MFB_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
-  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
+  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = f->rfac_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   struct Ctx { const double* s; } ctx{sin};
   // V_s = S_{A_s A_s} for every supernode (root-to-leaf gathers), then the
@@ -1049,7 +1093,7 @@ mfb_status_t mfb_completion_factored(mfb_factor_t f, const double* sin, void* st
   if (!f || (!sin && f->plan->nnz) || f->plan->relaxed) return MFB_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
-  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = false;
+  f->has_factor = f->s_valid = f->vinv_valid = f->gam_valid = f->rfac_valid = false;
   k_reset_status<<<1, 64, 0, s>>>(f->st);
   const mfb_plan_s* p = f->plan;
   // V_s = S_{A_s A_s} for the Hessian sweeps that may follow (the
@@ -1072,6 +1116,7 @@ mfb_status_t mfb_completion_factored(mfb_factor_t f, const double* sin, void* st
   }
   f->has_factor = true;
   f->s_valid = true;
+  f->rfac_valid = true;
   return launched();
 }
 
@@ -1081,6 +1126,7 @@ mfb_status_t mfb_cholesky_product(mfb_factor_t f, double* x, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   f->last = s;
   f->gam_valid = false;  // the sweep's update arena U holds the Hessian factor's G
+  f->rfac_valid = false;
   const mfb_plan_s* p = f->plan;
   double* xo = x;
   if (p->relaxed) x = f->Xw;  // on V', restricted to V below

@@ -69,6 +69,11 @@ void launch_completion_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, 
 void launch_completion_factored(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* Sin,
                                 double* R, double* LB, double* S, double* Ru, double* part, DevStatus* st,
                                 double* wsb, int64_t slot);
+// Inverse Hessian steps 1+2 with S_AA through the factors R_s left in Ru by
+// the factored completion (grid: fronts of list x right-hand sides).
+void launch_ihess_down_factored(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
+                                const double* LB, const double* Ru, const double* T, double* Kt, double* Va,
+                                int64_t upd, double* wsb, int64_t slot);
 // act: Hessian step 1's per-(RHS, supernode) activity flags (ns per RHS;
 // entries of pruned fronts are set to 0, others left as they are)
 void launch_hess_up_reg(int cls, dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list,

@@ -419,6 +419,132 @@ __global__ void __launch_bounds__(NT_DOWN) k_ihess_down(DevPlan P, const int32_t
   });
 }
 
+// Triangular solves with an upper triangular U (n x n; U(i, j), i <= j,
+// read through a functor) in one workgroup, in place on a column-major B
+// (leading dimension ldb, nc columns), blocked by NB: each diagonal block
+// is inverted in LDS (diag_trtri of its transpose), the rest are wg_gemm
+// updates.  TRANS = false: B <- U^-1 B (last block row first); TRANS =
+// true: B <- U^-T B (first block row first).  Ends with a barrier.
+template <bool TRANS, class UF>
+__device__ __forceinline__ void wg_upper_solve(const UF& U, int n, double* B, int64_t ldb, int nc, double* sm) {
+  double* Ld = sm + SMEM_GEMM;
+  double* Li = Ld + NB * LDD;
+  const int nblk = (n + NB - 1) / NB;
+  for (int t = 0; t < nblk; ++t) {
+    const int bk = TRANS ? t : nblk - 1 - t;
+    const int jb = bk * NB, nb = min(NB, n - jb), r1 = jb + nb;
+    if (!TRANS && r1 < n) {
+      wg_gemm(
+          nb, nc, n - r1, [&](int i, int k) { return U(jb + i, r1 + k); },
+          [&](int k, int j) { return B[(r1 + k) + j * ldb]; },
+          [&](int i, int j, double acc) { B[(jb + i) + j * ldb] -= acc; }, false, sm);
+      __syncthreads();
+    }
+    if (TRANS && jb > 0) {
+      wg_gemm(
+          nb, nc, jb, [&](int i, int k) { return U(k, jb + i); }, [&](int k, int j) { return B[k + j * ldb]; },
+          [&](int i, int j, double acc) { B[(jb + i) + j * ldb] -= acc; }, false, sm);
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (i >= j) Ld[i + j * LDD] = U(jb + j, jb + i);  // the block's transpose (lower)
+    }
+    __syncthreads();
+    diag_trtri(Ld, Li, nb);  // Li = U_bb^-T
+    wg_gemm(
+        nb, nc, nb,
+        [&](int i, int k) {
+          return TRANS ? (k <= i ? Li[i + k * LDD] : 0.0) : (k >= i ? Li[k + i * LDD] : 0.0);
+        },
+        [&](int k, int j) { return B[(jb + k) + j * ldb]; },
+        [&](int i, int j, double acc) { B[(jb + i) + j * ldb] = acc; }, false, sm);
+    __syncthreads();
+  }
+}
+
+// Inverse Hessian steps 1 and 2 as in k_ihess_down, with the improvement
+// noted after Algorithm 5.2: S_{A_s A_s} is used through its factor
+// V_s = R_s R_s^T (R_s upper triangular, packed as R_s^T lower in Ru,
+// left there by the completion with factored update matrices), so that
+// K_AN = R_s^-T R_s^-1 (M_AN D) by two triangular solves and no inverse
+// of S_AA is formed.  One workgroup per front and right-hand side.
+// Scratch: 2AN + 3N^2.
+__global__ void __launch_bounds__(NT) k_ihess_down_factored(DevPlan P, const int32_t* list, const double* R,
+                                                            const double* LB, const double* Ru,
+                                                            const double* T, double* Kt, double* Va,
+                                                            int64_t upd, double* wsb, int64_t slot) {
+  __shared__ double sm[SMEM_DOUBLES];
+  __shared__ int64_t colc[kColCache];
+  with_staged_cols(SnView(P, list[blockIdx.x]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int64_t r = blockIdx.y;
+    const double* t = T + r * P.nnz;
+    double* K = Kt + r * P.nnz;
+    double* va = Va + r * upd;
+    const int N = v.N, A = v.A;
+    double* MA = slot_ptr(wsb, slot);
+    double* Z = MA + (int64_t)A * N;
+    double* MN = Z + (int64_t)A * N;
+    double* Dm = MN + (int64_t)N * N;
+    double* W = Dm + (int64_t)N * N;
+    // D = C C^T (full)
+    wg_gemm(
+        N, N, N, [&](int i, int k) { return k <= i ? R[v.at(i, k)] : 0.0; },
+        [&](int k, int j) { return k <= j ? R[v.at(j, k)] : 0.0; },
+        [&](int i, int j, double acc) { Dm[i + (int64_t)j * N] = acc; }, false, sm);
+    __syncthreads();
+    // M_AN = T_AN + V' L (V'_s = T_{A_s A_s}, gathered beforehand)
+    const double* Vp = va + P.arena[v.s];
+    wg_gemm<false, true>(
+        A, N, A, [&](int i, int k) { return sym_packed(Vp, i, k, A); },
+        [&](int k, int j) { return LB[v.an(k, j)]; },
+        [&](int i, int j, double acc) { MA[i + (int64_t)j * A] = t[v.an(i, j)] + acc; }, false, sm);
+    __syncthreads();
+    // M_NN = T_NN + L^T M_AN + T_AN^T L
+    wg_gemm<true, true>(
+        N, N, 2 * A,
+        [&](int i, int k) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; },
+        [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; },
+        [&](int i, int j, double acc) {
+          const double m = t[v.at(i, j)] + acc;
+          MN[i + (int64_t)j * N] = m;
+          MN[j + (int64_t)i * N] = m;
+        },
+        true, sm);
+    __syncthreads();
+    // W = M_NN D, Z = M_AN D, K_NN = D W
+    wg_gemm<false, true>(
+        N, N, N, [&](int i, int k) { return MN[i + (int64_t)k * N]; },
+        [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { W[i + (int64_t)j * N] = acc; }, false, sm);
+    wg_gemm<false, true>(
+        A, N, N, [&](int i, int k) { return MA[i + (int64_t)k * A]; },
+        [&](int k, int j) { return Dm[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { Z[i + (int64_t)j * A] = acc; }, false, sm);
+    __syncthreads();
+    wg_gemm<false, true>(
+        N, N, N, [&](int i, int k) { return Dm[i + (int64_t)k * N]; },
+        [&](int k, int j) { return W[k + (int64_t)j * N]; },
+        [&](int i, int j, double acc) { K[v.at(i, j)] = acc; }, true, sm);
+    if (A == 0) return;  // (uniform)
+    // K_AN = R_s^-T (R_s^-1 Z)
+    const double* Rs = Ru + P.arena[v.s];
+    auto Rsf = [&](int i, int j) { return Rs[pk(j, i, A)]; };  // R_s(i, j), i <= j
+    wg_upper_solve<false>(Rsf, A, Z, A, N, sm);
+    wg_upper_solve<true>(Rsf, A, Z, A, N, sm);
+    for (int64_t e = threadIdx.x; e < (int64_t)A * N; e += NT) {
+      const int x = int(e % A), c = int(e / A);
+      K[v.an(x, c)] = Z[e];
+    }
+  });
+}
+
+void launch_ihess_down_factored(dim3 grid, hipStream_t s, const DevPlan& P, const int32_t* list, const double* R,
+                                const double* LB, const double* Ru, const double* T, double* Kt, double* Va,
+                                int64_t upd, double* wsb, int64_t slot) {
+  k_ihess_down_factored<<<grid, NT, 0, s>>>(P, list, R, LB, Ru, T, Kt, Va, upd, wsb, slot);
+}
+
 // Inverse Hessian step 3 (leaf-to-root), block form of Algorithm 5.2:
 // G' = sum E U'_c E^T; Y_NN = K_NN - G'11; Y_AN = L K_NN + K_AN - G'21;
 // U'_s = G'22 - L K_NN L^T - L K_AN^T - K_AN L^T.  Scratch: J*N + A*N.
@@ -576,50 +702,6 @@ __global__ void __launch_bounds__(NT) k_completion(DevPlan P, const int32_t* lis
       wg_lauum_inplace(Cvi, A, sm);
     }
   });
-}
-
-// Triangular solves with an upper triangular U (n x n; U(i, j), i <= j,
-// read through a functor) in one workgroup, in place on a column-major B
-// (leading dimension ldb, nc columns), blocked by NB: each diagonal block
-// is inverted in LDS (diag_trtri of its transpose), the rest are wg_gemm
-// updates.  TRANS = false: B <- U^-1 B (last block row first); TRANS =
-// true: B <- U^-T B (first block row first).  Ends with a barrier.
-template <bool TRANS, class UF>
-__device__ __forceinline__ void wg_upper_solve(const UF& U, int n, double* B, int64_t ldb, int nc, double* sm) {
-  double* Ld = sm + SMEM_GEMM;
-  double* Li = Ld + NB * LDD;
-  const int nblk = (n + NB - 1) / NB;
-  for (int t = 0; t < nblk; ++t) {
-    const int bk = TRANS ? t : nblk - 1 - t;
-    const int jb = bk * NB, nb = min(NB, n - jb), r1 = jb + nb;
-    if (!TRANS && r1 < n) {
-      wg_gemm(
-          nb, nc, n - r1, [&](int i, int k) { return U(jb + i, r1 + k); },
-          [&](int k, int j) { return B[(r1 + k) + j * ldb]; },
-          [&](int i, int j, double acc) { B[(jb + i) + j * ldb] -= acc; }, false, sm);
-      __syncthreads();
-    }
-    if (TRANS && jb > 0) {
-      wg_gemm(
-          nb, nc, jb, [&](int i, int k) { return U(k, jb + i); }, [&](int k, int j) { return B[k + j * ldb]; },
-          [&](int i, int j, double acc) { B[(jb + i) + j * ldb] -= acc; }, false, sm);
-      __syncthreads();
-    }
-    for (int e = threadIdx.x; e < nb * nb; e += NT) {
-      const int i = e % nb, j = e / nb;
-      if (i >= j) Ld[i + j * LDD] = U(jb + j, jb + i);  // the block's transpose (lower)
-    }
-    __syncthreads();
-    diag_trtri(Ld, Li, nb);  // Li = U_bb^-T
-    wg_gemm(
-        nb, nc, nb,
-        [&](int i, int k) {
-          return TRANS ? (k <= i ? Li[i + k * LDD] : 0.0) : (k >= i ? Li[k + i * LDD] : 0.0);
-        },
-        [&](int k, int j) { return B[(jb + k) + j * ldb]; },
-        [&](int i, int j, double acc) { B[(jb + i) + j * ldb] = acc; }, false, sm);
-    __syncthreads();
-  }
 }
 
 // Algorithm 7.3 with factored update matrices (the supernodal form of

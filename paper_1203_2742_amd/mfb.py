@@ -123,6 +123,7 @@ def _load():
         "mfb_gram": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_completion": (I32, [P, P, P]),
         "mfb_completion_factored": (I32, [P, P, P]),
+        "mfb_inv_hessian_factored": (I32, [P, I32, P, P, P, SZ, P]),
         "mfb_cholesky_product": (I32, [P, P, P]),
         "mfb_factor_export_ldl": (I32, [P, P, P]),
         "mfb_get_status": (I32, [P, ctypes.POINTER(I64)]),
@@ -377,6 +378,16 @@ def completion(f: Factor, s, stream=None):
          "completion")
 
 
+def inv_hessian_factored(f: Factor, t, y, arena, k=None, stream=None):
+    nnz = f.plan.nnz
+    k = _k_of(t, nnz) if k is None else int(k)
+    _dev_f64(t, k * nnz, "t")
+    _dev_f64(y, k * nnz, "y")
+    _chk(_lib.mfb_inv_hessian_factored(f.handle, k, _ptr(t), _ptr(y), _ptr(arena),
+                                       arena.numel() * arena.element_size(), _stream(stream)),
+         "inv_hessian_factored")
+
+
 def completion_factored(f: Factor, s, stream=None):
     _chk(_lib.mfb_completion_factored(f.handle, _ptr(_dev_f64(s, f.plan.nnz, "s")), _stream(stream)),
          "completion_factored")
@@ -483,6 +494,12 @@ class SparseBarrier:
         k = 1 if t.dim() == 1 else t.shape[0]
         y = torch_empty_like(t)
         inv_hessian(self.f, t, y, self.arena(k), k=k)
+        return y
+
+    def inv_hessian_factored(self, t):
+        k = 1 if t.dim() == 1 else t.shape[0]
+        y = torch_empty_like(t)
+        inv_hessian_factored(self.f, t, y, self.arena(k), k=k)
         return y
 
     def hessian_factor(self, y):

@@ -152,3 +152,59 @@ def test_factored_completion_edge_plans(name, flags, mfb):
     a = mfb.SparseBarrier(pat, flags=fl)
     a.completion(dev(s))
     close(None, got, host(a.export_ldl()))
+
+
+@pytest.mark.parametrize("name", ["fig1", "band200", "forest", "tree300", "arrow_small", "arrow_mixed", "dense528",
+                                  "roots_mixed", "grid2d_24", "grid3d_8", "band300_40"])
+def test_factored_inverse_hessian_matches_oracle(name, mfb):
+    """mfb_inv_hessian_factored (S_AA through the R_s of the factored
+    completion) against the oracle's Algorithm 5.2 at X, and against
+    mfb_inv_hessian (S_AA through its cached inverse factors)."""
+    pat = PATS[name]()
+    print(f"[gpu-factored] inverse Hessian {name}", flush=True)
+    x = V.make_x(*pat, seed=0)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    ts = V.make_ys(*pat, 3, seed=7)
+    b = mfb.SparseBarrier(pat)
+    b.completion_factored(dev(s))
+    got = host(b.inv_hessian_factored(dev(ts)))
+    for r in range(3):
+        close(pat, got[r], oracle.inv_hessian(pat, ldl, s, ts[r]))
+    # one right-hand side alone gives its bits inside the batch; the call
+    # leaves R_s in place (a second call gives the same bits)
+    assert np.array_equal(host(b.inv_hessian_factored(dev(ts[1]))), got[1])
+    a = mfb.SparseBarrier(pat)
+    a.completion(dev(s))
+    plain = host(a.inv_hessian(dev(ts)))
+    for r in range(3):
+        close(pat, got[r], plain[r])
+
+
+def test_factored_inverse_hessian_state_rules(mfb):
+    """R_s must come from the last factor of the handle: refused after a
+    plain factor, after a product or a plain inverse Hessian (both rewrite
+    the update arena); allowed after a Hessian, which does not."""
+    pat = PATS["arrow_mixed"]()
+    x = V.make_x(*pat, seed=0)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    t = dev(V.make_ys(*pat, 1, seed=2))
+    b = mfb.SparseBarrier(pat)
+    b.factor(dev(x))
+    for step in ("factor", "product", "plain", "hessian"):
+        if step != "factor":
+            b.completion_factored(dev(s))
+        if step == "product":
+            b.cholesky_product()
+        elif step == "plain":
+            b.inv_hessian(t)
+        elif step == "hessian":
+            b.hessian(t)
+        if step == "hessian":
+            y = host(b.inv_hessian_factored(t))
+            close(pat, y[0] if y.ndim == 2 else y, oracle.inv_hessian(pat, ldl, s, host(t)[0]))
+        else:
+            with pytest.raises(mfb.MfbError) as e:
+                b.inv_hessian_factored(t)
+            assert e.value.code == mfb.ESTATE, step

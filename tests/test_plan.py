@@ -125,7 +125,7 @@ def test_forest_and_diagonal_plans():
 
 def test_library_exports_every_header_symbol():
     names = mfb.header_symbols()
-    assert len(names) == 30
+    assert len(names) == 31
     lib = ctypes.CDLL(mfb.LIB_PATH)
     for name in names:
         assert hasattr(lib, name), name
