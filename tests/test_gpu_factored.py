@@ -208,3 +208,26 @@ def test_factored_inverse_hessian_state_rules(mfb):
             with pytest.raises(mfb.MfbError) as e:
                 b.inv_hessian_factored(t)
             assert e.value.code == mfb.ESTATE, step
+
+
+def test_factored_completion_large_grid_sampled(mfb):
+    """The 40^3 grid at full size: the factored completion of the gradient
+    S = P(X^-1) gives the factor of X, checked against the oracle's factor
+    values stored at 6712 sampled positions and its log det, and X-hat = X
+    on the whole array."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "grid3d_40_samples.npz"))
+    pat = get_config("grid3d_40")
+    idx = g["idx"]
+    x = V.make_x(*pat, seed=0)
+    print("[gpu-factored] grid3d_40: factor and gradient", flush=True)
+    b = mfb.SparseBarrier(pat)
+    b.factor(dev(x))
+    s = b.projected_inverse().clone()
+    print("[gpu-factored] grid3d_40: factored completion", flush=True)
+    b.completion_factored(s)
+    assert b.status() == (0, -1)
+    close(None, host(b.export_ldl())[idx], g["ldl"])
+    ld = float(host(b.logdet())[0])
+    assert abs(ld - float(g["logdet"])) / abs(float(g["logdet"])) <= TOL
+    close(pat, host(b.cholesky_product()), x)
