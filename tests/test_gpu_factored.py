@@ -231,3 +231,37 @@ def test_factored_completion_large_grid_sampled(mfb):
     ld = float(host(b.logdet())[0])
     assert abs(ld - float(g["logdet"])) / abs(float(g["logdet"])) <= TOL
     close(pat, host(b.cholesky_product()), x)
+
+
+ILL = [("chordal150", 1e-2), ("chordal150", 1e-4), ("chordal150", 1e-6), ("band200", 1e-4), ("band200", 1e-6),
+       ("arrow_small", 1e-6), ("arrow_mixed", 1e-5), ("grid2d_24", 1e-6)]
+
+
+@pytest.mark.parametrize("name,delta", ILL)
+def test_factored_paths_ill_conditioned(name, delta, mfb):
+    """X = (weighted graph Laplacian) + delta I, kappa up to about 1e8, with
+    the tolerances of test_gpu_parity.test_ill_conditioned: the factored
+    completion (Householder row deletion) to max(1e-10, 10 kappa eps), and
+    the inverse Hessian through its R_s to max(1e-10, 10 kappa^2 eps) while
+    that stays below 1e-6; both against the oracle."""
+    from tests.test_gpu_parity import CASES as C
+    pat = C[name]()
+    x = V.make_x_laplacian(*pat, delta, seed=3)
+    ev = np.linalg.eigvalsh(V.to_dense(*pat, x))
+    kappa = float(ev[-1] / ev[0])
+    eps = np.finfo(np.float64).eps
+    tol = max(TOL, 10 * kappa * eps)
+    tol_ih = max(TOL, 10 * kappa ** 2 * eps)
+    ldl = oracle.factor(pat, x)
+    s = oracle.projinv(pat, ldl)
+    b = mfb.SparseBarrier(pat)
+    b.completion_factored(dev(s))
+    assert b.status() == (0, -1)
+    errs = {"kappa": kappa}
+    errs["ldl"] = close(None, host(b.export_ldl()), oracle.completion_factored(pat, s), tol)
+    if tol_ih <= 1e-6:
+        t = oracle.hessian(pat, ldl, s, V.make_ys(*pat, 1, seed=4)[0])
+        errs["inv_hessian"] = close(pat, host(b.inv_hessian_factored(dev(t))), oracle.inv_hessian(pat, ldl, s, t),
+                                    tol_ih)
+    errs["xhat"] = close(pat, host(b.cholesky_product()), x, tol)
+    print(f"[gpu-factored] ill-conditioned {name} delta={delta:g}: {errs}", flush=True)
