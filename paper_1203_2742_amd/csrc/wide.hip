@@ -54,20 +54,6 @@ __device__ __forceinline__ void tri_tile(int l, int& ti, int& tj) {
   tj = l - t * (t + 1) / 2;
 }
 
-// Index of parent front position p in a child's increasing relative-index
-// list rl[0 .. Ac), or -1.
-__device__ __forceinline__ int find_rel(const int32_t* rl, int Ac, int p) {
-  int lo = 0, hi = Ac;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (rl[mid] < p)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return (lo < Ac && rl[lo] == p) ? lo : -1;
-}
-
 // First index t of a child's increasing relative-index list rl[0 .. Ac)
 // with rl[t] >= p (Ac when there is none), by a 64-way search of each
 // wavefront: every round probes 64 increasing positions at once and keeps
@@ -86,6 +72,20 @@ __device__ __forceinline__ int lower_rel(const int32_t* rl, int Ac, int p) {
   }
   const bool lt = lane < hi - lo && rl[lo + lane] < p;
   return lo + __popcll(__ballot(lt));
+}
+
+// map[t] = the position x in a child's increasing relative-index list
+// rl[0 .. Ac) with rl[x] = p0 + t, for the 64 parent positions p0 ..
+// p0 + 63 below pend, else -1.  The child's entries in that window are one
+// run of rl, found by two 64-way searches, then stored one per lane (a
+// strictly increasing list has at most 64 of them).  Called by one whole
+// wavefront; the caller synchronizes before map is read.
+__device__ __forceinline__ void rel_window(const int32_t* rl, int Ac, int p0, int pend, int* map) {
+  const int lane = int(threadIdx.x) & 63;
+  map[lane] = -1;
+  const int xb = lower_rel(rl, Ac, p0), xe = lower_rel(rl, Ac, min(p0 + WT, pend));
+  wave_sync();
+  if (xb + lane < xe) map[rl[xb + lane] - p0] = xb + lane;
 }
 
 // ---------------------------------------------------------------------------
@@ -174,9 +174,9 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
       const double* Uc = ua + P.arena[c];
       const int tid = threadIdx.x;
       if (tid < WT)
-        invr[tid] = i0 + tid < A ? find_rel(rl, Ac, N + i0 + tid) : -1;
+        rel_window(rl, Ac, N + i0, N + A, invr);
       else if (tid < 2 * WT)
-        invc[tid - WT] = j0 + tid - WT < A ? find_rel(rl, Ac, N + j0 + tid - WT) : -1;
+        rel_window(rl, Ac, N + j0, N + A, invc);
       __syncthreads();
       const int cx = invr[row];
       double u[16];
@@ -792,9 +792,9 @@ __global__ void __launch_bounds__(NT) k_fat_panel(DevPlan P, const int32_t* list
       const double* Uc = ua + P.arena[c];
       const int tid = threadIdx.x;
       if (tid < WT)
-        invr[tid] = i0 + tid < d.J ? find_rel(rl, Ac, i0 + tid) : -1;
+        rel_window(rl, Ac, i0, d.J, invr);
       else if (tid < 2 * WT)
-        invc[tid - WT] = j0 + tid - WT < d.N ? find_rel(rl, Ac, j0 + tid - WT) : -1;
+        rel_window(rl, Ac, j0, d.N, invc);
       __syncthreads();
       const int cx = invr[row];
       double u[16];
