@@ -1557,12 +1557,14 @@ __global__ void __launch_bounds__(NT) k_up_panel_tiles(DevPlan P, const int32_t*
         const int Ac = P.nrow[c] - P.ncol[c];
         const int32_t* rl = P.rel + P.relbase[c];
         const double* Uc = ua + P.arena[c];
-        const int xb = lower_rel(rl, Ac, lo), xe = lower_rel(rl, Ac, hi);
-        for (int yy = 0; yy < Ac; ++yy) {
-          const int ry = rl[yy];  // the same for every thread
-          if (ry >= N) break;
-          for (int x = max(xb, yy) + int(threadIdx.x); x < xe; x += NT)
-            G[(rl[x] - lo) + (int64_t)ry * ld] += Uc[pk(x, yy, Ac)];
+        // the child's rows in [lo, hi) (at most 64) times its columns that
+        // land in the front's N columns, all pairs at once: each pair has
+        // its own entry of G, which takes one term per child
+        const int xb = lower_rel(rl, Ac, lo), xe = lower_rel(rl, Ac, hi), yc = lower_rel(rl, Ac, N);
+        const int nx = xe - xb;
+        for (int e = int(threadIdx.x); e < yc * nx; e += NT) {
+          const int yy = e / nx, x = xb + (e - yy * nx);
+          if (x >= yy) G[(rl[x] - lo) + (int64_t)rl[yy] * ld] += Uc[pk(x, yy, Ac)];
         }
         __syncthreads();
       }
