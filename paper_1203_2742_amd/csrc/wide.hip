@@ -114,7 +114,9 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
                                                     int count, const double* R, const double* LB,
                                                     const double* Kt, double* Ua, int64_t upd,
                                                     const double* wsb, int64_t slot, const int32_t* act) {
-  __shared__ double p1[WKC * WLD], p2[WKC * WLD];
+  // the product's staging (tile_mma), then its 64 x 64 result in the
+  // threads' layout of the gather below
+  __shared__ double lds[2 * WKC * WLD];
   __shared__ int invr[WT], invc[WT];
   __shared__ int64_t colc[kColCache];
   const int b = blockIdx.x;
@@ -144,25 +146,15 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
       return k < N ? LB[v.an(y, k)] : K[v.an(y, k - N)];
     };
     const int KK = (OP == WU_FACTOR || OP == WU_PRODUCT) ? N : 2 * N;
+    {
+      MfmaTile T(threadIdx.x);
+      tile_mma(T, i0, j0, A, A, 0, KK, P1, [&](int k, int y) { return P2(y, k); }, lds);
+      tile_store(T, 0, 0, WT, WT, [&](int i, int j, double a) { lds[i + j * WLD] = a; }, false);
+    }
+    __syncthreads();
     double acc[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int k0 = 0; k0 < KK; k0 += WKC) {
-      for (int e = threadIdx.x; e < WKC * WT; e += NT) {
-        const int x = e & (WT - 1), kk = e >> 6;
-        const bool okk = k0 + kk < KK;
-        p1[kk * WLD + x] = (okk && i0 + x < A) ? P1(i0 + x, k0 + kk) : 0.0;
-        p2[kk * WLD + x] = (okk && j0 + x < A) ? P2(j0 + x, k0 + kk) : 0.0;
-      }
-      __syncthreads();
-      const int kn = min(WKC, KK - k0);
-      for (int kk = 0; kk < kn; ++kk) {
-        const double a = p1[kk * WLD + row];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = fma(a, p2[kk * WLD + cq + 4 * q], acc[q]);
-      }
-      __syncthreads();
-    }
+    for (int q = 0; q < 16; ++q) acc[q] = lds[row + (cq + 4 * q) * WLD];
     double g[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) g[q] = 0.0;
