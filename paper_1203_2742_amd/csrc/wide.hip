@@ -840,6 +840,7 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t*
                                                        int64_t slot) {
   constexpr FatSquare q{SQ};
   __shared__ double sm[SMEM_DOUBLES];
+  __shared__ double d64[NB2 * LD2];  // the diagonal block, factored and inverted in LDS
   __shared__ int64_t colc[kColCache];
   __shared__ int fail;
   const int f = blockIdx.y;
@@ -849,18 +850,31 @@ __global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t*
     double* F = fat_F(wsb, f, slot, q, v.N, v.A);
     double* Ci = F + (int64_t)J * v.N + (int64_t)(kb / WT) * WT * WT;
     if (threadIdx.x == 0) fail = -1;
-    __syncthreads();
     const DenseAt G{F + kb + (int64_t)kb * J, J};
-    wg_potrf_acc(G, nb, nb, sm, &fail);
+    const DenseAt D{d64, LD2};
     for (int e = threadIdx.x; e < WT * WT; e += NT) {
       const int i = e & (WT - 1), j = e >> 6;
-      Ci[e] = (i < nb && j < nb && i >= j) ? G(i, j) : 0.0;
-      if (!q.sq && i < nb && j < nb && i >= j) R[v.at(kb + i, kb + j)] = G(i, j);
+      D(i, j) = (i < nb && j < nb && i >= j) ? G(i, j) : 0.0;
     }
     __syncthreads();
-    wg_trtri_inplace(DenseAt{Ci, WT}, nb, sm);
+    wg_potrf_acc(D, nb, nb, sm, &fail);
+    __syncthreads();
     double lg = 0.0;
-    for (int c = threadIdx.x; c < nb; c += NT) lg += 2.0 * log(G(c, c));
+    for (int c = threadIdx.x; c < nb; c += NT) lg += 2.0 * log(D(c, c));
+    for (int e = threadIdx.x; e < WT * WT; e += NT) {
+      const int i = e & (WT - 1), j = e >> 6;
+      if (i < nb && j < nb && i >= j) {
+        G(i, j) = D(i, j);
+        if (!q.sq) R[v.at(kb + i, kb + j)] = D(i, j);
+      }
+    }
+    __syncthreads();
+    wg_trtri_inplace(D, nb, sm);
+    __syncthreads();
+    for (int e = threadIdx.x; e < WT * WT; e += NT) {
+      const int i = e & (WT - 1), j = e >> 6;
+      Ci[e] = (i < nb && j < nb && i >= j) ? D(i, j) : 0.0;
+    }
     lg = wg_sum(lg, sm);
     if (threadIdx.x == 0) {
       const double part_ = q.sq ? -lg : lg;
