@@ -1319,6 +1319,35 @@ __global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list
   });
 }
 
+// Stage 2 of k_fat_ihess on a segment whose fronts all have at most
+// SMALL_N columns: their one NN tile, one workgroup per front and
+// right-hand side (grid.x = 1), with only the vector-unit product compiled
+// in, so that the kernel keeps few registers and little LDS (more
+// workgroups per CU than the stage-2 kernel with its matrix-core paths).
+// The same sums as k_fat_ihess<2> on these fronts.
+__global__ void __launch_bounds__(NT) k_fat_ihess_small2(DevPlan P, const int32_t* list, int count,
+                                                         const double* LB, const double* Tin, double* wsb,
+                                                         int64_t slot) {
+  __shared__ double sm[4 * SMALL_N * (SMALL_N + 1) / 2];
+  __shared__ int64_t colc[kColCache];
+  const int f = blockIdx.y % count;
+  const int64_t r = blockIdx.y / count;
+  with_staged_cols(SnView(P, list[f]), colc, [&](const SnView& v) __attribute__((always_inline)) {
+    const int N = v.N, A = v.A;
+    const double* t = Tin + r * P.nnz;
+    double* MA = wsb + (r * count + f) * slot;
+    double* MN = MA + 2 * (int64_t)A * N;  // after MA and Z
+    auto fa = [&](int k, int i) { return k < A ? LB[v.an(k, i)] : t[v.an(k - A, i)]; };
+    auto fb = [&](int k, int j) { return k < A ? MA[k + (int64_t)j * A] : LB[v.an(k - A, j)]; };
+    auto out = [&](int i, int j, double acc) {
+      const double m = t[v.at(i, j)] + acc;
+      MN[i + (int64_t)j * N] = m;
+      MN[j + (int64_t)i * N] = m;
+    };
+    small_nn_dot(N, 2 * A, fa, fb, out, sm);
+  });
+}
+
 // Stages 4 (AN tiles) and 5 of the fat inverse Hessian, right-hand sides
 // batched along the columns (RhsCols; the cached V_s^-1 or C_V^-1 is read
 // once per 64 columns): STAGE 4: K_AN = V_s^-1 Z with the explicit inverse,
@@ -1789,7 +1818,10 @@ void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, 
     double* K = Kt + (int64_t)r0 * P.nnz;
     const double* va = Va + (int64_t)r0 * upd;
     k_fat_ihess<1><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
-    k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
+    if (g.maxN <= SMALL_N)
+      k_fat_ihess_small2<<<dim3(1, unsigned(count * kk)), NT, 0, s>>>(P, list, count, LB, t, wsb, slot);
+    else
+      k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
     k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
     k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
     if (g.maxA > 0) {
