@@ -1818,12 +1818,15 @@ void launch_fat_ihess(const FatGrid& g, int k, hipStream_t s, const DevPlan& P, 
     double* K = Kt + (int64_t)r0 * P.nnz;
     const double* va = Va + (int64_t)r0 * upd;
     k_fat_ihess<1><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
+    // stages 2 and 4 work on the NN tiles only: a segment whose fronts have
+    // at most 64 columns needs its tile 0 alone
+    const dim3 gnn(g.maxN <= WT ? 1u : unsigned(g.fin), unsigned(count * kk));
     if (g.maxN <= SMALL_N)
       k_fat_ihess_small2<<<dim3(1, unsigned(count * kk)), NT, 0, s>>>(P, list, count, LB, t, wsb, slot);
     else
-      k_fat_ihess<2><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
+      k_fat_ihess<2><<<gnn, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
     k_fat_ihess<3><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
-    k_fat_ihess<4><<<grid, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
+    k_fat_ihess<4><<<gnn, NT, 0, s>>>(P, list, count, R, LB, Vi, t, K, va, upd, wsb, slot, part, pstride, r0);
     if (g.maxA > 0) {
       const int ct = RhsCols(std::max(1, g.maxN), kk).ct, ta = (g.maxA + WT - 1) / WT;
       const dim3 gan(unsigned(ta * ct), unsigned(count));
