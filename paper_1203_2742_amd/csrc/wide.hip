@@ -110,7 +110,7 @@ __device__ __forceinline__ void rel_window(const int32_t* rl, int Ac, int p0, in
 enum { WU_FACTOR = 0, WU_HUP = 1, WU_IHUP = 2, WU_PRODUCT = 3 };
 
 template <int OP>
-__global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* list, const int32_t* pre,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_wide_update(DevPlan P, const int32_t* list, const int32_t* pre,
                                                     int count, const double* R, const double* LB,
                                                     const double* Kt, double* Ua, int64_t upd,
                                                     const double* wsb, int64_t slot, const int32_t* act) {
@@ -152,9 +152,8 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
       tile_store(T, 0, 0, WT, WT, [&](int i, int j, double a) { lds[i + j * WLD] = a; }, false);
     }
     __syncthreads();
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = lds[row + (cq + 4 * q) * WLD];
+    // the product stays in LDS through the children's gather (read back
+    // at the store), which keeps the gather's registers few
     double g[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) g[q] = 0.0;
@@ -188,7 +187,7 @@ __global__ void __launch_bounds__(NT) k_wide_update(DevPlan P, const int32_t* li
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int gj = j0 + cq + 4 * q;
-      if (gi < A && gj < A && gi >= gj) Us[pk(gi, gj, A)] = g[q] - acc[q];
+      if (gi < A && gj < A && gi >= gj) Us[pk(gi, gj, A)] = g[q] - lds[row + (cq + 4 * q) * WLD];
     }
   });
 }
@@ -683,7 +682,7 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_vz(DevPlan P, const int32_t* 
       false);
 }
 
-__global__ void __launch_bounds__(NT) k_wide_hdown_c(DevPlan P, const int32_t* list, SegTiles tl, int count,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_wide_hdown_c(DevPlan P, const int32_t* list, SegTiles tl, int count,
                                                      const double* LB, double* T, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
@@ -1219,7 +1218,7 @@ __global__ void __launch_bounds__(NT) k_fat_compl_lauum(DevPlan P, const int32_t
 //  4: K_NN = Dm W (lower NN tiles); the AN tiles and stage 5 run in
 //     k_fat_ihess_an with the right-hand sides batched.
 template <int STAGE>
-__global__ void __launch_bounds__(NT) k_fat_ihess(DevPlan P, const int32_t* list, int count, const double* R,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(STAGE == 2 ? 2 : 4))) k_fat_ihess(DevPlan P, const int32_t* list, int count, const double* R,
                                                   const double* LB, const double* Vi, const double* Tin,
                                                   double* Kt, const double* Va, int64_t upd, double* wsb,
                                                   int64_t slot, const double* part, int64_t pstride, int r0) {
@@ -1354,7 +1353,7 @@ __global__ void __launch_bounds__(NT) k_fat_ihess_small2(DevPlan P, const int32_
 // else MA = C_V^-1 Z; STAGE 5: K_AN = C_V^-T MA (factored form only).
 // blockIdx.y: front of the segment; blockIdx.x: 64-row tile x column tile.
 template <int STAGE>
-__global__ void __launch_bounds__(NT) k_fat_ihess_an(DevPlan P, const int32_t* list, int count, int k, int ct_max,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_fat_ihess_an(DevPlan P, const int32_t* list, int count, int k, int ct_max,
                                                      const double* Vi, double* Kt, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ int64_t colc[kColCache];
@@ -1566,7 +1565,7 @@ __global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* lis
 //     goes to the (front, right-hand side) scratch slot, after the J x N
 //     panel area, where k_wide_update reads it.
 template <int UP>
-__global__ void __launch_bounds__(NT) k_up_panel_tiles(DevPlan P, const int32_t* list, int count, int ta,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_up_panel_tiles(DevPlan P, const int32_t* list, int count, int ta,
                                                        const double* R, const double* LB, const double* Kt,
                                                        double* Y, const double* Ua, int64_t upd, double* wsb,
                                                        int64_t slot) {
