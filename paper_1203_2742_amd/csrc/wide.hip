@@ -507,7 +507,7 @@ struct RhsCols {
 // Algorithm 7.2 on wide fronts (after k_wide_extract has put V_s in place):
 // S_AN = -V_s L_AN over the AN tiles, then S_NN = D^-1 - S_AN^T L_AN over
 // the lower NN tiles.
-__global__ void __launch_bounds__(NT) k_wide_projinv_an(DevPlan P, const int32_t* list, const int32_t* pre,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_wide_projinv_an(DevPlan P, const int32_t* list, const int32_t* pre,
                                                         int count, const double* LB, double* S,
                                                         const double* Vs) {
   __shared__ double sm[SMEM_DOUBLES];
@@ -561,7 +561,7 @@ struct SegTiles {
   int n_aa, n_an, n_nn;
 };
 
-__global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* list, SegTiles tl, int count,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_wide_hdown_a(DevPlan P, const int32_t* list, SegTiles tl, int count,
                                                      const double* LB, const double* Kt, const double* T,
                                                      double* Va, int64_t upd, double* wsb, int64_t slot,
                                                      double* part, int64_t pstride) {
@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_a(DevPlan P, const int32_t* l
   });
 }
 
-__global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* list, SegTiles tl, int count,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_wide_hdown_b(DevPlan P, const int32_t* list, SegTiles tl, int count,
                                                      const double* LB, const double* Vs, double* T,
                                                      const double* Va, int64_t upd, double* wsb, int64_t slot,
                                                      const double* part, int64_t pstride) {
@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(NT) k_wide_hdown_b(DevPlan P, const int32_t* l
 
 // MA_r = V_s Z_r for every right-hand side r of every front of the segment
 // (blockIdx.y), 64-row tile x RhsCols column tile per workgroup.
-__global__ void __launch_bounds__(NT) k_wide_hdown_vz(DevPlan P, const int32_t* list, int count, int k, int ct_max,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_wide_hdown_vz(DevPlan P, const int32_t* list, int count, int k, int ct_max,
                                                       const double* Vs, double* wsb, int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
   const int f = blockIdx.y;
@@ -834,7 +834,7 @@ __device__ __forceinline__ double* fat_F(double* wsb, int f, int64_t slot, const
 }
 
 template <int SQ>
-__global__ void __launch_bounds__(NT) k_fat_potrf_diag(DevPlan P, const int32_t* list, int count, int kb,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_fat_potrf_diag(DevPlan P, const int32_t* list, int count, int kb,
                                                        double* R, double* part, DevStatus* st, double* wsb,
                                                        int64_t slot) {
   constexpr FatSquare q{SQ};
@@ -1018,7 +1018,7 @@ __global__ void __launch_bounds__(NT) k_fat_factor_fin(DevPlan P, const int32_t*
 //               after the panel), Y_AN = Q - G'21 (inverse Hessian step 3).
 enum { FAT_PRODUCT = 0, FAT_HUP = 1, FAT_IHUP = 2 };
 template <int OP>
-__global__ void __launch_bounds__(NT) k_fat_up_fin(DevPlan P, const int32_t* list, int count, const double* R,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_fat_up_fin(DevPlan P, const int32_t* list, int count, const double* R,
                                                    const double* LB, double* Out, double* Kt, double* wsb,
                                                    int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
@@ -1106,7 +1106,7 @@ __global__ void __launch_bounds__(NT) k_fat_up_fin(DevPlan P, const int32_t* lis
 //       C(i, j) = X(N-1-j, N-1-i), without inverting M explicitly;
 //  c:   R_NN = C and R_AN = L_AN C (NN and AN tiles);
 //  lauum: the explicit V_s^-1 for A <= kVExplicitMax, in place.
-__global__ void __launch_bounds__(NT) k_fat_compl_prep(DevPlan P, const int32_t* list, const double* Sin,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_fat_compl_prep(DevPlan P, const int32_t* list, const double* Sin,
                                                        double* S, const double* Vs, double* Vi, DevStatus* st) {
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ double d64[NB2 * LD2];
@@ -1133,7 +1133,7 @@ __global__ void __launch_bounds__(NT) k_fat_compl_prep(DevPlan P, const int32_t*
 }
 
 template <int STAGE>
-__global__ void __launch_bounds__(NT) k_fat_compl(DevPlan P, const int32_t* list, int count, const double* Sin,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_fat_compl(DevPlan P, const int32_t* list, int count, const double* Sin,
                                                   double* R, double* LB, const double* Vi, double* wsb,
                                                   int64_t slot) {
   __shared__ double sm[SMEM_DOUBLES];
@@ -1462,7 +1462,7 @@ __global__ void __launch_bounds__(NT) k_bigv_copy(DevPlan P, const int32_t* list
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(NT) k_bigv_diag(DevPlan P, const int32_t* list, int kb, double* Cb, double* Out,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_bigv_diag(DevPlan P, const int32_t* list, int kb, double* Cb, double* Out,
                                                   DevStatus* st) {
   constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_DOUBLES];
@@ -1497,7 +1497,7 @@ __global__ void __launch_bounds__(NT) k_bigv_diag(DevPlan P, const int32_t* list
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(NT) k_bigv_panel(DevPlan P, const int32_t* list, int kb, double* Cb,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_panel(DevPlan P, const int32_t* list, int kb, double* Cb,
                                                    const double* Out) {
   constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
@@ -1525,7 +1525,7 @@ __global__ void __launch_bounds__(NT) k_bigv_panel(DevPlan P, const int32_t* lis
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(NT) k_bigv_trtri(DevPlan P, const int32_t* list, int ib, const double* Cb,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_trtri(DevPlan P, const int32_t* list, int ib, const double* Cb,
                                                    double* Out) {
   constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
