@@ -1433,7 +1433,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
 //         diagonal block of Out, where the inverse ends up anyway);
 //  panel: its row tiles below, C_ik = (V_ik - C_i,<k C_k,<k^T) C_kk^-T;
 //  trtri: row block ib of X = C^-1 from the rows above it,
-//         X_ib,jb = -X_ib,ib sum_{jb <= m < ib} C_ib,m X_m,jb.
+//         X_ib,jb = -X_ib,ib sum_{jb <= m < ib} C_ib,m X_m,jb,
+//         in the launch of block column ib's panel.
 // MODE names the caller (0: the inverse Hessian's cache, 1: the
 // completion, 2: the Hessian factor); MODE 2 runs all of it on the
 // reversed view of the packed blocks (entry (i, j) of the view at the
@@ -1496,17 +1497,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
   if (threadIdx.x == 0 && fail >= 0) report(st, MODE == 1 ? MFB_ENOCOMPLETION : MFB_ENOTPD, P.vlabel[P.colbase[s]]);
 }
 
+// panel: row tile `tile` below the diagonal block of block column kb; sm
+// and rb are the workgroup's LDS.
 template <int MODE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_panel(DevPlan P, const int32_t* list, int kb, double* Cb,
-                                                   const double* Out) {
+__device__ __forceinline__ void bigv_panel_tile(const DevPlan& P, int s, int kb, int tile, double* Cb,
+                                                const double* Out, double* sm, double* rb) {
   constexpr bool REV = MODE == 2;
-  __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
-  __shared__ double rb[WT * WLD];
-  const int s = list[blockIdx.y];
   const int A = P.nrow[s] - P.ncol[s];
   if (A <= P.big_a || kb >= A) return;
   const int nb = min(WT, A - kb);
-  const int i0 = kb + nb + int(blockIdx.x) * WT;
+  const int i0 = kb + nb + tile * WT;
   if (i0 >= A) return;
   const PView<REV> F{Cb + P.arena[s], A};
   const PView<REV> X{const_cast<double*>(Out) + P.arena[s], A};
@@ -1524,15 +1524,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
   tile_store(T2, 0, 0, min(WT, A - i0), nb, [&](int i, int j, double acc) { F(i0 + i, kb + j) = acc; }, false);
 }
 
+// trtri: tile (ib, jb) of X = C^-1 below the diagonal.
 template <int MODE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_trtri(DevPlan P, const int32_t* list, int ib, const double* Cb,
-                                                   double* Out) {
+__device__ __forceinline__ void bigv_trtri_tile(const DevPlan& P, int s, int ib, int jb, const double* Cb,
+                                                double* Out, double* sm, double* rb) {
   constexpr bool REV = MODE == 2;
-  __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
-  __shared__ double rb[WT * WLD];
-  const int s = list[blockIdx.y];
   const int A = P.nrow[s] - P.ncol[s];
-  const int i0 = ib * WT, jb = blockIdx.x, j0 = jb * WT;
+  const int i0 = ib * WT, j0 = jb * WT;
   if (A <= P.big_a || i0 >= A || jb >= ib) return;
   const int nbi = min(WT, A - i0);
   const PView<REV> F{const_cast<double*>(Cb) + P.arena[s], A}, X{Out + P.arena[s], A};
@@ -1547,6 +1545,28 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
   tile_mma(T2, 0, 0, nbi, WT, 0, nbi, [&](int i, int k) { return k <= i ? X(i0 + i, i0 + k) : 0.0; },
            [&](int k, int j) { return rb[k + j * WLD]; }, sm);
   tile_store(T2, 0, 0, nbi, WT, [&](int i, int j, double acc) { X(i0 + i, j0 + j) = acc; }, false);
+}
+
+// The panel of block column kb and row block ib = kb / 64 of the inverse in
+// one launch: workgroups x < rows take panel row tile x, the others tile
+// (ib, x - rows) of the inverse.  The two parts touch disjoint data: the
+// panel writes the factor's column block kb below its diagonal block and
+// reads the inverse's diagonal block kb only; the inverse's row block ib
+// reads the factor's row block ib left of column block kb, finished by the
+// panels before kb, the inverse's rows above it and its diagonal block kb
+// (all from earlier launches), and writes its row block ib left of the
+// diagonal block.  So the inverse's rows run beside the factor's panels,
+// which alone leave most of the chip idle at the last block columns.
+template <int MODE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_panel_trtri(DevPlan P, const int32_t* list, int kb, int rows,
+                                                         double* Cb, double* Out) {
+  __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
+  __shared__ double rb[WT * WLD];
+  const int s = list[blockIdx.y], x = int(blockIdx.x);
+  if (x < rows)
+    bigv_panel_tile<MODE>(P, s, kb, x, Cb, Out, sm, rb);
+  else
+    bigv_trtri_tile<MODE>(P, s, kb / WT, x - rows, Cb, Out, sm, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1779,17 +1799,17 @@ static void bigv_launches(int maxA, int count, const int32_t* acnt, hipStream_t 
   const int64_t m = (int64_t)maxA * (maxA + 1) / 2;
   k_bigv_copy<MODE><<<dim3(unsigned(std::min<int64_t>(64, (m + NT * 16 - 1) / (NT * 16))), unsigned(count)), NT, 0,
                       s>>>(P, list, Vs, Cb);
+  // block column kb: its diagonal block, then its panel beside row block
+  // kb / 64 of the inverse (which needs that diagonal block's inverse and
+  // nothing of the panel)
   for (int kb = 0; kb < maxA; kb += WT) {
     const int rows = (maxA - kb - 1) / WT;  // row tiles below the diagonal block (largest front)
-    if (const int c = fronts(kb)) k_bigv_diag<MODE><<<dim3(1, unsigned(c)), NT, 0, s>>>(P, list, kb, Cb, Out, st);
-    if (rows > 0)
-      if (const int c = fronts(kb + WT))
-        k_bigv_panel<MODE><<<dim3(unsigned(rows), unsigned(c)), NT, 0, s>>>(P, list, kb, Cb, Out);
+    const int c = fronts(kb);
+    if (c == 0) break;
+    k_bigv_diag<MODE><<<dim3(1, unsigned(c)), NT, 0, s>>>(P, list, kb, Cb, Out, st);
+    if (rows + kb / WT > 0)
+      k_bigv_panel_trtri<MODE><<<dim3(unsigned(rows + kb / WT), unsigned(c)), NT, 0, s>>>(P, list, kb, rows, Cb, Out);
   }
-  const int ta = (maxA + WT - 1) / WT;
-  for (int ib = 1; ib < ta; ++ib)
-    if (const int c = fronts(ib * WT))
-      k_bigv_trtri<MODE><<<dim3(unsigned(ib), unsigned(c)), NT, 0, s>>>(P, list, ib, Cb, Out);
 }
 
 void launch_bigv(int mode, int maxA, int count, const int32_t* acnt, hipStream_t s, const DevPlan& P,
