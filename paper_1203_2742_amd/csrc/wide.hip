@@ -1557,16 +1557,46 @@ __device__ __forceinline__ void bigv_trtri_tile(const DevPlan& P, int s, int ib,
 // (all from earlier launches), and writes its row block ib left of the
 // diagonal block.  So the inverse's rows run beside the factor's panels,
 // which alone leave most of the chip idle at the last block columns.
+//
+// Grid: packed (T.packed) when the list is in decreasing order of A and the
+// largest front has at most kBigvMaxRows row tiles below the diagonal
+// block: the first T.off[1] workgroups are panel row tile 0 of the first
+// T.off[1] fronts (those that have it), the next T.off[2] - T.off[1] row
+// tile 1, ..., then tile jb of the inverse's row block for the first T.ctr
+// fronts (those with A > kb), jb-major.  Otherwise rectangular: tile
+// blockIdx.x of front blockIdx.y, tiles beyond a front's A exit.
+constexpr int kBigvMaxRows = 64;
+struct BigvTiles {
+  int packed, rows, ctr;
+  int off[kBigvMaxRows + 1];
+};
+
 template <int MODE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_panel_trtri(DevPlan P, const int32_t* list, int kb, int rows,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_panel_trtri(DevPlan P, const int32_t* list, int kb, BigvTiles T,
                                                          double* Cb, double* Out) {
   __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
   __shared__ double rb[WT * WLD];
-  const int s = list[blockIdx.y], x = int(blockIdx.x);
-  if (x < rows)
+  int f, x;
+  if (T.packed) {
+    const int w = int(blockIdx.x);
+    if (w < T.off[T.rows]) {
+      x = 0;
+      while (T.off[x + 1] <= w) ++x;  // ends at x < rows: off[rows] > w
+      f = w - T.off[x];
+    } else {
+      const int r = w - T.off[T.rows];
+      x = T.rows + r / T.ctr;
+      f = r % T.ctr;
+    }
+  } else {
+    f = int(blockIdx.y);
+    x = int(blockIdx.x);
+  }
+  const int s = list[f];
+  if (x < T.rows)
     bigv_panel_tile<MODE>(P, s, kb, x, Cb, Out, sm, rb);
   else
-    bigv_trtri_tile<MODE>(P, s, kb / WT, x - rows, Cb, Out, sm, rb);
+    bigv_trtri_tile<MODE>(P, s, kb / WT, x - T.rows, Cb, Out, sm, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1807,8 +1837,20 @@ static void bigv_launches(int maxA, int count, const int32_t* acnt, hipStream_t 
     const int c = fronts(kb);
     if (c == 0) break;
     k_bigv_diag<MODE><<<dim3(1, unsigned(c)), NT, 0, s>>>(P, list, kb, Cb, Out, st);
-    if (rows + kb / WT > 0)
-      k_bigv_panel_trtri<MODE><<<dim3(unsigned(rows + kb / WT), unsigned(c)), NT, 0, s>>>(P, list, kb, rows, Cb, Out);
+    const int ib = kb / WT;
+    if (rows + ib == 0) continue;
+    BigvTiles T{};
+    T.rows = rows;
+    T.ctr = c;
+    if (acnt && rows <= kBigvMaxRows) {
+      // row tile x lies at 64 (ib + x + 1): the fronts with A above that
+      T.packed = 1;
+      for (int x = 0; x < rows; ++x) T.off[x + 1] = T.off[x] + fronts(kb + (x + 1) * WT);
+      const int64_t total = T.off[rows] + (int64_t)ib * c;
+      if (total > 0) k_bigv_panel_trtri<MODE><<<dim3(unsigned(total)), NT, 0, s>>>(P, list, kb, T, Cb, Out);
+    } else {
+      k_bigv_panel_trtri<MODE><<<dim3(unsigned(rows + ib), unsigned(c)), NT, 0, s>>>(P, list, kb, T, Cb, Out);
+    }
   }
 }
 
