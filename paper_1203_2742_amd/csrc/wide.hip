@@ -1427,7 +1427,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
 // A > big_a ("bigv"), tile-parallel over all such fronts of a list:
 // left-looking by 64-column block columns, each tile of the factor formed
 // once as one matrix-core k-loop over the block columns before it.
-//  copy:  V into Cb (the factor is formed in place there);
+// Each tile of V is read from Vs once, by the step that forms the factor's
+// tile at its place in Cb (Cb is written in full, Vs only read):
 //  diag:  block column kb's diagonal tile T = V_kk - C_k,<k C_k,<k^T,
 //         factored in LDS (C_kk into Cb) and inverted (C_kk^-1 into the
 //         diagonal block of Out, where the inverse ends up anyway);
@@ -1453,18 +1454,8 @@ struct PView {
 };
 
 template <int MODE>
-__global__ void __launch_bounds__(NT) k_bigv_copy(DevPlan P, const int32_t* list, const double* Vs, double* Cb) {
-  const int s = list[blockIdx.y];
-  const int A = P.nrow[s] - P.ncol[s];
-  if (A <= P.big_a) return;
-  const int64_t m = (int64_t)A * (A + 1) / 2, off = P.arena[s];
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (int64_t)gridDim.x * NT)
-    Cb[off + e] = Vs[off + e];
-}
-
-template <int MODE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_bigv_diag(DevPlan P, const int32_t* list, int kb, double* Cb, double* Out,
-                                                  DevStatus* st) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_bigv_diag(DevPlan P, const int32_t* list, int kb, const double* Vs,
+                                                  double* Cb, double* Out, DevStatus* st) {
   constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_DOUBLES];
   __shared__ double d64[NB2 * LD2];
@@ -1474,13 +1465,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
   if (A <= P.big_a || kb >= A) return;
   const int nb = min(WT, A - kb);
   const PView<REV> F{Cb + P.arena[s], A}, X{Out + P.arena[s], A};
+  const PView<REV> Vv{const_cast<double*>(Vs) + P.arena[s], A};
   MfmaTile T(threadIdx.x);
   tile_mma<REV, REV>(T, 0, 0, nb, nb, 0, kb, [&](int i, int k) { return F(kb + i, k); },
                      [&](int k, int j) { return F(kb + j, k); }, sm);
   for (int e = threadIdx.x; e < NB2 * LD2; e += NT) d64[e] = 0.0;
   if (threadIdx.x == 0) fail = -1;
   __syncthreads();
-  tile_store(T, 0, 0, nb, nb, [&](int i, int j, double acc) { d64[i + j * LD2] = F(kb + i, kb + j) - acc; }, true);
+  tile_store(T, 0, 0, nb, nb, [&](int i, int j, double acc) { d64[i + j * LD2] = Vv(kb + i, kb + j) - acc; }, true);
   __syncthreads();
   const DenseAt D{d64, LD2};
   wg_potrf_acc(D, nb, nb, sm, &fail);
@@ -1500,8 +1492,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
 // panel: row tile `tile` below the diagonal block of block column kb; sm
 // and rb are the workgroup's LDS.
 template <int MODE>
-__device__ __forceinline__ void bigv_panel_tile(const DevPlan& P, int s, int kb, int tile, double* Cb,
-                                                const double* Out, double* sm, double* rb) {
+__device__ __forceinline__ void bigv_panel_tile(const DevPlan& P, int s, int kb, int tile, const double* Vs,
+                                                double* Cb, const double* Out, double* sm, double* rb) {
   constexpr bool REV = MODE == 2;
   const int A = P.nrow[s] - P.ncol[s];
   if (A <= P.big_a || kb >= A) return;
@@ -1510,12 +1502,13 @@ __device__ __forceinline__ void bigv_panel_tile(const DevPlan& P, int s, int kb,
   if (i0 >= A) return;
   const PView<REV> F{Cb + P.arena[s], A};
   const PView<REV> X{const_cast<double*>(Out) + P.arena[s], A};
+  const PView<REV> Vv{const_cast<double*>(Vs) + P.arena[s], A};
   MfmaTile T(threadIdx.x);
   tile_mma<REV, REV>(T, i0, 0, A, nb, 0, kb, [&](int i, int k) { return F(i, k); },
                      [&](int k, int j) { return F(kb + j, k); }, sm);
   for (int e = threadIdx.x; e < WT * WLD; e += NT) rb[e] = 0.0;
   __syncthreads();
-  tile_store(T, i0, 0, A, nb, [&](int i, int j, double acc) { rb[(i - i0) + j * WLD] = F(i, kb + j) - acc; },
+  tile_store(T, i0, 0, A, nb, [&](int i, int j, double acc) { rb[(i - i0) + j * WLD] = Vv(i, kb + j) - acc; },
              false);
   __syncthreads();
   MfmaTile T2(threadIdx.x);
@@ -1573,7 +1566,7 @@ struct BigvTiles {
 
 template <int MODE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_bigv_panel_trtri(DevPlan P, const int32_t* list, int kb, BigvTiles T,
-                                                         double* Cb, double* Out) {
+                                                         const double* Vs, double* Cb, double* Out) {
   __shared__ double sm[SMEM_GEMM];  // tile_mma staging only
   __shared__ double rb[WT * WLD];
   int f, x;
@@ -1594,7 +1587,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
   }
   const int s = list[f];
   if (x < T.rows)
-    bigv_panel_tile<MODE>(P, s, kb, x, Cb, Out, sm, rb);
+    bigv_panel_tile<MODE>(P, s, kb, x, Vs, Cb, Out, sm, rb);
   else
     bigv_trtri_tile<MODE>(P, s, kb / WT, x - T.rows, Cb, Out, sm, rb);
 }
@@ -1826,9 +1819,6 @@ static void bigv_launches(int maxA, int count, const int32_t* acnt, hipStream_t 
   // prefix of the list (decreasing A); without acnt every front is launched
   // and the others exit
   auto fronts = [&](int kb) { return acnt ? std::min(count, acnt[kb / WT]) : count; };
-  const int64_t m = (int64_t)maxA * (maxA + 1) / 2;
-  k_bigv_copy<MODE><<<dim3(unsigned(std::min<int64_t>(64, (m + NT * 16 - 1) / (NT * 16))), unsigned(count)), NT, 0,
-                      s>>>(P, list, Vs, Cb);
   // block column kb: its diagonal block, then its panel beside row block
   // kb / 64 of the inverse (which needs that diagonal block's inverse and
   // nothing of the panel)
@@ -1836,7 +1826,7 @@ static void bigv_launches(int maxA, int count, const int32_t* acnt, hipStream_t 
     const int rows = (maxA - kb - 1) / WT;  // row tiles below the diagonal block (largest front)
     const int c = fronts(kb);
     if (c == 0) break;
-    k_bigv_diag<MODE><<<dim3(1, unsigned(c)), NT, 0, s>>>(P, list, kb, Cb, Out, st);
+    k_bigv_diag<MODE><<<dim3(1, unsigned(c)), NT, 0, s>>>(P, list, kb, Vs, Cb, Out, st);
     const int ib = kb / WT;
     if (rows + ib == 0) continue;
     BigvTiles T{};
@@ -1847,9 +1837,9 @@ static void bigv_launches(int maxA, int count, const int32_t* acnt, hipStream_t 
       T.packed = 1;
       for (int x = 0; x < rows; ++x) T.off[x + 1] = T.off[x] + fronts(kb + (x + 1) * WT);
       const int64_t total = T.off[rows] + (int64_t)ib * c;
-      if (total > 0) k_bigv_panel_trtri<MODE><<<dim3(unsigned(total)), NT, 0, s>>>(P, list, kb, T, Cb, Out);
+      if (total > 0) k_bigv_panel_trtri<MODE><<<dim3(unsigned(total)), NT, 0, s>>>(P, list, kb, T, Vs, Cb, Out);
     } else {
-      k_bigv_panel_trtri<MODE><<<dim3(unsigned(rows + ib), unsigned(c)), NT, 0, s>>>(P, list, kb, T, Cb, Out);
+      k_bigv_panel_trtri<MODE><<<dim3(unsigned(rows + ib), unsigned(c)), NT, 0, s>>>(P, list, kb, T, Vs, Cb, Out);
     }
   }
 }
