@@ -1458,7 +1458,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                                                   double* Cb, double* Out, DevStatus* st) {
   constexpr bool REV = MODE == 2;
   __shared__ double sm[SMEM_DOUBLES];
-  __shared__ double d64[NB2 * LD2];
+  // the diagonal tile as a packed lower triangle: the factorization and the
+  // inversion touch entries (i >= j) only, and half the LDS of a square
+  // tile lets three workgroups share a CU
+  __shared__ double d64[NB2 * (NB2 + 1) / 2];
   __shared__ int fail;
   const int s = list[blockIdx.y];
   const int A = P.nrow[s] - P.ncol[s];
@@ -1469,22 +1472,22 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
   MfmaTile T(threadIdx.x);
   tile_mma<REV, REV>(T, 0, 0, nb, nb, 0, kb, [&](int i, int k) { return F(kb + i, k); },
                      [&](int k, int j) { return F(kb + j, k); }, sm);
-  for (int e = threadIdx.x; e < NB2 * LD2; e += NT) d64[e] = 0.0;
+  for (int e = threadIdx.x; e < NB2 * (NB2 + 1) / 2; e += NT) d64[e] = 0.0;
   if (threadIdx.x == 0) fail = -1;
   __syncthreads();
-  tile_store(T, 0, 0, nb, nb, [&](int i, int j, double acc) { d64[i + j * LD2] = Vv(kb + i, kb + j) - acc; }, true);
+  const PackedLowerW D{d64, NB2};
+  tile_store(T, 0, 0, nb, nb, [&](int i, int j, double acc) { D(i, j) = Vv(kb + i, kb + j) - acc; }, true);
   __syncthreads();
-  const DenseAt D{d64, LD2};
   wg_potrf_acc(D, nb, nb, sm, &fail);
   for (int e = threadIdx.x; e < nb * nb; e += NT) {
     const int i = e % nb, j = e / nb;
-    if (i >= j) F(kb + i, kb + j) = d64[i + j * LD2];
+    if (i >= j) F(kb + i, kb + j) = D(i, j);
   }
   __syncthreads();
   wg_trtri_inplace(D, nb, sm);
   for (int e = threadIdx.x; e < nb * nb; e += NT) {
     const int i = e % nb, j = e / nb;
-    if (i >= j) X(kb + i, kb + j) = d64[i + j * LD2];
+    if (i >= j) X(kb + i, kb + j) = D(i, j);
   }
   if (threadIdx.x == 0 && fail >= 0) report(st, MODE == 1 ? MFB_ENOCOMPLETION : MFB_ENOTPD, P.vlabel[P.colbase[s]]);
 }
